@@ -1,0 +1,135 @@
+"""Seeded synthetic workloads shared by the tests, the smoke check and the benchmark.
+
+This module holds only problem descriptions and seeded random draws: grid
+sizes, boundary types, stretching parameters, the physical parameters
+(Re, Ha, Pm, Ma, tau, lid speed) and smooth random initial fields.  It holds
+none of the method's arithmetic; the HIP library and the oracle each derive
+their lattice parameters and metric factors from these descriptions with
+their own code.
+
+The workloads follow the paper's benchmark families (Sec. 8): the
+body-force channel of Sec. 8.1, the lid-driven cavity of Sec. 8.3 and the
+Hartmann flow of Sec. 8.4, all on tanh-clustered grids (Sec. 6.1).
+"""
+from __future__ import annotations
+
+import dataclasses
+from dataclasses import dataclass, field
+
+import numpy as np
+
+STORAGES = ("f64", "f32", "f16dev", "bf16dev")
+
+
+@dataclass
+class Case:
+    name: str
+    nx: int
+    ny: int
+    bc_x: str = "periodic"            # "periodic" | "wall"
+    bc_y: str = "wall"
+    stretch_x: tuple = ("uniform", 0.0)   # ("uniform", 0) | ("tanh", beta) | ("roberts", gamma)
+    stretch_y: tuple = ("uniform", 0.0)
+    flow: str = "channel"             # "channel" | "cavity" | "hartmann" | "free"
+    Re: float = 10.0
+    Ha: float = 0.0
+    Pm: float = 1.0
+    Ma: float = 0.1
+    tau: float = 0.8                  # channel / free flows: shear relaxation time
+    u_lid: float = 0.0                # cavity: top-wall speed
+    rho0: float = 1.0
+    mu_m: float = 1.0
+    mhd: bool = False
+    storage: str = "f32"
+    steps: int = 100
+    gi_terms: int = 1
+    q3_sign: int = 0
+    lid_corners: int = 1
+    rho_terms: int = 0
+    body_force: tuple = (0.0, 0.0)    # "free" flows: explicit force density
+    init_seed: int | None = None      # smooth random initial fields when set
+    init_amp: float = 0.0
+
+    def replace(self, **kw) -> "Case":
+        return dataclasses.replace(self, **kw)
+
+
+# ---- the five benchmark configurations -------------------------------------
+
+def channel_64() -> Case:
+    """Plain channel, FP64: 64x64, periodic x, walls in y, tanh beta = 1.5,
+    Re = 10, tau = 0.8, 2000 steps (Poiseuille start-up)."""
+    return Case("channel_64", 64, 64, "periodic", "wall", ("uniform", 0.0), ("tanh", 1.5),
+                flow="channel", Re=10.0, tau=0.8, storage="f64", steps=2000)
+
+
+def cavity_1024() -> Case:
+    """Lid-driven cavity, FP32: 1024^2, tanh beta = 2 toward all walls,
+    Re = 1000, lid speed 0.05, 50k steps (parity at 1000)."""
+    return Case("cavity_1024", 1024, 1024, "wall", "wall", ("tanh", 2.0), ("tanh", 2.0),
+                flow="cavity", Re=1000.0, u_lid=0.05, storage="f32", steps=50000)
+
+
+def hartmann_4096() -> Case:
+    """Coupled MHD Hartmann channel, FP32: 4096x1024, tanh beta = 3 in y,
+    Ha = 100, Re = 100, Pm = 1, Ma = 0.1, applied B2."""
+    return Case("hartmann_4096x1024", 4096, 1024, "periodic", "wall", ("uniform", 0.0),
+                ("tanh", 3.0), flow="hartmann", Re=100.0, Ha=100.0, Pm=1.0, Ma=0.1,
+                mhd=True, storage="f32", steps=1000)
+
+
+def hartmann_4096_precision(storage: str) -> Case:
+    return hartmann_4096().replace(name=f"hartmann_4096x1024_{storage}", storage=storage)
+
+
+def batch_256(seed: int = 15362, n: int = 256):
+    """256 independent stretched channel / Hartmann runs: grids 128x64 .. 1024x512,
+    beta in [1, 3], Re in [10, 500], Ha in [0, 200], FP32."""
+    rng = np.random.default_rng(seed)
+    nx = rng.integers(128, 1025, n)
+    ny = rng.integers(64, 513, n)
+    beta = rng.uniform(1.0, 3.0, n)
+    Re = rng.uniform(10.0, 500.0, n)
+    Ha = rng.uniform(0.0, 200.0, n)
+    runs = []
+    for k in range(n):
+        runs.append(Case(f"batch_{k}", int(nx[k]), int(ny[k]), "periodic", "wall",
+                         ("uniform", 0.0), ("tanh", float(beta[k])), flow="hartmann",
+                         Re=float(Re[k]), Ha=float(Ha[k]), Pm=1.0, Ma=0.1, mhd=True,
+                         storage="f32", steps=1000))
+    return runs
+
+
+# ---- seeded smooth random fields ---------------------------------------------
+
+def smooth_fields(nx: int, ny: int, seed: int, amp: float, rho0: float = 1.0, modes: int = 3):
+    """Smooth periodic random fields (rho, U1, U2) of shape [ny, nx]:
+    rho = rho0 (1 + amp r), U = amp (u, v) with r, u, v sums of a few random
+    low Fourier modes of unit amplitude."""
+    rng = np.random.default_rng(seed)
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(x, y)
+
+    def field_():
+        out = np.zeros((ny, nx))
+        for _ in range(modes):
+            kx, ky = rng.integers(1, 4, 2)
+            ph = rng.uniform(0, 2 * np.pi, 2)
+            out += np.sin(2 * np.pi * kx * X + ph[0]) * np.cos(2 * np.pi * ky * Y + ph[1])
+        return out / modes
+
+    r, u, v = field_(), field_(), field_()
+    return rho0 * (1.0 + amp * r), amp * u, amp * v
+
+
+def sample_nodes(nx: int, ny: int, count: int, seed: int):
+    """Seeded node sample that always includes the corners and wall rows."""
+    rng = np.random.default_rng(seed)
+    ix = list(rng.integers(0, nx, count))
+    iy = list(rng.integers(0, ny, count))
+    for (i, j) in [(0, 0), (nx - 1, 0), (0, ny - 1), (nx - 1, ny - 1), (nx // 2, 0),
+                   (nx // 2, ny - 1), (0, ny // 2), (nx - 1, ny // 2), (1, 1), (nx - 2, ny - 2)]:
+        ix.append(i)
+        iy.append(j)
+    return np.asarray(ix, dtype=np.int32), np.asarray(iy, dtype=np.int32)
