@@ -1,0 +1,166 @@
+#!/usr/bin/env python3
+"""Benchmark of the GOC-LBM hot path on one MI355X.
+
+One step = one pass of the whole hot path (one fused collide-and-stream
+kernel launch of the central-moment GOC-LBM, plus the D2Q5 induction sweep
+for MHD workloads) over the synthetic workload, inputs resident in HBM.
+
+Prints ONE JSON line:
+  metric / value / unit      MLUPS of the workload (whole job, one GPU)
+  roofline                   HBM roofline of the step kernel: algorithmic
+                             bytes per launch / mean launch time (HIP events
+                             on the launch stream) against 8 TB/s, plus the
+                             measured HBM traffic when a counter profile of
+                             the current kernel source is committed
+  cpu_baseline               the FP64 oracle on the host cores, on a bounded
+                             sample of the same workload
+  forms                      the same GPU on the 4096x1024 MHD workload in
+                             FP32 and the FP16 / BF16 deviation-storage forms
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "MLUPS + % HBM peak; FP16-store & batched vs plain FP32 on same GPU"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("goc_device.hpp", "goc_step.hpp"):
+        with open(os.path.join(ROOT, "paper_2607_15362_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, bytes_alg_per_launch: float):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"step_kernel_{workload}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def time_run(run, steps: int, warmup: int):
+    from paper_2607_15362_amd import binding as B
+    run.step(warmup)
+    run.synchronize()
+    e0, e1 = B.Event(), B.Event()
+    t0 = time.perf_counter()
+    e0.record(run.stream_obj)
+    run.step(steps)
+    e1.record(run.stream_obj)
+    run.synchronize()
+    t1 = time.perf_counter()
+    return t1 - t0, e0.elapsed_ms(e1) / 1e3
+
+
+def cpu_baseline(case, seconds: float):
+    """The FP64 oracle, untuned, on the host cores: full grid of the same
+    workload, as many steps as fit in about `seconds`."""
+    import oracle
+    m = oracle.Model(case).init()
+    t0 = time.perf_counter()
+    m.step(1)
+    t1 = time.perf_counter() - t0
+    n = max(1, int(seconds / max(t1, 1e-6)))
+    t0 = time.perf_counter()
+    m.step(n)
+    dt = time.perf_counter() - t0
+    return {"value": case.nx * case.ny * n / dt / 1e6, "unit": "MLUPS", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{n} steps of the full {case.nx}x{case.ny} {case.name} grid in FP64 "
+                      f"({dt:.1f} s), after one untimed step"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--workload", default="cavity_1024", choices=["cavity_1024", "hartmann_4096"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
+              "(the hot path is a single-GPU build; see the design notes on sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2607_15362_amd import binding as B
+    from paper_2607_15362_amd import workloads as W
+
+    case = W.cavity_1024() if args.workload == "cavity_1024" else W.hartmann_4096()
+    run = B.Run(case)
+    wall, ev = time_run(run, args.steps, args.warmup)
+    d = run.derived()
+    nodes = case.nx * case.ny
+    mlups = nodes * args.steps / wall / 1e6
+    launch_s = ev / args.steps
+    bytes_per_launch = d["bytes_per_node"] * nodes
+    achieved = bytes_per_launch / launch_s / 1e9
+    traffic = measured_traffic(case.name, bytes_per_launch)
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32"}.get(case.storage, "f32"),
+        "data": "synthetic",
+        "config": {"workload": f"{case.name}: lid-driven cavity {case.nx}x{case.ny}, tanh beta=2 "
+                               f"on both axes, Re=1000, lid 0.05, FP32 storage and arithmetic"
+                   if case.flow == "cavity" else
+                   f"{case.name}: Hartmann channel {case.nx}x{case.ny}, tanh beta=3, Ha=100, "
+                   f"Re=100, Pm=1, D2Q9+D2Q5, FP32",
+                   "nx": case.nx, "ny": case.ny, "storage": case.storage,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic,
+                     "bytes_per_node": d["bytes_per_node"], "launch_us": round(launch_s * 1e6, 2),
+                     "kernel": "goc::step_kernel"},
+    }
+    run.close()
+
+    if not args.no_forms:
+        forms = {}
+        for st in ("f32", "f16dev", "bf16dev"):
+            c = W.hartmann_4096_precision(st) if st != "f32" else W.hartmann_4096()
+            r = B.Run(c)
+            n = max(200, args.steps // 10)
+            w, e = time_run(r, n, 100)
+            dd = r.derived()
+            forms[st] = {"workload": c.name, "MLUPS": round(c.nx * c.ny * n / w / 1e6, 1),
+                         "GB_s": round(dd["bytes_per_node"] * c.nx * c.ny / (e / n) / 1e9, 1),
+                         "bytes_per_node": dd["bytes_per_node"]}
+            r.close()
+        out["forms"] = forms
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,224 @@
+/*
+ * goc_lbm.h -- C-ABI of the MI355X GOC-LBM library (libgoclbm.so).
+ *
+ * The library advances the central-moment multiple-relaxation-time lattice
+ * Boltzmann method in general orthogonal coordinates (Yahia & Premnath,
+ * App. E, with the local shear stress of App. A and the boundary and initial
+ * conditions of App. C), optionally coupled to the D2Q5 vector-distribution
+ * scheme for the magnetic induction equation (App. G), on the uniform
+ * computational lattice of a straight clustered grid (metric factors
+ * h1(xi1), h2(xi2); theta12 = theta21 = 0, the case of App. B(i)).
+ *
+ * Conventions shared by every entry point:
+ *   - nodes (i, j), 0 <= i < nx, 0 <= j < ny, sit at xi = (i + 1/2, j + 1/2);
+ *     walls lie on the cell faces xi = 0 and xi = n (half-way bounce-back);
+ *   - node arrays are row-major [ny][nx] FP64, index j*nx + i;
+ *   - D2Q9 directions e_a = (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1)
+ *     (-1,-1) (1,-1); D2Q5 uses the first five;
+ *   - "device" pointers are HIP device allocations valid on the handle's
+ *     device (e.g. a torch tensor's data_ptr()); "host" pointers are plain
+ *     CPU memory.  Calls are ordered on the stream given at creation.
+ *   - Every function returns GOC_OK (0) or a negative goc_status; it never
+ *     aborts or prints.  goc_lbm_last_error() gives a thread-local message.
+ *   - One handle must not be used by two threads at once.
+ */
+#ifndef GOC_LBM_H
+#define GOC_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GOC_OK = 0,
+    GOC_EINVAL = -1,     /* bad argument                                  */
+    GOC_ENOMEM = -2,     /* device or host allocation failed              */
+    GOC_EDEVICE = -3,    /* a HIP call failed                             */
+    GOC_EUNSTABLE = -4,  /* the watchdog found a non-finite value         */
+    GOC_ESTATE = -5      /* state blob of the wrong size or version       */
+} goc_status;
+
+typedef enum { GOC_BC_PERIODIC = 0, GOC_BC_WALL = 1 } goc_bc;
+
+typedef enum {
+    GOC_F64 = 0,      /* populations FP64, arithmetic FP64                       */
+    GOC_F32 = 1,      /* populations FP32, arithmetic FP32                       */
+    GOC_F16DEV = 2,   /* populations FP16 as scaled deviations from the rest state,
+                         arithmetic FP32                                         */
+    GOC_BF16DEV = 3   /* as GOC_F16DEV with bfloat16                              */
+} goc_storage;
+
+typedef enum {
+    GOC_STRETCH_ARRAY = 0,    /* metric factors given as arrays                   */
+    GOC_STRETCH_UNIFORM = 1,  /* h = 1                                            */
+    GOC_STRETCH_TANH = 2,     /* Sec. 6.1 two-wall hyperbolic tangent, parameter beta */
+    GOC_STRETCH_ROBERTS = 3   /* Sec. 6.2 Roberts transformation, parameter gamma,
+                                 clustered at both walls (alpha = 1/2)           */
+} goc_stretch;
+
+typedef enum {
+    GOC_FLOW_CHANNEL = 0,   /* body-force channel, Sec. 8.1: Re = U (H/2)/nu, tau given */
+    GOC_FLOW_CAVITY = 1,    /* lid-driven cavity, Sec. 8.3: Re = U_lid L / nu           */
+    GOC_FLOW_HARTMANN = 2,  /* MHD channel, Sec. 8.4: Re = U_c H / nu, H half-width,
+                               U_c = Ma c_s, eta = nu / Pm                            */
+    GOC_FLOW_FREE = 3       /* no derived forcing: tau and F_ext given                */
+} goc_flow;
+
+/* Lattice and boundaries.  u_wall_lo / u_wall_hi are the tangential (xi1)
+   velocities of the walls at xi2 = 0 and xi2 = ny (momentum-augmented
+   bounce-back of App. C); they are used only when bc_y is GOC_BC_WALL. */
+typedef struct {
+    int32_t nx, ny;           /* >= 3 each                                   */
+    int32_t bc_x, bc_y;       /* goc_bc                                      */
+    double u_wall_lo, u_wall_hi;
+} goc_grid;
+
+/* Metric factors of a straight orthogonal grid.  For GOC_STRETCH_ARRAY the
+   caller passes h1[nx] and h2[ny] (host, FP64, > 0, borrowed for the call)
+   at the node centres, optionally their derivatives dh1[nx], dh2[ny]
+   (NULL: second-order finite differences, one-sided at the ends), and the
+   values on the wall faces h1_face[2] (xi1 = 0, nx) and h2_face[2]
+   (xi2 = 0, ny); a face value <= 0 means "the adjacent node's value".
+   For the analytic kinds only the kind and its parameter are read. */
+typedef struct {
+    int32_t kind_x, kind_y;   /* goc_stretch                                 */
+    double param_x, param_y;  /* beta (tanh) or gamma (Roberts)              */
+    const double *h1, *h2;
+    const double *dh1, *dh2;
+    double h1_face[2], h2_face[2];
+} goc_metric;
+
+/* Lattice parameters of a run (all in lattice units).  c_s^2 = q^2/3 with
+   q the minimum metric factor (Sec. 3.2.1) is derived by the library from
+   the metric, as is the MHD sound speed c_sm = c_s (App. G).  nu and zeta
+   follow from omega[4] (= omega[5] for the default reading) and omega[3]:
+   nu = c_s^2 (1/omega5 - 1/2), zeta = c_s^2 (1/omega3 - 1/2) (Sec. 5). */
+typedef struct {
+    double omega[9];          /* relaxation rates, each in (0, 2)            */
+    double rho0;              /* reference (initial) density                 */
+    double F_ext[2];          /* external body-force density, GOC components */
+    int32_t gi_terms;         /* 1: full correction coefficients (Sec. 5);
+                                 0: App. B(ii) low-Mach forms                */
+    int32_t q3_sign;          /* 0: binomial-transform sign of q21, q12; 1: as printed */
+    int32_t rho_terms;        /* 0: density-gradient coefficients from the
+                                 Chapman-Enskog analysis; 1: as printed      */
+    int32_t lid_corners;      /* 1: a moving y-wall owns the corner ghosts   */
+    int32_t mhd;              /* 1: couple the D2Q5 induction equation       */
+    double tau_m;             /* magnetic relaxation time (> 1/2)            */
+    double mu_m;              /* magnetic permeability                       */
+    double B0;                /* applied field: wall and initial B2          */
+} goc_params;
+
+/* Physical description used by goc_lbm_derive. */
+typedef struct {
+    int32_t flow;             /* goc_flow                                    */
+    double Re, Ha, Pm, Ma;
+    double tau;               /* channel / free flows: shear relaxation time */
+    double u_lid;             /* cavity: lid (xi2 = ny wall) speed           */
+    double rho0, mu_m;
+    double F_ext[2];          /* free flows: body force                      */
+} goc_physics;
+
+typedef struct goc_lbm goc_lbm_t;
+
+/* Derive lattice parameters from physical ones (Sec. 3.2.1, Sec. 5,
+   App. G, Sec. 8), for the given grid and metric: c_s^2 from the metric;
+   channel: nu = c_s^2 (tau - 1/2), U = Re nu/(H/2), F = 2 nu U rho0/(H/2)^2
+   with H = ny; cavity: nu = u_lid nx / Re and grid->u_wall_hi = u_lid;
+   Hartmann: U_c = Ma c_s, nu = U_c (ny/2)/Re, eta = nu/Pm, B0 from Ha, F
+   from the analytic centre-line speed; omega4 = omega5 from nu, the other
+   rates 1.  Writes *out and may update grid->u_wall_*.  Host only. */
+int goc_lbm_derive(goc_grid *grid, const goc_metric *metric, const goc_physics *phys,
+                   goc_params *out);
+
+/* Create a run on the current HIP device.  Copies the metric (FP64
+   precompute on the device: theta = dh/h^2, q = min h), allocates the
+   state (two slot buffers, the lagged force and, with MHD, the D2Q5
+   buffers) and initialises it at rest (rho0, U = 0, B = (0, B0)).
+   stream: a hipStream_t (NULL = the default stream).  *out receives the
+   handle, owned by the caller until goc_lbm_destroy. */
+int goc_lbm_create(goc_lbm_t **out, const goc_grid *grid, const goc_metric *metric,
+                   const goc_params *params, int32_t storage, void *stream);
+
+/* Initial state of App. C from node fields rho[ny*nx], u1, u2 (FP64,
+   device if on_device else host): f = P^-1 m^eq,eff(rho, U), g = g^eq(0)
+   with B = (0, B0); lagged force zero; step counter zero.  All three NULL
+   re-initialises at rest. */
+int goc_lbm_init(goc_lbm_t *h, const double *rho, const double *u1, const double *u2,
+                 int32_t on_device);
+
+/* Advance n >= 0 time steps (App. E steps 1-7 and App. G steps 1-6 per
+   step, one fused kernel launch each).  Asynchronous on the stream unless
+   the watchdog interval is due (goc_lbm_set_watchdog). */
+int goc_lbm_step(goc_lbm_t *h, int64_t n);
+
+/* Hydrodynamic and magnetic fields of the current state (App. E step 7,
+   App. G): rho[ny*nx], u[2*ny*nx] (U1 then U2; the Cartesian components
+   on a straight grid) and B[2*ny*nx] (B1 then B2, MHD runs only; NULL
+   allowed).  FP64; device pointers if on_device else host.  Synchronises
+   the stream when on_device is 0. */
+int goc_lbm_moments(goc_lbm_t *h, double *rho, double *u, double *B, int32_t on_device);
+
+/* Global sums in FP64 (host out[8]): [0] mass sum f, [1] sum h2 rho U1,
+   [2] sum h1 rho U2, [3] mean over columns of the flow rate sum_j h2 rho U1,
+   [4] sum h1 h2 B1, [5] sum h1 h2 B2, [6] max |U|, [7] number of
+   non-finite populations.  Synchronises the stream. */
+int goc_lbm_diagnostics(goc_lbm_t *h, double out[8]);
+
+/* Check every `every` steps (0 = never) for non-finite populations; a hit
+   makes goc_lbm_step return GOC_EUNSTABLE. */
+int goc_lbm_set_watchdog(goc_lbm_t *h, int64_t every);
+
+/* Post-stream populations in FP64 (the quantities App. E step 1 reads):
+   f[9][ny][nx], F[2][ny][nx] (the lagged effective force) and, for MHD,
+   g[10][ny][nx] (plane c*5 + a for component c of B).  set takes the same
+   layout and encodes it in the storage precision.  Device pointers if
+   on_device else host. */
+int goc_lbm_get_populations(goc_lbm_t *h, double *f, double *F, double *g, int32_t on_device);
+int goc_lbm_set_populations(goc_lbm_t *h, const double *f, const double *F, const double *g,
+                            int32_t on_device);
+
+/* Checkpoint in storage precision (host buffer).  get: with buf NULL writes
+   the required size to *bytes; otherwise *bytes must be >= that size.
+   set: bytes must match exactly (GOC_ESTATE otherwise).  The blob holds the
+   step counter and the raw state; restoring it and stepping reproduces an
+   uninterrupted run bit for bit. */
+int goc_lbm_get_state(goc_lbm_t *h, void *buf, size_t *bytes);
+int goc_lbm_set_state(goc_lbm_t *h, const void *buf, size_t bytes);
+
+/* Derived quantities (host out[16]): [0] c_s^2, [1] nu, [2] zeta, [3] q,
+   [4] c_sm^2, [5] eta, [6] tau_m, [7] B0, [8] F_ext1, [9] F_ext2,
+   [10] h2 on the xi2 = 0 face, [11] on the xi2 = ny face, [12] step count,
+   [13] storage bytes per node per step (algorithmic), [14] nx, [15] ny. */
+int goc_lbm_derived(const goc_lbm_t *h, double out[16]);
+
+/* Metric arrays as used by the kernels (FP64 host): h1, theta11 [nx],
+   h2, theta22 [ny]; any pointer may be NULL. */
+int goc_lbm_metric(const goc_lbm_t *h, double *h1, double *th11, double *h2, double *th22);
+
+void goc_lbm_destroy(goc_lbm_t *h);
+const char *goc_lbm_last_error(void);
+
+/* ---- batched form --------------------------------------------------------
+ * nruns independent runs (each its own grid, metric and parameters, same
+ * storage) advanced by one kernel launch per step over a shared work list;
+ * blocks of steps are captured in a HIP graph.  The arrays grid[], metric[]
+ * and params[] have nruns entries. */
+int goc_lbm_create_batch(goc_lbm_t **out, int32_t nruns, const goc_grid *grid,
+                         const goc_metric *metric, const goc_params *params, int32_t storage,
+                         void *stream);
+/* Fields of one run of a batch, as goc_lbm_moments. */
+int goc_lbm_moments_run(goc_lbm_t *h, int32_t run, double *rho, double *u, double *B,
+                        int32_t on_device);
+/* Populations of one run of a batch, as goc_lbm_get_populations. */
+int goc_lbm_get_populations_run(goc_lbm_t *h, int32_t run, double *f, double *F, double *g,
+                                int32_t on_device);
+int32_t goc_lbm_num_runs(const goc_lbm_t *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GOC_LBM_H */

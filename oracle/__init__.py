@@ -54,7 +54,13 @@ def lib():
         _lib.oracle_moment_map.argtypes = [C.c_int, P, C.c_double, C.c_double, P]
         _lib.oracle_central_eq.argtypes = [cfgp] + [C.c_double] * 7 + [P, P]
         _lib.oracle_mie_node.argtypes = [cfgp, P, P, P, P]
+        _lib.oracle_threads.restype = C.c_int
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(lib().oracle_threads())
 
 
 class OracleCfg(C.Structure):

@@ -44,6 +44,9 @@
  * Poiseuille / Couette / Hartmann closed forms.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -940,4 +943,14 @@ int oracle_mie_node(const OracleCfg *c, const double *gbin, const double *Uin, c
     for (int ci = 0; ci < 2; ++ci)
         for (int a = 0; a < NM; ++a) out[9 + ci * NM + a] = gt[ci][a];
     return 0;
+}
+
+/* Number of threads the OpenMP loops use (1 without OpenMP). */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

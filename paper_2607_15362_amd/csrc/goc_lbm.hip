@@ -1,0 +1,991 @@
+// goc_lbm.hip -- host runtime and C-ABI of libgoclbm.so (see include/goc_lbm.h).
+//
+// The runtime owns, per handle: a table of run descriptors (one per
+// independent run; the single-run API is a batch of one), pooled device
+// state (two slot buffers for ping-pong, the lagged force, the D2Q5 slots),
+// the metric pools (FP64), and HIP graphs of blocks of steps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/goc_lbm.h"
+#include "goc_aux.hpp"
+
+using goc::RunDesc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPOK(expr)                                                                          \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(GOC_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+    } while (0)
+
+constexpr int kGraphSteps = 100;    // steps per captured graph
+
+size_t storage_bytes(int storage)
+{
+    switch (storage) {
+    case GOC_F64: return 8;
+    case GOC_F32: return 4;
+    default: return 2;
+    }
+}
+size_t force_bytes(int storage) { return storage == GOC_F64 ? 8 : 4; }
+
+// ---------------------------------------------------------------- metric --
+// Host generation of h and dh/dxi at node centres xi = j + 1/2 (FP64) and
+// of h on the two faces, for the analytic stretchings of Sec. 6.
+struct Metric1D {
+    std::vector<double> h, dh;
+    double face_lo = 1.0, face_hi = 1.0;
+};
+
+int metric_1d(int n, int kind, double param, const double* harr, const double* dharr,
+              const double* faces, bool periodic, Metric1D& out)
+{
+    out.h.assign(n, 1.0);
+    out.dh.assign(n, 0.0);
+    const double L = n;
+    if (kind == GOC_STRETCH_UNIFORM || (kind == GOC_STRETCH_TANH && param == 0.0)) {
+        out.face_lo = out.face_hi = 1.0;
+        return GOC_OK;
+    }
+    if (kind == GOC_STRETCH_TANH) {
+        // y = (L/2) {1 - tanh[beta (1 - 2 xi/L)] / tanh beta}
+        const double b = param, c = b / std::tanh(b);
+        if (!(b > 0)) return fail(GOC_EINVAL, "tanh stretching needs beta > 0 (got %g)", b);
+        for (int j = 0; j < n; ++j) {
+            const double u = b * (1.0 - 2.0 * (j + 0.5) / L);
+            const double ch = std::cosh(u), s2 = 1.0 / (ch * ch);
+            out.h[j] = c * s2;
+            out.dh[j] = c * s2 * std::tanh(u) * (4.0 * b / L);
+        }
+        const double cb = std::cosh(b);
+        out.face_lo = out.face_hi = c / (cb * cb);
+        return GOC_OK;
+    }
+    if (kind == GOC_STRETCH_ROBERTS) {
+        // y = L [A l - B] / [C (1 + l)], l = lambda^s, s = (xi/L - 1/2)/(1/2),
+        // lambda = (gamma + 1)/(gamma - 1), A = gamma + 1, B = gamma - 1, C = 2
+        const double g = param;
+        if (!(g > 1.0)) return fail(GOC_EINVAL, "Roberts stretching needs gamma > 1 (got %g)", g);
+        const double lam = (g + 1.0) / (g - 1.0), A = g + 1.0, B = g - 1.0, C = 2.0;
+        const double k = std::log(lam) / (L * 0.5);
+        auto hd = [&](double xi, double& h, double& dh) {
+            const double s = (xi / L - 0.5) / 0.5, l = std::pow(lam, s);
+            h = (L / C) * (A + B) * k * l / ((1 + l) * (1 + l));
+            dh = (L / C) * (A + B) * k * k * l * (1 - l) / ((1 + l) * (1 + l) * (1 + l));
+        };
+        for (int j = 0; j < n; ++j) hd(j + 0.5, out.h[j], out.dh[j]);
+        double t;
+        hd(0.0, out.face_lo, t);
+        hd(L, out.face_hi, t);
+        return GOC_OK;
+    }
+    if (kind != GOC_STRETCH_ARRAY) return fail(GOC_EINVAL, "unknown stretch kind %d", kind);
+    if (!harr) return fail(GOC_EINVAL, "array metric without h");
+    for (int j = 0; j < n; ++j) {
+        if (!(harr[j] > 0.0) || !std::isfinite(harr[j]))
+            return fail(GOC_EINVAL, "metric factor h[%d] = %g must be positive", j, harr[j]);
+        out.h[j] = harr[j];
+    }
+    if (dharr) {
+        for (int j = 0; j < n; ++j) out.dh[j] = dharr[j];
+    } else {
+        // second-order differences: central, wrapped when periodic, one-sided at the ends
+        for (int j = 0; j < n; ++j) {
+            if (periodic) out.dh[j] = 0.5 * (out.h[(j + 1) % n] - out.h[(j + n - 1) % n]);
+            else if (j == 0) out.dh[j] = 0.5 * (-3 * out.h[0] + 4 * out.h[1] - out.h[2]);
+            else if (j == n - 1) out.dh[j] = 0.5 * (3 * out.h[n - 1] - 4 * out.h[n - 2] + out.h[n - 3]);
+            else out.dh[j] = 0.5 * (out.h[j + 1] - out.h[j - 1]);
+        }
+    }
+    out.face_lo = (faces && faces[0] > 0) ? faces[0] : out.h[0];
+    out.face_hi = (faces && faces[1] > 0) ? faces[1] : out.h[n - 1];
+    return GOC_OK;
+}
+
+int build_metric(const goc_grid& g, const goc_metric& m, Metric1D& mx, Metric1D& my)
+{
+    int rc = metric_1d(g.nx, m.kind_x, m.param_x, m.h1, m.dh1, m.h1_face, g.bc_x == GOC_BC_PERIODIC, mx);
+    if (rc) return rc;
+    return metric_1d(g.ny, m.kind_y, m.param_y, m.h2, m.dh2, m.h2_face, g.bc_y == GOC_BC_PERIODIC, my);
+}
+
+int check_grid(const goc_grid* g)
+{
+    if (!g) return fail(GOC_EINVAL, "grid is NULL");
+    if (g->nx < 3 || g->ny < 3) return fail(GOC_EINVAL, "grid %d x %d: both sizes must be >= 3", g->nx, g->ny);
+    if ((g->bc_x != 0 && g->bc_x != 1) || (g->bc_y != 0 && g->bc_y != 1))
+        return fail(GOC_EINVAL, "boundary kinds must be GOC_BC_PERIODIC or GOC_BC_WALL");
+    if ((int64_t)g->nx * g->ny > (int64_t)1 << 31) return fail(GOC_EINVAL, "grid too large");
+    return GOC_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ handle --
+struct goc_lbm {
+    int storage = GOC_F32;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int nruns = 0;
+    bool any_mhd = false;
+    std::vector<RunDesc> runs;
+    std::vector<goc_params> params;
+    std::vector<goc_grid> grids;
+    std::vector<Metric1D> mx, my;
+    std::vector<double> q;
+    RunDesc* runs_d = nullptr;
+    int32_t* block_run_d = nullptr;
+    int total_blocks = 0;
+    double *h1_d = nullptr, *th11_d = nullptr, *h2_d = nullptr, *th22_d = nullptr;
+    void* f[2] = {nullptr, nullptr};
+    void* F[2] = {nullptr, nullptr};
+    void* g[2] = {nullptr, nullptr};
+    size_t f_elems = 0, F_elems = 0, g_elems = 0;
+    int cur = 0;
+    int64_t step = 0;
+    int64_t watchdog = 0;
+    double* diag_part = nullptr;
+    double* diag_out = nullptr;
+    int diag_cap = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int rows_per_seg = 0;
+};
+
+namespace {
+
+template <class S>
+using PoolsOf = goc::Pools<S, typename goc::ForceOf<S>::type>;
+
+template <class S>
+PoolsOf<S> pools(const goc_lbm* h, int in)
+{
+    using FT = typename goc::ForceOf<S>::type;
+    PoolsOf<S> p;
+    p.fin = static_cast<const S*>(h->f[in]);
+    p.fout = static_cast<S*>(h->f[1 - in]);
+    p.Fin = static_cast<const FT*>(h->F[in]);
+    p.Fout = static_cast<FT*>(h->F[1 - in]);
+    p.gin = static_cast<const S*>(h->g[in]);
+    p.gout = static_cast<S*>(h->g[1 - in]);
+    p.h1 = h->h1_d;
+    p.th11 = h->th11_d;
+    p.h2 = h->h2_d;
+    p.th22 = h->th22_d;
+    return p;
+}
+
+template <class Fn>
+int dispatch(int storage, Fn&& fn)
+{
+    switch (storage) {
+    case GOC_F64: return fn(double{});
+    case GOC_F32: return fn(float{});
+    case GOC_F16DEV: return fn(__half{});
+    case GOC_BF16DEV: return fn(__hip_bfloat16{});
+    default: return fail(GOC_EINVAL, "unknown storage %d", storage);
+    }
+}
+
+// Launch one time step of every run (input buffer h->cur).
+int launch_step(goc_lbm* h)
+{
+    return dispatch(h->storage, [&](auto tag) -> int {
+        using S = decltype(tag);
+        const auto pl = pools<S>(h, h->cur);
+        if (h->any_mhd)
+            hipLaunchKernelGGL((goc::step_kernel<S, true>), dim3(h->total_blocks), dim3(goc::kWave), 0,
+                               h->stream, h->runs_d, h->block_run_d, pl);
+        else
+            hipLaunchKernelGGL((goc::step_kernel<S, false>), dim3(h->total_blocks), dim3(goc::kWave), 0,
+                               h->stream, h->runs_d, h->block_run_d, pl);
+        HIPOK(hipGetLastError());
+        return GOC_OK;
+    });
+}
+
+int per_node_grid(const RunDesc& d, dim3& grid, dim3& block)
+{
+    block = dim3(256);
+    grid = dim3((d.nx + 255) / 256, d.ny);
+    return GOC_OK;
+}
+
+int free_all(goc_lbm* h)
+{
+    for (int k = 0; k < 2; ++k) {
+        if (h->graph[k]) (void)hipGraphExecDestroy(h->graph[k]);
+        (void)hipFree(h->f[k]);
+        (void)hipFree(h->F[k]);
+        (void)hipFree(h->g[k]);
+    }
+    (void)hipFree(h->runs_d);
+    (void)hipFree(h->block_run_d);
+    (void)hipFree(h->h1_d);
+    (void)hipFree(h->th11_d);
+    (void)hipFree(h->h2_d);
+    (void)hipFree(h->th22_d);
+    (void)hipFree(h->diag_part);
+    (void)hipFree(h->diag_out);
+    return GOC_OK;
+}
+
+int check_params(const goc_params* p, const goc_grid* g, int run)
+{
+    if (!p) return fail(GOC_EINVAL, "params is NULL");
+    for (int k = 0; k < 9; ++k)
+        if (!(p->omega[k] > 0.0 && p->omega[k] < 2.0))
+            return fail(GOC_EINVAL, "run %d: omega[%d] = %g outside (0, 2)", run, k, p->omega[k]);
+    if (!(p->rho0 > 0.0)) return fail(GOC_EINVAL, "run %d: rho0 must be positive", run);
+    if (p->mhd && !(p->tau_m > 0.5)) return fail(GOC_EINVAL, "run %d: tau_m must exceed 1/2", run);
+    if (p->mhd && !(p->mu_m > 0.0)) return fail(GOC_EINVAL, "run %d: mu_m must be positive", run);
+    if (!std::isfinite(p->F_ext[0]) || !std::isfinite(p->F_ext[1]) || !std::isfinite(p->B0))
+        return fail(GOC_EINVAL, "run %d: non-finite forcing", run);
+    (void)g;
+    return GOC_OK;
+}
+
+int choose_rows(int ny, int strips, int target_waves)
+{
+    // rows per y-segment: enough work-groups to fill the chip, at least 4 rows
+    int segs = std::max(1, target_waves / std::max(1, strips));
+    int rows = std::max(4, (ny + segs - 1) / segs);
+    return rows;
+}
+
+int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metric* metric,
+                const goc_params* params, int32_t storage, void* stream)
+{
+    if (!out) return fail(GOC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nruns < 1) return fail(GOC_EINVAL, "nruns must be >= 1");
+    if (storage < GOC_F64 || storage > GOC_BF16DEV) return fail(GOC_EINVAL, "unknown storage %d", storage);
+    if (!grid || !metric || !params) return fail(GOC_EINVAL, "NULL grid, metric or params");
+    auto* h = new (std::nothrow) goc_lbm();
+    if (!h) return fail(GOC_ENOMEM, "host allocation failed");
+    h->storage = storage;
+    h->stream = static_cast<hipStream_t>(stream);
+    h->nruns = nruns;
+    int rc = GOC_OK;
+    auto bail = [&](int code) {
+        free_all(h);
+        delete h;
+        return code;
+    };
+    // validate every run before touching the device
+    for (int r = 0; r < nruns; ++r) {
+        Metric1D tx, ty;
+        if ((rc = check_grid(&grid[r])) != GOC_OK) return bail(rc);
+        if ((rc = check_params(&params[r], &grid[r], r)) != GOC_OK) return bail(rc);
+        if ((rc = build_metric(grid[r], metric[r], tx, ty)) != GOC_OK) return bail(rc);
+    }
+    if (hipGetDevice(&h->device) != hipSuccess) return bail(fail(GOC_EDEVICE, "no HIP device"));
+    int ncu = 256;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) ncu = prop.multiProcessorCount;
+    }
+    const size_t sb = storage_bytes(storage), fb = force_bytes(storage);
+    h->runs.resize(nruns);
+    h->params.assign(params, params + nruns);
+    h->grids.assign(grid, grid + nruns);
+    h->mx.resize(nruns);
+    h->my.resize(nruns);
+    h->q.resize(nruns);
+    int64_t sum_nx = 0, sum_ny = 0, f_elems = 0, F_elems = 0, g_elems = 0;
+    // one wave per work-group; aim for ~16 waves per CU over the whole batch
+    int64_t total_nodes = 0;
+    for (int r = 0; r < nruns; ++r) total_nodes += (int64_t)grid[r].nx * grid[r].ny;
+    std::vector<int32_t> block_run;
+    for (int r = 0; r < nruns; ++r) {
+        if ((rc = check_grid(&grid[r])) != GOC_OK) return bail(rc);
+        if ((rc = check_params(&params[r], &grid[r], r)) != GOC_OK) return bail(rc);
+        if ((rc = build_metric(grid[r], metric[r], h->mx[r], h->my[r])) != GOC_OK) return bail(rc);
+        const goc_grid& g = grid[r];
+        const goc_params& p = params[r];
+        RunDesc& d = h->runs[r];
+        std::memset(&d, 0, sizeof(d));
+        d.nx = g.nx;
+        d.ny = g.ny;
+        d.pitch = (g.nx + 63) / 64 * 64;
+        d.bc_x = g.bc_x;
+        d.bc_y = g.bc_y;
+        d.plane = (int64_t)d.pitch * g.ny + 256;
+        d.f_off = f_elems;
+        d.F_off = F_elems;
+        d.g_off = g_elems;
+        f_elems += 9 * d.plane;
+        F_elems += 2 * d.plane;
+        if (p.mhd) {
+            g_elems += 10 * d.plane;
+            h->any_mhd = true;
+        }
+        d.metric_off_x = sum_nx;
+        d.metric_off_y = sum_ny;
+        sum_nx += g.nx;
+        sum_ny += g.ny;
+        d.gi_terms = p.gi_terms;
+        d.q3_sign = p.q3_sign;
+        d.rho_terms = p.rho_terms;
+        d.lid_corners = p.lid_corners;
+        d.mhd = p.mhd;
+        for (int k = 0; k < 9; ++k) d.omega[k] = p.omega[k];
+        d.Fx1 = p.F_ext[0];
+        d.Fx2 = p.F_ext[1];
+        d.rho0 = p.rho0;
+        d.uw_lo = g.bc_y ? g.u_wall_lo : 0.0;
+        d.uw_hi = g.bc_y ? g.u_wall_hi : 0.0;
+        d.hw_lo = h->my[r].face_lo;
+        d.hw_hi = h->my[r].face_hi;
+        d.h1w_lo = h->mx[r].face_lo;
+        d.h1w_hi = h->mx[r].face_hi;
+        d.tau_m = p.mhd ? p.tau_m : 1.0;
+        d.inv_mu = p.mhd ? 1.0 / p.mu_m : 1.0;
+        d.B0 = p.mhd ? p.B0 : 0.0;
+        d.strips = (g.nx + goc::kOwn - 1) / goc::kOwn;
+        // share of the chip in proportion to the run's nodes
+        const double share = double((int64_t)g.nx * g.ny) / double(total_nodes);
+        const int target = std::max(1, int(share * 16.0 * ncu));
+        const int rows = choose_rows(g.ny, d.strips, target);
+        d.segs = std::max(1, std::min(g.ny / 2, (g.ny + rows - 1) / rows));
+        d.first_block = (int)block_run.size();
+        for (int b = 0; b < d.strips * d.segs; ++b) block_run.push_back(r);
+    }
+    h->total_blocks = (int)block_run.size();
+    h->f_elems = f_elems;
+    h->F_elems = F_elems;
+    h->g_elems = g_elems;
+
+    // metric pools and the FP64 precompute (theta, q)
+    std::vector<double> h1(sum_nx), dh1(sum_nx), h2(sum_ny), dh2(sum_ny);
+    for (int r = 0; r < nruns; ++r) {
+        std::copy(h->mx[r].h.begin(), h->mx[r].h.end(), h1.begin() + h->runs[r].metric_off_x);
+        std::copy(h->mx[r].dh.begin(), h->mx[r].dh.end(), dh1.begin() + h->runs[r].metric_off_x);
+        std::copy(h->my[r].h.begin(), h->my[r].h.end(), h2.begin() + h->runs[r].metric_off_y);
+        std::copy(h->my[r].dh.begin(), h->my[r].dh.end(), dh2.begin() + h->runs[r].metric_off_y);
+    }
+    double *dh1_d = nullptr, *dh2_d = nullptr, *bmin_d = nullptr;
+    auto dev_alloc = [&](void** p, size_t bytes) -> int {
+        if (hipMalloc(p, std::max<size_t>(bytes, 256)) != hipSuccess)
+            return fail(GOC_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+        return GOC_OK;
+    };
+    if ((rc = dev_alloc((void**)&h->h1_d, sum_nx * 8)) || (rc = dev_alloc((void**)&h->th11_d, sum_nx * 8)) ||
+        (rc = dev_alloc((void**)&h->h2_d, sum_ny * 8)) || (rc = dev_alloc((void**)&h->th22_d, sum_ny * 8)) ||
+        (rc = dev_alloc((void**)&dh1_d, sum_nx * 8)) || (rc = dev_alloc((void**)&dh2_d, sum_ny * 8)))
+        return bail(rc);
+    auto cleanup_tmp = [&]() { (void)hipFree(dh1_d); (void)hipFree(dh2_d); (void)hipFree(bmin_d); };
+    if (hipMemcpy(h->h1_d, h1.data(), sum_nx * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dh1_d, dh1.data(), sum_nx * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->h2_d, h2.data(), sum_ny * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dh2_d, dh2.data(), sum_ny * 8, hipMemcpyHostToDevice) != hipSuccess) {
+        cleanup_tmp();
+        return bail(fail(GOC_EDEVICE, "metric upload failed"));
+    }
+    for (int r = 0; r < nruns; ++r) {
+        RunDesc& d = h->runs[r];
+        const int nbx = (d.nx + 255) / 256, nby = (d.ny + 255) / 256;
+        (void)hipFree(bmin_d);
+        bmin_d = nullptr;
+        if (hipMalloc(&bmin_d, (nbx + nby) * 8) != hipSuccess) {
+            cleanup_tmp();
+            return bail(fail(GOC_ENOMEM, "hipMalloc failed"));
+        }
+        hipLaunchKernelGGL(goc::metric_kernel, dim3(nbx), dim3(256), 0, h->stream, h->h1_d + d.metric_off_x,
+                           dh1_d + d.metric_off_x, h->th11_d + d.metric_off_x, d.nx, bmin_d);
+        hipLaunchKernelGGL(goc::metric_kernel, dim3(nby), dim3(256), 0, h->stream, h->h2_d + d.metric_off_y,
+                           dh2_d + d.metric_off_y, h->th22_d + d.metric_off_y, d.ny, bmin_d + nbx);
+        std::vector<double> bm(nbx + nby);
+        if (hipMemcpyAsync(bm.data(), bmin_d, (nbx + nby) * 8, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+            hipStreamSynchronize(h->stream) != hipSuccess) {
+            cleanup_tmp();
+            return bail(fail(GOC_EDEVICE, "metric precompute failed"));
+        }
+        const double q = *std::min_element(bm.begin(), bm.end());
+        h->q[r] = q;
+        d.cs2 = q * q / 3.0;            // Sec. 3.2.1
+        d.csm2 = d.cs2;                 // App. G: the same CFL-limited sound speed
+        d.nu = d.cs2 * (1.0 / d.omega[4] - 0.5);
+        d.zeta = d.cs2 * (1.0 / d.omega[3] - 0.5);
+        d.eta = params[r].mhd ? d.csm2 * (params[r].tau_m - 0.5) : 0.0;
+        // 16-bit storage scales per direction class: deviations of the order
+        // of the rest-state magnitude times a Mach-number-sized factor map to
+        // O(1..100) stored values
+        const double c2 = d.cs2, r0 = d.rho0;
+        const double mag[4] = {r0, 0.5 * r0 * c2, 0.5 * r0 * c2, 0.25 * r0 * c2 * c2};
+        for (int k = 0; k < 4; ++k) d.sc[k] = 1.0 / std::max(mag[k] * 1e-2, 1e-30);
+        d.scg = 1.0 / std::max(std::fabs(d.B0) * 1e-2 + 1e-12, 1e-30);
+    }
+    cleanup_tmp();
+    {
+        std::vector<double> th1(sum_nx), th2(sum_ny);
+        if (hipMemcpy(th1.data(), h->th11_d, sum_nx * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(th2.data(), h->th22_d, sum_ny * 8, hipMemcpyDeviceToHost) != hipSuccess)
+            return bail(fail(GOC_EDEVICE, "metric download failed"));
+    }
+    // run table and work list
+    if ((rc = dev_alloc((void**)&h->runs_d, nruns * sizeof(RunDesc))) ||
+        (rc = dev_alloc((void**)&h->block_run_d, block_run.size() * 4)))
+        return bail(rc);
+    if (hipMemcpy(h->runs_d, h->runs.data(), nruns * sizeof(RunDesc), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->block_run_d, block_run.data(), block_run.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(GOC_EDEVICE, "run table upload failed"));
+    // state pools
+    for (int k = 0; k < 2; ++k) {
+        if ((rc = dev_alloc(&h->f[k], f_elems * sb)) || (rc = dev_alloc(&h->F[k], F_elems * fb)))
+            return bail(rc);
+        if (g_elems && (rc = dev_alloc(&h->g[k], g_elems * sb))) return bail(rc);
+        if (hipMemsetAsync(h->f[k], 0, f_elems * sb, h->stream) != hipSuccess ||
+            hipMemsetAsync(h->F[k], 0, F_elems * fb, h->stream) != hipSuccess ||
+            (g_elems && hipMemsetAsync(h->g[k], 0, g_elems * sb, h->stream) != hipSuccess))
+            return bail(fail(GOC_EDEVICE, "state clear failed"));
+    }
+    *out = h;
+    rc = goc_lbm_init(h, nullptr, nullptr, nullptr, 0);
+    if (rc != GOC_OK) {
+        *out = nullptr;
+        return bail(rc);
+    }
+    return GOC_OK;
+}
+
+goc_lbm* check_handle(goc_lbm_t* h)
+{
+    if (!h) fail(GOC_EINVAL, "handle is NULL");
+    return h;
+}
+
+// Allocate an FP64 device buffer of n doubles for host <-> device staging.
+struct DevBuf {
+    double* p = nullptr;
+    ~DevBuf() { (void)hipFree(p); }
+    int alloc(size_t n)
+    {
+        if (hipMalloc(&p, std::max<size_t>(n, 1) * 8) != hipSuccess)
+            return fail(GOC_ENOMEM, "hipMalloc of %zu doubles failed", n);
+        return GOC_OK;
+    }
+};
+
+int init_run(goc_lbm* h, int run, const double* rho, const double* u1, const double* u2)
+{
+    const RunDesc& d = h->runs[run];
+    dim3 grid, block;
+    per_node_grid(d, grid, block);
+    return dispatch(h->storage, [&](auto tag) -> int {
+        using S = decltype(tag);
+        // write into the current input buffer
+        auto pl = pools<S>(h, 1 - h->cur);
+        hipLaunchKernelGGL(goc::init_kernel<S>, grid, block, 0, h->stream, h->runs_d, run, pl, rho, u1, u2);
+        HIPOK(hipGetLastError());
+        return GOC_OK;
+    });
+}
+
+int gather_run(goc_lbm* h, int run, double* f, double* F, double* g, int on_device)
+{
+    const RunDesc& d = h->runs[run];
+    const size_t N = (size_t)d.nx * d.ny;
+    DevBuf bf, bF, bg;
+    double *fd = f, *Fd = F, *gd = g;
+    int rc;
+    if (!on_device) {
+        if ((rc = bf.alloc(9 * N)) || (rc = bF.alloc(2 * N))) return rc;
+        fd = bf.p;
+        Fd = bF.p;
+        if (d.mhd && g) {
+            if ((rc = bg.alloc(10 * N))) return rc;
+            gd = bg.p;
+        }
+    }
+    if (!d.mhd) gd = nullptr;
+    dim3 grid, block;
+    per_node_grid(d, grid, block);
+    rc = dispatch(h->storage, [&](auto tag) -> int {
+        using S = decltype(tag);
+        auto pl = pools<S>(h, h->cur);
+        hipLaunchKernelGGL(goc::gather_kernel<S>, grid, block, 0, h->stream, h->runs_d, run, pl, fd, Fd, gd);
+        HIPOK(hipGetLastError());
+        return GOC_OK;
+    });
+    if (rc) return rc;
+    if (!on_device) {
+        HIPOK(hipMemcpyAsync(f, fd, 9 * N * 8, hipMemcpyDeviceToHost, h->stream));
+        HIPOK(hipMemcpyAsync(F, Fd, 2 * N * 8, hipMemcpyDeviceToHost, h->stream));
+        if (gd) HIPOK(hipMemcpyAsync(g, gd, 10 * N * 8, hipMemcpyDeviceToHost, h->stream));
+        HIPOK(hipStreamSynchronize(h->stream));
+    }
+    return GOC_OK;
+}
+
+int fields_run(goc_lbm* h, int run, double* rho, double* u, double* B, int on_device)
+{
+    const RunDesc& d = h->runs[run];
+    const size_t N = (size_t)d.nx * d.ny;
+    DevBuf br, bu, bB;
+    double *rd = rho, *ud = u, *Bd = d.mhd ? B : nullptr;
+    int rc;
+    if (!on_device) {
+        if (rho && (rc = br.alloc(N))) return rc;
+        if (u && (rc = bu.alloc(2 * N))) return rc;
+        if (Bd && (rc = bB.alloc(2 * N))) return rc;
+        rd = rho ? br.p : nullptr;
+        ud = u ? bu.p : nullptr;
+        Bd = Bd ? bB.p : nullptr;
+    }
+    dim3 grid, block;
+    per_node_grid(d, grid, block);
+    rc = dispatch(h->storage, [&](auto tag) -> int {
+        using S = decltype(tag);
+        auto pl = pools<S>(h, h->cur);
+        hipLaunchKernelGGL(goc::fields_kernel<S>, grid, block, 0, h->stream, h->runs_d, run, pl, rd, ud, Bd);
+        HIPOK(hipGetLastError());
+        return GOC_OK;
+    });
+    if (rc) return rc;
+    if (!on_device) {
+        if (rho) HIPOK(hipMemcpyAsync(rho, rd, N * 8, hipMemcpyDeviceToHost, h->stream));
+        if (u) HIPOK(hipMemcpyAsync(u, ud, 2 * N * 8, hipMemcpyDeviceToHost, h->stream));
+        if (Bd) HIPOK(hipMemcpyAsync(B, Bd, 2 * N * 8, hipMemcpyDeviceToHost, h->stream));
+        HIPOK(hipStreamSynchronize(h->stream));
+    }
+    return GOC_OK;
+}
+
+int diag_run(goc_lbm* h, int run, double out[goc::kDiag])
+{
+    const RunDesc& d = h->runs[run];
+    const int64_t N = (int64_t)d.nx * d.ny;
+    const int nb = (int)((N + 255) / 256);
+    if (nb > h->diag_cap) {
+        (void)hipFree(h->diag_part);
+        h->diag_part = nullptr;
+        if (hipMalloc(&h->diag_part, (size_t)nb * goc::kDiag * 8) != hipSuccess)
+            return fail(GOC_ENOMEM, "diagnostics scratch allocation failed");
+        h->diag_cap = nb;
+    }
+    if (!h->diag_out && hipMalloc(&h->diag_out, goc::kDiag * 8) != hipSuccess)
+        return fail(GOC_ENOMEM, "diagnostics allocation failed");
+    int rc = dispatch(h->storage, [&](auto tag) -> int {
+        using S = decltype(tag);
+        auto pl = pools<S>(h, h->cur);
+        hipLaunchKernelGGL(goc::diag_kernel<S>, dim3(nb), dim3(256), 0, h->stream, h->runs_d, run, pl,
+                           h->diag_part);
+        HIPOK(hipGetLastError());
+        return GOC_OK;
+    });
+    if (rc) return rc;
+    hipLaunchKernelGGL(goc::diag_final_kernel, dim3(1), dim3(256), 0, h->stream, h->diag_part, nb, h->diag_out);
+    HIPOK(hipGetLastError());
+    HIPOK(hipMemcpyAsync(out, h->diag_out, goc::kDiag * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPOK(hipStreamSynchronize(h->stream));
+    return GOC_OK;
+}
+
+int capture_graph(goc_lbm* h, int parity)
+{
+    hipGraph_t g = nullptr;
+    const int saved = h->cur;
+    h->cur = parity;
+    if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        h->cur = saved;
+        return fail(GOC_EDEVICE, "graph capture could not start (the stream must not be the NULL stream)");
+    }
+    int rc = GOC_OK;
+    for (int s = 0; s < kGraphSteps && rc == GOC_OK; ++s) {
+        rc = launch_step(h);
+        h->cur ^= 1;
+    }
+    hipError_t e = hipStreamEndCapture(h->stream, &g);
+    h->cur = saved;
+    if (rc != GOC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(GOC_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&h->graph[parity], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(GOC_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    return GOC_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI ==
+extern "C" {
+
+const char* goc_lbm_last_error(void) { return g_err.c_str(); }
+
+int goc_lbm_derive(goc_grid* grid, const goc_metric* metric, const goc_physics* phys, goc_params* out)
+{
+    int rc;
+    if ((rc = check_grid(grid)) != GOC_OK) return rc;
+    if (!metric || !phys || !out) return fail(GOC_EINVAL, "NULL metric, physics or output");
+    Metric1D mx, my;
+    if ((rc = build_metric(*grid, *metric, mx, my)) != GOC_OK) return rc;
+    const double q = std::min(*std::min_element(mx.h.begin(), mx.h.end()),
+                              *std::min_element(my.h.begin(), my.h.end()));
+    const double cs2 = q * q / 3.0;
+    const double rho0 = phys->rho0 > 0 ? phys->rho0 : 1.0;
+    goc_params p;
+    std::memset(&p, 0, sizeof(p));
+    for (int k = 0; k < 9; ++k) p.omega[k] = 1.0;
+    p.rho0 = rho0;
+    p.gi_terms = 1;
+    p.lid_corners = 1;
+    p.mu_m = phys->mu_m > 0 ? phys->mu_m : 1.0;
+    p.tau_m = 1.0;
+    double nu = 0.0;
+    switch (phys->flow) {
+    case GOC_FLOW_CHANNEL: {
+        if (!(phys->tau > 0.5)) return fail(GOC_EINVAL, "channel flow needs tau > 1/2");
+        nu = cs2 * (phys->tau - 0.5);
+        const double half = 0.5 * grid->ny;
+        const double U = phys->Re * nu / half;
+        p.F_ext[0] = 2.0 * nu * U * rho0 / (half * half);
+        break;
+    }
+    case GOC_FLOW_CAVITY:
+        if (!(phys->Re > 0)) return fail(GOC_EINVAL, "cavity flow needs Re > 0");
+        nu = phys->u_lid * grid->nx / phys->Re;
+        grid->u_wall_hi = phys->u_lid;
+        break;
+    case GOC_FLOW_HARTMANN: {
+        if (!(phys->Re > 0) || !(phys->Pm > 0) || !(phys->Ma > 0))
+            return fail(GOC_EINVAL, "Hartmann flow needs Re, Pm, Ma > 0");
+        const double H = 0.5 * grid->ny;
+        const double Uc = phys->Ma * std::sqrt(cs2);
+        nu = Uc * H / phys->Re;
+        const double eta = nu / phys->Pm;
+        const double sigma = 1.0 / (eta * p.mu_m);
+        const double Ha = phys->Ha;
+        p.B0 = Ha > 0 ? Ha / (H * std::sqrt(sigma / (rho0 * nu))) : 0.0;
+        const double shape = Ha > 0 ? (1.0 - 1.0 / std::cosh(Ha)) / (Ha * std::tanh(Ha)) : 0.5;
+        p.F_ext[0] = Uc * rho0 * nu / (H * H * shape);
+        p.mhd = 1;
+        p.tau_m = eta / cs2 + 0.5;
+        break;
+    }
+    case GOC_FLOW_FREE:
+        if (!(phys->tau > 0.5)) return fail(GOC_EINVAL, "free flow needs tau > 1/2");
+        nu = cs2 * (phys->tau - 0.5);
+        p.F_ext[0] = phys->F_ext[0];
+        p.F_ext[1] = phys->F_ext[1];
+        break;
+    default:
+        return fail(GOC_EINVAL, "unknown flow kind %d", phys->flow);
+    }
+    if (!(nu > 0)) return fail(GOC_EINVAL, "derived viscosity %g is not positive", nu);
+    p.omega[4] = p.omega[5] = 1.0 / (nu / cs2 + 0.5);
+    *out = p;
+    return GOC_OK;
+}
+
+int goc_lbm_create(goc_lbm_t** out, const goc_grid* grid, const goc_metric* metric, const goc_params* params,
+                   int32_t storage, void* stream)
+{
+    return create_impl(out, 1, grid, metric, params, storage, stream);
+}
+
+int goc_lbm_create_batch(goc_lbm_t** out, int32_t nruns, const goc_grid* grid, const goc_metric* metric,
+                         const goc_params* params, int32_t storage, void* stream)
+{
+    return create_impl(out, nruns, grid, metric, params, storage, stream);
+}
+
+int32_t goc_lbm_num_runs(const goc_lbm_t* h) { return h ? h->nruns : 0; }
+
+void goc_lbm_destroy(goc_lbm_t* h)
+{
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    free_all(h);
+    delete h;
+}
+
+int goc_lbm_init(goc_lbm_t* h, const double* rho, const double* u1, const double* u2, int32_t on_device)
+{
+    if (!check_handle(h)) return GOC_EINVAL;
+    const bool given = rho || u1 || u2;
+    if (given && !(rho && u1 && u2)) return fail(GOC_EINVAL, "init needs all of rho, u1, u2 or none");
+    if (given && h->nruns != 1) return fail(GOC_EINVAL, "field initialisation is per single run");
+    // write into the input buffer: kernels write to "out" of pools(1 - cur)
+    if (!given) {
+        for (int r = 0; r < h->nruns; ++r) {
+            int rc = init_run(h, r, nullptr, nullptr, nullptr);
+            if (rc) return rc;
+        }
+    } else {
+        const RunDesc& d = h->runs[0];
+        const size_t N = (size_t)d.nx * d.ny;
+        DevBuf br, b1, b2;
+        const double *rd = rho, *d1 = u1, *d2 = u2;
+        if (!on_device) {
+            int rc;
+            if ((rc = br.alloc(N)) || (rc = b1.alloc(N)) || (rc = b2.alloc(N))) return rc;
+            HIPOK(hipMemcpyAsync(br.p, rho, N * 8, hipMemcpyHostToDevice, h->stream));
+            HIPOK(hipMemcpyAsync(b1.p, u1, N * 8, hipMemcpyHostToDevice, h->stream));
+            HIPOK(hipMemcpyAsync(b2.p, u2, N * 8, hipMemcpyHostToDevice, h->stream));
+            rd = br.p;
+            d1 = b1.p;
+            d2 = b2.p;
+        }
+        int rc = init_run(h, 0, rd, d1, d2);
+        if (rc) return rc;
+        HIPOK(hipStreamSynchronize(h->stream));
+    }
+    h->step = 0;
+    HIPOK(hipStreamSynchronize(h->stream));
+    return GOC_OK;
+}
+
+int goc_lbm_step(goc_lbm_t* h, int64_t n)
+{
+    if (!check_handle(h)) return GOC_EINVAL;
+    if (n < 0) return fail(GOC_EINVAL, "negative step count");
+    while (n > 0) {
+        int64_t chunk = n;
+        if (h->watchdog > 0) chunk = std::min<int64_t>(chunk, h->watchdog - (h->step % h->watchdog));
+        int64_t done = 0;
+        // whole graph blocks when a capturable stream is in use
+        while (h->stream && chunk - done >= kGraphSteps) {
+            if (!h->graph[h->cur]) {
+                int rc = capture_graph(h, h->cur);
+                if (rc) return rc;
+            }
+            HIPOK(hipGraphLaunch(h->graph[h->cur], h->stream));
+            done += kGraphSteps;   // an even count: parity unchanged
+        }
+        for (; done < chunk; ++done) {
+            int rc = launch_step(h);
+            if (rc) return rc;
+            h->cur ^= 1;
+        }
+        h->step += chunk;
+        n -= chunk;
+        if (h->watchdog > 0 && h->step % h->watchdog == 0) {
+            for (int r = 0; r < h->nruns; ++r) {
+                double o[goc::kDiag];
+                int rc = diag_run(h, r, o);
+                if (rc) return rc;
+                if (o[6] > 0) return fail(GOC_EUNSTABLE, "run %d: %g non-finite values at step %lld", r, o[6],
+                                          (long long)h->step);
+            }
+        }
+    }
+    return GOC_OK;
+}
+
+int goc_lbm_set_watchdog(goc_lbm_t* h, int64_t every)
+{
+    if (!check_handle(h)) return GOC_EINVAL;
+    if (every < 0) return fail(GOC_EINVAL, "negative watchdog interval");
+    h->watchdog = every;
+    return GOC_OK;
+}
+
+int goc_lbm_moments_run(goc_lbm_t* h, int32_t run, double* rho, double* u, double* B, int32_t on_device)
+{
+    if (!check_handle(h)) return GOC_EINVAL;
+    if (run < 0 || run >= h->nruns) return fail(GOC_EINVAL, "run %d out of range", run);
+    return fields_run(h, run, rho, u, B, on_device);
+}
+
+int goc_lbm_moments(goc_lbm_t* h, double* rho, double* u, double* B, int32_t on_device)
+{
+    return goc_lbm_moments_run(h, 0, rho, u, B, on_device);
+}
+
+int goc_lbm_diagnostics(goc_lbm_t* h, double out[8])
+{
+    if (!check_handle(h)) return GOC_EINVAL;
+    if (!out) return fail(GOC_EINVAL, "out is NULL");
+    double o[goc::kDiag];
+    int rc = diag_run(h, 0, o);
+    if (rc) return rc;
+    out[0] = o[0];
+    out[1] = o[1];
+    out[2] = o[2];
+    out[3] = o[1] / h->runs[0].nx;
+    out[4] = o[3];
+    out[5] = o[4];
+    out[6] = o[5];
+    out[7] = o[6];
+    return GOC_OK;
+}
+
+int goc_lbm_get_populations_run(goc_lbm_t* h, int32_t run, double* f, double* F, double* g, int32_t on_device)
+{
+    if (!check_handle(h)) return GOC_EINVAL;
+    if (run < 0 || run >= h->nruns) return fail(GOC_EINVAL, "run %d out of range", run);
+    if (!f || !F) return fail(GOC_EINVAL, "f and F are required");
+    return gather_run(h, run, f, F, g, on_device);
+}
+
+int goc_lbm_get_populations(goc_lbm_t* h, double* f, double* F, double* g, int32_t on_device)
+{
+    return goc_lbm_get_populations_run(h, 0, f, F, g, on_device);
+}
+
+int goc_lbm_set_populations(goc_lbm_t* h, const double* f, const double* F, const double* g, int32_t on_device)
+{
+    if (!check_handle(h)) return GOC_EINVAL;
+    if (!f || !F) return fail(GOC_EINVAL, "f and F are required");
+    const RunDesc& d = h->runs[0];
+    if (d.mhd && !g) return fail(GOC_EINVAL, "MHD run needs g");
+    const size_t N = (size_t)d.nx * d.ny;
+    DevBuf bf, bF, bg;
+    const double *fd = f, *Fd = F, *gd = d.mhd ? g : nullptr;
+    int rc;
+    if (!on_device) {
+        if ((rc = bf.alloc(9 * N)) || (rc = bF.alloc(2 * N))) return rc;
+        HIPOK(hipMemcpyAsync(bf.p, f, 9 * N * 8, hipMemcpyHostToDevice, h->stream));
+        HIPOK(hipMemcpyAsync(bF.p, F, 2 * N * 8, hipMemcpyHostToDevice, h->stream));
+        fd = bf.p;
+        Fd = bF.p;
+        if (gd) {
+            if ((rc = bg.alloc(10 * N))) return rc;
+            HIPOK(hipMemcpyAsync(bg.p, g, 10 * N * 8, hipMemcpyHostToDevice, h->stream));
+            gd = bg.p;
+        }
+    }
+    dim3 grid, block;
+    per_node_grid(d, grid, block);
+    rc = dispatch(h->storage, [&](auto tag) -> int {
+        using S = decltype(tag);
+        auto pl = pools<S>(h, 1 - h->cur);   // out = current input buffer
+        hipLaunchKernelGGL(goc::scatter_kernel<S>, grid, block, 0, h->stream, h->runs_d, 0, pl, fd, Fd, gd);
+        HIPOK(hipGetLastError());
+        return GOC_OK;
+    });
+    if (rc) return rc;
+    HIPOK(hipStreamSynchronize(h->stream));
+    return GOC_OK;
+}
+
+namespace {
+struct StateHeader {
+    char magic[8];
+    int32_t version, storage, nruns, mhd;
+    int64_t step, f_bytes, F_bytes, g_bytes;
+};
+}
+
+int goc_lbm_get_state(goc_lbm_t* h, void* buf, size_t* bytes)
+{
+    if (!check_handle(h)) return GOC_EINVAL;
+    if (!bytes) return fail(GOC_EINVAL, "bytes is NULL");
+    const size_t sb = storage_bytes(h->storage), fb = force_bytes(h->storage);
+    StateHeader hd;
+    std::memset(&hd, 0, sizeof(hd));
+    std::memcpy(hd.magic, "GOCLBM01", 8);
+    hd.version = 1;
+    hd.storage = h->storage;
+    hd.nruns = h->nruns;
+    hd.mhd = h->any_mhd;
+    hd.step = h->step;
+    hd.f_bytes = h->f_elems * sb;
+    hd.F_bytes = h->F_elems * fb;
+    hd.g_bytes = h->g_elems * sb;
+    const size_t need = sizeof(hd) + hd.f_bytes + hd.F_bytes + hd.g_bytes;
+    if (!buf) {
+        *bytes = need;
+        return GOC_OK;
+    }
+    if (*bytes < need) return fail(GOC_EINVAL, "state buffer of %zu bytes, need %zu", *bytes, need);
+    char* p = static_cast<char*>(buf);
+    std::memcpy(p, &hd, sizeof(hd));
+    p += sizeof(hd);
+    HIPOK(hipMemcpyAsync(p, h->f[h->cur], hd.f_bytes, hipMemcpyDeviceToHost, h->stream));
+    HIPOK(hipMemcpyAsync(p + hd.f_bytes, h->F[h->cur], hd.F_bytes, hipMemcpyDeviceToHost, h->stream));
+    if (hd.g_bytes)
+        HIPOK(hipMemcpyAsync(p + hd.f_bytes + hd.F_bytes, h->g[h->cur], hd.g_bytes, hipMemcpyDeviceToHost,
+                             h->stream));
+    HIPOK(hipStreamSynchronize(h->stream));
+    *bytes = need;
+    return GOC_OK;
+}
+
+int goc_lbm_set_state(goc_lbm_t* h, const void* buf, size_t bytes)
+{
+    if (!check_handle(h)) return GOC_EINVAL;
+    if (!buf) return fail(GOC_EINVAL, "buf is NULL");
+    size_t need = 0;
+    goc_lbm_get_state(h, nullptr, &need);
+    if (bytes != need) return fail(GOC_ESTATE, "state blob of %zu bytes, this run needs %zu", bytes, need);
+    StateHeader hd;
+    std::memcpy(&hd, buf, sizeof(hd));
+    if (std::memcmp(hd.magic, "GOCLBM01", 8) != 0 || hd.version != 1 || hd.storage != h->storage ||
+        hd.nruns != h->nruns)
+        return fail(GOC_ESTATE, "state blob does not match this run (magic, version, storage or run count)");
+    const char* p = static_cast<const char*>(buf) + sizeof(hd);
+    HIPOK(hipMemcpyAsync(h->f[h->cur], p, hd.f_bytes, hipMemcpyHostToDevice, h->stream));
+    HIPOK(hipMemcpyAsync(h->F[h->cur], p + hd.f_bytes, hd.F_bytes, hipMemcpyHostToDevice, h->stream));
+    if (hd.g_bytes)
+        HIPOK(hipMemcpyAsync(h->g[h->cur], p + hd.f_bytes + hd.F_bytes, hd.g_bytes, hipMemcpyHostToDevice,
+                             h->stream));
+    HIPOK(hipStreamSynchronize(h->stream));
+    h->step = hd.step;
+    return GOC_OK;
+}
+
+int goc_lbm_derived(const goc_lbm_t* h, double out[16])
+{
+    if (!h) return fail(GOC_EINVAL, "handle is NULL");
+    if (!out) return fail(GOC_EINVAL, "out is NULL");
+    const RunDesc& d = h->runs[0];
+    const double sb = (double)storage_bytes(h->storage), fb = (double)force_bytes(h->storage);
+    out[0] = d.cs2;
+    out[1] = d.nu;
+    out[2] = d.zeta;
+    out[3] = h->q[0];
+    out[4] = d.csm2;
+    out[5] = d.eta;
+    out[6] = d.tau_m;
+    out[7] = d.B0;
+    out[8] = d.Fx1;
+    out[9] = d.Fx2;
+    out[10] = d.hw_lo;
+    out[11] = d.hw_hi;
+    out[12] = (double)h->step;
+    out[13] = 2.0 * (9.0 * sb + 2.0 * fb + (d.mhd ? 10.0 * sb : 0.0));
+    out[14] = d.nx;
+    out[15] = d.ny;
+    return GOC_OK;
+}
+
+int goc_lbm_metric(const goc_lbm_t* h, double* h1, double* th11, double* h2, double* th22)
+{
+    if (!h) return fail(GOC_EINVAL, "handle is NULL");
+    const RunDesc& d = h->runs[0];
+    if (h1) HIPOK(hipMemcpy(h1, h->h1_d + d.metric_off_x, d.nx * 8, hipMemcpyDeviceToHost));
+    if (th11) HIPOK(hipMemcpy(th11, h->th11_d + d.metric_off_x, d.nx * 8, hipMemcpyDeviceToHost));
+    if (h2) HIPOK(hipMemcpy(h2, h->h2_d + d.metric_off_y, d.ny * 8, hipMemcpyDeviceToHost));
+    if (th22) HIPOK(hipMemcpy(th22, h->th22_d + d.metric_off_y, d.ny * 8, hipMemcpyDeviceToHost));
+    return GOC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every entry point its header declares, and its host-only parameter
+derivation agrees with the oracle's independent one."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2607_15362_amd import binding as B
+from paper_2607_15362_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "goc_lbm.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(goc_lbm_\w+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        from paper_2607_15362_amd import build
+        build.build(force=True)
+    return B.lib()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    syms = _declared_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(lib, s), f"{s} declared in goc_lbm.h but not exported"
+        assert s in B.SIGNATURES, f"{s} has no binding signature"
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(B, "_lib", None)
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(ImportError):
+        B.lib()
+
+
+@pytest.mark.parametrize("case", [W.channel_64(), W.cavity_1024(), W.hartmann_4096(),
+                                  W.Case("r", 6, 50, "periodic", "wall", ("uniform", 0), ("roberts", 1.06),
+                                         flow="free", tau=1.0, body_force=(1e-6, 0.0))])
+def test_derive_matches_oracle(lib, oracle_lib, case):
+    g, m, p = B.derive(case)
+    o = oracle_lib
+    h1 = o.metric_1d(case.nx, case.stretch_x)[0]
+    h2 = o.metric_1d(case.ny, case.stretch_y)[0]
+    lat = o.derive(case, h1, h2)
+    assert p.omega[4] == pytest.approx(lat.omega[4], rel=1e-13)
+    assert p.omega[5] == pytest.approx(lat.omega[5], rel=1e-13)
+    for k in (0, 1, 2, 3, 6, 7, 8):
+        assert p.omega[k] == 1.0
+    assert p.F_ext[0] == pytest.approx(lat.Fext[0], rel=1e-12, abs=1e-300)
+    assert p.F_ext[1] == pytest.approx(lat.Fext[1], rel=1e-12, abs=1e-300)
+    assert g.u_wall_hi == pytest.approx(lat.u_wall_hi)
+    if case.mhd:
+        assert p.mhd == 1
+        assert p.B0 == pytest.approx(lat.B0, rel=1e-12)
+        assert p.tau_m == pytest.approx(lat.tau_m, rel=1e-12)
+
+
+def test_derive_rejects_bad_input(lib):
+    case = W.channel_64()
+    g, m, ph = B.case_structs(case)
+    p = B.Params()
+    g.nx = 2
+    assert lib.goc_lbm_derive(g, m, ph, p) == B.GOC_EINVAL
+    assert "3" in lib.goc_lbm_last_error().decode()
+    g, m, ph = B.case_structs(case)
+    ph.tau = 0.4
+    assert lib.goc_lbm_derive(g, m, ph, p) == B.GOC_EINVAL
+    g, m, ph = B.case_structs(case)
+    m.kind_y, m.param_y = B.STRETCH["tanh"], -1.0
+    assert lib.goc_lbm_derive(g, m, ph, p) == B.GOC_EINVAL
+    g, m, ph = B.case_structs(case)
+    m.kind_y = B.STRETCH["array"]   # array kind without arrays
+    assert lib.goc_lbm_derive(g, m, ph, p) == B.GOC_EINVAL
+
+
+def test_create_rejects_bad_input_before_touching_the_device(lib):
+    case = W.channel_64()
+    g, m, p = B.derive(case)
+    h = B.VP()
+    p.omega[4] = 2.5
+    assert lib.goc_lbm_create(B.C.byref(h), g, m, p, 1, None) == B.GOC_EINVAL
+    assert not h.value
+    assert lib.goc_lbm_create(None, g, m, p, 1, None) == B.GOC_EINVAL
+    g, m, p = B.derive(case)
+    assert lib.goc_lbm_create(B.C.byref(h), g, m, p, 7, None) == B.GOC_EINVAL
