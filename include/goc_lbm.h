@@ -61,9 +61,11 @@ typedef enum {
 
 typedef enum {
     GOC_FLOW_CHANNEL = 0,   /* body-force channel, Sec. 8.1: Re = U (H/2)/nu, tau given */
-    GOC_FLOW_CAVITY = 1,    /* lid-driven cavity, Sec. 8.3: Re = U_lid L / nu           */
+    GOC_FLOW_CAVITY = 1,    /* lid-driven cavity, Sec. 8.3: Re = U_lid L / nu,
+                               U_lid = u_lid, or Ma c_s when u_lid <= 0               */
     GOC_FLOW_HARTMANN = 2,  /* MHD channel, Sec. 8.4: Re = U_c H / nu, H half-width,
-                               U_c = Ma c_s, eta = nu / Pm                            */
+                               U_c = Ma c_s lowered so that tau <= tau_max when
+                               tau_max > 1/2; eta = nu / Pm                          */
     GOC_FLOW_FREE = 3       /* no derived forcing: tau and F_ext given                */
 } goc_flow;
 
@@ -117,6 +119,7 @@ typedef struct {
     int32_t flow;             /* goc_flow                                    */
     double Re, Ha, Pm, Ma;
     double tau;               /* channel / free flows: shear relaxation time */
+    double tau_max;           /* Hartmann: cap on the shear relaxation time  */
     double u_lid;             /* cavity: lid (xi2 = ny wall) speed           */
     double rho0, mu_m;
     double F_ext[2];          /* free flows: body force                      */
@@ -127,10 +130,11 @@ typedef struct goc_lbm goc_lbm_t;
 /* Derive lattice parameters from physical ones (Sec. 3.2.1, Sec. 5,
    App. G, Sec. 8), for the given grid and metric: c_s^2 from the metric;
    channel: nu = c_s^2 (tau - 1/2), U = Re nu/(H/2), F = 2 nu U rho0/(H/2)^2
-   with H = ny; cavity: nu = u_lid nx / Re and grid->u_wall_hi = u_lid;
-   Hartmann: U_c = Ma c_s, nu = U_c (ny/2)/Re, eta = nu/Pm, B0 from Ha, F
-   from the analytic centre-line speed; omega4 = omega5 from nu, the other
-   rates 1.  Writes *out and may update grid->u_wall_*.  Host only. */
+   with H = ny; cavity: nu = U_lid nx / Re and grid->u_wall_hi = U_lid;
+   Hartmann: U_c = Ma c_s (reduced if tau would exceed tau_max),
+   nu = U_c (ny/2)/Re, eta = nu/Pm, B0 from Ha, F from the analytic
+   centre-line speed; omega4 = omega5 from nu, the other rates 1.  Writes
+   *out and may update grid->u_wall_*.  Host only. */
 int goc_lbm_derive(goc_grid *grid, const goc_metric *metric, const goc_physics *phys,
                    goc_params *out);
 

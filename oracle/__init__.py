@@ -139,11 +139,15 @@ def derive(case, h1, h2) -> Lattice:
         Fext = (F, 0.0)
         extra.update(U=U)
     elif case.flow == "cavity":
-        nu = case.u_lid * case.nx / case.Re
-        u_hi = case.u_lid
+        u_hi = case.u_lid if case.u_lid > 0 else case.Ma * np.sqrt(cs2)
+        nu = u_hi * case.nx / case.Re
     elif case.flow == "hartmann":
         H = case.ny / 2.0
         Uc = case.Ma * np.sqrt(cs2)
+        tmax = getattr(case, "tau_max", 0.0)
+        if tmax > 0 and params.viscosity_from_tau(cs2, tmax) < Uc * H / case.Re:
+            # reading: cap the shear relaxation time (Re = Uc H / nu kept)
+            Uc = params.viscosity_from_tau(cs2, tmax) * case.Re / H
         hp = params.hartmann(H, case.Ha, case.Re, case.Pm, Uc, rho0, case.mu_m)
         nu, eta, B0 = hp["nu"], hp["eta"], hp["B0"]
         Fext = (hp["F"], 0.0)

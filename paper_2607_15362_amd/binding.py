@@ -49,7 +49,8 @@ class Params(C.Structure):
 
 class Physics(C.Structure):
     _fields_ = [("flow", C.c_int32), ("Re", C.c_double), ("Ha", C.c_double), ("Pm", C.c_double),
-                ("Ma", C.c_double), ("tau", C.c_double), ("u_lid", C.c_double), ("rho0", C.c_double),
+                ("Ma", C.c_double), ("tau", C.c_double), ("tau_max", C.c_double),
+                ("u_lid", C.c_double), ("rho0", C.c_double),
                 ("mu_m", C.c_double), ("F_ext", C.c_double * 2)]
 
 
@@ -126,6 +127,7 @@ def case_structs(case):
     ph.flow = FLOW[case.flow]
     ph.Re, ph.Ha, ph.Pm, ph.Ma = case.Re, case.Ha, case.Pm, case.Ma
     ph.tau, ph.u_lid, ph.rho0, ph.mu_m = case.tau, case.u_lid, case.rho0, case.mu_m
+    ph.tau_max = getattr(case, "tau_max", 0.0)
     ph.F_ext[0], ph.F_ext[1] = case.body_force
     return g, m, ph
 
@@ -334,7 +336,7 @@ class Run:
                 "step", "bytes_per_node", "nx", "ny"]
         return dict(zip(keys, out))
 
-    def metric(self):
+    def metric_arrays(self):
         h1, t1 = np.zeros(self.nx), np.zeros(self.nx)
         h2, t2 = np.zeros(self.ny), np.zeros(self.ny)
         _check(lib().goc_lbm_metric(self.h, _dptr(h1), _dptr(t1), _dptr(h2), _dptr(t2)))

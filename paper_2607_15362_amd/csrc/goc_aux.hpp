@@ -1,13 +1,14 @@
 // goc_aux.hpp -- once-per-run and read-out kernels: metric precompute,
-// initial state, slot <-> population conversion, fields and global sums.
-// One thread per node; none of these is on the per-step path.
+// column / row tables, initial state, slot <-> population conversion,
+// fields and global sums.  One thread per node (or per column / row); none
+// of these is on the per-step path.
 #pragma once
 
 #include "goc_step.hpp"
 
 namespace goc {
 
-// (a) Metric precompute in FP64: theta = (dh/dxi) / h^2 (Sec. 2.1, diagonal
+// Metric precompute in FP64: theta = (dh/dxi) / h^2 (Sec. 2.1, diagonal
 // elements on a straight grid) and the block minima of h for q (Sec. 3.2.1).
 __global__ void metric_kernel(const double* __restrict__ h, const double* __restrict__ dh,
                               double* __restrict__ th, int n, double* __restrict__ block_min)
@@ -28,34 +29,34 @@ __global__ void metric_kernel(const double* __restrict__ h, const double* __rest
     if (threadIdx.x == 0) block_min[blockIdx.x] = smin[0];
 }
 
-// Per-node codec context (one column).
-template <class S, class T>
-__device__ inline RowCtx<S, T> node_ctx(const RunDesc& d, const Pools<S, typename ForceOf<S>::type>& pl,
-                                        int col, Lane& L)
+// Column (or row) tables in FP64 from h and theta along one axis:
+// h, 1/h, theta, P0/2 (1/h(i) - 1/h(i+-1)), W1 B0 (h(i) - h(i+-1)); the
+// neighbour terms are zero where the neighbour lies beyond a wall (the slot
+// is then read back by the node itself) and wrap when periodic.
+__global__ void table_kernel(const double* __restrict__ h, const double* __restrict__ th, int n,
+                             int periodic, double P0, double W1B0, double* __restrict__ tab)
 {
-    RowCtx<S, T> c{d, pl, d.f_off, d.F_off, d.metric_off_y, T(d.rho0), T(d.cs2), T(1), T(1), T(1), {}};
-    const int64_t mx = d.metric_off_x;
-    L.col = col;
-    L.cvalid = true;
-    L.own = true;
-    c.h1c = T(pl.h1[mx + col]);
-    if constexpr (Store<S>::dev) {
-        const int cm = d.bc_x == 0 ? (col + d.nx - 1) % d.nx : max(col - 1, 0);
-        const int cp = d.bc_x == 0 ? (col + 1) % d.nx : min(col + 1, d.nx - 1);
-        c.h1m1 = T(pl.h1[mx + cm]);
-        c.h1p1 = T(pl.h1[mx + cp]);
-        for (int k = 0; k < 4; ++k) c.sinv[k] = T(1.0 / d.sc[k]);
-    }
-    return c;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int ip = periodic ? (i + 1) % n : i + 1;
+    const int im = periodic ? (i + n - 1) % n : i - 1;
+    const bool hp = ip < n, hm = im >= 0;
+    double* t = tab + (int64_t)i * kTab;
+    t[T_H] = h[i];
+    t[T_IH] = 1.0 / h[i];
+    t[T_TH] = th[i];
+    t[T_AP] = hp ? 0.5 * P0 * (1.0 / h[i] - 1.0 / h[ip]) : 0.0;
+    t[T_AM] = hm ? 0.5 * P0 * (1.0 / h[i] - 1.0 / h[im]) : 0.0;
+    t[T_BP] = hp ? W1B0 * (h[i] - h[ip]) : 0.0;
+    t[T_BM] = hm ? W1B0 * (h[i] - h[im]) : 0.0;
+    t[7] = 0.0;
 }
 
 // Destination slot of population a arriving at node (i, j): the slot its
 // pull reads (inverse of the gather of the step kernel).
-__device__ inline void slot_of(const RunDesc& d, int i, int j, int a, int& si, int& sj, int& pa)
+__device__ inline int64_t slot_index(const RunDesc& d, int i, int j, int a)
 {
-    si = i - ex_(a);
-    sj = j - ey_(a);
-    pa = a;
+    int si = i - ex_(a), sj = j - ey_(a), pa = a;
     bool wall = false;
     if (si < 0 || si >= d.nx) {
         if (d.bc_x == 0) si = si < 0 ? si + d.nx : si - d.nx;
@@ -66,33 +67,29 @@ __device__ inline void slot_of(const RunDesc& d, int i, int j, int a, int& si, i
         else wall = true;
     }
     if (wall) { si = i; sj = j; pa = opp_(a); }
+    return (int64_t)pa * d.plane + (int64_t)sj * d.pitch + si;
 }
 
-template <class S, class T>
-__device__ inline void put_slot(const RunDesc& d, const Pools<S, typename ForceOf<S>::type>& pl, S* buf,
-                                int64_t off, int si, int sj, int pa, T v, bool mhd_plane, int ci)
+__device__ inline double sc_of(const RunDesc& d, int a, bool scaled) { return scaled ? d.sc[cls_(a)] : 1.0; }
+
+// Per-node metric of run d (FP64).
+struct NodeM {
+    double h1, h2;
+};
+template <class S, class FT>
+__device__ inline NodeM node_metric(const RunDesc& d, const Pools<S, FT>& pl, int i, int j)
 {
-    T rest = T(0), s = T(1);
-    if constexpr (Store<S>::dev) {
-        const T h1 = T(pl.h1[d.metric_off_x + si]);
-        const T h2 = T(pl.h2[d.metric_off_y + sj]);
-        if (!mhd_plane) {
-            rest = rest_pop<T>(pa, h1, h2, T(d.rho0), T(d.cs2));
-            s = T(d.sc[cls_(pa)]);
-        } else {
-            const T W = pa % kM == 0 ? T(1.0 - 2.0 * d.csm2) : T(0.5 * d.csm2);
-            rest = ci == 1 ? W * h1 * h2 * T(d.B0) : T(0);
-            s = T(d.scg);
-        }
-    }
-    Store<S>::st(buf, off + (int64_t)pa * d.plane + (int64_t)sj * d.pitch + si, v, rest, s);
+    NodeM m;
+    m.h1 = pl.col[(d.col_off + i) * kTab + T_H];
+    m.h2 = pl.row[(d.row_off + j) * kTab + T_H];
+    return m;
 }
 
 // Initial state of App. C from node fields (rho, U1, U2), FP64 inputs
-// [ny][nx] (nullptr: rest state rho0, U = 0): raw equilibria of Sec. 3 with
-// the corrections of Sec. 5 (finite-difference gradients of the fields),
-// f = P^-1 m, scattered to the slots; D2Q5: g = g^eq(0) with B = (0, B0);
-// lagged force zero.
+// [ny][nx] (nullptr: rest state rho0, U = 0).  The deviation from the rest
+// state of the raw equilibria of Sec. 3 with the corrections of Sec. 5
+// (finite-difference gradients of the fields) is mapped through P^-1 and
+// scattered to the slots; D2Q5: g^eq(0) with B = (0, B0); lagged force zero.
 template <class S>
 __global__ void init_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename ForceOf<S>::type> pl,
                             const double* __restrict__ rho_in, const double* __restrict__ u1_in,
@@ -105,14 +102,21 @@ __global__ void init_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, 
     const int j = blockIdx.y;
     if (i >= d.nx || j >= d.ny) return;
     const NodeParams<T> p = node_params<T>(d);
-    const T h1 = T(pl.h1[d.metric_off_x + i]), h2 = T(pl.h2[d.metric_off_y + j]);
-    const T th11 = T(pl.th11[d.metric_off_x + i]), th22 = T(pl.th22[d.metric_off_y + j]);
-    auto at = [&](const double* a, int ii, int jj) -> T {
-        return T(a[(int64_t)jj * d.nx + ii]);
-    };
-    T rho = T(d.rho0), U1 = T(0), U2 = T(0), d1U1 = T(0), d2U2 = T(0), d1r = T(0), d2r = T(0);
+    const double* ct = pl.col + (d.col_off + i) * kTab;
+    const double* rt = pl.row + (d.row_off + j) * kTab;
+    NodeMetric<T> g;
+    g.h1 = T(ct[T_H]);
+    g.ih1 = T(ct[T_IH]);
+    g.th11 = T(ct[T_TH]);
+    g.h2 = T(rt[T_H]);
+    g.ih2 = T(rt[T_IH]);
+    g.th22 = T(rt[T_TH]);
+    auto at = [&](const double* a, int ii, int jj) -> T { return T(a[(int64_t)jj * d.nx + ii]); };
+    T rho = p.rho0, U1 = T(0), U2 = T(0), d1U1 = T(0), d2U2 = T(0), d1r = T(0), d2r = T(0);
+    T drho = T(0);
     if (rho_in) {
         rho = at(rho_in, i, j);
+        drho = T(rho_in[(int64_t)j * d.nx + i] - d.rho0);
         U1 = at(u1_in, i, j);
         U2 = at(u2_in, i, j);
         // second-order differences: central, wrapped when periodic, one-sided at walls
@@ -136,17 +140,18 @@ __global__ void init_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, 
         d2r = fdy(rho_in);
     }
     T F1, F2, n3, n4;
-    force_and_corrections<T>(p, h1, h2, th11, th22, rho, U1, U2, d1U1, d2U2, d1r, d2r, p.Fx1, p.Fx2,
-                             F1, F2, n3, n4);
-    const T P = rho * p.cs2, r21 = h2 / h1, r12 = h1 / h2;
-    const T k2s = r21 * rho * U1 * U1 + r12 * rho * U2 * U2 + (r21 + r12) * P + n3;
-    const T k2d = r21 * rho * U1 * U1 - r12 * rho * U2 * U2 + (r21 - r12) * P + n4;
-    const T m00 = h1 * h2 * rho, m10 = h2 * rho * U1, m01 = h1 * rho * U2;
+    force_and_corrections<T>(p, g, rho, U1, U2, d1U1, d2U2, d1r, d2r, p.Fx1, p.Fx2, F1, F2, n3, n4);
+    // raw-equilibrium deviations from the rest moments
+    const T r21 = g.h2 * g.ih1, r12 = g.h1 * g.ih2, cs2 = p.cs2;
+    const T dP = drho * cs2;
+    const T k2s = r21 * (rho * U1 * U1 + dP) + r12 * (rho * U2 * U2 + dP) + n3;
+    const T k2d = r21 * (rho * U1 * U1 + dP) - r12 * (rho * U2 * U2 + dP) + n4;
+    const T m00 = g.h1 * g.h2 * drho, m10 = g.h2 * rho * U1, m01 = g.h1 * rho * U2;
     const T m20 = T(0.5) * (k2s + k2d), m02 = T(0.5) * (k2s - k2d);
     const T m11 = rho * U1 * U2;
-    const T m21 = rho * (p.cs2 + U1 * U1) * U2 / h1;
-    const T m12 = rho * (p.cs2 + U2 * U2) * U1 / h2;
-    const T m22 = rho * p.cs2 * p.cs2 + rho * p.cs2 * (U1 * U1 + U2 * U2) + rho * U1 * U1 * U2 * U2;
+    const T m21 = rho * (cs2 + U1 * U1) * U2 * g.ih1;
+    const T m12 = rho * (cs2 + U2 * U2) * U1 * g.ih2;
+    const T m22 = drho * cs2 * cs2 + rho * cs2 * (U1 * U1 + U2 * U2) + rho * U1 * U1 * U2 * U2;
     T f[kQ];
     f[0] = m00 - m20 - m02 + m22;
     f[1] = T(0.5) * (m10 + m20 - m12 - m22);
@@ -157,66 +162,56 @@ __global__ void init_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, 
     f[6] = T(0.25) * (-m11 + m21 - m12 + m22);
     f[7] = T(0.25) * (m11 - m21 - m12 + m22);
     f[8] = T(0.25) * (-m11 - m21 + m12 + m22);
-    for (int a = 0; a < kQ; ++a) {
-        int si, sj, pa;
-        slot_of(d, i, j, a, si, sj, pa);
-        put_slot<S, T>(d, pl, pl.fout, d.f_off, si, sj, pa, f[a], false, 0);
-    }
+    for (int a = 0; a < kQ; ++a)
+        Store<S>::st(pl.fout + d.f_off, slot_index(d, i, j, a), f[a], T(sc_of(d, a, Store<S>::scaled)));
     const int64_t n = (int64_t)j * d.pitch + i;
     pl.Fout[d.F_off + n] = FT(0);
     pl.Fout[d.F_off + n + d.plane] = FT(0);
     if (d.mhd) {
         const T B[2] = {T(0), p.B0};
         const T U[2] = {U1, U2};
-        const T hh = h1 * h2;
+        const T sg = Store<S>::scaled ? T(d.scg) : T(1);
         for (int ci = 0; ci < 2; ++ci) {
             const T A1 = U[0] * B[ci] - B[0] * U[ci];
             const T A2 = U[1] * B[ci] - B[1] * U[ci];
             for (int a = 0; a < kM; ++a) {
                 const T W = a == 0 ? p.W0 : p.W1;
-                const T g = W * (hh * B[ci] + (T(ex_(a)) * h2 * A1 + T(ey_(a)) * h1 * A2) * p.inv_csm2);
-                int si, sj, pa;
-                slot_of(d, i, j, a, si, sj, pa);
-                put_slot<S, T>(d, pl, pl.gout, d.g_off, si, sj, ci * kM + pa, g, true, ci);
+                // g^eq(0) minus the rest state W h1 h2 B_rest (B = B_rest here)
+                const T dg = W * (T(ex_(a)) * g.h2 * A1 + T(ey_(a)) * g.h1 * A2) * p.inv_csm2;
+                Store<S>::st(pl.gout + d.g_off + ci * kM * d.plane, slot_index(d, i, j, a), dg, sg);
             }
         }
     }
 }
 
-// Post-stream populations (gather) or their inverse (scatter), FP64 node
-// arrays f[9][ny][nx], F[2][ny][nx], g[10][ny][nx].
+// Post-stream populations f = deviation + rest state of the node (the
+// reader), FP64 node arrays f[9][ny][nx], F[2][ny][nx], g[10][ny][nx].
 template <class S>
 __global__ void gather_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename ForceOf<S>::type> pl,
                               double* __restrict__ f, double* __restrict__ F, double* __restrict__ g)
 {
-    using T = typename ComputeOf<S>::type;
     const RunDesc& d = runs[run];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= d.nx || j >= d.ny) return;
-    Lane L;
-    RowCtx<S, T> c = node_ctx<S, T>(d, pl, i, L);
-    T fl[kQ];
-    pull9<S, T>(c, L, j, fl);
+    const NodeM m = node_metric(d, pl, i, j);
     const int64_t N = (int64_t)d.nx * d.ny, o = (int64_t)j * d.nx + i;
-    for (int a = 0; a < kQ; ++a) f[a * N + o] = double(fl[a]);
+    const bool sc = Store<S>::scaled;
+    for (int a = 0; a < kQ; ++a) {
+        const double dv = double(Store<S>::ld(pl.fin + d.f_off, slot_index(d, i, j, a), 1.0f)) / sc_of(d, a, sc);
+        f[a * N + o] = dv + rest_pop(a, m.h1, m.h2, d.rho0, d.cs2);
+    }
     const int64_t n = (int64_t)j * d.pitch + i;
     F[o] = double(pl.Fin[d.F_off + n]);
     F[N + o] = double(pl.Fin[d.F_off + n + d.plane]);
     if (d.mhd && g) {
+        const double scg = sc ? d.scg : 1.0;
         for (int ci = 0; ci < 2; ++ci)
             for (int a = 0; a < kM; ++a) {
-                int si, sj, pa;
-                slot_of(d, i, j, a, si, sj, pa);
-                const int plane = ci * kM + pa;
-                T rest = T(0), inv = T(1);
-                if constexpr (Store<S>::dev) {
-                    const T W = pa == 0 ? T(1.0 - 2.0 * d.csm2) : T(0.5 * d.csm2);
-                    rest = ci == 1 ? W * T(pl.h1[d.metric_off_x + si]) * T(pl.h2[d.metric_off_y + sj]) * T(d.B0) : T(0);
-                    inv = T(1.0 / d.scg);
-                }
-                g[(ci * kM + a) * N + o] = double(Store<S>::ld(
-                    pl.gin, d.g_off + plane * d.plane + (int64_t)sj * d.pitch + si, rest, inv));
+                const double dv = double(Store<S>::ld(pl.gin + d.g_off + ci * kM * d.plane,
+                                                      slot_index(d, i, j, a), 1.0f)) / scg;
+                const double W = a == 0 ? 1.0 - 2.0 * d.csm2 : 0.5 * d.csm2;
+                g[(ci * kM + a) * N + o] = dv + (ci == 1 ? W * m.h1 * m.h2 * d.B0 : 0.0);
             }
     }
 }
@@ -232,11 +227,12 @@ __global__ void scatter_kernel(const RunDesc* __restrict__ runs, int run, Pools<
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= d.nx || j >= d.ny) return;
+    const NodeM m = node_metric(d, pl, i, j);
     const int64_t N = (int64_t)d.nx * d.ny, o = (int64_t)j * d.nx + i;
+    const bool sc = Store<S>::scaled;
     for (int a = 0; a < kQ; ++a) {
-        int si, sj, pa;
-        slot_of(d, i, j, a, si, sj, pa);
-        put_slot<S, T>(d, pl, pl.fout, d.f_off, si, sj, pa, T(f[a * N + o]), false, 0);
+        const double dv = f[a * N + o] - rest_pop(a, m.h1, m.h2, d.rho0, d.cs2);
+        Store<S>::st(pl.fout + d.f_off, slot_index(d, i, j, a), T(dv), T(sc_of(d, a, sc)));
     }
     const int64_t n = (int64_t)j * d.pitch + i;
     pl.Fout[d.F_off + n] = FT(F[o]);
@@ -244,12 +240,27 @@ __global__ void scatter_kernel(const RunDesc* __restrict__ runs, int run, Pools<
     if (d.mhd && g) {
         for (int ci = 0; ci < 2; ++ci)
             for (int a = 0; a < kM; ++a) {
-                int si, sj, pa;
-                slot_of(d, i, j, a, si, sj, pa);
-                put_slot<S, T>(d, pl, pl.gout, d.g_off, si, sj, ci * kM + pa, T(g[(ci * kM + a) * N + o]),
-                               true, ci);
+                const double W = a == 0 ? 1.0 - 2.0 * d.csm2 : 0.5 * d.csm2;
+                const double dv = g[(ci * kM + a) * N + o] - (ci == 1 ? W * m.h1 * m.h2 * d.B0 : 0.0);
+                Store<S>::st(pl.gout + d.g_off + ci * kM * d.plane, slot_index(d, i, j, a), T(dv),
+                             T(sc ? d.scg : 1.0));
             }
     }
+}
+
+// Deviations of node (i, j) pulled from the input buffer.
+template <class S, class T>
+__device__ inline void node_devs(const RunDesc& d, const Pools<S, typename ForceOf<S>::type>& pl, int i, int j,
+                                 T* f, T (*dg)[kM])
+{
+    const bool sc = Store<S>::scaled;
+    for (int a = 0; a < kQ; ++a)
+        f[a] = Store<S>::ld(pl.fin + d.f_off, slot_index(d, i, j, a), T(1.0 / sc_of(d, a, sc)));
+    if (dg)
+        for (int ci = 0; ci < 2; ++ci)
+            for (int a = 0; a < kM; ++a)
+                dg[ci][a] = Store<S>::ld(pl.gin + d.g_off + ci * kM * d.plane, slot_index(d, i, j, a),
+                                         T(sc ? 1.0 / d.scg : 1.0));
 }
 
 // Hydrodynamic and magnetic fields of the current state (FP64 outputs).
@@ -262,12 +273,16 @@ __global__ void fields_kernel(const RunDesc* __restrict__ runs, int run, Pools<S
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= d.nx || j >= d.ny) return;
-    Lane L;
-    RowCtx<S, T> c = node_ctx<S, T>(d, pl, i, L);
-    T fl[kQ], rho, U1, U2;
-    pull9<S, T>(c, L, j, fl);
-    const T h2 = T(pl.h2[d.metric_off_y + j]);
-    row_moments<S, T>(c, L, j, fl, h2, rho, U1, U2);
+    const double* ct = pl.col + (d.col_off + i) * kTab;
+    const double* rt = pl.row + (d.row_off + j) * kTab;
+    T f[kQ], dg[2][kM];
+    node_devs<S, T>(d, pl, i, j, f, d.mhd ? dg : nullptr);
+    LaneCol L;
+    L.col = i;
+    L.valid = true;
+    T rho, U1, U2;
+    row_moments<typename ForceOf<S>::type, T>(d, pl.Fin, L, j, f, T(d.rho0), T(ct[T_IH]), T(rt[T_IH]), rho,
+                                              U1, U2);
     const int64_t N = (int64_t)d.nx * d.ny, o = (int64_t)j * d.nx + i;
     if (rho_o) rho_o[o] = double(rho);
     if (u_o) {
@@ -275,23 +290,14 @@ __global__ void fields_kernel(const RunDesc* __restrict__ runs, int run, Pools<S
         u_o[N + o] = double(U2);
     }
     if (d.mhd && B_o) {
-        T S2[2] = {T(0), T(0)};
-        for (int ci = 0; ci < 2; ++ci)
-            for (int a = 0; a < kM; ++a) {
-                int si, sj, pa;
-                slot_of(d, i, j, a, si, sj, pa);
-                T rest = T(0), inv = T(1);
-                if constexpr (Store<S>::dev) {
-                    const T W = pa == 0 ? T(1.0 - 2.0 * d.csm2) : T(0.5 * d.csm2);
-                    rest = ci == 1 ? W * T(pl.h1[d.metric_off_x + si]) * T(pl.h2[d.metric_off_y + sj]) * T(d.B0) : T(0);
-                    inv = T(1.0 / d.scg);
-                }
-                S2[ci] += Store<S>::ld(pl.gin, d.g_off + (ci * kM + pa) * d.plane + (int64_t)sj * d.pitch + si,
-                                       rest, inv);
-            }
-        const T ihh = T(1) / (c.h1c * h2);
-        B_o[o] = double(S2[0] * ihh);
-        B_o[N + o] = double(S2[1] * ihh);
+        double S1 = 0, S2 = 0;
+        for (int a = 0; a < kM; ++a) {
+            S1 += double(dg[0][a]);
+            S2 += double(dg[1][a]);
+        }
+        const double ihh = ct[T_IH] * rt[T_IH];
+        B_o[o] = S1 * ihh;
+        B_o[N + o] = d.B0 + S2 * ihh;
     }
 }
 
@@ -311,43 +317,41 @@ __global__ void diag_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, 
     double v[kDiag] = {0, 0, 0, 0, 0, 0, 0};
     if (idx < N) {
         const int i = (int)(idx % d.nx), j = (int)(idx / d.nx);
-        Lane L;
-        RowCtx<S, T> c = node_ctx<S, T>(d, pl, i, L);
-        T fl[kQ], rho, U1, U2;
-        pull9<S, T>(c, L, j, fl);
-        const T h2 = T(pl.h2[d.metric_off_y + j]);
-        row_moments<S, T>(c, L, j, fl, h2, rho, U1, U2);
-        double m = 0;
+        const double* ct = pl.col + (d.col_off + i) * kTab;
+        const double* rt = pl.row + (d.row_off + j) * kTab;
+        T f[kQ], dg[2][kM];
+        node_devs<S, T>(d, pl, i, j, f, d.mhd ? dg : nullptr);
+        LaneCol L;
+        L.col = i;
+        L.valid = true;
+        T rho, U1, U2;
+        row_moments<typename ForceOf<S>::type, T>(d, pl.Fin, L, j, f, T(d.rho0), T(ct[T_IH]), T(rt[T_IH]),
+                                                  rho, U1, U2);
+        const double h1 = ct[T_H], h2 = rt[T_H];
+        double m = h1 * h2 * d.rho0;   // sum of the rest-state populations
         int bad = 0;
         for (int a = 0; a < kQ; ++a) {
-            m += double(fl[a]);
-            bad += isfinite(double(fl[a])) ? 0 : 1;
+            m += double(f[a]);
+            bad += isfinite(double(f[a])) ? 0 : 1;
         }
         v[0] = m;
-        v[1] = double(h2) * double(rho) * double(U1);
-        v[2] = double(c.h1c) * double(rho) * double(U2);
+        v[1] = h2 * double(rho) * double(U1);
+        v[2] = h1 * double(rho) * double(U2);
         if (d.mhd) {
-            for (int ci = 0; ci < 2; ++ci) {
-                double s = 0;
-                for (int a = 0; a < kM; ++a) {
-                    int si, sj, pa;
-                    slot_of(d, i, j, a, si, sj, pa);
-                    T rest = T(0), inv = T(1);
-                    if constexpr (Store<S>::dev) {
-                        const T W = pa == 0 ? T(1.0 - 2.0 * d.csm2) : T(0.5 * d.csm2);
-                        rest = ci == 1 ? W * T(pl.h1[d.metric_off_x + si]) * T(pl.h2[d.metric_off_y + sj]) * T(d.B0) : T(0);
-                        inv = T(1.0 / d.scg);
-                    }
-                    const double gv = double(Store<S>::ld(
-                        pl.gin, d.g_off + (ci * kM + pa) * d.plane + (int64_t)sj * d.pitch + si, rest, inv));
-                    s += gv;
-                    bad += isfinite(gv) ? 0 : 1;
-                }
-                v[3 + ci] = s;
+            double S1 = 0, S2 = 0;
+            for (int a = 0; a < kM; ++a) {
+                S1 += double(dg[0][a]);
+                S2 += double(dg[1][a]);
+                bad += (isfinite(double(dg[0][a])) ? 0 : 1) + (isfinite(double(dg[1][a])) ? 0 : 1);
             }
+            v[3] = S1;
+            v[4] = h1 * h2 * d.B0 + S2;
         }
         v[5] = sqrt(double(U1) * double(U1) + double(U2) * double(U2));
-        if (!isfinite(v[5])) { v[5] = 0; bad += 1; }
+        if (!isfinite(v[5])) {
+            v[5] = 0;
+            bad += 1;
+        }
         v[6] = bad;
     }
     for (int k = 0; k < kDiag; ++k) sh[k][threadIdx.x] = v[k];

@@ -1,4 +1,5 @@
-// goc_device.hpp -- gfx950 device code of the GOC-LBM step.
+// goc_device.hpp -- gfx950 device code of the GOC-LBM step: data layout,
+// storage codecs and the per-node arithmetic.
 //
 // One fused pull-scheme kernel advances a whole time step of the
 // central-moment MRT GOC-LBM (App. E of Yahia & Premnath, with the local
@@ -9,21 +10,25 @@
 // to its reduced form F~ (tau12 is not needed).
 //
 // State layout in HBM (structure of arrays, one plane per direction):
-//   slot(a, x) in plane a at the writer node x holds the post-collision
-//   population that leaves x along e_a, with the wall condition of its
-//   reader already applied by the writer (momentum-augmented bounce-back
-//   of App. C, anti-bounce-back of App. G).  A reader y therefore pulls
-//   f_a(y) = slot(a, y - e_a) in the interior and slot(opp(a), y) through a
-//   wall: streaming is a pure gather and every slot has exactly one reader.
+//   slot(a, x) in plane a at the writer node x holds the population that
+//   leaves x along e_a after collision, minus the rest-state population of
+//   its reader (the node that pulls it), with the reader's wall condition
+//   already applied by the writer (momentum-augmented bounce-back of App. C,
+//   anti-bounce-back of App. G).  A reader y pulls slot(a, y - e_a) in the
+//   interior and slot(opp(a), y) through a wall and gets its own deviation
+//   d_a(y) = f_a(y) - f_a^rest(y) directly: streaming is a pure gather and
+//   every slot has exactly one reader.  The rest state is the App. C initial
+//   state at (rho0, U = 0); storing deviations keeps the full relative
+//   precision of FP32 (and of the 16-bit forms) although the rest
+//   populations themselves span h1 h2 (up to ~3) down to c_s^4/4 (~1e-8).
 //   Lagged effective force: two planes per node (no streaming).
 //
 // Work decomposition: one wave64 work-group per (x-strip, y-segment).  The
 // 64 lanes cover 64 consecutive columns, of which the inner 62 are owned;
 // the wave marches up the rows of its segment keeping the moments of rows
 // j-2 .. j+1 in registers, so the finite differences of App. E step 3(a)
-// need no second pass: halo columns come from neighbouring lanes, halo
-// rows from the march (recomputed at segment ends from the pulled
-// populations).
+// need no second pass: halo columns come from neighbouring lanes, halo rows
+// from the march (recomputed at segment ends from the pulled populations).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -37,10 +42,22 @@ constexpr int kQ = 9;
 constexpr int kM = 5;
 constexpr int kWave = 64;
 constexpr int kOwn = kWave - 2;
+constexpr int kTab = 8;   // doubles per column / row table entry
 
 __host__ __device__ constexpr int ex_(int a) { return (a == 1 || a == 5 || a == 8) ? 1 : (a == 3 || a == 6 || a == 7) ? -1 : 0; }
 __host__ __device__ constexpr int ey_(int a) { return (a == 2 || a == 5 || a == 6) ? 1 : (a == 4 || a == 7 || a == 8) ? -1 : 0; }
 __host__ __device__ constexpr int opp_(int a) { return a == 0 ? 0 : (a <= 4 ? ((a + 1) % 4) + 1 : ((a - 5 + 2) % 4) + 5); }
+// Scale class of a direction: 0 rest, 1 xi1-axis, 2 xi2-axis, 3 diagonal.
+__host__ __device__ constexpr int cls_(int a) { return a == 0 ? 0 : (a == 1 || a == 3) ? 1 : (a == 2 || a == 4) ? 2 : 3; }
+
+// Column / row metric tables (FP64, one entry of kTab doubles each):
+//   col: h1, 1/h1, theta11, a1p, a1m, b1p, b1m, -
+//   row: h2, 1/h2, theta22, a2p, a2m, b2p, b2m, -
+// a1p = P0/2 (1/h1(i) - 1/h1(i+1)) is the difference between the rest-state
+// xi1-axis population of a node and of its +xi1 neighbour divided by h2
+// (zero when that neighbour lies beyond a wall); a1m the same toward -xi1;
+// b1p, b1m the D2Q5 analogues W1 B0 (h1(i) - h1(i+-1)).  Rows likewise.
+enum { T_H = 0, T_IH, T_TH, T_AP, T_AM, T_BP, T_BM };
 
 // ---------------------------------------------------------------------------
 // Run descriptor: one entry per independent run (a single run is a batch of 1).
@@ -53,7 +70,7 @@ struct RunDesc {
     int32_t pad_;
     int64_t plane;                 // elements per plane (row pitch * ny + padding)
     int64_t f_off, F_off, g_off;   // element offsets of plane 0 in the f, force, g pools
-    int64_t metric_off_x, metric_off_y;   // offsets into the metric pools
+    int64_t col_off, row_off;      // entry offsets into the column / row tables
     double cs2, nu, zeta;
     double omega[9];
     double Fx1, Fx2, rho0;
@@ -74,89 +91,121 @@ struct Pools {
     FT* Fout;
     const S* gin;
     S* gout;
-    const double* h1;    // [sum nx]
-    const double* th11;
-    const double* h2;    // [sum ny]
-    const double* th22;
+    const double* col;   // column tables
+    const double* row;   // row tables
 };
 
 // ---------------------------------------------------------------------------
-// Storage codecs.  FP64 / FP32 store populations as they are.  The 16-bit
-// forms store s * (value - rest), rest being the writer node's population at
-// rest (rho0, U = 0, App. C closed form), with one scale s per direction class.
+// Storage codecs: FP64 and FP32 store the deviation itself, the 16-bit forms
+// store s * deviation with one scale s per direction class.
 template <class S> struct Store;
 template <> struct Store<double> {
-    static constexpr bool dev = false;
-    __device__ static double ld(const double* p, int64_t i, double, double) { return p[i]; }
-    __device__ static void st(double* p, int64_t i, double v, double, double) { p[i] = v; }
+    static constexpr bool scaled = false;
+    __device__ static double ld(const double* p, int64_t i, double) { return p[i]; }
+    __device__ static void st(double* p, int64_t i, double v, double) { p[i] = v; }
 };
 template <> struct Store<float> {
-    static constexpr bool dev = false;
-    __device__ static float ld(const float* p, int64_t i, float, float) { return p[i]; }
-    __device__ static void st(float* p, int64_t i, float v, float, float) { p[i] = v; }
+    static constexpr bool scaled = false;
+    __device__ static float ld(const float* p, int64_t i, float) { return p[i]; }
+    __device__ static void st(float* p, int64_t i, float v, float) { p[i] = v; }
 };
 template <> struct Store<__half> {
-    static constexpr bool dev = true;
-    __device__ static float ld(const __half* p, int64_t i, float rest, float inv_s) {
-        return fmaf(__half2float(p[i]), inv_s, rest);
-    }
-    __device__ static void st(__half* p, int64_t i, float v, float rest, float s) {
-        p[i] = __float2half_rn((v - rest) * s);
-    }
+    static constexpr bool scaled = true;
+    __device__ static float ld(const __half* p, int64_t i, float inv_s) { return __half2float(p[i]) * inv_s; }
+    __device__ static void st(__half* p, int64_t i, float v, float s) { p[i] = __float2half_rn(v * s); }
 };
 template <> struct Store<__hip_bfloat16> {
-    static constexpr bool dev = true;
-    __device__ static float ld(const __hip_bfloat16* p, int64_t i, float rest, float inv_s) {
-        return fmaf(__bfloat162float(p[i]), inv_s, rest);
+    static constexpr bool scaled = true;
+    __device__ static float ld(const __hip_bfloat16* p, int64_t i, float inv_s) {
+        return __bfloat162float(p[i]) * inv_s;
     }
-    __device__ static void st(__hip_bfloat16* p, int64_t i, float v, float rest, float s) {
-        p[i] = __float2bfloat16((v - rest) * s);
-    }
+    __device__ static void st(__hip_bfloat16* p, int64_t i, float v, float s) { p[i] = __float2bfloat16(v * s); }
 };
 
-// Scale class of a direction: 0 rest, 1 xi1-axis, 2 xi2-axis, 3 diagonal.
-__host__ __device__ constexpr int cls_(int a) { return a == 0 ? 0 : (a == 1 || a == 3) ? 1 : (a == 2 || a == 4) ? 2 : 3; }
+// Reciprocal: correctly rounded division for FP64, hardware reciprocal plus
+// one Newton step (< 1 ulp) for FP32.
+__device__ inline double recip(double x) { return 1.0 / x; }
+__device__ inline float recip(float x)
+{
+    float r = __builtin_amdgcn_rcpf(x);
+    return r * (2.0f - x * r);
+}
 
 // Rest-state populations at (rho0, U = 0): P^-1 of the Sec. 3 equilibria.
-template <class T>
-__device__ inline T rest_pop(int a, T h1, T h2, T rho0, T cs2) {
-    const T P0 = rho0 * cs2, k22 = rho0 * cs2 * cs2;
+__host__ __device__ inline double rest_pop(int a, double h1, double h2, double rho0, double cs2)
+{
+    const double P0 = rho0 * cs2, k22 = rho0 * cs2 * cs2;
     const int c = cls_(a);
     if (c == 0) return h1 * h2 * rho0 - (h2 / h1 + h1 / h2) * P0 + k22;
-    if (c == 1) return T(0.5) * (h2 / h1 * P0 - k22);
-    if (c == 2) return T(0.5) * (h1 / h2 * P0 - k22);
-    return T(0.25) * k22;
+    if (c == 1) return 0.5 * (h2 / h1 * P0 - k22);
+    if (c == 2) return 0.5 * (h1 / h2 * P0 - k22);
+    return 0.25 * k22;
 }
 
 // ---------------------------------------------------------------------------
-// Node-level arithmetic.
+// Node-level arithmetic in deviation form.
 
 template <class T>
 struct NodeParams {
-    T cs2, inv_cs2, nu, zeta, w[9], Fx1, Fx2;
+    T cs2, inv_cs2, nu, zeta, rho0, P0, w[9], Fx1, Fx2;
     int gi_terms, q3_sign, rho_terms;
     // MHD
     T csm2, inv_csm2, tau_m, inv_tau_m, eta, inv_mu, B0, W0, W1;
 };
 
+template <class T>
+__device__ inline NodeParams<T> node_params(const RunDesc& d)
+{
+    NodeParams<T> p;
+    p.cs2 = T(d.cs2);
+    p.inv_cs2 = T(1.0 / d.cs2);
+    p.nu = T(d.nu);
+    p.zeta = T(d.zeta);
+    p.rho0 = T(d.rho0);
+    p.P0 = T(d.rho0 * d.cs2);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) p.w[k] = T(d.omega[k]);
+    p.Fx1 = T(d.Fx1);
+    p.Fx2 = T(d.Fx2);
+    p.gi_terms = d.gi_terms;
+    p.q3_sign = d.q3_sign;
+    p.rho_terms = d.rho_terms;
+    p.csm2 = T(d.csm2);
+    p.inv_csm2 = T(1.0 / d.csm2);
+    p.tau_m = T(d.tau_m);
+    p.inv_tau_m = T(1.0 / d.tau_m);
+    p.eta = T(d.eta);
+    p.inv_mu = T(d.inv_mu);
+    p.B0 = T(d.B0);
+    p.W0 = T(1.0 - 2.0 * d.csm2);
+    p.W1 = T(0.5 * d.csm2);
+    return p;
+}
+
+// Metric at one node.
+template <class T>
+struct NodeMetric {
+    T h1, h2, ih1, ih2, th11, th22;
+};
+
 // Effective force on a straight grid (Sec. 2.2 with theta12 = theta21 = 0):
 //   F1 = h2 [F1ext - theta11 P + theta11 (tau11 - rho U1^2)],
 //   F2 = h1 [F2ext - theta22 P + theta22 (tau22 - rho U2^2)],
-// tau11, tau22 the normal viscous stresses of Sec. 2.2.
-// Equilibrium corrections n3^eq(1), n4^eq(1) of Sec. 5 on a straight grid.
+// tau11, tau22 the normal viscous stresses of Sec. 2.2, and the equilibrium
+// corrections n3^eq(1), n4^eq(1) of Sec. 5 on a straight grid.
 template <class T>
-__device__ inline void force_and_corrections(const NodeParams<T>& p, T h1, T h2, T th11, T th22,
-                                             T rho, T U1, T U2, T d1U1, T d2U2, T d1r, T d2r,
-                                             T Fe1, T Fe2, T& F1, T& F2, T& n3, T& n4)
+__device__ inline void force_and_corrections(const NodeParams<T>& p, const NodeMetric<T>& g, T rho,
+                                             T U1, T U2, T d1U1, T d2U2, T d1r, T d2r, T Fe1, T Fe2,
+                                             T& F1, T& F2, T& n3, T& n4)
 {
     const T nu = p.nu, ze = p.zeta, ics = p.inv_cs2;
-    const T ih1 = T(1) / h1, ih2 = T(1) / h2;
+    const T h1 = g.h1, h2 = g.h2, ih1 = g.ih1, ih2 = g.ih2;
     const T P = rho * p.cs2;
     const T a1 = d1U1 * ih1, a2 = d2U2 * ih2;
     const T tau11 = rho * ((ze + nu) * a1 + (ze - nu) * a2);
     const T tau22 = rho * ((ze + nu) * a2 + (ze - nu) * a1);
-    F1 = h2 * (Fe1 - th11 * P + th11 * (tau11 - rho * U1 * U1));
-    F2 = h1 * (Fe2 - th22 * P + th22 * (tau22 - rho * U2 * U2));
+    F1 = h2 * (Fe1 + g.th11 * (tau11 - rho * U1 * U1 - P));
+    F2 = h1 * (Fe2 + g.th22 * (tau22 - rho * U2 * U2 - P));
 
     const T r21 = h2 * ih1, r12 = h1 * ih2;          // h2/h1, h1/h2
     const T s1 = r21 * ih1, s2 = r12 * ih2;          // h2/h1^2, h1/h2^2
@@ -183,8 +232,8 @@ __device__ inline void force_and_corrections(const NodeParams<T>& p, T h1, T h2,
         D34 = -ze * b2;
         D43 = -nu * c1;
         D44 = -nu * c2;
-        const T g1 = U1 * (u1s + T(1)) * r21 * th11;
-        const T g2 = U2 * (u2s + T(1)) * r12 * th22;
+        const T g1 = U1 * (u1s + T(1)) * r21 * g.th11;
+        const T g2 = U2 * (u2s + T(1)) * r12 * g.th22;
         C3 = T(2) * rho * ze * (g1 + g2);
         C4 = T(2) * rho * nu * (g1 - g2);
     } else {                  // App. B(ii)
@@ -193,7 +242,7 @@ __device__ inline void force_and_corrections(const NodeParams<T>& p, T h1, T h2,
         D41 = rho * (nu * h2 * ics + (ze - nu) * ih2 - (T(2) * nu + ze) * s1);
         D42 = rho * (-nu * h1 * ics - (ze - nu) * ih1 + (T(2) * nu + ze) * s2);
         D33 = D34 = D43 = D44 = T(0);
-        const T g1 = U1 * r21 * th11, g2 = U2 * r12 * th22;
+        const T g1 = U1 * r21 * g.th11, g2 = U2 * r12 * g.th22;
         C3 = T(2) * rho * ze * (g1 + g2);
         C4 = T(2) * rho * nu * (g1 - g2);
     }
@@ -201,175 +250,168 @@ __device__ inline void force_and_corrections(const NodeParams<T>& p, T h1, T h2,
     n4 = D41 * d1U1 + D42 * d2U2 + D43 * d1r + D44 * d2r + C4;
 }
 
-// Central-moment collision of App. E (steps 1-5) at one node.
-// In: pre-collision populations f, fields rho, U, effective force F,
-// corrections n3, n4.  Out: post-collision populations ft.
+// Raw-moment deviations dm = P d (App. E step 1) for d = f - f^rest.
 template <class T>
-__device__ inline void cm_collide(const NodeParams<T>& p, T h1, T h2, const T* f, T rho, T U1,
-                                  T U2, T F1, T F2, T n3, T n4, T* ft)
+struct RawDev {
+    T m00, m10, m01, m20, m02, m11, m21, m12, m22;
+};
+
+template <class T>
+__device__ inline RawDev<T> raw_dev(const T* d)
 {
-    // step 1: raw moments (bare basis k00 k10 k01 k20 k02 k11 k21 k12 k22)
-    const T s13 = f[1] + f[3], s24 = f[2] + f[4];
-    const T d13 = f[1] - f[3], d24 = f[2] - f[4];
-    const T a58 = f[5] + f[8], a67 = f[6] + f[7];    // e2-odd pairs summed in e1
-    const T p56 = f[5] + f[6], p78 = f[7] + f[8];
-    const T q58 = f[5] - f[8], q67 = f[6] - f[7];
-    const T sd = p56 + p78;                           // k22
-    const T m00 = f[0] + s13 + s24 + sd;
-    const T m10 = d13 + (a58 - a67);
-    const T m01 = d24 + (p56 - p78);
-    const T m20 = s13 + sd;
-    const T m02 = s24 + sd;
-    const T m11 = q58 - q67;
-    const T m21 = p56 - p78;
-    const T m12 = a58 - a67;
-    const T m22 = sd;
-    // step 2: central moments with U
+    RawDev<T> m;
+    const T s13 = d[1] + d[3], s24 = d[2] + d[4];
+    const T a58 = d[5] + d[8], a67 = d[6] + d[7];
+    const T p56 = d[5] + d[6], p78 = d[7] + d[8];
+    m.m22 = p56 + p78;
+    m.m00 = d[0] + s13 + s24 + m.m22;
+    m.m10 = (d[1] - d[3]) + (a58 - a67);
+    m.m01 = (d[2] - d[4]) + (p56 - p78);
+    m.m20 = s13 + m.m22;
+    m.m02 = s24 + m.m22;
+    m.m11 = (d[5] - d[8]) - (d[6] - d[7]);
+    m.m21 = p56 - p78;
+    m.m12 = a58 - a67;
+    return m;
+}
+
+// Central-moment collision of App. E (steps 2-5) at one node in deviation
+// form.  With m = m^r + dm, m^r the rest-state raw moments (h1 h2 rho0, 0, 0,
+// (h2/h1) P0, (h1/h2) P0, 0, 0, 0, rho0 c_s^4), every transform and
+// relaxation is linear in the moments, so the rest part is carried
+// analytically: products of U with the large rest moments are formed from
+// the full moments, every leading term from the deviations.  Output: the
+// post-collision deviations dt = f~ - f^rest.
+template <class T>
+__device__ inline void cm_collide(const NodeParams<T>& p, const NodeMetric<T>& g, const RawDev<T>& m,
+                                  T rho, T drho, T U1, T U2, T F1, T F2, T n3, T n4, T* dt)
+{
+    const T h1 = g.h1, h2 = g.h2;
+    const T r21 = h2 * g.ih1, r12 = h1 * g.ih2;
+    const T M0 = h1 * h2 * p.rho0, A = r21 * p.P0, Bm = r12 * p.P0;
+    const T c00 = M0 + m.m00, c20 = A + m.m20, c02 = Bm + m.m02;   // full moments
+    // step 2: central-moment deviations (rest central moments = m^r)
     const T U11 = U1 * U1, U22 = U2 * U2, U12 = U1 * U2;
-    const T k10 = m10 - U1 * m00;
-    const T k01 = m01 - U2 * m00;
-    const T k20 = m20 - T(2) * U1 * m10 + U11 * m00;
-    const T k02 = m02 - T(2) * U2 * m01 + U22 * m00;
-    const T k11 = m11 - U2 * m10 - U1 * m01 + U12 * m00;
-    const T k21 = m21 - T(2) * U1 * m11 + U11 * m01 - U2 * m20 + T(2) * U12 * m10 - U11 * U2 * m00;
-    const T k12 = m12 - T(2) * U2 * m11 + U22 * m10 - U1 * m02 + T(2) * U12 * m01 - U1 * U22 * m00;
-    const T k22 = m22 - T(2) * U1 * m12 + U11 * m02 - T(2) * U2 * m21 + T(4) * U12 * m11
-                - T(2) * U11 * U2 * m01 + U22 * m20 - T(2) * U1 * U22 * m10 + U11 * U22 * m00;
-    // step 3: central equilibria (binomial transform of the Sec. 3 equilibria) + corrections
+    const T k10 = m.m10 - U1 * c00;
+    const T k01 = m.m01 - U2 * c00;
+    const T k20 = m.m20 - T(2) * U1 * m.m10 + U11 * c00;
+    const T k02 = m.m02 - T(2) * U2 * m.m01 + U22 * c00;
+    const T k11 = m.m11 - U2 * m.m10 - U1 * m.m01 + U12 * c00;
+    const T k21 = m.m21 - T(2) * U1 * m.m11 + U11 * m.m01 - U2 * c20 + T(2) * U12 * m.m10 - U11 * U2 * c00;
+    const T k12 = m.m12 - T(2) * U2 * m.m11 + U22 * m.m10 - U1 * c02 + T(2) * U12 * m.m01 - U1 * U22 * c00;
+    const T k22 = m.m22 - T(2) * U1 * m.m12 + U11 * c02 - T(2) * U2 * m.m21 + T(4) * U12 * m.m11
+                - T(2) * U11 * U2 * m.m01 + U22 * c20 - T(2) * U1 * U22 * m.m10 + U11 * U22 * c00;
+    // step 3: deviations of the central equilibria (binomial transform of the
+    // Sec. 3 equilibria) with the corrections of Sec. 5
     const T h1m = h1 - T(1), h2m = h2 - T(1);
-    const T r21 = h2 / h1, r12 = h1 / h2;
     const T q20 = r21 * h1m * h1m, q02 = r12 * h2m * h2m, q11 = h1m * h2m;
-    T q21 = h1m * h1m * h2m / h1, q12 = h1m * h2m * h2m / h2;   // printed sign
-    if (!p.q3_sign) { q21 = -q21; q12 = -q12; }                 // binomial transform
-    const T rc = rho * p.cs2;
+    T q21 = h1m * h1m * h2m * g.ih1, q12 = h1m * h2m * h2m * g.ih2;   // printed sign
+    if (!p.q3_sign) { q21 = -q21; q12 = -q12; }                       // binomial transform
+    const T rc = rho * p.cs2, drc = drho * p.cs2;
     const T e10 = -h1m * h2 * rho * U1;
     const T e01 = -h2m * h1 * rho * U2;
-    const T e2s = q20 * rho * U11 + q02 * rho * U22 + (r21 + r12) * rc + n3;
-    const T e2d = q20 * rho * U11 - q02 * rho * U22 + (r21 - r12) * rc + n4;
+    const T e2s = q20 * rho * U11 + q02 * rho * U22 + (r21 + r12) * drc + n3;
+    const T e2d = q20 * rho * U11 - q02 * rho * U22 + (r21 - r12) * drc + n4;
     const T e11 = q11 * rho * U12;
-    const T e21 = q21 * rho * U11 * U2 - h2m * rc * U2 / h1;
-    const T e12 = q12 * rho * U1 * U22 - h1m * rc * U1 / h2;
-    const T e22 = rc * p.cs2;
+    const T e21 = q21 * rho * U11 * U2 - h2m * rc * U2 * g.ih1;
+    const T e12 = q12 * rho * U1 * U22 - h1m * rc * U1 * g.ih2;
+    const T e22 = drc * p.cs2;
     // central sources
-    const T ih1m = T(1) / h1 - T(1), ih2m = T(1) / h2 - T(1);
+    const T ih1m = g.ih1 - T(1), ih2m = g.ih2 - T(1);
     const T sa = T(2) * ih1m * F1 * U1, sb = T(2) * ih2m * F2 * U2;
-    const T s2s = sa + sb, s2d = sa - sb;
     const T s11 = ih2m * F1 * U2 + ih1m * F2 * U1;
-    // relaxation (k00 kept exactly, mass conserved to rounding)
+    // relaxation (k00 kept: mass conserved to rounding)
     const T* w = p.w;
     const T k2s = k20 + k02, k2d = k20 - k02;
     const T t10 = k10 + w[1] * (e10 - k10) + (T(1) - T(0.5) * w[1]) * F1;
     const T t01 = k01 + w[2] * (e01 - k01) + (T(1) - T(0.5) * w[2]) * F2;
-    const T t2s = k2s + w[3] * (e2s - k2s) + (T(1) - T(0.5) * w[3]) * s2s;
-    const T t2d = k2d + w[4] * (e2d - k2d) + (T(1) - T(0.5) * w[4]) * s2d;
+    const T t2s = k2s + w[3] * (e2s - k2s) + (T(1) - T(0.5) * w[3]) * (sa + sb);
+    const T t2d = k2d + w[4] * (e2d - k2d) + (T(1) - T(0.5) * w[4]) * (sa - sb);
     const T t11 = k11 + w[5] * (e11 - k11) + (T(1) - T(0.5) * w[5]) * s11;
     const T t21 = k21 + w[6] * (e21 - k21);
     const T t12 = k12 + w[7] * (e12 - k12);
     const T t22 = k22 + w[8] * (e22 - k22);
     const T t20 = T(0.5) * (t2s + t2d), t02 = T(0.5) * (t2s - t2d);
-    const T t00 = m00;
-    // step 4: raw moments from central ones, F(-U)
-    const T n10 = t10 + U1 * t00;
-    const T n01 = t01 + U2 * t00;
-    const T n20 = t20 + T(2) * U1 * t10 + U11 * t00;
-    const T n02 = t02 + T(2) * U2 * t01 + U22 * t00;
-    const T n11 = t11 + U2 * t10 + U1 * t01 + U12 * t00;
-    const T n21 = t21 + T(2) * U1 * t11 + U11 * t01 + U2 * t20 + T(2) * U12 * t10 + U11 * U2 * t00;
-    const T n12 = t12 + T(2) * U2 * t11 + U22 * t10 + U1 * t02 + T(2) * U12 * t01 + U1 * U22 * t00;
-    const T n22 = t22 + T(2) * U1 * t12 + U11 * t02 + T(2) * U2 * t21 + T(4) * U12 * t11
-                + T(2) * U11 * U2 * t01 + U22 * t20 + T(2) * U1 * U22 * t10 + U11 * U22 * t00;
+    const T T00 = c00, T20 = A + t20, T02 = Bm + t02;                 // full k~00, k~20, k~02
+    // step 4: raw-moment deviations from the central ones, F(-U)
+    const T n10 = t10 + U1 * T00;
+    const T n01 = t01 + U2 * T00;
+    const T n20 = t20 + T(2) * U1 * t10 + U11 * T00;
+    const T n02 = t02 + T(2) * U2 * t01 + U22 * T00;
+    const T n11 = t11 + U2 * t10 + U1 * t01 + U12 * T00;
+    const T n21 = t21 + T(2) * U1 * t11 + U11 * t01 + U2 * T20 + T(2) * U12 * t10 + U11 * U2 * T00;
+    const T n12 = t12 + T(2) * U2 * t11 + U22 * t10 + U1 * T02 + T(2) * U12 * t01 + U1 * U22 * T00;
+    const T n22 = t22 + T(2) * U1 * t12 + U11 * T02 + T(2) * U2 * t21 + T(4) * U12 * t11
+                + T(2) * U11 * U2 * t01 + U22 * T20 + T(2) * U1 * U22 * t10 + U11 * U22 * T00;
+    const T n00 = m.m00;
     // step 5: populations, P^-1
-    ft[0] = t00 - n20 - n02 + n22;
+    dt[0] = n00 - n20 - n02 + n22;
     const T hx = T(0.5) * (n20 - n22), hy = T(0.5) * (n02 - n22);
     const T gx = T(0.5) * (n10 - n12), gy = T(0.5) * (n01 - n21);
-    ft[1] = hx + gx;
-    ft[3] = hx - gx;
-    ft[2] = hy + gy;
-    ft[4] = hy - gy;
+    dt[1] = hx + gx;
+    dt[3] = hx - gx;
+    dt[2] = hy + gy;
+    dt[4] = hy - gy;
     const T qa = T(0.25) * (n22 + n11), qb = T(0.25) * (n22 - n11);
     const T qc = T(0.25) * (n21 + n12), qd = T(0.25) * (n21 - n12);
-    ft[5] = qa + qc;
-    ft[6] = qb + qd;
-    ft[7] = qa - qc;
-    ft[8] = qb - qd;
+    dt[5] = qa + qc;
+    dt[6] = qb + qd;
+    dt[7] = qa - qc;
+    dt[8] = qb - qd;
 }
 
-// D2Q5 induction scheme of App. G on a straight grid (Y = 0: no source).
-// gb[c][a]: transformed populations of component c.  Computes B, the local
-// derivatives dB from the non-equilibrium first moments, J3, the Lorentz
-// force, and (if gt != nullptr) the post-collision populations.
+// D2Q5 induction scheme of App. G on a straight grid (Y = 0: no source), in
+// deviation form: dg[c][a] = g_ca - W_a h1 h2 B_rest,c with B_rest = (0, B0).
+// Computes B, the local derivatives dB from the non-equilibrium first
+// moments, J3, the Lorentz force and (if dgt != nullptr) the post-collision
+// deviations.
 template <class T>
-__device__ inline void mie_node(const NodeParams<T>& p, T h1, T h2, T th11, T th22,
-                                const T (*gb)[kM], T U1, T U2, T& B1, T& B2, T& FL1, T& FL2,
-                                T (*gt)[kM])
+__device__ inline void mie_node(const NodeParams<T>& p, const NodeMetric<T>& g, const T (*dg)[kM],
+                                T U1, T U2, T& B1, T& B2, T& FL1, T& FL2, T (*dgt)[kM])
 {
-    const T hh = h1 * h2, ihh = T(1) / hh;
-    B1 = (gb[0][0] + gb[0][1] + gb[0][2] + gb[0][3] + gb[0][4]) * ihh;
-    B2 = (gb[1][0] + gb[1][1] + gb[1][2] + gb[1][3] + gb[1][4]) * ihh;
+    const T h1 = g.h1, h2 = g.h2, hh = h1 * h2, ihh = g.ih1 * g.ih2;
+    T S[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) S[i] = dg[i][0] + dg[i][1] + dg[i][2] + dg[i][3] + dg[i][4];
+    B1 = S[0] * ihh;
+    B2 = p.B0 + S[1] * ihh;
     const T B[2] = {B1, B2};
     // flux tensor A_i1 = U1 B_i - B1 U_i, A_i2 = U2 B_i - B2 U_i
-    const T A11 = T(0), A12 = U2 * B1 - B2 * U1;
-    const T A21 = U1 * B2 - B1 * U2, A22 = T(0);
-    const T L1eq[2] = {h2 * A11, h2 * A21};   // first moments of g^eq(0) along xi1
-    const T L2eq[2] = {h1 * A12, h1 * A22};   // along xi2
+    const T A12 = U2 * B1 - B2 * U1;
+    const T A21 = U1 * B2 - B1 * U2;
+    const T L1eq[2] = {T(0), h2 * A21};   // first moments of g^eq(0) along xi1 (A11 = 0)
+    const T L2eq[2] = {h1 * A12, T(0)};   // along xi2 (A22 = 0)
     const T cs = p.csm2, tm = p.tau_m;
-    const T den1 = T(1) / (cs * (T(0.5) * hh + (tm - T(0.5)) * h2 / h1));
-    const T den2 = T(1) / (cs * (T(0.5) * hh + (tm - T(0.5)) * h1 / h2));
+    const T den1 = recip(cs * (T(0.5) * hh + (tm - T(0.5)) * h2 * g.ih1));
+    const T den2 = recip(cs * (T(0.5) * hh + (tm - T(0.5)) * h1 * g.ih2));
     T dB1[2], dB2[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-        const T L1 = (gb[i][1] - gb[i][3]) - L1eq[i];
-        const T L2 = (gb[i][2] - gb[i][4]) - L2eq[i];
-        dB1[i] = -(L1 + T(0.5) * cs * h1 * hh * th11 * B[i]) * den1;
-        dB2[i] = -(L2 + T(0.5) * cs * hh * h2 * th22 * B[i]) * den2;
+        const T L1 = (dg[i][1] - dg[i][3]) - L1eq[i];
+        const T L2 = (dg[i][2] - dg[i][4]) - L2eq[i];
+        dB1[i] = -(L1 + T(0.5) * cs * h1 * hh * g.th11 * B[i]) * den1;
+        dB2[i] = -(L2 + T(0.5) * cs * hh * h2 * g.th22 * B[i]) * den2;
     }
     const T J3 = p.inv_mu * ihh * (h2 * dB1[1] - h1 * dB2[0]);
     FL1 = -J3 * B2;
     FL2 = J3 * B1;
-    if (gt == nullptr) return;
+    if (dgt == nullptr) return;
     const T itm = p.inv_tau_m, ics = p.inv_csm2;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-        const T Lc1 = p.eta * ((hh - h2 / h1) * dB1[i] + h1 * hh * th11 * B[i]);
-        const T Lc2 = p.eta * ((hh - h1 / h2) * dB2[i] + hh * h2 * th22 * B[i]);
+        const T Lc1 = p.eta * ((hh - h2 * g.ih1) * dB1[i] + h1 * hh * g.th11 * B[i]);
+        const T Lc2 = p.eta * ((hh - h1 * g.ih2) * dB2[i] + hh * h2 * g.th22 * B[i]);
         const T m1 = (L1eq[i] + Lc1) * ics, m2 = (L2eq[i] + Lc2) * ics;
-        const T base = hh * B[i];
-        const T geq0 = p.W0 * base;
-        const T geq1 = p.W1 * (base + m1), geq3 = p.W1 * (base - m1);
-        const T geq2 = p.W1 * (base + m2), geq4 = p.W1 * (base - m2);
-        gt[i][0] = gb[i][0] - (gb[i][0] - geq0) * itm;
-        gt[i][1] = gb[i][1] - (gb[i][1] - geq1) * itm;
-        gt[i][2] = gb[i][2] - (gb[i][2] - geq2) * itm;
-        gt[i][3] = gb[i][3] - (gb[i][3] - geq3) * itm;
-        gt[i][4] = gb[i][4] - (gb[i][4] - geq4) * itm;
+        const T base = S[i];   // h1 h2 (B_i - B_rest,i)
+        const T e0 = p.W0 * base;
+        const T e1 = p.W1 * (base + m1), e3 = p.W1 * (base - m1);
+        const T e2 = p.W1 * (base + m2), e4 = p.W1 * (base - m2);
+        dgt[i][0] = dg[i][0] - (dg[i][0] - e0) * itm;
+        dgt[i][1] = dg[i][1] - (dg[i][1] - e1) * itm;
+        dgt[i][2] = dg[i][2] - (dg[i][2] - e2) * itm;
+        dgt[i][3] = dg[i][3] - (dg[i][3] - e3) * itm;
+        dgt[i][4] = dg[i][4] - (dg[i][4] - e4) * itm;
     }
-}
-
-template <class T>
-__device__ inline NodeParams<T> node_params(const RunDesc& d)
-{
-    NodeParams<T> p;
-    p.cs2 = T(d.cs2);
-    p.inv_cs2 = T(1.0 / d.cs2);
-    p.nu = T(d.nu);
-    p.zeta = T(d.zeta);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) p.w[k] = T(d.omega[k]);
-    p.Fx1 = T(d.Fx1);
-    p.Fx2 = T(d.Fx2);
-    p.gi_terms = d.gi_terms;
-    p.q3_sign = d.q3_sign;
-    p.rho_terms = d.rho_terms;
-    p.csm2 = T(d.csm2);
-    p.inv_csm2 = T(1.0 / d.csm2);
-    p.tau_m = T(d.tau_m);
-    p.inv_tau_m = T(1.0 / d.tau_m);
-    p.eta = T(d.eta);
-    p.inv_mu = T(d.inv_mu);
-    p.B0 = T(d.B0);
-    p.W0 = T(1.0 - 2.0 * d.csm2);
-    p.W1 = T(0.5 * d.csm2);
-    return p;
 }
 
 // ---------------------------------------------------------------------------
@@ -385,7 +427,7 @@ __device__ inline void seg_rows(int ny, int segs, int s, int& y0, int& y1)
 // First column covered by lane 0 of strip k.  With x-walls the last strip
 // is shifted so that it always holds the three columns the one-sided
 // difference at the last column needs.
-__device__ inline int lane_base(int nx, int bc_x, int k)
+__host__ __device__ inline int lane_base(int nx, int bc_x, int k)
 {
     const int x0 = k * kOwn;
     if (bc_x && nx - x0 < 2 && nx >= kWave - 1) return nx - (kWave - 1);

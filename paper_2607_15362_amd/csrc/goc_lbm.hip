@@ -161,6 +161,7 @@ struct goc_lbm {
     int32_t* block_run_d = nullptr;
     int total_blocks = 0;
     double *h1_d = nullptr, *th11_d = nullptr, *h2_d = nullptr, *th22_d = nullptr;
+    double *col_d = nullptr, *row_d = nullptr;   // per-column / per-row tables
     void* f[2] = {nullptr, nullptr};
     void* F[2] = {nullptr, nullptr};
     void* g[2] = {nullptr, nullptr};
@@ -191,10 +192,8 @@ PoolsOf<S> pools(const goc_lbm* h, int in)
     p.Fout = static_cast<FT*>(h->F[1 - in]);
     p.gin = static_cast<const S*>(h->g[in]);
     p.gout = static_cast<S*>(h->g[1 - in]);
-    p.h1 = h->h1_d;
-    p.th11 = h->th11_d;
-    p.h2 = h->h2_d;
-    p.th22 = h->th22_d;
+    p.col = h->col_d;
+    p.row = h->row_d;
     return p;
 }
 
@@ -248,6 +247,8 @@ int free_all(goc_lbm* h)
     (void)hipFree(h->th11_d);
     (void)hipFree(h->h2_d);
     (void)hipFree(h->th22_d);
+    (void)hipFree(h->col_d);
+    (void)hipFree(h->row_d);
     (void)hipFree(h->diag_part);
     (void)hipFree(h->diag_out);
     return GOC_OK;
@@ -343,8 +344,8 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
             g_elems += 10 * d.plane;
             h->any_mhd = true;
         }
-        d.metric_off_x = sum_nx;
-        d.metric_off_y = sum_ny;
+        d.col_off = sum_nx;
+        d.row_off = sum_ny;
         sum_nx += g.nx;
         sum_ny += g.ny;
         d.gi_terms = p.gi_terms;
@@ -382,10 +383,10 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
     // metric pools and the FP64 precompute (theta, q)
     std::vector<double> h1(sum_nx), dh1(sum_nx), h2(sum_ny), dh2(sum_ny);
     for (int r = 0; r < nruns; ++r) {
-        std::copy(h->mx[r].h.begin(), h->mx[r].h.end(), h1.begin() + h->runs[r].metric_off_x);
-        std::copy(h->mx[r].dh.begin(), h->mx[r].dh.end(), dh1.begin() + h->runs[r].metric_off_x);
-        std::copy(h->my[r].h.begin(), h->my[r].h.end(), h2.begin() + h->runs[r].metric_off_y);
-        std::copy(h->my[r].dh.begin(), h->my[r].dh.end(), dh2.begin() + h->runs[r].metric_off_y);
+        std::copy(h->mx[r].h.begin(), h->mx[r].h.end(), h1.begin() + h->runs[r].col_off);
+        std::copy(h->mx[r].dh.begin(), h->mx[r].dh.end(), dh1.begin() + h->runs[r].col_off);
+        std::copy(h->my[r].h.begin(), h->my[r].h.end(), h2.begin() + h->runs[r].row_off);
+        std::copy(h->my[r].dh.begin(), h->my[r].dh.end(), dh2.begin() + h->runs[r].row_off);
     }
     double *dh1_d = nullptr, *dh2_d = nullptr, *bmin_d = nullptr;
     auto dev_alloc = [&](void** p, size_t bytes) -> int {
@@ -395,7 +396,9 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
     };
     if ((rc = dev_alloc((void**)&h->h1_d, sum_nx * 8)) || (rc = dev_alloc((void**)&h->th11_d, sum_nx * 8)) ||
         (rc = dev_alloc((void**)&h->h2_d, sum_ny * 8)) || (rc = dev_alloc((void**)&h->th22_d, sum_ny * 8)) ||
-        (rc = dev_alloc((void**)&dh1_d, sum_nx * 8)) || (rc = dev_alloc((void**)&dh2_d, sum_ny * 8)))
+        (rc = dev_alloc((void**)&dh1_d, sum_nx * 8)) || (rc = dev_alloc((void**)&dh2_d, sum_ny * 8)) ||
+        (rc = dev_alloc((void**)&h->col_d, sum_nx * goc::kTab * 8)) ||
+        (rc = dev_alloc((void**)&h->row_d, sum_ny * goc::kTab * 8)))
         return bail(rc);
     auto cleanup_tmp = [&]() { (void)hipFree(dh1_d); (void)hipFree(dh2_d); (void)hipFree(bmin_d); };
     if (hipMemcpy(h->h1_d, h1.data(), sum_nx * 8, hipMemcpyHostToDevice) != hipSuccess ||
@@ -414,10 +417,10 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
             cleanup_tmp();
             return bail(fail(GOC_ENOMEM, "hipMalloc failed"));
         }
-        hipLaunchKernelGGL(goc::metric_kernel, dim3(nbx), dim3(256), 0, h->stream, h->h1_d + d.metric_off_x,
-                           dh1_d + d.metric_off_x, h->th11_d + d.metric_off_x, d.nx, bmin_d);
-        hipLaunchKernelGGL(goc::metric_kernel, dim3(nby), dim3(256), 0, h->stream, h->h2_d + d.metric_off_y,
-                           dh2_d + d.metric_off_y, h->th22_d + d.metric_off_y, d.ny, bmin_d + nbx);
+        hipLaunchKernelGGL(goc::metric_kernel, dim3(nbx), dim3(256), 0, h->stream, h->h1_d + d.col_off,
+                           dh1_d + d.col_off, h->th11_d + d.col_off, d.nx, bmin_d);
+        hipLaunchKernelGGL(goc::metric_kernel, dim3(nby), dim3(256), 0, h->stream, h->h2_d + d.row_off,
+                           dh2_d + d.row_off, h->th22_d + d.row_off, d.ny, bmin_d + nbx);
         std::vector<double> bm(nbx + nby);
         if (hipMemcpyAsync(bm.data(), bmin_d, (nbx + nby) * 8, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
             hipStreamSynchronize(h->stream) != hipSuccess) {
@@ -431,13 +434,26 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
         d.nu = d.cs2 * (1.0 / d.omega[4] - 0.5);
         d.zeta = d.cs2 * (1.0 / d.omega[3] - 0.5);
         d.eta = params[r].mhd ? d.csm2 * (params[r].tau_m - 0.5) : 0.0;
-        // 16-bit storage scales per direction class: deviations of the order
-        // of the rest-state magnitude times a Mach-number-sized factor map to
-        // O(1..100) stored values
+        // 16-bit storage scales per direction class: a tenth of the class's
+        // rest-state magnitude maps to one, which keeps the deviations of
+        // flows up to Mach 0.1 well inside the FP16 normal range
         const double c2 = d.cs2, r0 = d.rho0;
         const double mag[4] = {r0, 0.5 * r0 * c2, 0.5 * r0 * c2, 0.25 * r0 * c2 * c2};
-        for (int k = 0; k < 4; ++k) d.sc[k] = 1.0 / std::max(mag[k] * 1e-2, 1e-30);
-        d.scg = 1.0 / std::max(std::fabs(d.B0) * 1e-2 + 1e-12, 1e-30);
+        for (int k = 0; k < 4; ++k) d.sc[k] = 1.0 / std::max(mag[k] * 0.1, 1e-300);
+        // D2Q5 deviations scale like h U B0 with U ~ Ma c_s
+        d.scg = 1.0 / std::max(0.01 * std::fabs(d.B0) * std::sqrt(c2), 1e-12);
+        // column / row tables (FP64, on the device)
+        const double P0 = d.rho0 * d.cs2, W1B0 = 0.5 * d.csm2 * d.B0;
+        hipLaunchKernelGGL(goc::table_kernel, dim3(nbx), dim3(256), 0, h->stream, h->h1_d + d.col_off,
+                           h->th11_d + d.col_off, d.nx, d.bc_x == 0 ? 1 : 0, P0, W1B0,
+                           h->col_d + d.col_off * goc::kTab);
+        hipLaunchKernelGGL(goc::table_kernel, dim3(nby), dim3(256), 0, h->stream, h->h2_d + d.row_off,
+                           h->th22_d + d.row_off, d.ny, d.bc_y == 0 ? 1 : 0, P0, W1B0,
+                           h->row_d + d.row_off * goc::kTab);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess) {
+            cleanup_tmp();
+            return bail(fail(GOC_EDEVICE, "metric tables failed"));
+        }
     }
     cleanup_tmp();
     {
@@ -668,17 +684,24 @@ int goc_lbm_derive(goc_grid* grid, const goc_metric* metric, const goc_physics* 
         p.F_ext[0] = 2.0 * nu * U * rho0 / (half * half);
         break;
     }
-    case GOC_FLOW_CAVITY:
+    case GOC_FLOW_CAVITY: {
         if (!(phys->Re > 0)) return fail(GOC_EINVAL, "cavity flow needs Re > 0");
-        nu = phys->u_lid * grid->nx / phys->Re;
-        grid->u_wall_hi = phys->u_lid;
+        const double ul = phys->u_lid > 0 ? phys->u_lid : phys->Ma * std::sqrt(cs2);
+        if (!(ul > 0)) return fail(GOC_EINVAL, "cavity flow needs u_lid > 0 or Ma > 0");
+        nu = ul * grid->nx / phys->Re;
+        grid->u_wall_hi = ul;
         break;
+    }
     case GOC_FLOW_HARTMANN: {
         if (!(phys->Re > 0) || !(phys->Pm > 0) || !(phys->Ma > 0))
             return fail(GOC_EINVAL, "Hartmann flow needs Re, Pm, Ma > 0");
         const double H = 0.5 * grid->ny;
-        const double Uc = phys->Ma * std::sqrt(cs2);
+        double Uc = phys->Ma * std::sqrt(cs2);
         nu = Uc * H / phys->Re;
+        if (phys->tau_max > 0.5 && nu > cs2 * (phys->tau_max - 0.5)) {
+            nu = cs2 * (phys->tau_max - 0.5);     // relaxation-time cap, Re kept
+            Uc = nu * phys->Re / H;
+        }
         const double eta = nu / phys->Pm;
         const double sigma = 1.0 / (eta * p.mu_m);
         const double Ha = phys->Ha;
@@ -981,10 +1004,10 @@ int goc_lbm_metric(const goc_lbm_t* h, double* h1, double* th11, double* h2, dou
 {
     if (!h) return fail(GOC_EINVAL, "handle is NULL");
     const RunDesc& d = h->runs[0];
-    if (h1) HIPOK(hipMemcpy(h1, h->h1_d + d.metric_off_x, d.nx * 8, hipMemcpyDeviceToHost));
-    if (th11) HIPOK(hipMemcpy(th11, h->th11_d + d.metric_off_x, d.nx * 8, hipMemcpyDeviceToHost));
-    if (h2) HIPOK(hipMemcpy(h2, h->h2_d + d.metric_off_y, d.ny * 8, hipMemcpyDeviceToHost));
-    if (th22) HIPOK(hipMemcpy(th22, h->th22_d + d.metric_off_y, d.ny * 8, hipMemcpyDeviceToHost));
+    if (h1) HIPOK(hipMemcpy(h1, h->h1_d + d.col_off, d.nx * 8, hipMemcpyDeviceToHost));
+    if (th11) HIPOK(hipMemcpy(th11, h->th11_d + d.col_off, d.nx * 8, hipMemcpyDeviceToHost));
+    if (h2) HIPOK(hipMemcpy(h2, h->h2_d + d.row_off, d.ny * 8, hipMemcpyDeviceToHost));
+    if (th22) HIPOK(hipMemcpy(th22, h->th22_d + d.row_off, d.ny * 8, hipMemcpyDeviceToHost));
     return GOC_OK;
 }
 

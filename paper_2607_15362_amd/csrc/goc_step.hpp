@@ -1,4 +1,4 @@
-// goc_step.hpp -- the fused time-step kernel and the state conversion kernels.
+// goc_step.hpp -- the fused time-step kernel.
 #pragma once
 
 #include "goc_device.hpp"
@@ -12,85 +12,110 @@ template <> struct ComputeOf<double> { using type = double; };
 template <class S> struct ForceOf { using type = float; };
 template <> struct ForceOf<double> { using type = double; };
 
-// Per-lane geometry of one work-group.
-struct Lane {
-    int col;        // column (wrapped for periodic x); valid iff cvalid
-    bool cvalid;
-    bool own;       // this lane writes its column
-    int colm1, colp1;  // neighbour columns for the rest state of the 16-bit codec
+// Column geometry of one lane: the node column, its two neighbours (wrapped
+// when periodic) and whether they lie beyond a wall.
+struct LaneCol {
+    int col, cm, cp;
+    bool valid;     // col inside the grid
+    bool wm, wp;    // -xi1 / +xi1 neighbour beyond a wall
 };
 
-template <class S, class T>
-struct RowCtx {
-    const RunDesc& d;
-    const Pools<S, typename ForceOf<S>::type>& pl;
-    int64_t base;     // element offset of this run's f plane 0
-    int64_t Fbase;    // element offset of this run's force plane 0
-    int64_t moff;     // element offset of this run's row metric
-    T rho0, cs2;
-    T h1c, h1m1, h1p1;   // h1 at the lane's column and its neighbours (16-bit codec)
-    T sinv[4];
+__device__ inline LaneCol lane_col(const RunDesc& d, int craw)
+{
+    LaneCol L;
+    if (d.bc_x == 0) {
+        L.col = ((craw % d.nx) + d.nx) % d.nx;
+        L.valid = true;
+        L.cm = L.col == 0 ? d.nx - 1 : L.col - 1;
+        L.cp = L.col == d.nx - 1 ? 0 : L.col + 1;
+        L.wm = L.wp = false;
+    } else {
+        L.col = craw;
+        L.valid = craw >= 0 && craw < d.nx;
+        L.cm = craw - 1;
+        L.cp = craw + 1;
+        L.wm = craw == 0;
+        L.wp = craw == d.nx - 1;
+    }
+    return L;
+}
+
+// Row geometry: a row, its neighbours (wrapped when periodic) and walls.
+struct RowGeo {
+    int r, rm, rp;
+    bool wm, wp;
 };
 
-// Row index wrap / validity.
+__device__ inline RowGeo row_geo(const RunDesc& d, int r)
+{
+    RowGeo G;
+    G.r = r;
+    if (d.bc_y == 0) {
+        G.rm = r == 0 ? d.ny - 1 : r - 1;
+        G.rp = r == d.ny - 1 ? 0 : r + 1;
+        G.wm = G.wp = false;
+    } else {
+        G.rm = r - 1;
+        G.rp = r + 1;
+        G.wm = r == 0;
+        G.wp = r == d.ny - 1;
+    }
+    return G;
+}
+
 __device__ inline bool row_ok(const RunDesc& d, int r) { return d.bc_y == 0 || (r >= 0 && r < d.ny); }
 __device__ inline int row_wrap(const RunDesc& d, int r) { return d.bc_y == 0 ? (r % d.ny + d.ny) % d.ny : r; }
 
-// Pull the nine pre-collision populations of node (col, r) (App. E step 6
-// as a gather; wall slots were written by the wall-adjacent node itself).
-template <class S, class T>
-__device__ inline void pull9(const RowCtx<S, T>& c, const Lane& L, int r, T* f)
+// Element offset (within a run's pool region) of the slot pulled by
+// direction a into node (L.col, G.r): slot(a, x - e_a) in the interior,
+// slot(opp(a), x) through a wall.
+__device__ inline int64_t pull_index(const RunDesc& d, const LaneCol& L, const RowGeo& G, int a)
 {
-    const RunDesc& d = c.d;
-    const int64_t pitch = d.pitch, plane = d.plane;
-#pragma unroll
-    for (int a = 0; a < kQ; ++a) {
-        int sx = L.col - ex_(a), sy = r - ey_(a);
-        int pa = a;
-        bool wall = false;
-        if (sx < 0 || sx >= d.nx) {
-            if (d.bc_x == 0) sx = sx < 0 ? sx + d.nx : sx - d.nx;
-            else wall = true;
-        }
-        if (sy < 0 || sy >= d.ny) {
-            if (d.bc_y == 0) sy = sy < 0 ? sy + d.ny : sy - d.ny;
-            else wall = true;
-        }
-        if (wall) { sx = L.col; sy = r; pa = opp_(a); }
-        T rest = T(0), inv = T(1);
-        if constexpr (Store<S>::dev) {
-            const T h1s = (sx == L.col) ? c.h1c : (ex_(a) > 0 ? c.h1m1 : c.h1p1);
-            const T h2s = T(c.pl.h2[c.moff + sy]);
-            rest = rest_pop<T>(pa, h1s, h2s, c.rho0, c.cs2);
-            inv = c.sinv[cls_(pa)];
-        }
-        f[a] = L.cvalid ? Store<S>::ld(c.pl.fin, c.base + pa * plane + (int64_t)sy * pitch + sx, rest, inv)
-                        : T(0);
+    const int ex = ex_(a), ey = ey_(a);
+    const bool wx = (ex > 0 && L.wm) || (ex < 0 && L.wp);
+    const bool wy = (ey > 0 && G.wm) || (ey < 0 && G.wp);
+    int sx = ex > 0 ? L.cm : (ex < 0 ? L.cp : L.col);
+    int sy = ey > 0 ? G.rm : (ey < 0 ? G.rp : G.r);
+    int pa = a;
+    if (wx || wy) {
+        sx = L.col;
+        sy = G.r;
+        pa = opp_(a);
     }
+    return (int64_t)pa * d.plane + (int64_t)sy * d.pitch + sx;
 }
 
-template <class S>
-__device__ inline int64_t node_index(const RunDesc& d, int col, int r) { return (int64_t)r * d.pitch + col; }
-
-// Moments of a pulled row: rho = k00/(h1 h2), U1 = (k10 + F1/2)/(rho h2),
-// U2 = (k01 + F2/2)/(rho h1) with the lagged force (App. E step 7).
+// Pull the nine deviations of node (col, r).
 template <class S, class T>
-__device__ inline void row_moments(const RowCtx<S, T>& c, const Lane& L, int r, const T* f, T h2,
-                                   T& rho, T& U1, T& U2)
+__device__ inline void pull9(const RunDesc& d, const S* __restrict__ fin, const LaneCol& L, const RowGeo& G,
+                             const T* sinv, T* f)
+{
+    const S* base = fin + d.f_off;
+#pragma unroll
+    for (int a = 0; a < kQ; ++a)
+        f[a] = L.valid ? T(Store<S>::ld(base, pull_index(d, L, G, a), sinv[cls_(a)])) : T(0);
+}
+
+// Moments of a pulled row: rho = rho0 + dm00/(h1 h2),
+// U1 = (dm10 + F1/2)/(rho h2), U2 = (dm01 + F2/2)/(rho h1) with the lagged
+// effective force (App. E step 7).
+template <class FT, class T>
+__device__ inline void row_moments(const RunDesc& d, const FT* __restrict__ Fin, const LaneCol& L, int r,
+                                   const T* f, T rho0, T ih1, T ih2, T& rho, T& U1, T& U2)
 {
     const T m00 = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
     const T m10 = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
     const T m01 = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
     T Fp1 = T(0), Fp2 = T(0);
-    if (L.cvalid) {
-        const int64_t n = c.Fbase + node_index<S>(c.d, L.col, r);
-        Fp1 = T(c.pl.Fin[n]);
-        Fp2 = T(c.pl.Fin[n + c.d.plane]);
+    if (L.valid) {
+        const int64_t n = d.F_off + (int64_t)r * d.pitch + L.col;
+        Fp1 = T(Fin[n]);
+        Fp2 = T(Fin[n + d.plane]);
     }
-    const T h1 = c.h1c;
-    rho = L.cvalid ? m00 / (h1 * h2) : T(1);
-    U1 = L.cvalid ? (m10 + T(0.5) * Fp1) / (rho * h2) : T(0);
-    U2 = L.cvalid ? (m01 + T(0.5) * Fp2) / (rho * h1) : T(0);
+    rho = rho0 + m00 * ih1 * ih2;
+    const T irho = recip(rho);
+    U1 = (m10 + T(0.5) * Fp1) * ih2 * irho;
+    U2 = (m01 + T(0.5) * Fp2) * ih1 * irho;
 }
 
 // One time step for every run of the launch.
@@ -111,72 +136,76 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
     const int lane = threadIdx.x;
     const NodeParams<T> p = node_params<T>(d);
 
-    // lane geometry
-    Lane L;
+    // lane geometry and column metric
     const int lb = lane_base(d.nx, d.bc_x, strip);
     const int craw = lb + lane;
+    const LaneCol L = lane_col(d, craw);
     const int x0 = strip * kOwn;
     const int x1 = min(x0 + kOwn, d.nx);
-    if (d.bc_x == 0) {
-        L.col = ((craw % d.nx) + d.nx) % d.nx;
-        L.cvalid = true;
-    } else {
-        L.col = craw;
-        L.cvalid = craw >= 0 && craw < d.nx;
-    }
-    L.own = lane >= 1 && lane <= kWave - 2 && craw >= x0 && craw < x1;
+    const bool own = lane >= 1 && lane <= kWave - 2 && craw >= x0 && craw < x1;
     const bool xwall_lo = d.bc_x != 0 && L.col == 0;
     const bool xwall_hi = d.bc_x != 0 && L.col == d.nx - 1;
-
-    RowCtx<S, T> c{d, pl, d.f_off, d.F_off, d.metric_off_y, T(d.rho0), T(d.cs2), T(1), T(1), T(1), {}};
-    const int64_t mx = d.metric_off_x;
-    const T h1 = L.cvalid ? T(pl.h1[mx + L.col]) : T(1);
-    const T th11 = L.cvalid ? T(pl.th11[mx + L.col]) : T(0);
-    c.h1c = h1;
-    if constexpr (Store<S>::dev) {
-        const int cm = d.bc_x == 0 ? (L.col + d.nx - 1) % d.nx : max(L.col - 1, 0);
-        const int cp = d.bc_x == 0 ? (L.col + 1) % d.nx : min(L.col + 1, d.nx - 1);
-        c.h1m1 = L.cvalid ? T(pl.h1[mx + cm]) : T(1);
-        c.h1p1 = L.cvalid ? T(pl.h1[mx + cp]) : T(1);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) c.sinv[k] = T(1.0 / d.sc[k]);
+    T h1 = T(1), ih1 = T(1), th11 = T(0), a1p = T(0), a1m = T(0), b1p = T(0), b1m = T(0);
+    if (L.valid) {
+        const double* ct = pl.col + (d.col_off + L.col) * kTab;
+        h1 = T(ct[T_H]);
+        ih1 = T(ct[T_IH]);
+        th11 = T(ct[T_TH]);
+        a1p = T(ct[T_AP]);
+        a1m = T(ct[T_AM]);
+        b1p = T(ct[T_BP]);
+        b1m = T(ct[T_BM]);
     }
+    T sinv[4], sfw[4], sginv = T(1), sgw = T(1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        sinv[k] = Store<S>::scaled ? T(1.0 / d.sc[k]) : T(1);
+        sfw[k] = Store<S>::scaled ? T(d.sc[k]) : T(1);
+    }
+    if (Store<S>::scaled) {
+        sginv = T(1.0 / d.scg);
+        sgw = T(d.scg);
+    }
+    const double* rowtab = pl.row + d.row_off * kTab;
+    auto ih2_of = [&](int r) { return T(rowtab[r * kTab + T_IH]); };
 
     int y0, y1;
     seg_rows(d.ny, d.segs, seg, y0, y1);
 
     // Window of row moments: rows j-2, j-1, j, j+1 (rho, U2) and row j (U1, f).
-    T wr[4] = {T(1), T(1), T(1), T(1)}, wu[4] = {T(0), T(0), T(0), T(0)};
+    T wr[4] = {p.rho0, p.rho0, p.rho0, p.rho0}, wu[4] = {T(0), T(0), T(0), T(0)};
     T fc[kQ], fn[kQ];
     T U1c = T(0), U1n = T(0);
-    auto h2_of = [&](int r) { return T(pl.h2[d.metric_off_y + row_wrap(d, r)]); };
     if (row_ok(d, y0 - 1)) {
         const int r = row_wrap(d, y0 - 1);
         T ft[kQ], u1;
-        pull9<S, T>(c, L, r, ft);
-        row_moments<S, T>(c, L, r, ft, h2_of(r), wr[1], u1, wu[1]);
+        pull9<S, T>(d, pl.fin, L, row_geo(d, r), sinv, ft);
+        row_moments<FT, T>(d, pl.Fin, L, r, ft, p.rho0, ih1, ih2_of(r), wr[1], u1, wu[1]);
     }
-    {
-        pull9<S, T>(c, L, y0, fc);
-        row_moments<S, T>(c, L, y0, fc, h2_of(y0), wr[2], U1c, wu[2]);
-    }
+    pull9<S, T>(d, pl.fin, L, row_geo(d, y0), sinv, fc);
+    row_moments<FT, T>(d, pl.Fin, L, y0, fc, p.rho0, ih1, ih2_of(y0), wr[2], U1c, wu[2]);
 
     const int64_t plane = d.plane;
-    const T Fe1 = p.Fx1, Fe2 = p.Fx2;
     for (int j = y0; j < y1; ++j) {
         if (row_ok(d, j + 1)) {
             const int r = row_wrap(d, j + 1);
-            pull9<S, T>(c, L, r, fn);
-            row_moments<S, T>(c, L, r, fn, h2_of(r), wr[3], U1n, wu[3]);
+            pull9<S, T>(d, pl.fin, L, row_geo(d, r), sinv, fn);
+            row_moments<FT, T>(d, pl.Fin, L, r, fn, p.rho0, ih1, ih2_of(r), wr[3], U1n, wu[3]);
         }
-        const T h2 = h2_of(j);
-        const T th22 = T(pl.th22[d.metric_off_y + j]);
+        const double* rt = rowtab + j * kTab;
+        NodeMetric<T> g;
+        g.h1 = h1;
+        g.ih1 = ih1;
+        g.th11 = th11;
+        g.h2 = T(rt[T_H]);
+        g.ih2 = T(rt[T_IH]);
+        g.th22 = T(rt[T_TH]);
         // finite differences along xi2 (one-sided next to walls)
         T d2U2, d2r;
         if (d.bc_y != 0 && j == 0) {
             T f2[kQ], r2, u12, u22;
-            pull9<S, T>(c, L, 2, f2);
-            row_moments<S, T>(c, L, 2, f2, h2_of(2), r2, u12, u22);
+            pull9<S, T>(d, pl.fin, L, row_geo(d, 2), sinv, f2);
+            row_moments<FT, T>(d, pl.Fin, L, 2, f2, p.rho0, ih1, ih2_of(2), r2, u12, u22);
             d2U2 = T(0.5) * (T(-3) * wu[2] + T(4) * wu[3] - u22);
             d2r = T(0.5) * (T(-3) * wr[2] + T(4) * wr[3] - r2);
         } else if (d.bc_y != 0 && j == d.ny - 1) {
@@ -205,106 +234,81 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
         }
 
         // App. G: magnetic field, local derivatives, Lorentz force, collision
-        T Fx1 = Fe1, Fx2 = Fe2;
-        T gt[2][kM];
+        T Fx1 = p.Fx1, Fx2 = p.Fx2;
+        T dgt[2][kM];
         const bool mhd_run = MHD && d.mhd;   // a batch may mix MHD and plain runs
+        const RowGeo Gj = row_geo(d, j);
         if (mhd_run) {
-            T gb[2][kM];
+            T dg[2][kM];
+            const S* gb = pl.gin + d.g_off;
 #pragma unroll
             for (int ci = 0; ci < 2; ++ci)
 #pragma unroll
-                for (int a = 0; a < kM; ++a) {
-                    int sx = L.col - ex_(a), sy = j - ey_(a);
-                    int pa = a;
-                    bool wall = false;
-                    if (sx < 0 || sx >= d.nx) {
-                        if (d.bc_x == 0) sx = sx < 0 ? sx + d.nx : sx - d.nx;
-                        else wall = true;
-                    }
-                    if (sy < 0 || sy >= d.ny) {
-                        if (d.bc_y == 0) sy = sy < 0 ? sy + d.ny : sy - d.ny;
-                        else wall = true;
-                    }
-                    if (wall) { sx = L.col; sy = j; pa = opp_(a); }
-                    T rest = T(0), inv = T(1);
-                    if constexpr (Store<S>::dev) {
-                        const T h1s = (sx == L.col) ? h1 : (ex_(a) > 0 ? c.h1m1 : c.h1p1);
-                        const T h2s = T(pl.h2[d.metric_off_y + sy]);
-                        rest = (ci == 1 ? (pa == 0 ? p.W0 : p.W1) * h1s * h2s * p.B0 : T(0));
-                        inv = T(1.0 / d.scg);
-                    }
-                    gb[ci][a] = L.cvalid ? Store<S>::ld(pl.gin, d.g_off + (ci * kM + pa) * plane +
-                                                                     (int64_t)sy * d.pitch + sx, rest, inv)
-                                         : T(0);
-                }
+                for (int a = 0; a < kM; ++a)
+                    dg[ci][a] = L.valid ? T(Store<S>::ld(gb, ci * kM * plane + pull_index(d, L, Gj, a), sginv))
+                                        : T(0);
             T B1, B2, FL1, FL2;
-            mie_node<T>(p, h1, h2, th11, th22, gb, U1, U2, B1, B2, FL1, FL2, gt);
+            mie_node<T>(p, g, dg, U1, U2, B1, B2, FL1, FL2, dgt);
             Fx1 += FL1;
             Fx2 += FL2;
         }
 
-        T F1, F2, n3, n4, ft[kQ];
-        force_and_corrections<T>(p, h1, h2, th11, th22, rho, U1, U2, d1U1, d2U2, d1r, d2r, Fx1, Fx2,
-                                 F1, F2, n3, n4);
-        cm_collide<T>(p, h1, h2, fc, rho, U1, U2, F1, F2, n3, n4, ft);
+        T F1, F2, n3, n4, dt[kQ];
+        force_and_corrections<T>(p, g, rho, U1, U2, d1U1, d2U2, d1r, d2r, Fx1, Fx2, F1, F2, n3, n4);
+        cm_collide<T>(p, g, raw_dev<T>(fc), rho, rho - p.rho0, U1, U2, F1, F2, n3, n4, dt);
 
-        if (L.own) {
-            // writer-side wall conditions: momentum-augmented bounce-back of
-            // App. C for populations leaving through a y-wall
-            const bool top = d.bc_y != 0 && j == d.ny - 1;
-            const bool bot = d.bc_y != 0 && j == 0;
-            if (top && d.uw_hi != 0.0) {
+        if (own) {
+            // rest-state offsets of the interior axis slots (the reader is
+            // the neighbour; its rest state differs through the metric)
+            const T a2p = T(rt[T_AP]), a2m = T(rt[T_AM]);
+            dt[1] += g.h2 * a1p;
+            dt[3] += g.h2 * a1m;
+            dt[2] += g.h1 * a2p;
+            dt[4] += g.h1 * a2m;
+            // writer-side momentum-augmented bounce-back of App. C for
+            // populations leaving through a moving y-wall
+            if (Gj.wp && d.uw_hi != 0.0) {
                 const T cw = rho * p.cs2 * T(d.uw_hi) / (T(2) * T(d.hw_hi));
                 // slot 5 is read back as f7, slot 6 as f8: f7 = ft5 - cw, f8 = ft6 + cw
-                if (d.lid_corners || !xwall_hi) ft[5] -= cw;
-                if (d.lid_corners || !xwall_lo) ft[6] += cw;
+                if (d.lid_corners || !xwall_hi) dt[5] -= cw;
+                if (d.lid_corners || !xwall_lo) dt[6] += cw;
             }
-            if (bot && d.uw_lo != 0.0) {
+            if (Gj.wm && d.uw_lo != 0.0) {
                 const T cw = rho * p.cs2 * T(d.uw_lo) / (T(2) * T(d.hw_lo));
                 // slot 7 is read back as f5, slot 8 as f6: f5 = ft7 + cw, f6 = ft8 - cw
-                if (d.lid_corners || !xwall_lo) ft[7] += cw;
-                if (d.lid_corners || !xwall_hi) ft[8] -= cw;
+                if (d.lid_corners || !xwall_lo) dt[7] += cw;
+                if (d.lid_corners || !xwall_hi) dt[8] -= cw;
             }
-            const int64_t nn = node_index<S>(d, L.col, j);
-            const int64_t n = d.f_off + nn;
+            const int64_t nn = (int64_t)j * d.pitch + L.col;
+            S* fo = pl.fout + d.f_off + nn;
 #pragma unroll
-            for (int a = 0; a < kQ; ++a) {
-                T rest = T(0), s = T(1);
-                if constexpr (Store<S>::dev) {
-                    rest = rest_pop<T>(a, h1, h2, c.rho0, c.cs2);
-                    s = T(d.sc[cls_(a)]);
-                }
-                Store<S>::st(pl.fout, n + a * plane, ft[a], rest, s);
-            }
+            for (int a = 0; a < kQ; ++a) Store<S>::st(fo, a * plane, dt[a], sfw[cls_(a)]);
             pl.Fout[d.F_off + nn] = FT(F1);
             pl.Fout[d.F_off + nn + plane] = FT(F2);
             if (mhd_run) {
-                // anti-bounce-back of App. G for populations leaving through a
-                // wall: the reader sees -gt + 2 W h_wall B_wall (B_wall = (0, B0))
+                const T b2p = T(rt[T_BP]), b2m = T(rt[T_BM]);
+                const T hh = g.h1 * g.h2;
 #pragma unroll
                 for (int a = 1; a < kM; ++a) {
-                    const int tx = L.col + ex_(a), ty = j + ey_(a);
-                    const bool wx = d.bc_x != 0 && (tx < 0 || tx >= d.nx);
-                    const bool wy = d.bc_y != 0 && (ty < 0 || ty >= d.ny);
+                    const int ex = ex_(a), ey = ey_(a);
+                    const bool wx = (ex > 0 && L.wp) || (ex < 0 && L.wm);
+                    const bool wy = (ey > 0 && Gj.wp) || (ey < 0 && Gj.wm);
                     if (wx || wy) {
-                        T hwall;
-                        if (wy) hwall = h1 * T(ty < 0 ? d.hw_lo : d.hw_hi);
-                        else hwall = T(tx < 0 ? d.h1w_lo : d.h1w_hi) * h2;
-                        gt[0][a] = -gt[0][a];
-                        gt[1][a] = -gt[1][a] + T(2) * p.W1 * hwall * p.B0;
+                        // anti-bounce-back of App. G: the reader (this node) sees
+                        // -g~ + 2 W h_wall B_wall with B_wall = (0, B0)
+                        const T hwall = wy ? g.h1 * T(ey < 0 ? d.hw_lo : d.hw_hi)
+                                           : T(ex < 0 ? d.h1w_lo : d.h1w_hi) * g.h2;
+                        dgt[0][a] = -dgt[0][a];
+                        dgt[1][a] = -dgt[1][a] + T(2) * p.W1 * p.B0 * (hwall - hh);
+                    } else {
+                        dgt[1][a] += a == 1 ? g.h2 * b1p : a == 3 ? g.h2 * b1m : a == 2 ? g.h1 * b2p : g.h1 * b2m;
                     }
                 }
+                S* go = pl.gout + d.g_off + nn;
 #pragma unroll
                 for (int ci = 0; ci < 2; ++ci)
 #pragma unroll
-                    for (int a = 0; a < kM; ++a) {
-                        T rest = T(0), s = T(1);
-                        if constexpr (Store<S>::dev) {
-                            rest = ci == 1 ? (a == 0 ? p.W0 : p.W1) * h1 * h2 * p.B0 : T(0);
-                            s = T(d.scg);
-                        }
-                        Store<S>::st(pl.gout, d.g_off + nn + (ci * kM + a) * plane, gt[ci][a], rest, s);
-                    }
+                    for (int a = 0; a < kM; ++a) Store<S>::st(go, (ci * kM + a) * plane, dgt[ci][a], sgw);
             }
         }
         // shift the window
