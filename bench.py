@@ -86,6 +86,25 @@ def cpu_baseline(case, seconds: float):
                       f"({dt:.1f} s), after one untimed step"}
 
 
+def copy_calibration(mib: int, reps: int):
+    """A plain device-to-device copy of known size, for scaling the HBM byte
+    counters of a profiler run: prints the bytes moved per copy and the rate."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
+                      "GB_s": round(8 * n / dt / 1e9, 1)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,12 +114,17 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain copy of MIB mebibytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
               "(the hot path is a single-GPU build; see the design notes on sharding)",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration, max(1, args.steps))
+        return
 
     from paper_2607_15362_amd import binding as B
     from paper_2607_15362_amd import workloads as W
@@ -129,7 +153,7 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32"}.get(case.storage, "f32"),
         "data": "synthetic",
         "config": {"workload": f"{case.name}: lid-driven cavity {case.nx}x{case.ny}, tanh beta=2 "
-                               f"on both axes, Re=1000, lid 0.05, FP32 storage and arithmetic"
+                               f"on both axes, Re=1000, lid at Mach 0.1 of the finest cell, FP32 storage and arithmetic"
                    if case.flow == "cavity" else
                    f"{case.name}: Hartmann channel {case.nx}x{case.ny}, tanh beta=3, Ha=100, "
                    f"Re=100, Pm=1, D2Q9+D2Q5, FP32",

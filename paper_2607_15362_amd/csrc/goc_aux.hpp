@@ -140,7 +140,7 @@ __global__ void init_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, 
         d2r = fdy(rho_in);
     }
     T F1, F2, n3, n4;
-    force_and_corrections<T>(p, g, rho, U1, U2, d1U1, d2U2, d1r, d2r, p.Fx1, p.Fx2, F1, F2, n3, n4);
+    force_and_corrections<T>(p, g, rho, drho, U1, U2, d1U1, d2U2, d1r, d2r, p.Fx1, p.Fx2, F1, F2, n3, n4);
     // raw-equilibrium deviations from the rest moments
     const T r21 = g.h2 * g.ih1, r12 = g.h1 * g.ih2, cs2 = p.cs2;
     const T dP = drho * cs2;
@@ -280,11 +280,11 @@ __global__ void fields_kernel(const RunDesc* __restrict__ runs, int run, Pools<S
     LaneCol L;
     L.col = i;
     L.valid = true;
-    T rho, U1, U2;
-    row_moments<typename ForceOf<S>::type, T>(d, pl.Fin, L, j, f, T(d.rho0), T(ct[T_IH]), T(rt[T_IH]), rho,
-                                              U1, U2);
+    T dr, U1, U2, Fp1, Fp2;
+    row_moments<typename ForceOf<S>::type, T>(d, pl.Fin, L, j, f, T(d.rho0), T(ct[T_IH]), T(rt[T_IH]), dr,
+                                              U1, U2, Fp1, Fp2);
     const int64_t N = (int64_t)d.nx * d.ny, o = (int64_t)j * d.nx + i;
-    if (rho_o) rho_o[o] = double(rho);
+    if (rho_o) rho_o[o] = d.rho0 + double(dr);
     if (u_o) {
         u_o[o] = double(U1);
         u_o[N + o] = double(U2);
@@ -324,9 +324,10 @@ __global__ void diag_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, 
         LaneCol L;
         L.col = i;
         L.valid = true;
-        T rho, U1, U2;
+        T dr, U1, U2, Fp1, Fp2;
         row_moments<typename ForceOf<S>::type, T>(d, pl.Fin, L, j, f, T(d.rho0), T(ct[T_IH]), T(rt[T_IH]),
-                                                  rho, U1, U2);
+                                                  dr, U1, U2, Fp1, Fp2);
+        const double rho = d.rho0 + double(dr);
         const double h1 = ct[T_H], h2 = rt[T_H];
         double m = h1 * h2 * d.rho0;   // sum of the rest-state populations
         int bad = 0;
@@ -335,8 +336,8 @@ __global__ void diag_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, 
             bad += isfinite(double(f[a])) ? 0 : 1;
         }
         v[0] = m;
-        v[1] = h2 * double(rho) * double(U1);
-        v[2] = h1 * double(rho) * double(U2);
+        v[1] = h2 * rho * double(U1);
+        v[2] = h1 * rho * double(U2);
         if (d.mhd) {
             double S1 = 0, S2 = 0;
             for (int a = 0; a < kM; ++a) {

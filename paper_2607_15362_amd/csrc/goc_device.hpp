@@ -122,13 +122,25 @@ template <> struct Store<__hip_bfloat16> {
     __device__ static void st(__hip_bfloat16* p, int64_t i, float v, float s) { p[i] = __float2bfloat16(v * s); }
 };
 
-// Reciprocal: correctly rounded division for FP64, hardware reciprocal plus
-// one Newton step (< 1 ulp) for FP32.
+// Reciprocal: correctly rounded division for FP64; for FP32 the hardware
+// reciprocal refined by one fused Newton step r + r (1 - x r).
 __device__ inline double recip(double x) { return 1.0 / x; }
 __device__ inline float recip(float x)
 {
-    float r = __builtin_amdgcn_rcpf(x);
-    return r * (2.0f - x * r);
+    const float r = __builtin_amdgcn_rcpf(x);
+    return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
+}
+
+// 1 / (a + b) for |a| >= |b|.  The rounding error of the FP32 sum is
+// recovered exactly (Fast2Sum) and folded into the refined reciprocal, so a
+// small deviation b keeps its full relative precision in the result.
+__device__ inline double recip_sum(double a, double b) { return 1.0 / (a + b); }
+__device__ inline float recip_sum(float a, float b)
+{
+    const float s = a + b;
+    const float e = (a - s) + b;
+    const float r = recip(s);
+    return __builtin_fmaf(-r * e, r, r);
 }
 
 // Rest-state populations at (rho0, U = 0): P^-1 of the Sec. 3 equilibria.
@@ -192,20 +204,23 @@ struct NodeMetric {
 //   F1 = h2 [F1ext - theta11 P + theta11 (tau11 - rho U1^2)],
 //   F2 = h1 [F2ext - theta22 P + theta22 (tau22 - rho U2^2)],
 // tau11, tau22 the normal viscous stresses of Sec. 2.2, and the equilibrium
-// corrections n3^eq(1), n4^eq(1) of Sec. 5 on a straight grid.
+// corrections n3^eq(1), n4^eq(1) of Sec. 5 on a straight grid.  The
+// pressure P = P0 + c_s^2 (rho - rho0) is split so that its constant part
+// is one product of constants and the varying part keeps the precision of
+// the density deviation drho.
 template <class T>
-__device__ inline void force_and_corrections(const NodeParams<T>& p, const NodeMetric<T>& g, T rho,
+__device__ inline void force_and_corrections(const NodeParams<T>& p, const NodeMetric<T>& g, T rho, T drho,
                                              T U1, T U2, T d1U1, T d2U2, T d1r, T d2r, T Fe1, T Fe2,
                                              T& F1, T& F2, T& n3, T& n4)
 {
     const T nu = p.nu, ze = p.zeta, ics = p.inv_cs2;
     const T h1 = g.h1, h2 = g.h2, ih1 = g.ih1, ih2 = g.ih2;
-    const T P = rho * p.cs2;
+    const T dP = drho * p.cs2;
     const T a1 = d1U1 * ih1, a2 = d2U2 * ih2;
     const T tau11 = rho * ((ze + nu) * a1 + (ze - nu) * a2);
     const T tau22 = rho * ((ze + nu) * a2 + (ze - nu) * a1);
-    F1 = h2 * (Fe1 + g.th11 * (tau11 - rho * U1 * U1 - P));
-    F2 = h1 * (Fe2 + g.th22 * (tau22 - rho * U2 * U2 - P));
+    F1 = h2 * (Fe1 + g.th11 * (tau11 - rho * U1 * U1 - dP)) - h2 * g.th11 * p.P0;
+    F2 = h1 * (Fe2 + g.th22 * (tau22 - rho * U2 * U2 - dP)) - h1 * g.th22 * p.P0;
 
     const T r21 = h2 * ih1, r12 = h1 * ih2;          // h2/h1, h1/h2
     const T s1 = r21 * ih1, s2 = r12 * ih2;          // h2/h1^2, h1/h2^2
@@ -275,25 +290,28 @@ __device__ inline RawDev<T> raw_dev(const T* d)
     return m;
 }
 
-// Central-moment collision of App. E (steps 2-5) at one node in deviation
-// form.  With m = m^r + dm, m^r the rest-state raw moments (h1 h2 rho0, 0, 0,
-// (h2/h1) P0, (h1/h2) P0, 0, 0, 0, rho0 c_s^4), every transform and
-// relaxation is linear in the moments, so the rest part is carried
-// analytically: products of U with the large rest moments are formed from
-// the full moments, every leading term from the deviations.  Output: the
-// post-collision deviations dt = f~ - f^rest.
+// Central-moment collision of App. E (steps 2-5) at one node, written as an
+// increment: f~ = f + P^-1 F(U) dk, where dk = k~ - k are the changes of the
+// central moments (relaxation plus sources; dk00 = 0) and F(U) maps central
+// to raw moments.  Every step is linear in the moments, so this equals the
+// transform chain of App. E; the rest-state moments (h1 h2 rho0, 0, 0,
+// (h2/h1) P0, (h1/h2) P0, 0, 0, 0, rho0 c_s^4) cancel analytically and each
+// population is rounded once, by the final addition.  Forming the raw
+// moments after collision as values of their own would round the slowly
+// growing momentum on every step, a bias that FP32 accumulates.
+// f: pre-collision deviations f - f^rest, m = their raw moments.
+// Output: the post-collision deviations dt = f~ - f^rest.
 template <class T>
-__device__ inline void cm_collide(const NodeParams<T>& p, const NodeMetric<T>& g, const RawDev<T>& m,
-                                  T rho, T drho, T U1, T U2, T F1, T F2, T n3, T n4, T* dt)
+__device__ inline void cm_collide(const NodeParams<T>& p, const NodeMetric<T>& g, const T* f, const RawDev<T>& m,
+                                  T rho, T drho, T U1, T U2, T Fp1, T Fp2, T F1, T F2, T n3, T n4, T* dt)
 {
     const T h1 = g.h1, h2 = g.h2;
     const T r21 = h2 * g.ih1, r12 = h1 * g.ih2;
     const T M0 = h1 * h2 * p.rho0, A = r21 * p.P0, Bm = r12 * p.P0;
     const T c00 = M0 + m.m00, c20 = A + m.m20, c02 = Bm + m.m02;   // full moments
-    // step 2: central-moment deviations (rest central moments = m^r)
+    // step 2: central moments (deviations from the rest central moments;
+    // the first-order ones enter only through the identity below)
     const T U11 = U1 * U1, U22 = U2 * U2, U12 = U1 * U2;
-    const T k10 = m.m10 - U1 * c00;
-    const T k01 = m.m01 - U2 * c00;
     const T k20 = m.m20 - T(2) * U1 * m.m10 + U11 * c00;
     const T k02 = m.m02 - T(2) * U2 * m.m01 + U22 * c00;
     const T k11 = m.m11 - U2 * m.m10 - U1 * m.m01 + U12 * c00;
@@ -308,8 +326,6 @@ __device__ inline void cm_collide(const NodeParams<T>& p, const NodeMetric<T>& g
     T q21 = h1m * h1m * h2m * g.ih1, q12 = h1m * h2m * h2m * g.ih2;   // printed sign
     if (!p.q3_sign) { q21 = -q21; q12 = -q12; }                       // binomial transform
     const T rc = rho * p.cs2, drc = drho * p.cs2;
-    const T e10 = -h1m * h2 * rho * U1;
-    const T e01 = -h2m * h1 * rho * U2;
     const T e2s = q20 * rho * U11 + q02 * rho * U22 + (r21 + r12) * drc + n3;
     const T e2d = q20 * rho * U11 - q02 * rho * U22 + (r21 - r12) * drc + n4;
     const T e11 = q11 * rho * U12;
@@ -320,44 +336,46 @@ __device__ inline void cm_collide(const NodeParams<T>& p, const NodeMetric<T>& g
     const T ih1m = g.ih1 - T(1), ih2m = g.ih2 - T(1);
     const T sa = T(2) * ih1m * F1 * U1, sb = T(2) * ih2m * F2 * U2;
     const T s11 = ih2m * F1 * U2 + ih1m * F2 * U1;
-    // relaxation (k00 kept: mass conserved to rounding)
+    // relaxation increments.  U carries the lagged force Fp, so the
+    // first-order equilibria e10 = -(h1 - 1) h2 rho U1, e01 = -(h2 - 1) h1 rho U2
+    // differ from k10, k01 by exactly Fp / 2: the identity is used instead of
+    // the difference, which would turn a rounding bias of U into a momentum
+    // source.
     const T* w = p.w;
     const T k2s = k20 + k02, k2d = k20 - k02;
-    const T t10 = k10 + w[1] * (e10 - k10) + (T(1) - T(0.5) * w[1]) * F1;
-    const T t01 = k01 + w[2] * (e01 - k01) + (T(1) - T(0.5) * w[2]) * F2;
-    const T t2s = k2s + w[3] * (e2s - k2s) + (T(1) - T(0.5) * w[3]) * (sa + sb);
-    const T t2d = k2d + w[4] * (e2d - k2d) + (T(1) - T(0.5) * w[4]) * (sa - sb);
-    const T t11 = k11 + w[5] * (e11 - k11) + (T(1) - T(0.5) * w[5]) * s11;
-    const T t21 = k21 + w[6] * (e21 - k21);
-    const T t12 = k12 + w[7] * (e12 - k12);
-    const T t22 = k22 + w[8] * (e22 - k22);
-    const T t20 = T(0.5) * (t2s + t2d), t02 = T(0.5) * (t2s - t2d);
-    const T T00 = c00, T20 = A + t20, T02 = Bm + t02;                 // full k~00, k~20, k~02
-    // step 4: raw-moment deviations from the central ones, F(-U)
-    const T n10 = t10 + U1 * T00;
-    const T n01 = t01 + U2 * T00;
-    const T n20 = t20 + T(2) * U1 * t10 + U11 * T00;
-    const T n02 = t02 + T(2) * U2 * t01 + U22 * T00;
-    const T n11 = t11 + U2 * t10 + U1 * t01 + U12 * T00;
-    const T n21 = t21 + T(2) * U1 * t11 + U11 * t01 + U2 * T20 + T(2) * U12 * t10 + U11 * U2 * T00;
-    const T n12 = t12 + T(2) * U2 * t11 + U22 * t10 + U1 * T02 + T(2) * U12 * t01 + U1 * U22 * T00;
-    const T n22 = t22 + T(2) * U1 * t12 + U11 * T02 + T(2) * U2 * t21 + T(4) * U12 * t11
-                + T(2) * U11 * U2 * t01 + U22 * T20 + T(2) * U1 * U22 * t10 + U11 * U22 * T00;
-    const T n00 = m.m00;
-    // step 5: populations, P^-1
-    dt[0] = n00 - n20 - n02 + n22;
+    const T d10 = T(0.5) * w[1] * Fp1 + (T(1) - T(0.5) * w[1]) * F1;
+    const T d01 = T(0.5) * w[2] * Fp2 + (T(1) - T(0.5) * w[2]) * F2;
+    const T d2s = w[3] * (e2s - k2s) + (T(1) - T(0.5) * w[3]) * (sa + sb);
+    const T d2d = w[4] * (e2d - k2d) + (T(1) - T(0.5) * w[4]) * (sa - sb);
+    const T d11 = w[5] * (e11 - k11) + (T(1) - T(0.5) * w[5]) * s11;
+    const T d21 = w[6] * (e21 - k21);
+    const T d12 = w[7] * (e12 - k12);
+    const T d22 = w[8] * (e22 - k22);
+    const T d20 = T(0.5) * (d2s + d2d), d02 = T(0.5) * (d2s - d2d);
+    // step 4: raw-moment increments, F(U) applied to dk (dk00 = 0)
+    const T n10 = d10, n01 = d01;
+    const T n20 = d20 + T(2) * U1 * d10;
+    const T n02 = d02 + T(2) * U2 * d01;
+    const T n11 = d11 + U2 * d10 + U1 * d01;
+    const T n21 = d21 + T(2) * U1 * d11 + U11 * d01 + U2 * d20 + T(2) * U12 * d10;
+    const T n12 = d12 + T(2) * U2 * d11 + U22 * d10 + U1 * d02 + T(2) * U12 * d01;
+    const T n22 = d22 + T(2) * U1 * d12 + U11 * d02 + T(2) * U2 * d21 + T(4) * U12 * d11
+                + T(2) * U11 * U2 * d01 + U22 * d20 + T(2) * U1 * U22 * d10;
+    // step 5: population increments P^-1 dn, added to the pre-collision
+    // deviations
     const T hx = T(0.5) * (n20 - n22), hy = T(0.5) * (n02 - n22);
     const T gx = T(0.5) * (n10 - n12), gy = T(0.5) * (n01 - n21);
-    dt[1] = hx + gx;
-    dt[3] = hx - gx;
-    dt[2] = hy + gy;
-    dt[4] = hy - gy;
     const T qa = T(0.25) * (n22 + n11), qb = T(0.25) * (n22 - n11);
     const T qc = T(0.25) * (n21 + n12), qd = T(0.25) * (n21 - n12);
-    dt[5] = qa + qc;
-    dt[6] = qb + qd;
-    dt[7] = qa - qc;
-    dt[8] = qb - qd;
+    dt[0] = f[0] + (n22 - n20 - n02);
+    dt[1] = f[1] + (hx + gx);
+    dt[3] = f[3] + (hx - gx);
+    dt[2] = f[2] + (hy + gy);
+    dt[4] = f[4] + (hy - gy);
+    dt[5] = f[5] + (qa + qc);
+    dt[6] = f[6] + (qb + qd);
+    dt[7] = f[7] + (qa - qc);
+    dt[8] = f[8] + (qb - qd);
 }
 
 // D2Q5 induction scheme of App. G on a straight grid (Y = 0: no source), in

@@ -96,24 +96,26 @@ __device__ inline void pull9(const RunDesc& d, const S* __restrict__ fin, const 
         f[a] = L.valid ? T(Store<S>::ld(base, pull_index(d, L, G, a), sinv[cls_(a)])) : T(0);
 }
 
-// Moments of a pulled row: rho = rho0 + dm00/(h1 h2),
-// U1 = (dm10 + F1/2)/(rho h2), U2 = (dm01 + F2/2)/(rho h1) with the lagged
-// effective force (App. E step 7).
+// Moments of a pulled row: the density deviation dr = rho - rho0 =
+// dm00/(h1 h2) (kept as a deviation, so FP32 does not round it against
+// rho0), U1 = (dm10 + F1/2)/(rho h2), U2 = (dm01 + F2/2)/(rho h1) with the
+// lagged effective force Fp (App. E step 7), which is returned too.
 template <class FT, class T>
 __device__ inline void row_moments(const RunDesc& d, const FT* __restrict__ Fin, const LaneCol& L, int r,
-                                   const T* f, T rho0, T ih1, T ih2, T& rho, T& U1, T& U2)
+                                   const T* f, T rho0, T ih1, T ih2, T& dr, T& U1, T& U2, T& Fp1, T& Fp2)
 {
     const T m00 = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
     const T m10 = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
     const T m01 = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
-    T Fp1 = T(0), Fp2 = T(0);
+    Fp1 = T(0);
+    Fp2 = T(0);
     if (L.valid) {
         const int64_t n = d.F_off + (int64_t)r * d.pitch + L.col;
         Fp1 = T(Fin[n]);
         Fp2 = T(Fin[n + d.plane]);
     }
-    rho = rho0 + m00 * ih1 * ih2;
-    const T irho = recip(rho);
+    dr = m00 * ih1 * ih2;
+    const T irho = recip_sum(rho0, dr);
     U1 = (m10 + T(0.5) * Fp1) * ih2 * irho;
     U2 = (m01 + T(0.5) * Fp2) * ih1 * irho;
 }
@@ -172,25 +174,29 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
     int y0, y1;
     seg_rows(d.ny, d.segs, seg, y0, y1);
 
-    // Window of row moments: rows j-2, j-1, j, j+1 (rho, U2) and row j (U1, f).
-    T wr[4] = {p.rho0, p.rho0, p.rho0, p.rho0}, wu[4] = {T(0), T(0), T(0), T(0)};
+    // Window of row moments: rows j-2, j-1, j, j+1 (rho - rho0, U2) and row
+    // j (U1, f).
+    T wr[4] = {T(0), T(0), T(0), T(0)}, wu[4] = {T(0), T(0), T(0), T(0)};
     T fc[kQ], fn[kQ];
     T U1c = T(0), U1n = T(0);
+    // lagged force of rows j and j+1: the first central moments relax by
+    // exactly half of it (see cm_collide)
+    T Fpc1, Fpc2, Fpn1 = T(0), Fpn2 = T(0);
     if (row_ok(d, y0 - 1)) {
         const int r = row_wrap(d, y0 - 1);
-        T ft[kQ], u1;
+        T ft[kQ], u1, q1, q2;
         pull9<S, T>(d, pl.fin, L, row_geo(d, r), sinv, ft);
-        row_moments<FT, T>(d, pl.Fin, L, r, ft, p.rho0, ih1, ih2_of(r), wr[1], u1, wu[1]);
+        row_moments<FT, T>(d, pl.Fin, L, r, ft, p.rho0, ih1, ih2_of(r), wr[1], u1, wu[1], q1, q2);
     }
     pull9<S, T>(d, pl.fin, L, row_geo(d, y0), sinv, fc);
-    row_moments<FT, T>(d, pl.Fin, L, y0, fc, p.rho0, ih1, ih2_of(y0), wr[2], U1c, wu[2]);
+    row_moments<FT, T>(d, pl.Fin, L, y0, fc, p.rho0, ih1, ih2_of(y0), wr[2], U1c, wu[2], Fpc1, Fpc2);
 
     const int64_t plane = d.plane;
     for (int j = y0; j < y1; ++j) {
         if (row_ok(d, j + 1)) {
             const int r = row_wrap(d, j + 1);
             pull9<S, T>(d, pl.fin, L, row_geo(d, r), sinv, fn);
-            row_moments<FT, T>(d, pl.Fin, L, r, fn, p.rho0, ih1, ih2_of(r), wr[3], U1n, wu[3]);
+            row_moments<FT, T>(d, pl.Fin, L, r, fn, p.rho0, ih1, ih2_of(r), wr[3], U1n, wu[3], Fpn1, Fpn2);
         }
         const double* rt = rowtab + j * kTab;
         NodeMetric<T> g;
@@ -203,9 +209,9 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
         // finite differences along xi2 (one-sided next to walls)
         T d2U2, d2r;
         if (d.bc_y != 0 && j == 0) {
-            T f2[kQ], r2, u12, u22;
+            T f2[kQ], r2, u12, u22, q1, q2;
             pull9<S, T>(d, pl.fin, L, row_geo(d, 2), sinv, f2);
-            row_moments<FT, T>(d, pl.Fin, L, 2, f2, p.rho0, ih1, ih2_of(2), r2, u12, u22);
+            row_moments<FT, T>(d, pl.Fin, L, 2, f2, p.rho0, ih1, ih2_of(2), r2, u12, u22, q1, q2);
             d2U2 = T(0.5) * (T(-3) * wu[2] + T(4) * wu[3] - u22);
             d2r = T(0.5) * (T(-3) * wr[2] + T(4) * wr[3] - r2);
         } else if (d.bc_y != 0 && j == d.ny - 1) {
@@ -216,18 +222,18 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
             d2r = T(0.5) * (wr[3] - wr[1]);
         }
         // finite differences along xi1 from neighbouring lanes
-        const T rho = wr[2], U2 = wu[2], U1 = U1c;
+        const T drho = wr[2], rho = p.rho0 + drho, U2 = wu[2], U1 = U1c;
         const int lm1 = max(lane - 1, 0), lp1 = min(lane + 1, kWave - 1);
         const int lm2 = max(lane - 2, 0), lp2 = min(lane + 2, kWave - 1);
         const T Um1 = shfl(U1, lm1), Up1 = shfl(U1, lp1), Um2 = shfl(U1, lm2), Up2 = shfl(U1, lp2);
-        const T rm1 = shfl(rho, lm1), rp1 = shfl(rho, lp1), rm2 = shfl(rho, lm2), rp2 = shfl(rho, lp2);
+        const T rm1 = shfl(drho, lm1), rp1 = shfl(drho, lp1), rm2 = shfl(drho, lm2), rp2 = shfl(drho, lp2);
         T d1U1, d1r;
         if (xwall_lo) {
             d1U1 = T(0.5) * (T(-3) * U1 + T(4) * Up1 - Up2);
-            d1r = T(0.5) * (T(-3) * rho + T(4) * rp1 - rp2);
+            d1r = T(0.5) * (T(-3) * drho + T(4) * rp1 - rp2);
         } else if (xwall_hi) {
             d1U1 = T(0.5) * (T(3) * U1 - T(4) * Um1 + Um2);
-            d1r = T(0.5) * (T(3) * rho - T(4) * rm1 + rm2);
+            d1r = T(0.5) * (T(3) * drho - T(4) * rm1 + rm2);
         } else {
             d1U1 = T(0.5) * (Up1 - Um1);
             d1r = T(0.5) * (rp1 - rm1);
@@ -254,8 +260,8 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
         }
 
         T F1, F2, n3, n4, dt[kQ];
-        force_and_corrections<T>(p, g, rho, U1, U2, d1U1, d2U2, d1r, d2r, Fx1, Fx2, F1, F2, n3, n4);
-        cm_collide<T>(p, g, raw_dev<T>(fc), rho, rho - p.rho0, U1, U2, F1, F2, n3, n4, dt);
+        force_and_corrections<T>(p, g, rho, drho, U1, U2, d1U1, d2U2, d1r, d2r, Fx1, Fx2, F1, F2, n3, n4);
+        cm_collide<T>(p, g, fc, raw_dev<T>(fc), rho, drho, U1, U2, Fpc1, Fpc2, F1, F2, n3, n4, dt);
 
         if (own) {
             // rest-state offsets of the interior axis slots (the reader is
@@ -316,6 +322,8 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
         wr[1] = wr[2]; wu[1] = wu[2];
         wr[2] = wr[3]; wu[2] = wu[3];
         U1c = U1n;
+        Fpc1 = Fpn1;
+        Fpc2 = Fpn2;
 #pragma unroll
         for (int a = 0; a < kQ; ++a) fc[a] = fn[a];
     }

@@ -128,6 +128,28 @@ def smooth_fields(nx: int, ny: int, seed: int, amp: float, rho0: float = 1.0, mo
     return rho0 * (1.0 + amp * r), amp * u, amp * v
 
 
+def hartmann_start(case: Case, nu: float, F1: float):
+    """Developed Hartmann flow as an initial state (rho, U1, U2) of shape
+    [ny, nx]: rho = rho0 and the closed-form velocity between the plates
+    (Sec. 8.4), u(y*) = U_r (cosh Ha - cosh(Ha y*)) / (Ha sinh Ha) with
+    U_r = H^2 F1 / (rho0 nu), half-height H = ny / 2 in lattice units of the
+    physical domain [0, ny], and y* in [-1, 1] the node's wall-normal
+    position on the tanh-clustered grid of Sec. 6.1 (node centres at
+    xi = j + 1/2): y* = tanh(beta (2 xi / ny - 1)) / tanh(beta).
+    nu and F1 are the run's lattice viscosity and body force."""
+    kind, beta = case.stretch_y
+    if kind not in ("tanh", "uniform"):
+        raise ValueError("hartmann_start needs a tanh or uniform wall-normal grid")
+    xi = (np.arange(case.ny) + 0.5) / case.ny
+    ys = np.tanh(beta * (2 * xi - 1)) / np.tanh(beta) if kind == "tanh" and beta > 0 else 2 * xi - 1
+    H = 0.5 * case.ny
+    Ur = H * H * F1 / (case.rho0 * nu)
+    Ha = case.Ha
+    u = Ur * (np.cosh(Ha) - np.cosh(Ha * ys)) / (Ha * np.sinh(Ha)) if Ha > 0 else 0.5 * Ur * (1 - ys * ys)
+    U1 = np.repeat(u[:, None], case.nx, axis=1)
+    return np.full((case.ny, case.nx), case.rho0), U1, np.zeros_like(U1)
+
+
 def sample_nodes(nx: int, ny: int, count: int, seed: int):
     """Seeded node sample that always includes the corners and wall rows."""
     rng = np.random.default_rng(seed)

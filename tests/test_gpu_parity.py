@@ -10,11 +10,10 @@ ulps of the largest population, in the field's units, times sqrt(N) --
 passes whatever its relative size: a field that is rounding noise on both
 sides (U2 of an x-homogeneous channel) is not a relative quantity.
 
-The induced field B1 of the MHD runs comes from the local current density
-of App. G, i.e. from the non-equilibrium first moment of the D2Q5
-populations; at 1000 steps from rest that moment is ~4e-3 of the stored
-advective populations, so FP32 storage resolves B1 to ~2e-5 only: the FP32
-MHD test holds B1 to 3e-5 and every other field to 1e-5.
+FP32 arithmetic keeps every field within 1e-5 after 1000 steps because the
+collision is evaluated as an increment of the pulled populations: the
+post-collision momentum is never rounded as a value of its own, which in
+FP32 would bias the slowly growing flow on every step.
 """
 import math
 
@@ -126,9 +125,9 @@ def test_cavity_fp64_ragged(oracle_lib, nx, ny):
 
 
 def test_cavity_fp32_1000_steps(oracle_lib):
-    """Cavity in FP32 (configuration 2 parameters on a 130x97 grid: tanh
-    beta = 2 on both axes, lid at Mach 0.1, Re scaled with the size) after
-    1000 steps within 1e-5."""
+    """Cavity in FP32 (the parameters of the 1024x1024 Re=1000 cavity on a
+    130x97 grid: tanh beta = 2 on both axes, lid at Mach 0.1, Re scaled with
+    the size) after 1000 steps within 1e-5."""
     case = W.cavity_1024().replace(name="cav32", nx=130, ny=97, Re=1000.0 * 130 / 1024)
     check(oracle_lib, case, 1000, 1e-5)
 
@@ -140,22 +139,21 @@ def test_mhd_fp64_ragged(oracle_lib):
 
 
 def test_mhd_fp32_1000_steps(oracle_lib):
-    """Coupled Hartmann flow in FP32 (configuration 3 parameters on a
-    reduced 200x96 grid) after 1000 steps within 1e-5."""
+    """Coupled Hartmann flow in FP32 (the parameters of the 4096x1024
+    Ha=100 channel on a reduced 200x96 grid) after 1000 steps within 1e-5."""
     case = W.hartmann_4096().replace(name="h32", nx=200, ny=96)
-    check(oracle_lib, case, 1000, 1e-5, field_tol={"B1": 3e-5})
+    check(oracle_lib, case, 1000, 1e-5)
 
 
-@pytest.mark.parametrize("storage,tol", [("f16dev", 1e-3), ("bf16dev", 1e-2)])
+@pytest.mark.parametrize("storage,tol", [("f16dev", 1e-3), ("bf16dev", 1e-3)])
 def test_mhd_16bit_storage(oracle_lib, storage, tol):
     """Deviation storage in 16 bits with FP32 arithmetic on the reduced
-    Hartmann flow after 1000 steps against the FP64 oracle.  FP16 meets
-    1e-3; BF16 (8 significand bits) is held to the 1e-2 it reaches."""
+    Hartmann flow after 1000 steps against the FP64 oracle, within 1e-3."""
     case = W.hartmann_4096().replace(name="h16", nx=200, ny=96, storage=storage)
     check(oracle_lib, case, 1000, tol)
 
 
-@pytest.mark.parametrize("storage,tol", [("f16dev", 1e-3), ("bf16dev", 1e-2)])
+@pytest.mark.parametrize("storage,tol", [("f16dev", 1e-3), ("bf16dev", 1e-3)])
 def test_cavity_16bit_storage(oracle_lib, storage, tol):
     case = W.cavity_1024().replace(name="cav16", nx=130, ny=97, Re=1000.0 * 130 / 1024, storage=storage)
     check(oracle_lib, case, 1000, tol)
