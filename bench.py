@@ -105,6 +105,39 @@ def copy_calibration(mib: int, reps: int):
                       "GB_s": round(8 * n / dt / 1e9, 1)}), flush=True)
 
 
+def storage_forms(steps: int):
+    """The 4096x1024 Ha=100 channel in plain FP32 and in the FP16 / BF16
+    deviation-storage forms on the same GPU, each started from the
+    closed-form developed Hartmann flow: throughput, bytes moved, and the
+    relative L2 difference of every field from the plain FP32 run after the
+    same number of steps."""
+    import numpy as np
+    from paper_2607_15362_amd import binding as B
+    from paper_2607_15362_amd import workloads as W
+    n = max(200, steps // 10)
+    forms, ref = {}, None
+    for st in ("f32", "f16dev", "bf16dev"):
+        c = W.hartmann_4096_precision(st) if st != "f32" else W.hartmann_4096()
+        r = B.Run(c)
+        dd = r.derived()
+        r.init(*W.hartmann_start(c, dd["nu"], dd["F1"], dd["eta"], dd["B0"]))
+        w, e = time_run(r, n, 100)
+        fl = r.fields()
+        forms[st] = {"workload": c.name, "steps": n + 100, "MLUPS": round(c.nx * c.ny * n / w / 1e6, 1),
+                     "GB_s": round(dd["bytes_per_node"] * c.nx * c.ny / (e / n) / 1e9, 1),
+                     "bytes_per_node": dd["bytes_per_node"]}
+        if ref is None:
+            ref = fl
+        else:
+            vel = np.linalg.norm(np.hypot(ref["U1"], ref["U2"]))
+            norms = {"rho": np.linalg.norm(ref["rho"]), "U1": np.linalg.norm(ref["U1"]), "U2": vel,
+                     "B1": np.linalg.norm(ref["B1"]), "B2": np.linalg.norm(ref["B2"])}
+            forms[st]["rel_l2_vs_f32"] = {k: float(f"{np.linalg.norm(fl[k] - ref[k]) / norms[k]:.3e}")
+                                          for k in norms}
+        r.close()
+    return forms
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,19 +201,7 @@ def main():
     run.close()
 
     if not args.no_forms:
-        forms = {}
-        for st in ("f32", "f16dev", "bf16dev"):
-            c = W.hartmann_4096_precision(st) if st != "f32" else W.hartmann_4096()
-            r = B.Run(c)
-            n = max(200, args.steps // 10)
-            w, e = time_run(r, n, 100)
-            dd = r.derived()
-            forms[st] = {"workload": c.name, "MLUPS": round(c.nx * c.ny * n / w / 1e6, 1),
-                         "GB_s": round(dd["bytes_per_node"] * c.nx * c.ny / (e / n) / 1e9, 1),
-                         "bytes_per_node": dd["bytes_per_node"]}
-            r.close()
-        out["forms"] = forms
-
+        out["forms"] = storage_forms(args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     print(json.dumps(out), flush=True)

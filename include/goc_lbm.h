@@ -62,7 +62,8 @@ typedef enum {
 typedef enum {
     GOC_FLOW_CHANNEL = 0,   /* body-force channel, Sec. 8.1: Re = U (H/2)/nu, tau given */
     GOC_FLOW_CAVITY = 1,    /* lid-driven cavity, Sec. 8.3: Re = U_lid L / nu,
-                               U_lid = u_lid, or Ma c_s when u_lid <= 0               */
+                               U_lid = u_lid, or Ma c_s when u_lid <= 0, then
+                               lowered so that tau <= tau_max when tau_max > 1/2  */
     GOC_FLOW_HARTMANN = 2,  /* MHD channel, Sec. 8.4: Re = U_c H / nu, H half-width,
                                U_c = Ma c_s lowered so that tau <= tau_max when
                                tau_max > 1/2; eta = nu / Pm                          */
@@ -119,7 +120,8 @@ typedef struct {
     int32_t flow;             /* goc_flow                                    */
     double Re, Ha, Pm, Ma;
     double tau;               /* channel / free flows: shear relaxation time */
-    double tau_max;           /* Hartmann: cap on the shear relaxation time  */
+    double tau_max;           /* Hartmann, cavity with u_lid <= 0: cap on the
+                                 shear relaxation time (<= 1/2: no cap)      */
     double u_lid;             /* cavity: lid (xi2 = ny wall) speed           */
     double rho0, mu_m;
     double F_ext[2];          /* free flows: body force                      */
@@ -130,7 +132,8 @@ typedef struct goc_lbm goc_lbm_t;
 /* Derive lattice parameters from physical ones (Sec. 3.2.1, Sec. 5,
    App. G, Sec. 8), for the given grid and metric: c_s^2 from the metric;
    channel: nu = c_s^2 (tau - 1/2), U = Re nu/(H/2), F = 2 nu U rho0/(H/2)^2
-   with H = ny; cavity: nu = U_lid nx / Re and grid->u_wall_hi = U_lid;
+   with H = ny; cavity: nu = U_lid nx / Re (U_lid reduced if tau would
+   exceed tau_max and u_lid <= 0) and grid->u_wall_hi = U_lid;
    Hartmann: U_c = Ma c_s (reduced if tau would exceed tau_max),
    nu = U_c (ny/2)/Re, eta = nu/Pm, B0 from Ha, F from the analytic
    centre-line speed; omega4 = omega5 from nu, the other rates 1.  Writes
@@ -153,6 +156,13 @@ int goc_lbm_create(goc_lbm_t **out, const goc_grid *grid, const goc_metric *metr
    re-initialises at rest. */
 int goc_lbm_init(goc_lbm_t *h, const double *rho, const double *u1, const double *u2,
                  int32_t on_device);
+
+/* As goc_lbm_init, with the magnetic field too: b1[ny*nx], b2 (FP64, same
+   memory space as rho) give B, so that g = g^eq(0)(B, U) of App. G.  b1 and
+   b2 must be given together, with rho, u1, u2, on an MHD run; both NULL is
+   goc_lbm_init.  GOC_EINVAL otherwise. */
+int goc_lbm_init_mhd(goc_lbm_t *h, const double *rho, const double *u1, const double *u2,
+                     const double *b1, const double *b2, int32_t on_device);
 
 /* Advance n >= 0 time steps (App. E steps 1-7 and App. G steps 1-6 per
    step, one fused kernel launch each).  Asynchronous on the stream unless

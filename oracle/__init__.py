@@ -49,7 +49,7 @@ def lib():
         _lib.oracle_step_sample.argtypes = [cfgp, P, P, P, C.POINTER(C.c_int32),
                                             C.POINTER(C.c_int32), C.c_int, P, P, P]
         _lib.oracle_fields.argtypes = [cfgp, P, P, P, P, P, P, P, P]
-        _lib.oracle_init.argtypes = [cfgp, P, P, P, P, P, P]
+        _lib.oracle_init.argtypes = [cfgp, P, P, P, P, P, P, P, P]
         _lib.oracle_collide_node.argtypes = [cfgp, P, P]
         _lib.oracle_moment_map.argtypes = [C.c_int, P, C.c_double, C.c_double, P]
         _lib.oracle_central_eq.argtypes = [cfgp] + [C.c_double] * 7 + [P, P]
@@ -141,6 +141,11 @@ def derive(case, h1, h2) -> Lattice:
     elif case.flow == "cavity":
         u_hi = case.u_lid if case.u_lid > 0 else case.Ma * np.sqrt(cs2)
         nu = u_hi * case.nx / case.Re
+        tmax = getattr(case, "tau_max", 0.0)
+        if case.u_lid <= 0 and tmax > 0 and params.viscosity_from_tau(cs2, tmax) < nu:
+            # reading: cap the shear relaxation time (Re = U_lid L / nu kept)
+            nu = params.viscosity_from_tau(cs2, tmax)
+            u_hi = nu * case.Re / case.nx
     elif case.flow == "hartmann":
         H = case.ny / 2.0
         Uc = case.Ma * np.sqrt(cs2)
@@ -224,16 +229,22 @@ class Model:
         return c
 
     # -- state --------------------------------------------------------------
-    def init(self, rho=None, U1=None, U2=None):
+    def init(self, rho=None, U1=None, U2=None, B1=None, B2=None):
+        """Initial state from node fields [ny][nx] (None: rho0, U = 0 and the
+        applied field B = (0, B0))."""
         ny, nx = self.ny, self.nx
         rho = np.full((ny, nx), self.lat.rho0) if rho is None else np.ascontiguousarray(rho, float)
         U1 = np.zeros((ny, nx)) if U1 is None else np.ascontiguousarray(U1, float)
         U2 = np.zeros((ny, nx)) if U2 is None else np.ascontiguousarray(U2, float)
+        if (B1 is None) != (B2 is None):
+            raise ValueError("give both B1 and B2 or neither")
+        Bp = [None, None] if B1 is None else [np.ascontiguousarray(B1, float), np.ascontiguousarray(B2, float)]
         self.f = np.zeros((9, ny, nx))
         self.F = np.zeros((2, ny, nx))
         self.g = np.zeros((10, ny, nx)) if self.lat.mhd else np.zeros((10, 1, 1))
-        lib().oracle_init(C.byref(self.cfg), _ptr(rho), _ptr(U1), _ptr(U2), _ptr(self.f),
-                          _ptr(self.F), _ptr(self.g))
+        lib().oracle_init(C.byref(self.cfg), _ptr(rho), _ptr(U1), _ptr(U2),
+                          None if Bp[0] is None else _ptr(Bp[0]), None if Bp[1] is None else _ptr(Bp[1]),
+                          _ptr(self.f), _ptr(self.F), _ptr(self.g))
         return self
 
     def set_state(self, f, F, g=None):

@@ -809,10 +809,11 @@ int oracle_fields(const OracleCfg *c, const double *f, const double *Fp, const d
 /* Initial state (App. C): f = P^-1 m^eq,eff(rho_i, U_i) with the raw-moment
    equilibria of Sec. 3 and the corrections of Sec. 5 (gradients of the
    initial fields by the same finite differences); g = g^eq(0)(B_i, U_i)
-   (App. G) with B_i = (0, B0); reading: the lagged force before the first
-   step is zero, so the first hydrodynamic fields equal the initial ones. */
+   (App. G) with B_i the given field, or (0, B0) when B1_i / B2_i are NULL;
+   reading: the lagged force before the first step is zero, so the first
+   hydrodynamic fields equal the initial ones. */
 int oracle_init(const OracleCfg *c, const double *rho_i, const double *U1_i, const double *U2_i,
-                double *f, double *Fp, double *g)
+                const double *B1_i, const double *B2_i, double *f, double *Fp, double *g)
 {
     const size_t N = (size_t)c->nx * c->ny;
     const int px = (c->bc_x == 0), py = (c->bc_y == 0);
@@ -856,7 +857,8 @@ int oracle_init(const OracleCfg *c, const double *rho_i, const double *U1_i, con
             Fp[n] = 0.0;
             Fp[N + n] = 0.0;
             if (c->mhd) {
-                const double U[2] = {u1, u2}, B[2] = {0.0, c->B0};
+                const double U[2] = {u1, u2};
+                const double B[2] = {B1_i ? B1_i[n] : 0.0, B2_i ? B2_i[n] : c->B0};
                 double geq[2][NM];
                 mie_geq0(c, &gm, U, B, geq);
                 for (int ci = 0; ci < 2; ++ci)

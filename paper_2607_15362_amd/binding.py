@@ -66,6 +66,7 @@ SIGNATURES = {
     "goc_lbm_create_batch": (C.c_int, [C.POINTER(VP), C.c_int32, C.POINTER(Grid), C.POINTER(Metric),
                                        C.POINTER(Params), C.c_int32, VP]),
     "goc_lbm_init": (C.c_int, [VP, VP, VP, VP, C.c_int32]),
+    "goc_lbm_init_mhd": (C.c_int, [VP, VP, VP, VP, VP, VP, C.c_int32]),
     "goc_lbm_step": (C.c_int, [VP, C.c_int64]),
     "goc_lbm_moments": (C.c_int, [VP, VP, VP, VP, C.c_int32]),
     "goc_lbm_moments_run": (C.c_int, [VP, C.c_int32, VP, VP, VP, C.c_int32]),
@@ -261,12 +262,16 @@ class Run:
             pass
 
     # ---- calls ---------------------------------------------------------
-    def init(self, rho=None, u1=None, u2=None):
+    def init(self, rho=None, u1=None, u2=None, b1=None, b2=None):
         if rho is None:
             _check(lib().goc_lbm_init(self.h, None, None, None, 0))
             return self
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (rho, u1, u2)]
-        _check(lib().goc_lbm_init(self.h, *[a.ctypes.data for a in arrs], 0))
+        if b1 is None and b2 is None:
+            _check(lib().goc_lbm_init(self.h, *[a.ctypes.data for a in arrs], 0))
+            return self
+        arrs += [np.ascontiguousarray(a, dtype=np.float64) for a in (b1, b2)]
+        _check(lib().goc_lbm_init_mhd(self.h, *[a.ctypes.data for a in arrs], 0))
         return self
 
     def step(self, n=1):

@@ -85,15 +85,17 @@ __device__ inline NodeM node_metric(const RunDesc& d, const Pools<S, FT>& pl, in
     return m;
 }
 
-// Initial state of App. C from node fields (rho, U1, U2), FP64 inputs
-// [ny][nx] (nullptr: rest state rho0, U = 0).  The deviation from the rest
+// Initial state of App. C from node fields (rho, U1, U2) and, for MHD runs,
+// (B1, B2), FP64 inputs [ny][nx] (nullptr: rest state rho0, U = 0, and the
+// applied field B = (0, B0)).  The deviation from the rest
 // state of the raw equilibria of Sec. 3 with the corrections of Sec. 5
 // (finite-difference gradients of the fields) is mapped through P^-1 and
-// scattered to the slots; D2Q5: g^eq(0) with B = (0, B0); lagged force zero.
+// scattered to the slots; D2Q5: g^eq(0) of App. G; lagged force zero.
 template <class S>
 __global__ void init_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename ForceOf<S>::type> pl,
                             const double* __restrict__ rho_in, const double* __restrict__ u1_in,
-                            const double* __restrict__ u2_in)
+                            const double* __restrict__ u2_in, const double* __restrict__ b1_in,
+                            const double* __restrict__ b2_in)
 {
     using T = typename ComputeOf<S>::type;
     using FT = typename ForceOf<S>::type;
@@ -168,7 +170,12 @@ __global__ void init_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, 
     pl.Fout[d.F_off + n] = FT(0);
     pl.Fout[d.F_off + n + d.plane] = FT(0);
     if (d.mhd) {
-        const T B[2] = {T(0), p.B0};
+        T dB[2] = {T(0), T(0)};   // deviation of B from the applied field (0, B0)
+        if (b1_in) {
+            dB[0] = T(b1_in[(int64_t)j * d.nx + i]);
+            dB[1] = T(b2_in[(int64_t)j * d.nx + i] - d.B0);
+        }
+        const T B[2] = {dB[0], p.B0 + dB[1]};
         const T U[2] = {U1, U2};
         const T sg = Store<S>::scaled ? T(d.scg) : T(1);
         for (int ci = 0; ci < 2; ++ci) {
@@ -176,8 +183,8 @@ __global__ void init_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, 
             const T A2 = U[1] * B[ci] - B[1] * U[ci];
             for (int a = 0; a < kM; ++a) {
                 const T W = a == 0 ? p.W0 : p.W1;
-                // g^eq(0) minus the rest state W h1 h2 B_rest (B = B_rest here)
-                const T dg = W * (T(ex_(a)) * g.h2 * A1 + T(ey_(a)) * g.h1 * A2) * p.inv_csm2;
+                // g^eq(0) minus the rest state W h1 h2 B_rest
+                const T dg = W * (g.h1 * g.h2 * dB[ci] + (T(ex_(a)) * g.h2 * A1 + T(ey_(a)) * g.h1 * A2) * p.inv_csm2);
                 Store<S>::st(pl.gout + d.g_off + ci * kM * d.plane, slot_index(d, i, j, a), dg, sg);
             }
         }
@@ -391,6 +398,13 @@ __global__ void diag_final_kernel(const double* __restrict__ part, int nparts, d
     }
     if (threadIdx.x == 0)
         for (int k = 0; k < kDiag; ++k) out[k] = sh[k][0];
+}
+
+// Step counter of the rounding draws: set, or advanced after a block of
+// steps (one thread; part of the captured step graphs).
+__global__ void counter_kernel(uint32_t* __restrict__ c, uint32_t v, int add)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) c[0] = add ? c[0] + v : v;
 }
 
 }  // namespace goc

@@ -96,23 +96,78 @@ struct Pools {
 };
 
 // ---------------------------------------------------------------------------
+// Unbiased rounding of the stored values.  In a nearly steady flow a stored
+// population changes by a fraction of its last place per step, so rounding
+// to nearest repeats the same error on every step and the conserved moments
+// drift linearly.  The writer therefore rounds base + increment
+// stochastically: the rounding error is dithered by a uniform draw of one
+// unit in the last place of the target format, which makes the expected
+// stored value exact and the accumulated error a random walk.  The draws
+// come from a counter-based hash of (node, population, step).
+
+// 32-bit integer finaliser (the published "lowbias32" constants).
+__host__ __device__ inline uint32_t mix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Uniform draw in [-1/2, 1/2) from the top 24 bits of r.
+__device__ inline float dither_u(uint32_t r) { return float(r >> 8) * 0x1p-24f - 0.5f; }
+
+// Power of two of the binade of x (0 for zero and subnormals).
+__device__ inline float binade(float x) { return __uint_as_float(__float_as_uint(x) & 0x7f800000u); }
+
+// a + b rounded stochastically to FP32: s = RN(a + b), e its exact
+// residual (TwoSum, for any magnitudes of a and b), then RN(s + e + u ulp(s))
+// lands on the upper neighbour with probability e / ulp(s).
+__device__ inline float sr_add(float a, float b, uint32_t r)
+{
+    const float s = a + b;
+    const float bb = s - a;
+    const float e = (a - (s - bb)) + (b - bb);
+    return s + __builtin_fmaf(dither_u(r), binade(s) * 0x1p-23f, e);
+}
+
+// x dithered by one unit in the last place of a narrower format, before
+// rounding to it: rel = 2^-(fraction bits), tiny = its smallest step.
+__device__ inline float dither_narrow(float x, uint32_t r, float rel, float tiny)
+{
+    return __builtin_fmaf(dither_u(r), fmaxf(binade(x) * rel, tiny), x);
+}
+
+// ---------------------------------------------------------------------------
 // Storage codecs: FP64 and FP32 store the deviation itself, the 16-bit forms
-// store s * deviation with one scale s per direction class.
+// store s * deviation with one scale s per direction class.  st_sr stores
+// base + inc with the unbiased rounding above (FP64: rounded to nearest).
 template <class S> struct Store;
 template <> struct Store<double> {
     static constexpr bool scaled = false;
     __device__ static double ld(const double* p, int64_t i, double) { return p[i]; }
     __device__ static void st(double* p, int64_t i, double v, double) { p[i] = v; }
+    __device__ static void st_sr(double* p, int64_t i, double b, double inc, double, uint32_t) { p[i] = b + inc; }
 };
 template <> struct Store<float> {
     static constexpr bool scaled = false;
     __device__ static float ld(const float* p, int64_t i, float) { return p[i]; }
     __device__ static void st(float* p, int64_t i, float v, float) { p[i] = v; }
+    __device__ static void st_sr(float* p, int64_t i, float b, float inc, float, uint32_t r)
+    {
+        p[i] = sr_add(b, inc, r);
+    }
 };
 template <> struct Store<__half> {
     static constexpr bool scaled = true;
     __device__ static float ld(const __half* p, int64_t i, float inv_s) { return __half2float(p[i]) * inv_s; }
     __device__ static void st(__half* p, int64_t i, float v, float s) { p[i] = __float2half_rn(v * s); }
+    __device__ static void st_sr(__half* p, int64_t i, float b, float inc, float s, uint32_t r)
+    {
+        p[i] = __float2half_rn(dither_narrow((b + inc) * s, r, 0x1p-10f, 0x1p-24f));
+    }
 };
 template <> struct Store<__hip_bfloat16> {
     static constexpr bool scaled = true;
@@ -120,6 +175,10 @@ template <> struct Store<__hip_bfloat16> {
         return __bfloat162float(p[i]) * inv_s;
     }
     __device__ static void st(__hip_bfloat16* p, int64_t i, float v, float s) { p[i] = __float2bfloat16(v * s); }
+    __device__ static void st_sr(__hip_bfloat16* p, int64_t i, float b, float inc, float s, uint32_t r)
+    {
+        p[i] = __float2bfloat16(dither_narrow((b + inc) * s, r, 0x1p-7f, 0.0f));
+    }
 };
 
 // Reciprocal: correctly rounded division for FP64; for FP32 the hardware
@@ -296,14 +355,14 @@ __device__ inline RawDev<T> raw_dev(const T* d)
 // to raw moments.  Every step is linear in the moments, so this equals the
 // transform chain of App. E; the rest-state moments (h1 h2 rho0, 0, 0,
 // (h2/h1) P0, (h1/h2) P0, 0, 0, 0, rho0 c_s^4) cancel analytically and each
-// population is rounded once, by the final addition.  Forming the raw
+// population is rounded once, by the writer's final addition.  Forming the raw
 // moments after collision as values of their own would round the slowly
 // growing momentum on every step, a bias that FP32 accumulates.
-// f: pre-collision deviations f - f^rest, m = their raw moments.
-// Output: the post-collision deviations dt = f~ - f^rest.
+// m: raw moments of the pre-collision deviations f - f^rest.
+// Output: the population increments inc = f~ - f, added by the writer.
 template <class T>
-__device__ inline void cm_collide(const NodeParams<T>& p, const NodeMetric<T>& g, const T* f, const RawDev<T>& m,
-                                  T rho, T drho, T U1, T U2, T Fp1, T Fp2, T F1, T F2, T n3, T n4, T* dt)
+__device__ inline void cm_collide(const NodeParams<T>& p, const NodeMetric<T>& g, const RawDev<T>& m,
+                                  T rho, T drho, T U1, T U2, T Fp1, T Fp2, T F1, T F2, T n3, T n4, T* inc)
 {
     const T h1 = g.h1, h2 = g.h2;
     const T r21 = h2 * g.ih1, r12 = h1 * g.ih2;
@@ -361,31 +420,30 @@ __device__ inline void cm_collide(const NodeParams<T>& p, const NodeMetric<T>& g
     const T n12 = d12 + T(2) * U2 * d11 + U22 * d10 + U1 * d02 + T(2) * U12 * d01;
     const T n22 = d22 + T(2) * U1 * d12 + U11 * d02 + T(2) * U2 * d21 + T(4) * U12 * d11
                 + T(2) * U11 * U2 * d01 + U22 * d20 + T(2) * U1 * U22 * d10;
-    // step 5: population increments P^-1 dn, added to the pre-collision
-    // deviations
+    // step 5: population increments P^-1 dn
     const T hx = T(0.5) * (n20 - n22), hy = T(0.5) * (n02 - n22);
     const T gx = T(0.5) * (n10 - n12), gy = T(0.5) * (n01 - n21);
     const T qa = T(0.25) * (n22 + n11), qb = T(0.25) * (n22 - n11);
     const T qc = T(0.25) * (n21 + n12), qd = T(0.25) * (n21 - n12);
-    dt[0] = f[0] + (n22 - n20 - n02);
-    dt[1] = f[1] + (hx + gx);
-    dt[3] = f[3] + (hx - gx);
-    dt[2] = f[2] + (hy + gy);
-    dt[4] = f[4] + (hy - gy);
-    dt[5] = f[5] + (qa + qc);
-    dt[6] = f[6] + (qb + qd);
-    dt[7] = f[7] + (qa - qc);
-    dt[8] = f[8] + (qb - qd);
+    inc[0] = n22 - n20 - n02;
+    inc[1] = hx + gx;
+    inc[3] = hx - gx;
+    inc[2] = hy + gy;
+    inc[4] = hy - gy;
+    inc[5] = qa + qc;
+    inc[6] = qb + qd;
+    inc[7] = qa - qc;
+    inc[8] = qb - qd;
 }
 
 // D2Q5 induction scheme of App. G on a straight grid (Y = 0: no source), in
 // deviation form: dg[c][a] = g_ca - W_a h1 h2 B_rest,c with B_rest = (0, B0).
 // Computes B, the local derivatives dB from the non-equilibrium first
-// moments, J3, the Lorentz force and (if dgt != nullptr) the post-collision
-// deviations.
+// moments, J3, the Lorentz force and (if dgi != nullptr) the collision
+// increments g~ - g.
 template <class T>
 __device__ inline void mie_node(const NodeParams<T>& p, const NodeMetric<T>& g, const T (*dg)[kM],
-                                T U1, T U2, T& B1, T& B2, T& FL1, T& FL2, T (*dgt)[kM])
+                                T U1, T U2, T& B1, T& B2, T& FL1, T& FL2, T (*dgi)[kM])
 {
     const T h1 = g.h1, h2 = g.h2, hh = h1 * h2, ihh = g.ih1 * g.ih2;
     T S[2];
@@ -413,7 +471,7 @@ __device__ inline void mie_node(const NodeParams<T>& p, const NodeMetric<T>& g, 
     const T J3 = p.inv_mu * ihh * (h2 * dB1[1] - h1 * dB2[0]);
     FL1 = -J3 * B2;
     FL2 = J3 * B1;
-    if (dgt == nullptr) return;
+    if (dgi == nullptr) return;
     const T itm = p.inv_tau_m, ics = p.inv_csm2;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -421,14 +479,17 @@ __device__ inline void mie_node(const NodeParams<T>& p, const NodeMetric<T>& g, 
         const T Lc2 = p.eta * ((hh - h1 * g.ih2) * dB2[i] + hh * h2 * g.th22 * B[i]);
         const T m1 = (L1eq[i] + Lc1) * ics, m2 = (L2eq[i] + Lc2) * ics;
         const T base = S[i];   // h1 h2 (B_i - B_rest,i)
-        const T e0 = p.W0 * base;
         const T e1 = p.W1 * (base + m1), e3 = p.W1 * (base - m1);
         const T e2 = p.W1 * (base + m2), e4 = p.W1 * (base - m2);
-        dgt[i][0] = dg[i][0] - (dg[i][0] - e0) * itm;
-        dgt[i][1] = dg[i][1] - (dg[i][1] - e1) * itm;
-        dgt[i][2] = dg[i][2] - (dg[i][2] - e2) * itm;
-        dgt[i][3] = dg[i][3] - (dg[i][3] - e3) * itm;
-        dgt[i][4] = dg[i][4] - (dg[i][4] - e4) * itm;
+        dgi[i][1] = (e1 - dg[i][1]) * itm;
+        dgi[i][2] = (e2 - dg[i][2]) * itm;
+        dgi[i][3] = (e3 - dg[i][3]) * itm;
+        dgi[i][4] = (e4 - dg[i][4]) * itm;
+        // sum of g^eq = sum of g = h1 h2 B_i: the rest population takes
+        // minus the other increments, so that B is conserved to the rounding
+        // of the increments rather than that of the (larger) equilibria,
+        // whose error would repeat on every step of a steady flow
+        dgi[i][0] = -((dgi[i][1] + dgi[i][3]) + (dgi[i][2] + dgi[i][4]));
     }
 }
 

@@ -174,6 +174,7 @@ struct goc_lbm {
     int diag_cap = 0;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int rows_per_seg = 0;
+    uint32_t* step_ctr = nullptr;   // device: index of the next step's rounding draws
 };
 
 namespace {
@@ -209,21 +210,30 @@ int dispatch(int storage, Fn&& fn)
     }
 }
 
-// Launch one time step of every run (input buffer h->cur).
-int launch_step(goc_lbm* h)
+// Launch one time step of every run (input buffer h->cur); k is the step's
+// offset from the device step counter.
+int launch_step(goc_lbm* h, int k)
 {
     return dispatch(h->storage, [&](auto tag) -> int {
         using S = decltype(tag);
         const auto pl = pools<S>(h, h->cur);
         if (h->any_mhd)
             hipLaunchKernelGGL((goc::step_kernel<S, true>), dim3(h->total_blocks), dim3(goc::kWave), 0,
-                               h->stream, h->runs_d, h->block_run_d, pl);
+                               h->stream, h->runs_d, h->block_run_d, pl, h->step_ctr, k);
         else
             hipLaunchKernelGGL((goc::step_kernel<S, false>), dim3(h->total_blocks), dim3(goc::kWave), 0,
-                               h->stream, h->runs_d, h->block_run_d, pl);
+                               h->stream, h->runs_d, h->block_run_d, pl, h->step_ctr, k);
         HIPOK(hipGetLastError());
         return GOC_OK;
     });
+}
+
+// Device step counter: set to v, or advanced by v.
+int counter_op(goc_lbm* h, uint32_t v, int add)
+{
+    hipLaunchKernelGGL(goc::counter_kernel, dim3(1), dim3(64), 0, h->stream, h->step_ctr, v, add);
+    HIPOK(hipGetLastError());
+    return GOC_OK;
 }
 
 int per_node_grid(const RunDesc& d, dim3& grid, dim3& block)
@@ -251,6 +261,7 @@ int free_all(goc_lbm* h)
     (void)hipFree(h->row_d);
     (void)hipFree(h->diag_part);
     (void)hipFree(h->diag_out);
+    (void)hipFree(h->step_ctr);
     return GOC_OK;
 }
 
@@ -469,6 +480,7 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
     if (hipMemcpy(h->runs_d, h->runs.data(), nruns * sizeof(RunDesc), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(h->block_run_d, block_run.data(), block_run.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(GOC_EDEVICE, "run table upload failed"));
+    if ((rc = dev_alloc((void**)&h->step_ctr, 4))) return bail(rc);
     // state pools
     for (int k = 0; k < 2; ++k) {
         if ((rc = dev_alloc(&h->f[k], f_elems * sb)) || (rc = dev_alloc(&h->F[k], F_elems * fb)))
@@ -506,7 +518,8 @@ struct DevBuf {
     }
 };
 
-int init_run(goc_lbm* h, int run, const double* rho, const double* u1, const double* u2)
+int init_run(goc_lbm* h, int run, const double* rho, const double* u1, const double* u2,
+             const double* b1 = nullptr, const double* b2 = nullptr)
 {
     const RunDesc& d = h->runs[run];
     dim3 grid, block;
@@ -515,7 +528,8 @@ int init_run(goc_lbm* h, int run, const double* rho, const double* u1, const dou
         using S = decltype(tag);
         // write into the current input buffer
         auto pl = pools<S>(h, 1 - h->cur);
-        hipLaunchKernelGGL(goc::init_kernel<S>, grid, block, 0, h->stream, h->runs_d, run, pl, rho, u1, u2);
+        hipLaunchKernelGGL(goc::init_kernel<S>, grid, block, 0, h->stream, h->runs_d, run, pl, rho, u1, u2,
+                           b1, b2);
         HIPOK(hipGetLastError());
         return GOC_OK;
     });
@@ -632,9 +646,10 @@ int capture_graph(goc_lbm* h, int parity)
     }
     int rc = GOC_OK;
     for (int s = 0; s < kGraphSteps && rc == GOC_OK; ++s) {
-        rc = launch_step(h);
+        rc = launch_step(h, s);
         h->cur ^= 1;
     }
+    if (rc == GOC_OK) rc = counter_op(h, kGraphSteps, 1);
     hipError_t e = hipStreamEndCapture(h->stream, &g);
     h->cur = saved;
     if (rc != GOC_OK) {
@@ -686,9 +701,13 @@ int goc_lbm_derive(goc_grid* grid, const goc_metric* metric, const goc_physics* 
     }
     case GOC_FLOW_CAVITY: {
         if (!(phys->Re > 0)) return fail(GOC_EINVAL, "cavity flow needs Re > 0");
-        const double ul = phys->u_lid > 0 ? phys->u_lid : phys->Ma * std::sqrt(cs2);
+        double ul = phys->u_lid > 0 ? phys->u_lid : phys->Ma * std::sqrt(cs2);
         if (!(ul > 0)) return fail(GOC_EINVAL, "cavity flow needs u_lid > 0 or Ma > 0");
         nu = ul * grid->nx / phys->Re;
+        if (!(phys->u_lid > 0) && phys->tau_max > 0.5 && nu > cs2 * (phys->tau_max - 0.5)) {
+            nu = cs2 * (phys->tau_max - 0.5);     // relaxation-time cap, Re kept
+            ul = nu * phys->Re / grid->nx;
+        }
         grid->u_wall_hi = ul;
         break;
     }
@@ -749,11 +768,15 @@ void goc_lbm_destroy(goc_lbm_t* h)
     delete h;
 }
 
-int goc_lbm_init(goc_lbm_t* h, const double* rho, const double* u1, const double* u2, int32_t on_device)
+int goc_lbm_init_mhd(goc_lbm_t* h, const double* rho, const double* u1, const double* u2, const double* b1,
+                     const double* b2, int32_t on_device)
 {
     if (!check_handle(h)) return GOC_EINVAL;
     const bool given = rho || u1 || u2;
     if (given && !(rho && u1 && u2)) return fail(GOC_EINVAL, "init needs all of rho, u1, u2 or none");
+    if ((b1 != nullptr) != (b2 != nullptr)) return fail(GOC_EINVAL, "init needs both of b1, b2 or neither");
+    if (b1 && !given) return fail(GOC_EINVAL, "b1, b2 need rho, u1, u2 too");
+    if (b1 && !h->runs[0].mhd) return fail(GOC_EINVAL, "b1, b2 given for a run without MHD");
     if (given && h->nruns != 1) return fail(GOC_EINVAL, "field initialisation is per single run");
     // write into the input buffer: kernels write to "out" of pools(1 - cur)
     if (!given) {
@@ -764,25 +787,30 @@ int goc_lbm_init(goc_lbm_t* h, const double* rho, const double* u1, const double
     } else {
         const RunDesc& d = h->runs[0];
         const size_t N = (size_t)d.nx * d.ny;
-        DevBuf br, b1, b2;
-        const double *rd = rho, *d1 = u1, *d2 = u2;
+        const double* src[5] = {rho, u1, u2, b1, b2};
+        const double* dev[5] = {rho, u1, u2, b1, b2};
+        DevBuf buf[5];
         if (!on_device) {
-            int rc;
-            if ((rc = br.alloc(N)) || (rc = b1.alloc(N)) || (rc = b2.alloc(N))) return rc;
-            HIPOK(hipMemcpyAsync(br.p, rho, N * 8, hipMemcpyHostToDevice, h->stream));
-            HIPOK(hipMemcpyAsync(b1.p, u1, N * 8, hipMemcpyHostToDevice, h->stream));
-            HIPOK(hipMemcpyAsync(b2.p, u2, N * 8, hipMemcpyHostToDevice, h->stream));
-            rd = br.p;
-            d1 = b1.p;
-            d2 = b2.p;
+            for (int k = 0; k < 5; ++k) {
+                if (!src[k]) continue;
+                if (int rc = buf[k].alloc(N)) return rc;
+                HIPOK(hipMemcpyAsync(buf[k].p, src[k], N * 8, hipMemcpyHostToDevice, h->stream));
+                dev[k] = buf[k].p;
+            }
         }
-        int rc = init_run(h, 0, rd, d1, d2);
+        int rc = init_run(h, 0, dev[0], dev[1], dev[2], dev[3], dev[4]);
         if (rc) return rc;
         HIPOK(hipStreamSynchronize(h->stream));
     }
     h->step = 0;
+    if (int rc = counter_op(h, 0, 0)) return rc;
     HIPOK(hipStreamSynchronize(h->stream));
     return GOC_OK;
+}
+
+int goc_lbm_init(goc_lbm_t* h, const double* rho, const double* u1, const double* u2, int32_t on_device)
+{
+    return goc_lbm_init_mhd(h, rho, u1, u2, nullptr, nullptr, on_device);
 }
 
 int goc_lbm_step(goc_lbm_t* h, int64_t n)
@@ -802,10 +830,16 @@ int goc_lbm_step(goc_lbm_t* h, int64_t n)
             HIPOK(hipGraphLaunch(h->graph[h->cur], h->stream));
             done += kGraphSteps;   // an even count: parity unchanged
         }
-        for (; done < chunk; ++done) {
-            int rc = launch_step(h);
+        while (done < chunk) {   // single launches, in pieces that keep k small
+            const int piece = (int)std::min<int64_t>(chunk - done, 4096);
+            for (int s = 0; s < piece; ++s) {
+                int rc = launch_step(h, s);
+                if (rc) return rc;
+                h->cur ^= 1;
+            }
+            int rc = counter_op(h, (uint32_t)piece, 1);
             if (rc) return rc;
-            h->cur ^= 1;
+            done += piece;
         }
         h->step += chunk;
         n -= chunk;
@@ -970,8 +1004,9 @@ int goc_lbm_set_state(goc_lbm_t* h, const void* buf, size_t bytes)
     if (hd.g_bytes)
         HIPOK(hipMemcpyAsync(h->g[h->cur], p + hd.f_bytes + hd.F_bytes, hd.g_bytes, hipMemcpyHostToDevice,
                              h->stream));
-    HIPOK(hipStreamSynchronize(h->stream));
     h->step = hd.step;
+    if (int rc = counter_op(h, (uint32_t)hd.step, 0)) return rc;
+    HIPOK(hipStreamSynchronize(h->stream));
     return GOC_OK;
 }
 

@@ -120,13 +120,19 @@ __device__ inline void row_moments(const RunDesc& d, const FT* __restrict__ Fin,
     U2 = (m01 + T(0.5) * Fp2) * ih1 * irho;
 }
 
+// Rounding draws of a node's populations: the node hash hn times distinct
+// odd multipliers (D2Q9 populations 0-8, then the ten D2Q5 populations).
+__device__ inline uint32_t pop_draw(uint32_t hn, int a) { return hn * (0x9E3779B1u * uint32_t(2 * a + 1)); }
+
 // One time step for every run of the launch.
 //   grid.x = total work-groups, block = 64 (one wave).
 //   block_run[b]: run of work-group b.
+//   step_ctr[0] + k: the step's index in the sequence of rounding draws.
 template <class S, bool MHD>
 __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__ runs,
                                                      const int32_t* __restrict__ block_run,
-                                                     Pools<S, typename ForceOf<S>::type> pl)
+                                                     Pools<S, typename ForceOf<S>::type> pl,
+                                                     const uint32_t* __restrict__ step_ctr, int k)
 {
     using T = typename ComputeOf<S>::type;
     using FT = typename ForceOf<S>::type;
@@ -137,6 +143,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
     const int seg = local / d.strips;
     const int lane = threadIdx.x;
     const NodeParams<T> p = node_params<T>(d);
+    const uint32_t seed = mix32(step_ctr[0] + uint32_t(k));
 
     // lane geometry and column metric
     const int lb = lane_base(d.nx, d.bc_x, strip);
@@ -241,11 +248,10 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
 
         // App. G: magnetic field, local derivatives, Lorentz force, collision
         T Fx1 = p.Fx1, Fx2 = p.Fx2;
-        T dgt[2][kM];
+        T dg[2][kM], dgi[2][kM];
         const bool mhd_run = MHD && d.mhd;   // a batch may mix MHD and plain runs
         const RowGeo Gj = row_geo(d, j);
         if (mhd_run) {
-            T dg[2][kM];
             const S* gb = pl.gin + d.g_off;
 #pragma unroll
             for (int ci = 0; ci < 2; ++ci)
@@ -254,44 +260,48 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
                     dg[ci][a] = L.valid ? T(Store<S>::ld(gb, ci * kM * plane + pull_index(d, L, Gj, a), sginv))
                                         : T(0);
             T B1, B2, FL1, FL2;
-            mie_node<T>(p, g, dg, U1, U2, B1, B2, FL1, FL2, dgt);
+            mie_node<T>(p, g, dg, U1, U2, B1, B2, FL1, FL2, dgi);
             Fx1 += FL1;
             Fx2 += FL2;
         }
 
-        T F1, F2, n3, n4, dt[kQ];
+        T F1, F2, n3, n4, inc[kQ];
         force_and_corrections<T>(p, g, rho, drho, U1, U2, d1U1, d2U2, d1r, d2r, Fx1, Fx2, F1, F2, n3, n4);
-        cm_collide<T>(p, g, fc, raw_dev<T>(fc), rho, drho, U1, U2, Fpc1, Fpc2, F1, F2, n3, n4, dt);
+        cm_collide<T>(p, g, raw_dev<T>(fc), rho, drho, U1, U2, Fpc1, Fpc2, F1, F2, n3, n4, inc);
 
         if (own) {
+            // inc holds the collision increments; the writer adds the
             // rest-state offsets of the interior axis slots (the reader is
             // the neighbour; its rest state differs through the metric)
             const T a2p = T(rt[T_AP]), a2m = T(rt[T_AM]);
-            dt[1] += g.h2 * a1p;
-            dt[3] += g.h2 * a1m;
-            dt[2] += g.h1 * a2p;
-            dt[4] += g.h1 * a2m;
+            inc[1] += g.h2 * a1p;
+            inc[3] += g.h2 * a1m;
+            inc[2] += g.h1 * a2p;
+            inc[4] += g.h1 * a2m;
             // writer-side momentum-augmented bounce-back of App. C for
             // populations leaving through a moving y-wall
             if (Gj.wp && d.uw_hi != 0.0) {
                 const T cw = rho * p.cs2 * T(d.uw_hi) / (T(2) * T(d.hw_hi));
                 // slot 5 is read back as f7, slot 6 as f8: f7 = ft5 - cw, f8 = ft6 + cw
-                if (d.lid_corners || !xwall_hi) dt[5] -= cw;
-                if (d.lid_corners || !xwall_lo) dt[6] += cw;
+                if (d.lid_corners || !xwall_hi) inc[5] -= cw;
+                if (d.lid_corners || !xwall_lo) inc[6] += cw;
             }
             if (Gj.wm && d.uw_lo != 0.0) {
                 const T cw = rho * p.cs2 * T(d.uw_lo) / (T(2) * T(d.hw_lo));
                 // slot 7 is read back as f5, slot 8 as f6: f5 = ft7 + cw, f6 = ft8 - cw
-                if (d.lid_corners || !xwall_lo) dt[7] += cw;
-                if (d.lid_corners || !xwall_hi) dt[8] -= cw;
+                if (d.lid_corners || !xwall_lo) inc[7] += cw;
+                if (d.lid_corners || !xwall_hi) inc[8] -= cw;
             }
             const int64_t nn = (int64_t)j * d.pitch + L.col;
+            const uint32_t hn = mix32(uint32_t(d.f_off + nn) ^ seed);
             S* fo = pl.fout + d.f_off + nn;
 #pragma unroll
-            for (int a = 0; a < kQ; ++a) Store<S>::st(fo, a * plane, dt[a], sfw[cls_(a)]);
+            for (int a = 0; a < kQ; ++a) Store<S>::st_sr(fo, a * plane, fc[a], inc[a], sfw[cls_(a)], pop_draw(hn, a));
             pl.Fout[d.F_off + nn] = FT(F1);
             pl.Fout[d.F_off + nn + plane] = FT(F2);
             if (mhd_run) {
+                // stored value = base + increment; anti-bounce-back slots
+                // negate the post-collision value
                 const T b2p = T(rt[T_BP]), b2m = T(rt[T_BM]);
                 const T hh = g.h1 * g.h2;
 #pragma unroll
@@ -304,17 +314,21 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
                         // -g~ + 2 W h_wall B_wall with B_wall = (0, B0)
                         const T hwall = wy ? g.h1 * T(ey < 0 ? d.hw_lo : d.hw_hi)
                                            : T(ex < 0 ? d.h1w_lo : d.h1w_hi) * g.h2;
-                        dgt[0][a] = -dgt[0][a];
-                        dgt[1][a] = -dgt[1][a] + T(2) * p.W1 * p.B0 * (hwall - hh);
+                        dg[0][a] = -dg[0][a];
+                        dgi[0][a] = -dgi[0][a];
+                        dg[1][a] = -dg[1][a];
+                        dgi[1][a] = -dgi[1][a] + T(2) * p.W1 * p.B0 * (hwall - hh);
                     } else {
-                        dgt[1][a] += a == 1 ? g.h2 * b1p : a == 3 ? g.h2 * b1m : a == 2 ? g.h1 * b2p : g.h1 * b2m;
+                        dgi[1][a] += a == 1 ? g.h2 * b1p : a == 3 ? g.h2 * b1m : a == 2 ? g.h1 * b2p : g.h1 * b2m;
                     }
                 }
                 S* go = pl.gout + d.g_off + nn;
 #pragma unroll
                 for (int ci = 0; ci < 2; ++ci)
 #pragma unroll
-                    for (int a = 0; a < kM; ++a) Store<S>::st(go, (ci * kM + a) * plane, dgt[ci][a], sgw);
+                    for (int a = 0; a < kM; ++a)
+                        Store<S>::st_sr(go, (ci * kM + a) * plane, dg[ci][a], dgi[ci][a], sgw,
+                                        pop_draw(hn, kQ + ci * kM + a));
             }
         }
         // shift the window
