@@ -29,12 +29,14 @@ __global__ void metric_kernel(const double* __restrict__ h, const double* __rest
     if (threadIdx.x == 0) block_min[blockIdx.x] = smin[0];
 }
 
-// Column (or row) tables in FP64 from h and theta along one axis:
+// Column (or row) tables in FP64 (and an FP32 copy) from h and theta along
+// one axis:
 // h, 1/h, theta, P0/2 (1/h(i) - 1/h(i+-1)), W1 B0 (h(i) - h(i+-1)); the
 // neighbour terms are zero where the neighbour lies beyond a wall (the slot
 // is then read back by the node itself) and wrap when periodic.
 __global__ void table_kernel(const double* __restrict__ h, const double* __restrict__ th, int n,
-                             int periodic, double P0, double W1B0, double* __restrict__ tab)
+                             int periodic, double P0, double W1B0, double* __restrict__ tab,
+                             float* __restrict__ tabf)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -50,6 +52,7 @@ __global__ void table_kernel(const double* __restrict__ h, const double* __restr
     t[T_BP] = hp ? W1B0 * (h[i] - h[ip]) : 0.0;
     t[T_BM] = hm ? W1B0 * (h[i] - h[im]) : 0.0;
     t[7] = 0.0;
+    for (int k = 0; k < kTab; ++k) tabf[(int64_t)i * kTab + k] = float(t[k]);
 }
 
 // Destination slot of population a arriving at node (i, j): the slot its

@@ -93,6 +93,8 @@ struct Pools {
     S* gout;
     const double* col;   // column tables
     const double* row;   // row tables
+    const float* colf;   // the same tables rounded to FP32
+    const float* rowf;
 };
 
 // ---------------------------------------------------------------------------
@@ -133,13 +135,6 @@ __device__ inline float sr_add(float a, float b, uint32_t r)
     return s + __builtin_fmaf(dither_u(r), binade(s) * 0x1p-23f, e);
 }
 
-// x dithered by one unit in the last place of a narrower format, before
-// rounding to it: rel = 2^-(fraction bits), tiny = its smallest step.
-__device__ inline float dither_narrow(float x, uint32_t r, float rel, float tiny)
-{
-    return __builtin_fmaf(dither_u(r), fmaxf(binade(x) * rel, tiny), x);
-}
-
 // ---------------------------------------------------------------------------
 // Storage codecs: FP64 and FP32 store the deviation itself, the 16-bit forms
 // store s * deviation with one scale s per direction class.  st_sr stores
@@ -147,12 +142,14 @@ __device__ inline float dither_narrow(float x, uint32_t r, float rel, float tiny
 template <class S> struct Store;
 template <> struct Store<double> {
     static constexpr bool scaled = false;
+    __device__ static double dec(double v, double) { return v; }
     __device__ static double ld(const double* p, int64_t i, double) { return p[i]; }
     __device__ static void st(double* p, int64_t i, double v, double) { p[i] = v; }
     __device__ static void st_sr(double* p, int64_t i, double b, double inc, double, uint32_t) { p[i] = b + inc; }
 };
 template <> struct Store<float> {
     static constexpr bool scaled = false;
+    __device__ static float dec(float v, float) { return v; }
     __device__ static float ld(const float* p, int64_t i, float) { return p[i]; }
     __device__ static void st(float* p, int64_t i, float v, float) { p[i] = v; }
     __device__ static void st_sr(float* p, int64_t i, float b, float inc, float, uint32_t r)
@@ -160,24 +157,35 @@ template <> struct Store<float> {
         p[i] = sr_add(b, inc, r);
     }
 };
+// The 16-bit stores use the stochastic-rounding conversions of gfx950
+// (v_cvt_sr_f16_f32 / v_cvt_sr_bf16_f32), which take the high 16 bits of
+// the draw as the dither.
+typedef __fp16 goc_f16x2 __attribute__((__vector_size__(2 * sizeof(__fp16))));
+typedef __bf16 goc_bf16x2 __attribute__((__vector_size__(2 * sizeof(__bf16))));
 template <> struct Store<__half> {
     static constexpr bool scaled = true;
+    __device__ static float dec(__half v, float inv_s) { return __half2float(v) * inv_s; }
     __device__ static float ld(const __half* p, int64_t i, float inv_s) { return __half2float(p[i]) * inv_s; }
     __device__ static void st(__half* p, int64_t i, float v, float s) { p[i] = __float2half_rn(v * s); }
     __device__ static void st_sr(__half* p, int64_t i, float b, float inc, float s, uint32_t r)
     {
-        p[i] = __float2half_rn(dither_narrow((b + inc) * s, r, 0x1p-10f, 0x1p-24f));
+        goc_f16x2 h = {};
+        h = __builtin_amdgcn_cvt_sr_f16_f32(h, (b + inc) * s, r, false);
+        reinterpret_cast<uint16_t*>(p)[i] = uint16_t(__builtin_bit_cast(uint32_t, h));
     }
 };
 template <> struct Store<__hip_bfloat16> {
     static constexpr bool scaled = true;
+    __device__ static float dec(__hip_bfloat16 v, float inv_s) { return __bfloat162float(v) * inv_s; }
     __device__ static float ld(const __hip_bfloat16* p, int64_t i, float inv_s) {
         return __bfloat162float(p[i]) * inv_s;
     }
     __device__ static void st(__hip_bfloat16* p, int64_t i, float v, float s) { p[i] = __float2bfloat16(v * s); }
     __device__ static void st_sr(__hip_bfloat16* p, int64_t i, float b, float inc, float s, uint32_t r)
     {
-        p[i] = __float2bfloat16(dither_narrow((b + inc) * s, r, 0x1p-7f, 0.0f));
+        goc_bf16x2 h = {};
+        h = __builtin_amdgcn_cvt_sr_bf16_f32(h, (b + inc) * s, r, false);
+        reinterpret_cast<uint16_t*>(p)[i] = uint16_t(__builtin_bit_cast(uint32_t, h));
     }
 };
 

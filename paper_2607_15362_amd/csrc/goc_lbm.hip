@@ -162,6 +162,7 @@ struct goc_lbm {
     int total_blocks = 0;
     double *h1_d = nullptr, *th11_d = nullptr, *h2_d = nullptr, *th22_d = nullptr;
     double *col_d = nullptr, *row_d = nullptr;   // per-column / per-row tables
+    float *colf_d = nullptr, *rowf_d = nullptr;   // their FP32 copies
     void* f[2] = {nullptr, nullptr};
     void* F[2] = {nullptr, nullptr};
     void* g[2] = {nullptr, nullptr};
@@ -195,6 +196,8 @@ PoolsOf<S> pools(const goc_lbm* h, int in)
     p.gout = static_cast<S*>(h->g[1 - in]);
     p.col = h->col_d;
     p.row = h->row_d;
+    p.colf = h->colf_d;
+    p.rowf = h->rowf_d;
     return p;
 }
 
@@ -259,6 +262,8 @@ int free_all(goc_lbm* h)
     (void)hipFree(h->th22_d);
     (void)hipFree(h->col_d);
     (void)hipFree(h->row_d);
+    (void)hipFree(h->colf_d);
+    (void)hipFree(h->rowf_d);
     (void)hipFree(h->diag_part);
     (void)hipFree(h->diag_out);
     (void)hipFree(h->step_ctr);
@@ -409,7 +414,9 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
         (rc = dev_alloc((void**)&h->h2_d, sum_ny * 8)) || (rc = dev_alloc((void**)&h->th22_d, sum_ny * 8)) ||
         (rc = dev_alloc((void**)&dh1_d, sum_nx * 8)) || (rc = dev_alloc((void**)&dh2_d, sum_ny * 8)) ||
         (rc = dev_alloc((void**)&h->col_d, sum_nx * goc::kTab * 8)) ||
-        (rc = dev_alloc((void**)&h->row_d, sum_ny * goc::kTab * 8)))
+        (rc = dev_alloc((void**)&h->row_d, sum_ny * goc::kTab * 8)) ||
+        (rc = dev_alloc((void**)&h->colf_d, sum_nx * goc::kTab * 4)) ||
+        (rc = dev_alloc((void**)&h->rowf_d, sum_ny * goc::kTab * 4)))
         return bail(rc);
     auto cleanup_tmp = [&]() { (void)hipFree(dh1_d); (void)hipFree(dh2_d); (void)hipFree(bmin_d); };
     if (hipMemcpy(h->h1_d, h1.data(), sum_nx * 8, hipMemcpyHostToDevice) != hipSuccess ||
@@ -453,14 +460,14 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
         for (int k = 0; k < 4; ++k) d.sc[k] = 1.0 / std::max(mag[k] * 0.1, 1e-300);
         // D2Q5 deviations scale like h U B0 with U ~ Ma c_s
         d.scg = 1.0 / std::max(0.01 * std::fabs(d.B0) * std::sqrt(c2), 1e-12);
-        // column / row tables (FP64, on the device)
+        // column / row tables (FP64 and an FP32 copy, on the device)
         const double P0 = d.rho0 * d.cs2, W1B0 = 0.5 * d.csm2 * d.B0;
         hipLaunchKernelGGL(goc::table_kernel, dim3(nbx), dim3(256), 0, h->stream, h->h1_d + d.col_off,
                            h->th11_d + d.col_off, d.nx, d.bc_x == 0 ? 1 : 0, P0, W1B0,
-                           h->col_d + d.col_off * goc::kTab);
+                           h->col_d + d.col_off * goc::kTab, h->colf_d + d.col_off * goc::kTab);
         hipLaunchKernelGGL(goc::table_kernel, dim3(nby), dim3(256), 0, h->stream, h->h2_d + d.row_off,
                            h->th22_d + d.row_off, d.ny, d.bc_y == 0 ? 1 : 0, P0, W1B0,
-                           h->row_d + d.row_off * goc::kTab);
+                           h->row_d + d.row_off * goc::kTab, h->rowf_d + d.row_off * goc::kTab);
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess) {
             cleanup_tmp();
             return bail(fail(GOC_EDEVICE, "metric tables failed"));

@@ -124,10 +124,126 @@ __device__ inline void row_moments(const RunDesc& d, const FT* __restrict__ Fin,
 // odd multipliers (D2Q9 populations 0-8, then the ten D2Q5 populations).
 __device__ inline uint32_t pop_draw(uint32_t hn, int a) { return hn * (0x9E3779B1u * uint32_t(2 * a + 1)); }
 
+// Metric table of the compute type: the FP64 tables for FP64 arithmetic,
+// their FP32 copy otherwise.
+template <class T> __device__ inline const T* table_of(const double* d, const float* f);
+template <> __device__ inline const double* table_of<double>(const double* d, const float*) { return d; }
+template <> __device__ inline const float* table_of<float>(const double*, const float* f) { return f; }
+
+// Whole-wave lane shifts (DPP wave_shr:1 / wave_shl:1): lane i receives the
+// value of lane i - 1 / i + 1, and the edge lane keeps its own.
+__device__ inline int dpp_prev(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false); }
+__device__ inline int dpp_next(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
+__device__ inline float from_prev(float v) { return __int_as_float(dpp_prev(__float_as_int(v))); }
+__device__ inline float from_next(float v) { return __int_as_float(dpp_next(__float_as_int(v))); }
+__device__ inline double from_prev(double v)
+{
+    const int lo = dpp_prev(__double2loint(v)), hi = dpp_prev(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+__device__ inline double from_next(double v)
+{
+    const int lo = dpp_next(__double2loint(v)), hi = dpp_next(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// State of one pulled row in the marching window: the raw slots (storage
+// type, possibly still in flight), the decoded deviations and the moments.
+template <class S, class T, class FT>
+struct RowSlot {
+    S raw[kQ];
+    FT Fr[2];       // lagged force F^(n-1)
+    S graw[2][kM];  // D2Q5 slots of the row (MHD)
+    T f[kQ];
+    T dr, U1, U2, Fp1, Fp2;
+};
+
+// Issue the loads of the nine slots pulled into row r (and its lagged
+// force).  Interior rows (0 < r < ny - 1): every direction's source row is
+// uniform, so the address is a per-(plane, row) base plus the lane's
+// constant offset off[a].  Rows 0 and ny - 1 (walls or periodic wrap) take
+// the general index.
+template <class S, class FT>
+__device__ inline void issue_row(const RunDesc& d, const S* __restrict__ fin, const FT* __restrict__ Fin,
+                                 const LaneCol& Ls, const int32_t* off, int r, S* raw, FT* Fr)
+{
+    const S* fb = fin + d.f_off;
+    if (r > 0 && r < d.ny - 1) {
+#pragma unroll
+        for (int a = 0; a < kQ; ++a)
+            raw[a] = (fb + (int64_t)a * d.plane + (int64_t)(r - ey_(a)) * d.pitch)[off[a]];
+    } else {
+        const RowGeo G = row_geo(d, r);
+#pragma unroll
+        for (int a = 0; a < kQ; ++a) raw[a] = fb[pull_index(d, Ls, G, a)];
+    }
+    const FT* Fb = Fin + d.F_off + (int64_t)r * d.pitch;
+    Fr[0] = Fb[Ls.col];
+    Fr[1] = Fb[Ls.col + d.plane];
+}
+
+// The same for the ten D2Q5 slots of row r.
+template <class S>
+__device__ inline void issue_row_g(const RunDesc& d, const S* __restrict__ gin, const LaneCol& Ls,
+                                   const int32_t* off, int r, S (*graw)[kM])
+{
+    const S* gb = gin + d.g_off;
+    if (r > 0 && r < d.ny - 1) {
+#pragma unroll
+        for (int ci = 0; ci < 2; ++ci)
+#pragma unroll
+            for (int a = 0; a < kM; ++a)
+                graw[ci][a] = (gb + (int64_t)(ci * kM + a) * d.plane + (int64_t)(r - ey_(a)) * d.pitch)[off[a]];
+    } else {
+        const RowGeo G = row_geo(d, r);
+#pragma unroll
+        for (int ci = 0; ci < 2; ++ci)
+#pragma unroll
+            for (int a = 0; a < kM; ++a) graw[ci][a] = gb[(int64_t)ci * kM * d.plane + pull_index(d, Ls, G, a)];
+    }
+}
+
+// Decode a pulled row and form its moments: dr = rho - rho0 = dm00/(h1 h2),
+// U1 = (dm10 + F1/2)/(rho h2), U2 = (dm01 + F2/2)/(rho h1) with the lagged
+// effective force (App. E step 7).
+template <class S, class T, class FT>
+__device__ inline void decode_row(RowSlot<S, T, FT>& R, const T* sinv, T rho0, T ih1, T ih2)
+{
+#pragma unroll
+    for (int a = 0; a < kQ; ++a) R.f[a] = Store<S>::dec(R.raw[a], sinv[cls_(a)]);
+    const T* f = R.f;
+    const T m00 = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    const T m10 = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
+    const T m01 = (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
+    R.Fp1 = T(R.Fr[0]);
+    R.Fp2 = T(R.Fr[1]);
+    R.dr = m00 * ih1 * ih2;
+    const T irho = recip_sum(rho0, R.dr);
+    R.U1 = (m10 + T(0.5) * R.Fp1) * ih2 * irho;
+    R.U2 = (m01 + T(0.5) * R.Fp2) * ih1 * irho;
+}
+
+// Work-group -> (strip, segment) of its run.  The hardware deals
+// consecutive work-groups to the eight XCDs in turn; the tiles are renumbered
+// so that each XCD gets a contiguous band (segment-major), whose halo rows
+// and columns its L2 then shares.
+__device__ inline void tile_of(const RunDesc& d, int local, int& strip, int& seg)
+{
+    const int B = d.strips * d.segs;
+    const int x = local & 7, idx = local >> 3;
+    const int q = B >> 3, rem = B & 7;
+    const int t = x * q + min(x, rem) + idx;
+    seg = t / d.strips;
+    strip = t - seg * d.strips;
+}
+
 // One time step for every run of the launch.
 //   grid.x = total work-groups, block = 64 (one wave).
 //   block_run[b]: run of work-group b.
 //   step_ctr[0] + k: the step's index in the sequence of rounding draws.
+// A wave owns 62 columns (lanes 1..62; lanes 0 and 63 are the x-halo) and a
+// segment of rows, and marches up the rows with three row slots (rows j-1,
+// j, j+1); the loads of row j+2 are in flight while row j is collided.
 template <class S, bool MHD>
 __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__ runs,
                                                      const int32_t* __restrict__ block_run,
@@ -136,150 +252,166 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
 {
     using T = typename ComputeOf<S>::type;
     using FT = typename ForceOf<S>::type;
+    using Slot = RowSlot<S, T, FT>;
     const int run = block_run[blockIdx.x];
     const RunDesc& d = runs[run];
-    const int local = blockIdx.x - d.first_block;
-    const int strip = local % d.strips;
-    const int seg = local / d.strips;
+    int strip, seg;
+    tile_of(d, blockIdx.x - d.first_block, strip, seg);
     const int lane = threadIdx.x;
     const NodeParams<T> p = node_params<T>(d);
     const uint32_t seed = mix32(step_ctr[0] + uint32_t(k));
+    const bool mhd_run = MHD && d.mhd;   // a batch may mix MHD and plain runs
 
     // lane geometry and column metric
     const int lb = lane_base(d.nx, d.bc_x, strip);
     const int craw = lb + lane;
     const LaneCol L = lane_col(d, craw);
+    LaneCol Ls = L;   // the same with in-grid columns for the loads of lanes beyond an x-wall
+    if (!L.valid) {
+        Ls.col = min(max(craw, 0), d.nx - 1);
+        Ls.cm = Ls.cp = Ls.col;
+        Ls.wm = Ls.wp = false;
+    }
     const int x0 = strip * kOwn;
     const int x1 = min(x0 + kOwn, d.nx);
     const bool own = lane >= 1 && lane <= kWave - 2 && craw >= x0 && craw < x1;
     const bool xwall_lo = d.bc_x != 0 && L.col == 0;
     const bool xwall_hi = d.bc_x != 0 && L.col == d.nx - 1;
-    T h1 = T(1), ih1 = T(1), th11 = T(0), a1p = T(0), a1m = T(0), b1p = T(0), b1m = T(0);
-    if (L.valid) {
-        const double* ct = pl.col + (d.col_off + L.col) * kTab;
-        h1 = T(ct[T_H]);
-        ih1 = T(ct[T_IH]);
-        th11 = T(ct[T_TH]);
-        a1p = T(ct[T_AP]);
-        a1m = T(ct[T_AM]);
-        b1p = T(ct[T_BP]);
-        b1m = T(ct[T_BM]);
+    const T* ctab = table_of<T>(pl.col, pl.colf) + (int64_t)(d.col_off + Ls.col) * kTab;
+    const T* rtab = table_of<T>(pl.row, pl.rowf) + (int64_t)d.row_off * kTab;
+    const T h1 = ctab[T_H], ih1 = ctab[T_IH], th11 = ctab[T_TH];
+    const T a1p = ctab[T_AP], a1m = ctab[T_AM], b1p = ctab[T_BP], b1m = ctab[T_BM];
+    // per-lane pull offsets of interior rows, relative to the (plane a,
+    // row r - ey) base: the source column, or through an x-wall the lane's
+    // own node in the opposite plane
+    int32_t off[kQ];
+#pragma unroll
+    for (int a = 0; a < kQ; ++a) {
+        const int ex = ex_(a), ey = ey_(a);
+        if (ex == 0) {
+            off[a] = Ls.col;
+        } else {
+            const bool wx = ex > 0 ? Ls.wm : Ls.wp;
+            off[a] = wx ? (opp_(a) - a) * (int32_t)d.plane + ey * d.pitch + Ls.col : (ex > 0 ? Ls.cm : Ls.cp);
+        }
     }
     T sinv[4], sfw[4], sginv = T(1), sgw = T(1);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        sinv[k] = Store<S>::scaled ? T(1.0 / d.sc[k]) : T(1);
-        sfw[k] = Store<S>::scaled ? T(d.sc[k]) : T(1);
+    for (int c = 0; c < 4; ++c) {
+        sinv[c] = Store<S>::scaled ? T(1.0 / d.sc[c]) : T(1);
+        sfw[c] = Store<S>::scaled ? T(d.sc[c]) : T(1);
     }
     if (Store<S>::scaled) {
         sginv = T(1.0 / d.scg);
         sgw = T(d.scg);
     }
-    const double* rowtab = pl.row + d.row_off * kTab;
-    auto ih2_of = [&](int r) { return T(rowtab[r * kTab + T_IH]); };
+    auto ih2_of = [&](int r) { return rtab[(int64_t)r * kTab + T_IH]; };
 
     int y0, y1;
     seg_rows(d.ny, d.segs, seg, y0, y1);
 
-    // Window of row moments: rows j-2, j-1, j, j+1 (rho - rho0, U2) and row
-    // j (U1, f).
-    T wr[4] = {T(0), T(0), T(0), T(0)}, wu[4] = {T(0), T(0), T(0), T(0)};
-    T fc[kQ], fn[kQ];
-    T U1c = T(0), U1n = T(0);
-    // lagged force of rows j and j+1: the first central moments relax by
-    // exactly half of it (see cm_collide)
-    T Fpc1, Fpc2, Fpn1 = T(0), Fpn2 = T(0);
+    // window: A = row y0 - 1, B = row y0, C = row y0 + 1 (loads in flight)
+    Slot A, B, C;
+    A.dr = A.U2 = T(0);
     if (row_ok(d, y0 - 1)) {
         const int r = row_wrap(d, y0 - 1);
-        T ft[kQ], u1, q1, q2;
-        pull9<S, T>(d, pl.fin, L, row_geo(d, r), sinv, ft);
-        row_moments<FT, T>(d, pl.Fin, L, r, ft, p.rho0, ih1, ih2_of(r), wr[1], u1, wu[1], q1, q2);
+        issue_row<S, FT>(d, pl.fin, pl.Fin, Ls, off, r, A.raw, A.Fr);
+        decode_row<S, T, FT>(A, sinv, p.rho0, ih1, ih2_of(r));
     }
-    pull9<S, T>(d, pl.fin, L, row_geo(d, y0), sinv, fc);
-    row_moments<FT, T>(d, pl.Fin, L, y0, fc, p.rho0, ih1, ih2_of(y0), wr[2], U1c, wu[2], Fpc1, Fpc2);
+    issue_row<S, FT>(d, pl.fin, pl.Fin, Ls, off, y0, B.raw, B.Fr);
+    if (mhd_run) issue_row_g<S>(d, pl.gin, Ls, off, y0, B.graw);
+    if (row_ok(d, y0 + 1)) issue_row<S, FT>(d, pl.fin, pl.Fin, Ls, off, row_wrap(d, y0 + 1), C.raw, C.Fr);
+    decode_row<S, T, FT>(B, sinv, p.rho0, ih1, ih2_of(y0));
 
     const int64_t plane = d.plane;
-    for (int j = y0; j < y1; ++j) {
-        if (row_ok(d, j + 1)) {
-            const int r = row_wrap(d, j + 1);
-            pull9<S, T>(d, pl.fin, L, row_geo(d, r), sinv, fn);
-            row_moments<FT, T>(d, pl.Fin, L, r, fn, p.rho0, ih1, ih2_of(r), wr[3], U1n, wu[3], Fpn1, Fpn2);
-        }
-        const double* rt = rowtab + j * kTab;
+    // one row: P = row j - 1, Cs = row j, N = row j + 1
+    auto row_step = [&](Slot& P, Slot& Cs, Slot& N, int j) {
+        // 1. loads of row j + 2 (into P, whose populations are done) and the
+        //    D2Q5 slots of row j + 1
+        const bool have_next = row_ok(d, j + 1);
+        const bool load2 = j + 2 <= y1 && row_ok(d, j + 2);
+        if (load2) issue_row<S, FT>(d, pl.fin, pl.Fin, Ls, off, row_wrap(d, j + 2), P.raw, P.Fr);
+        if (mhd_run && j + 1 < y1) issue_row_g<S>(d, pl.gin, Ls, off, row_wrap(d, j + 1), N.graw);
+        // 2. moments of row j + 1
+        if (have_next) decode_row<S, T, FT>(N, sinv, p.rho0, ih1, ih2_of(row_wrap(d, j + 1)));
+
         NodeMetric<T> g;
         g.h1 = h1;
         g.ih1 = ih1;
         g.th11 = th11;
-        g.h2 = T(rt[T_H]);
-        g.ih2 = T(rt[T_IH]);
-        g.th22 = T(rt[T_TH]);
-        // finite differences along xi2 (one-sided next to walls)
+        const T* rt = rtab + (int64_t)j * kTab;
+        g.h2 = rt[T_H];
+        g.ih2 = rt[T_IH];
+        g.th22 = rt[T_TH];
+        // 3. differences along xi2 (one-sided next to walls)
         T d2U2, d2r;
         if (d.bc_y != 0 && j == 0) {
-            T f2[kQ], r2, u12, u22, q1, q2;
-            pull9<S, T>(d, pl.fin, L, row_geo(d, 2), sinv, f2);
-            row_moments<FT, T>(d, pl.Fin, L, 2, f2, p.rho0, ih1, ih2_of(2), r2, u12, u22, q1, q2);
-            d2U2 = T(0.5) * (T(-3) * wu[2] + T(4) * wu[3] - u22);
-            d2r = T(0.5) * (T(-3) * wr[2] + T(4) * wr[3] - r2);
+            Slot W;
+            issue_row<S, FT>(d, pl.fin, pl.Fin, Ls, off, 2, W.raw, W.Fr);
+            decode_row<S, T, FT>(W, sinv, p.rho0, ih1, ih2_of(2));
+            d2U2 = T(0.5) * (T(-3) * Cs.U2 + T(4) * N.U2 - W.U2);
+            d2r = T(0.5) * (T(-3) * Cs.dr + T(4) * N.dr - W.dr);
         } else if (d.bc_y != 0 && j == d.ny - 1) {
-            d2U2 = T(0.5) * (T(3) * wu[2] - T(4) * wu[1] + wu[0]);
-            d2r = T(0.5) * (T(3) * wr[2] - T(4) * wr[1] + wr[0]);
+            Slot W;
+            issue_row<S, FT>(d, pl.fin, pl.Fin, Ls, off, j - 2, W.raw, W.Fr);
+            decode_row<S, T, FT>(W, sinv, p.rho0, ih1, ih2_of(j - 2));
+            d2U2 = T(0.5) * (T(3) * Cs.U2 - T(4) * P.U2 + W.U2);
+            d2r = T(0.5) * (T(3) * Cs.dr - T(4) * P.dr + W.dr);
         } else {
-            d2U2 = T(0.5) * (wu[3] - wu[1]);
-            d2r = T(0.5) * (wr[3] - wr[1]);
+            d2U2 = T(0.5) * (N.U2 - P.U2);
+            d2r = T(0.5) * (N.dr - P.dr);
         }
-        // finite differences along xi1 from neighbouring lanes
-        const T drho = wr[2], rho = p.rho0 + drho, U2 = wu[2], U1 = U1c;
-        const int lm1 = max(lane - 1, 0), lp1 = min(lane + 1, kWave - 1);
-        const int lm2 = max(lane - 2, 0), lp2 = min(lane + 2, kWave - 1);
-        const T Um1 = shfl(U1, lm1), Up1 = shfl(U1, lp1), Um2 = shfl(U1, lm2), Up2 = shfl(U1, lp2);
-        const T rm1 = shfl(drho, lm1), rp1 = shfl(drho, lp1), rm2 = shfl(drho, lm2), rp2 = shfl(drho, lp2);
-        T d1U1, d1r;
-        if (xwall_lo) {
-            d1U1 = T(0.5) * (T(-3) * U1 + T(4) * Up1 - Up2);
-            d1r = T(0.5) * (T(-3) * drho + T(4) * rp1 - rp2);
-        } else if (xwall_hi) {
-            d1U1 = T(0.5) * (T(3) * U1 - T(4) * Um1 + Um2);
-            d1r = T(0.5) * (T(3) * drho - T(4) * rm1 + rm2);
-        } else {
-            d1U1 = T(0.5) * (Up1 - Um1);
-            d1r = T(0.5) * (rp1 - rm1);
+        // differences along xi1 from the neighbouring lanes
+        const T drho = Cs.dr, rho = p.rho0 + drho, U1 = Cs.U1, U2 = Cs.U2;
+        // (the lane shifts run with every lane active: a shift inside a
+        // lane-divergent branch would read inactive lanes)
+        const T Um1 = from_prev(U1), Up1 = from_next(U1);
+        const T rm1 = from_prev(drho), rp1 = from_next(drho);
+        T d1U1 = T(0.5) * (Up1 - Um1), d1r = T(0.5) * (rp1 - rm1);
+        if (d.bc_x != 0) {   // one-sided next to x-walls
+            const T Up2 = from_next(Up1), rp2 = from_next(rp1);
+            const T Um2 = from_prev(Um1), rm2 = from_prev(rm1);
+            if (xwall_lo) {
+                d1U1 = T(0.5) * (T(-3) * U1 + T(4) * Up1 - Up2);
+                d1r = T(0.5) * (T(-3) * drho + T(4) * rp1 - rp2);
+            } else if (xwall_hi) {
+                d1U1 = T(0.5) * (T(3) * U1 - T(4) * Um1 + Um2);
+                d1r = T(0.5) * (T(3) * drho - T(4) * rm1 + rm2);
+            }
         }
 
-        // App. G: magnetic field, local derivatives, Lorentz force, collision
+        // 4. App. G: magnetic field, local derivatives, Lorentz force, collision
         T Fx1 = p.Fx1, Fx2 = p.Fx2;
         T dg[2][kM], dgi[2][kM];
-        const bool mhd_run = MHD && d.mhd;   // a batch may mix MHD and plain runs
-        const RowGeo Gj = row_geo(d, j);
         if (mhd_run) {
-            const S* gb = pl.gin + d.g_off;
 #pragma unroll
             for (int ci = 0; ci < 2; ++ci)
 #pragma unroll
-                for (int a = 0; a < kM; ++a)
-                    dg[ci][a] = L.valid ? T(Store<S>::ld(gb, ci * kM * plane + pull_index(d, L, Gj, a), sginv))
-                                        : T(0);
+                for (int a = 0; a < kM; ++a) dg[ci][a] = T(Store<S>::dec(Cs.graw[ci][a], sginv));
             T B1, B2, FL1, FL2;
             mie_node<T>(p, g, dg, U1, U2, B1, B2, FL1, FL2, dgi);
             Fx1 += FL1;
             Fx2 += FL2;
         }
 
+        // 5. effective force, corrections, central-moment collision
         T F1, F2, n3, n4, inc[kQ];
         force_and_corrections<T>(p, g, rho, drho, U1, U2, d1U1, d2U2, d1r, d2r, Fx1, Fx2, F1, F2, n3, n4);
-        cm_collide<T>(p, g, raw_dev<T>(fc), rho, drho, U1, U2, Fpc1, Fpc2, F1, F2, n3, n4, inc);
+        cm_collide<T>(p, g, raw_dev<T>(Cs.f), rho, drho, U1, U2, Cs.Fp1, Cs.Fp2, F1, F2, n3, n4, inc);
 
+        // 6. writes: inc holds the collision increments; the writer adds the
+        //    rest-state offsets of the interior axis slots (the reader is the
+        //    neighbour; its rest state differs through the metric) and the
+        //    reader's wall terms
         if (own) {
-            // inc holds the collision increments; the writer adds the
-            // rest-state offsets of the interior axis slots (the reader is
-            // the neighbour; its rest state differs through the metric)
-            const T a2p = T(rt[T_AP]), a2m = T(rt[T_AM]);
+            const T a2p = rt[T_AP], a2m = rt[T_AM];
             inc[1] += g.h2 * a1p;
             inc[3] += g.h2 * a1m;
             inc[2] += g.h1 * a2p;
             inc[4] += g.h1 * a2m;
-            // writer-side momentum-augmented bounce-back of App. C for
-            // populations leaving through a moving y-wall
+            const RowGeo Gj = row_geo(d, j);
+            // momentum-augmented bounce-back of App. C for populations
+            // leaving through a moving y-wall
             if (Gj.wp && d.uw_hi != 0.0) {
                 const T cw = rho * p.cs2 * T(d.uw_hi) / (T(2) * T(d.hw_hi));
                 // slot 5 is read back as f7, slot 6 as f8: f7 = ft5 - cw, f8 = ft6 + cw
@@ -296,13 +428,14 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
             const uint32_t hn = mix32(uint32_t(d.f_off + nn) ^ seed);
             S* fo = pl.fout + d.f_off + nn;
 #pragma unroll
-            for (int a = 0; a < kQ; ++a) Store<S>::st_sr(fo, a * plane, fc[a], inc[a], sfw[cls_(a)], pop_draw(hn, a));
+            for (int a = 0; a < kQ; ++a)
+                Store<S>::st_sr(fo, a * plane, Cs.f[a], inc[a], sfw[cls_(a)], pop_draw(hn, a));
             pl.Fout[d.F_off + nn] = FT(F1);
             pl.Fout[d.F_off + nn + plane] = FT(F2);
             if (mhd_run) {
                 // stored value = base + increment; anti-bounce-back slots
                 // negate the post-collision value
-                const T b2p = T(rt[T_BP]), b2m = T(rt[T_BM]);
+                const T b2p = rt[T_BP], b2m = rt[T_BM];
                 const T hh = g.h1 * g.h2;
 #pragma unroll
                 for (int a = 1; a < kM; ++a) {
@@ -331,15 +464,15 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
                                         pop_draw(hn, kQ + ci * kM + a));
             }
         }
-        // shift the window
-        wr[0] = wr[1]; wu[0] = wu[1];
-        wr[1] = wr[2]; wu[1] = wu[2];
-        wr[2] = wr[3]; wu[2] = wu[3];
-        U1c = U1n;
-        Fpc1 = Fpn1;
-        Fpc2 = Fpn2;
-#pragma unroll
-        for (int a = 0; a < kQ; ++a) fc[a] = fn[a];
+    };
+
+    // march with the three slots rotating roles (no moves between rows)
+    for (int j = y0; j < y1; j += 3) {
+        row_step(A, B, C, j);
+        if (j + 1 >= y1) break;
+        row_step(B, C, A, j + 1);
+        if (j + 2 >= y1) break;
+        row_step(C, A, B, j + 2);
     }
 }
 
