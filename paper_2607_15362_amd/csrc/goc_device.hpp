@@ -61,6 +61,13 @@ enum { T_H = 0, T_IH, T_TH, T_AP, T_AM, T_BP, T_BM };
 
 // ---------------------------------------------------------------------------
 // Run descriptor: one entry per independent run (a single run is a batch of 1).
+// Indices of the ready-to-use step parameters of a run.
+enum {
+    P_CS2 = 0, P_ICS2, P_NU, P_ZETA, P_RHO0, P_P0, P_W, P_FX1 = P_W + 9, P_FX2, P_CSM2, P_ICSM2, P_TAUM,
+    P_ITAUM, P_ETA, P_IMU, P_B0, P_WM0, P_WM1, P_SC, P_ISC = P_SC + 4, P_SCG = P_ISC + 4, P_ISCG, P_CWLO,
+    P_CWHI, P_HWLO, P_HWHI, P_H1WLO, P_H1WHI, kNP
+};
+
 struct RunDesc {
     int32_t nx, ny, pitch;
     int32_t bc_x, bc_y;            // 0 periodic, 1 wall
@@ -80,7 +87,55 @@ struct RunDesc {
     double csm2, tau_m, eta, inv_mu, B0;
     double sc[4];                  // 16-bit storage: scale per direction class
     double scg;                    // 16-bit storage: scale of the D2Q5 deviations
+    // the step's parameters ready to use (no arithmetic on the device), in
+    // FP64 and rounded to FP32; filled by set_step_params
+    double pd[kNP];
+    float pf[kNP];
 };
+
+// Fill pd / pf from the fields above.
+inline void set_step_params(RunDesc& d)
+{
+    double v[kNP];
+    v[P_CS2] = d.cs2;
+    v[P_ICS2] = 1.0 / d.cs2;
+    v[P_NU] = d.nu;
+    v[P_ZETA] = d.zeta;
+    v[P_RHO0] = d.rho0;
+    v[P_P0] = d.rho0 * d.cs2;
+    for (int k = 0; k < 9; ++k) v[P_W + k] = d.omega[k];
+    v[P_FX1] = d.Fx1;
+    v[P_FX2] = d.Fx2;
+    v[P_CSM2] = d.csm2;
+    v[P_ICSM2] = d.csm2 > 0 ? 1.0 / d.csm2 : 0.0;
+    v[P_TAUM] = d.tau_m;
+    v[P_ITAUM] = 1.0 / d.tau_m;
+    v[P_ETA] = d.eta;
+    v[P_IMU] = d.inv_mu;
+    v[P_B0] = d.B0;
+    v[P_WM0] = 1.0 - 2.0 * d.csm2;
+    v[P_WM1] = 0.5 * d.csm2;
+    for (int k = 0; k < 4; ++k) {
+        v[P_SC + k] = d.sc[k];
+        v[P_ISC + k] = 1.0 / d.sc[k];
+    }
+    v[P_SCG] = d.scg;
+    v[P_ISCG] = 1.0 / d.scg;
+    v[P_CWLO] = d.hw_lo > 0 ? d.cs2 * d.uw_lo / (2.0 * d.hw_lo) : 0.0;
+    v[P_CWHI] = d.hw_hi > 0 ? d.cs2 * d.uw_hi / (2.0 * d.hw_hi) : 0.0;
+    v[P_HWLO] = d.hw_lo;
+    v[P_HWHI] = d.hw_hi;
+    v[P_H1WLO] = d.h1w_lo;
+    v[P_H1WHI] = d.h1w_hi;
+    for (int k = 0; k < kNP; ++k) {
+        d.pd[k] = v[k];
+        d.pf[k] = float(v[k]);
+    }
+}
+
+template <class T> __device__ inline const T* step_params(const RunDesc& d);
+template <> __device__ inline const double* step_params<double>(const RunDesc& d) { return d.pd; }
+template <> __device__ inline const float* step_params<float>(const RunDesc& d) { return d.pf; }
 
 // Pointers shared by all runs of a launch.
 template <class S, class FT>
@@ -235,31 +290,41 @@ struct NodeParams {
 template <class T>
 __device__ inline NodeParams<T> node_params(const RunDesc& d)
 {
+    const T* v = step_params<T>(d);
     NodeParams<T> p;
-    p.cs2 = T(d.cs2);
-    p.inv_cs2 = T(1.0 / d.cs2);
-    p.nu = T(d.nu);
-    p.zeta = T(d.zeta);
-    p.rho0 = T(d.rho0);
-    p.P0 = T(d.rho0 * d.cs2);
+    p.cs2 = v[P_CS2];
+    p.inv_cs2 = v[P_ICS2];
+    p.nu = v[P_NU];
+    p.zeta = v[P_ZETA];
+    p.rho0 = v[P_RHO0];
+    p.P0 = v[P_P0];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) p.w[k] = T(d.omega[k]);
-    p.Fx1 = T(d.Fx1);
-    p.Fx2 = T(d.Fx2);
+    for (int k = 0; k < 9; ++k) p.w[k] = v[P_W + k];
+    p.Fx1 = v[P_FX1];
+    p.Fx2 = v[P_FX2];
     p.gi_terms = d.gi_terms;
     p.q3_sign = d.q3_sign;
     p.rho_terms = d.rho_terms;
-    p.csm2 = T(d.csm2);
-    p.inv_csm2 = T(1.0 / d.csm2);
-    p.tau_m = T(d.tau_m);
-    p.inv_tau_m = T(1.0 / d.tau_m);
-    p.eta = T(d.eta);
-    p.inv_mu = T(d.inv_mu);
-    p.B0 = T(d.B0);
-    p.W0 = T(1.0 - 2.0 * d.csm2);
-    p.W1 = T(0.5 * d.csm2);
+    p.csm2 = v[P_CSM2];
+    p.inv_csm2 = v[P_ICSM2];
+    p.tau_m = v[P_TAUM];
+    p.inv_tau_m = v[P_ITAUM];
+    p.eta = v[P_ETA];
+    p.inv_mu = v[P_IMU];
+    p.B0 = v[P_B0];
+    p.W0 = v[P_WM0];
+    p.W1 = v[P_WM1];
     return p;
 }
+
+// Opaque copies: an empty asm statement that takes the value as an
+// in-out operand, so the compiler can no longer prove it loop-invariant.
+// Applied to the lane constants at the top of each marched row, it keeps the
+// loop from hoisting their many products out of the loop, where each would
+// hold a vector register for the whole sweep.
+__device__ inline void opaque_v(float& x) { asm volatile("" : "+v"(x)); }
+__device__ inline void opaque_v(double& x) { asm volatile("" : "+v"(x)); }
+__device__ inline void opaque_v(int32_t& x) { asm volatile("" : "+v"(x)); }
 
 // Metric at one node.
 template <class T>

@@ -460,6 +460,7 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
         for (int k = 0; k < 4; ++k) d.sc[k] = 1.0 / std::max(mag[k] * 0.1, 1e-300);
         // D2Q5 deviations scale like h U B0 with U ~ Ma c_s
         d.scg = 1.0 / std::max(0.01 * std::fabs(d.B0) * std::sqrt(c2), 1e-12);
+        goc::set_step_params(d);
         // column / row tables (FP64 and an FP32 copy, on the device)
         const double P0 = d.rho0 * d.cs2, W1B0 = 0.5 * d.csm2 * d.B0;
         hipLaunchKernelGGL(goc::table_kernel, dim3(nbx), dim3(256), 0, h->stream, h->h1_d + d.col_off,

@@ -258,7 +258,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
     int strip, seg;
     tile_of(d, blockIdx.x - d.first_block, strip, seg);
     const int lane = threadIdx.x;
-    const NodeParams<T> p = node_params<T>(d);
+    const NodeParams<T> p0 = node_params<T>(d);
     const uint32_t seed = mix32(step_ctr[0] + uint32_t(k));
     const bool mhd_run = MHD && d.mhd;   // a batch may mix MHD and plain runs
 
@@ -279,8 +279,8 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
     const bool xwall_hi = d.bc_x != 0 && L.col == d.nx - 1;
     const T* ctab = table_of<T>(pl.col, pl.colf) + (int64_t)(d.col_off + Ls.col) * kTab;
     const T* rtab = table_of<T>(pl.row, pl.rowf) + (int64_t)d.row_off * kTab;
-    const T h1 = ctab[T_H], ih1 = ctab[T_IH], th11 = ctab[T_TH];
-    const T a1p = ctab[T_AP], a1m = ctab[T_AM], b1p = ctab[T_BP], b1m = ctab[T_BM];
+    const T h1_0 = ctab[T_H], ih1_0 = ctab[T_IH], th11_0 = ctab[T_TH];
+    const T a1p_0 = ctab[T_AP], a1m_0 = ctab[T_AM], b1p_0 = ctab[T_BP], b1m_0 = ctab[T_BM];
     // per-lane pull offsets of interior rows, relative to the (plane a,
     // row r - ey) base: the source column, or through an x-wall the lane's
     // own node in the opposite plane
@@ -295,15 +295,16 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
             off[a] = wx ? (opp_(a) - a) * (int32_t)d.plane + ey * d.pitch + Ls.col : (ex > 0 ? Ls.cm : Ls.cp);
         }
     }
+    const T* sp = step_params<T>(d);
     T sinv[4], sfw[4], sginv = T(1), sgw = T(1);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        sinv[c] = Store<S>::scaled ? T(1.0 / d.sc[c]) : T(1);
-        sfw[c] = Store<S>::scaled ? T(d.sc[c]) : T(1);
+        sinv[c] = Store<S>::scaled ? sp[P_ISC + c] : T(1);
+        sfw[c] = Store<S>::scaled ? sp[P_SC + c] : T(1);
     }
     if (Store<S>::scaled) {
-        sginv = T(1.0 / d.scg);
-        sgw = T(d.scg);
+        sginv = sp[P_ISCG];
+        sgw = sp[P_SCG];
     }
     auto ih2_of = [&](int r) { return rtab[(int64_t)r * kTab + T_IH]; };
 
@@ -316,22 +317,34 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
     if (row_ok(d, y0 - 1)) {
         const int r = row_wrap(d, y0 - 1);
         issue_row<S, FT>(d, pl.fin, pl.Fin, Ls, off, r, A.raw, A.Fr);
-        decode_row<S, T, FT>(A, sinv, p.rho0, ih1, ih2_of(r));
+        decode_row<S, T, FT>(A, sinv, p0.rho0, ih1_0, ih2_of(r));
     }
     issue_row<S, FT>(d, pl.fin, pl.Fin, Ls, off, y0, B.raw, B.Fr);
     if (mhd_run) issue_row_g<S>(d, pl.gin, Ls, off, y0, B.graw);
     if (row_ok(d, y0 + 1)) issue_row<S, FT>(d, pl.fin, pl.Fin, Ls, off, row_wrap(d, y0 + 1), C.raw, C.Fr);
-    decode_row<S, T, FT>(B, sinv, p.rho0, ih1, ih2_of(y0));
+    decode_row<S, T, FT>(B, sinv, p0.rho0, ih1_0, ih2_of(y0));
 
     const int64_t plane = d.plane;
     // one row: P = row j - 1, Cs = row j, N = row j + 1
     auto row_step = [&](Slot& P, Slot& Cs, Slot& N, int j) {
-        // 1. loads of row j + 2 (into P, whose populations are done) and the
-        //    D2Q5 slots of row j + 1
+        // the scheduler keeps each row to itself (interleaving the unrolled
+        // rows only lengthens live ranges); the loads issued here complete
+        // during the row's arithmetic
+        __builtin_amdgcn_sched_barrier(0);
+        // per-row opaque copies of the lane constants
+        const NodeParams<T>& p = p0;
+        T h1 = h1_0, ih1 = ih1_0, th11 = th11_0, a1p = a1p_0, a1m = a1m_0, b1p = b1p_0, b1m = b1m_0;
+        opaque_v(h1);
+        opaque_v(ih1);
+        opaque_v(th11);
+        opaque_v(a1p);
+        opaque_v(a1m);
+        opaque_v(b1p);
+        opaque_v(b1m);
+        // 1. loads of row j + 2 (into P, whose populations are done)
         const bool have_next = row_ok(d, j + 1);
         const bool load2 = j + 2 <= y1 && row_ok(d, j + 2);
         if (load2) issue_row<S, FT>(d, pl.fin, pl.Fin, Ls, off, row_wrap(d, j + 2), P.raw, P.Fr);
-        if (mhd_run && j + 1 < y1) issue_row_g<S>(d, pl.gin, Ls, off, row_wrap(d, j + 1), N.graw);
         // 2. moments of row j + 1
         if (have_next) decode_row<S, T, FT>(N, sinv, p.rho0, ih1, ih2_of(row_wrap(d, j + 1)));
 
@@ -380,10 +393,16 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
             }
         }
 
-        // 4. App. G: magnetic field, local derivatives, Lorentz force, collision
+        // 4. App. G: magnetic field, local derivatives, Lorentz force,
+        //    collision and the D2Q5 writes (stored value = base + increment;
+        //    anti-bounce-back slots negate the post-collision value); then the
+        //    D2Q5 loads of row j + 1, in flight during the fluid collision
         T Fx1 = p.Fx1, Fx2 = p.Fx2;
-        T dg[2][kM], dgi[2][kM];
+        const RowGeo Gj = row_geo(d, j);
+        const int64_t nn = (int64_t)j * d.pitch + L.col;
+        const uint32_t hn = mix32(uint32_t(d.f_off + nn) ^ seed);
         if (mhd_run) {
+            T dg[2][kM], dgi[2][kM];
 #pragma unroll
             for (int ci = 0; ci < 2; ++ci)
 #pragma unroll
@@ -392,49 +411,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
             mie_node<T>(p, g, dg, U1, U2, B1, B2, FL1, FL2, dgi);
             Fx1 += FL1;
             Fx2 += FL2;
-        }
-
-        // 5. effective force, corrections, central-moment collision
-        T F1, F2, n3, n4, inc[kQ];
-        force_and_corrections<T>(p, g, rho, drho, U1, U2, d1U1, d2U2, d1r, d2r, Fx1, Fx2, F1, F2, n3, n4);
-        cm_collide<T>(p, g, raw_dev<T>(Cs.f), rho, drho, U1, U2, Cs.Fp1, Cs.Fp2, F1, F2, n3, n4, inc);
-
-        // 6. writes: inc holds the collision increments; the writer adds the
-        //    rest-state offsets of the interior axis slots (the reader is the
-        //    neighbour; its rest state differs through the metric) and the
-        //    reader's wall terms
-        if (own) {
-            const T a2p = rt[T_AP], a2m = rt[T_AM];
-            inc[1] += g.h2 * a1p;
-            inc[3] += g.h2 * a1m;
-            inc[2] += g.h1 * a2p;
-            inc[4] += g.h1 * a2m;
-            const RowGeo Gj = row_geo(d, j);
-            // momentum-augmented bounce-back of App. C for populations
-            // leaving through a moving y-wall
-            if (Gj.wp && d.uw_hi != 0.0) {
-                const T cw = rho * p.cs2 * T(d.uw_hi) / (T(2) * T(d.hw_hi));
-                // slot 5 is read back as f7, slot 6 as f8: f7 = ft5 - cw, f8 = ft6 + cw
-                if (d.lid_corners || !xwall_hi) inc[5] -= cw;
-                if (d.lid_corners || !xwall_lo) inc[6] += cw;
-            }
-            if (Gj.wm && d.uw_lo != 0.0) {
-                const T cw = rho * p.cs2 * T(d.uw_lo) / (T(2) * T(d.hw_lo));
-                // slot 7 is read back as f5, slot 8 as f6: f5 = ft7 + cw, f6 = ft8 - cw
-                if (d.lid_corners || !xwall_lo) inc[7] += cw;
-                if (d.lid_corners || !xwall_hi) inc[8] -= cw;
-            }
-            const int64_t nn = (int64_t)j * d.pitch + L.col;
-            const uint32_t hn = mix32(uint32_t(d.f_off + nn) ^ seed);
-            S* fo = pl.fout + d.f_off + nn;
-#pragma unroll
-            for (int a = 0; a < kQ; ++a)
-                Store<S>::st_sr(fo, a * plane, Cs.f[a], inc[a], sfw[cls_(a)], pop_draw(hn, a));
-            pl.Fout[d.F_off + nn] = FT(F1);
-            pl.Fout[d.F_off + nn + plane] = FT(F2);
-            if (mhd_run) {
-                // stored value = base + increment; anti-bounce-back slots
-                // negate the post-collision value
+            if (own) {
                 const T b2p = rt[T_BP], b2m = rt[T_BM];
                 const T hh = g.h1 * g.h2;
 #pragma unroll
@@ -445,8 +422,8 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
                     if (wx || wy) {
                         // anti-bounce-back of App. G: the reader (this node) sees
                         // -g~ + 2 W h_wall B_wall with B_wall = (0, B0)
-                        const T hwall = wy ? g.h1 * T(ey < 0 ? d.hw_lo : d.hw_hi)
-                                           : T(ex < 0 ? d.h1w_lo : d.h1w_hi) * g.h2;
+                        const T hwall = wy ? g.h1 * sp[ey < 0 ? P_HWLO : P_HWHI]
+                                           : sp[ex < 0 ? P_H1WLO : P_H1WHI] * g.h2;
                         dg[0][a] = -dg[0][a];
                         dgi[0][a] = -dgi[0][a];
                         dg[1][a] = -dg[1][a];
@@ -463,7 +440,46 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
                         Store<S>::st_sr(go, (ci * kM + a) * plane, dg[ci][a], dgi[ci][a], sgw,
                                         pop_draw(hn, kQ + ci * kM + a));
             }
+            if (j + 1 < y1) issue_row_g<S>(d, pl.gin, Ls, off, row_wrap(d, j + 1), N.graw);
         }
+
+        // 5. effective force, corrections, central-moment collision
+        T F1, F2, n3, n4, inc[kQ];
+        force_and_corrections<T>(p, g, rho, drho, U1, U2, d1U1, d2U2, d1r, d2r, Fx1, Fx2, F1, F2, n3, n4);
+        cm_collide<T>(p, g, raw_dev<T>(Cs.f), rho, drho, U1, U2, Cs.Fp1, Cs.Fp2, F1, F2, n3, n4, inc);
+
+        // 6. D2Q9 writes: inc holds the collision increments; the writer adds the
+        //    rest-state offsets of the interior axis slots (the reader is the
+        //    neighbour; its rest state differs through the metric) and the
+        //    reader's wall terms
+        if (own) {
+            const T a2p = rt[T_AP], a2m = rt[T_AM];
+            inc[1] += g.h2 * a1p;
+            inc[3] += g.h2 * a1m;
+            inc[2] += g.h1 * a2p;
+            inc[4] += g.h1 * a2m;
+            // momentum-augmented bounce-back of App. C for populations
+            // leaving through a moving y-wall
+            if (Gj.wp && d.uw_hi != 0.0) {
+                const T cw = rho * sp[P_CWHI];
+                // slot 5 is read back as f7, slot 6 as f8: f7 = ft5 - cw, f8 = ft6 + cw
+                if (d.lid_corners || !xwall_hi) inc[5] -= cw;
+                if (d.lid_corners || !xwall_lo) inc[6] += cw;
+            }
+            if (Gj.wm && d.uw_lo != 0.0) {
+                const T cw = rho * sp[P_CWLO];
+                // slot 7 is read back as f5, slot 8 as f6: f5 = ft7 + cw, f6 = ft8 - cw
+                if (d.lid_corners || !xwall_lo) inc[7] += cw;
+                if (d.lid_corners || !xwall_hi) inc[8] -= cw;
+            }
+            S* fo = pl.fout + d.f_off + nn;
+#pragma unroll
+            for (int a = 0; a < kQ; ++a)
+                Store<S>::st_sr(fo, a * plane, Cs.f[a], inc[a], sfw[cls_(a)], pop_draw(hn, a));
+            pl.Fout[d.F_off + nn] = FT(F1);
+            pl.Fout[d.F_off + nn + plane] = FT(F2);
+        }
+        __builtin_amdgcn_sched_barrier(0);
     };
 
     // march with the three slots rotating roles (no moves between rows)
