@@ -121,11 +121,12 @@ def storage_forms(steps: int):
         r = B.Run(c)
         dd = r.derived()
         r.init(*W.hartmann_start(c, dd["nu"], dd["F1"], dd["eta"], dd["B0"]))
+        tuned = r.tune(10)
         w, e = time_run(r, n, 100)
         fl = r.fields()
         forms[st] = {"workload": c.name, "steps": n + 100, "MLUPS": round(c.nx * c.ny * n / w / 1e6, 1),
                      "GB_s": round(dd["bytes_per_node"] * c.nx * c.ny / (e / n) / 1e9, 1),
-                     "bytes_per_node": dd["bytes_per_node"]}
+                     "bytes_per_node": dd["bytes_per_node"], "waves_per_cu": tuned["waves_per_cu"]}
         if ref is None:
             ref = fl
         else:
@@ -164,6 +165,8 @@ def main():
 
     case = W.cavity_1024() if args.workload == "cavity_1024" else W.hartmann_4096()
     run = B.Run(case)
+    tuned = run.tune(20)          # launch-plan autotuner (state unchanged)
+    launch = run.launch_info()
     wall, ev = time_run(run, args.steps, args.warmup)
     d = run.derived()
     nodes = case.nx * case.ny
@@ -196,7 +199,10 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic,
                      "bytes_per_node": d["bytes_per_node"], "launch_us": round(launch_s * 1e6, 2),
-                     "kernel": "goc::step_kernel"},
+                     "kernel": "goc::step_kernel",
+                     "launch_plan": {"waves_per_cu": launch["waves_per_cu"], "work_groups": launch["blocks"],
+                                     "rows_per_segment": round(launch["rows_per_segment"], 2),
+                                     "untuned_us": round(tuned["us_before"], 2)}},
     }
     run.close()
 

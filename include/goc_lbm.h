@@ -186,6 +186,26 @@ int goc_lbm_diagnostics(goc_lbm_t *h, double out[8]);
    makes goc_lbm_step return GOC_EUNSTABLE. */
 int goc_lbm_set_watchdog(goc_lbm_t *h, int64_t every);
 
+/* Launch plan of the step kernel.  One work-group (a wave of 64 lanes)
+   owns 62 columns of a run and a segment of rows; every run gets segments
+   in proportion to its nodes so that the launch holds about waves_per_cu
+   work-groups per compute unit (default 16).  Fewer, longer segments re-read
+   fewer halo rows; more segments fill the chip.  goc_lbm_set_launch applies
+   waves_per_cu in [0.5, 256] (synchronous; GOC_EINVAL outside).
+   goc_lbm_launch_info writes out[0] = waves_per_cu, out[1] = work-groups
+   per step, out[2] = mean rows per segment, out[3] = strips (all runs). */
+int goc_lbm_set_launch(goc_lbm_t *h, double waves_per_cu);
+int goc_lbm_launch_info(const goc_lbm_t *h, double out[4]);
+
+/* Autotuner of the launch plan: times trial_steps step launches (1..10000,
+   plus one warm-up) for each waves_per_cu in {2, 3, 4, 6, 8, 12, 16, 24, 32,
+   48} on the handle's stream and keeps the fastest.  The state does not
+   change: trial launches read the current buffers and write the spare ones.
+   out[0] = chosen waves_per_cu, out[1] = its microseconds per step,
+   out[2] = microseconds per step of the plan in use before (-1 if it was not
+   a candidate), out[3] = number of candidates.  Synchronous. */
+int goc_lbm_tune(goc_lbm_t *h, int32_t trial_steps, double out[4]);
+
 /* Post-stream populations in FP64 (the quantities App. E step 1 reads):
    f[9][ny][nx], F[2][ny][nx] (the lagged effective force) and, for MHD,
    g[10][ny][nx] (plane c*5 + a for component c of B).  set takes the same

@@ -82,6 +82,9 @@ SIGNATURES = {
     "goc_lbm_destroy": (None, [VP]),
     "goc_lbm_last_error": (C.c_char_p, []),
     "goc_lbm_num_runs": (C.c_int32, [VP]),
+    "goc_lbm_set_launch": (C.c_int, [VP, C.c_double]),
+    "goc_lbm_launch_info": (C.c_int, [VP, P_D]),
+    "goc_lbm_tune": (C.c_int, [VP, C.c_int32, P_D]),
 }
 
 
@@ -340,6 +343,21 @@ class Run:
         keys = ["cs2", "nu", "zeta", "q", "csm2", "eta", "tau_m", "B0", "F1", "F2", "hw_lo", "hw_hi",
                 "step", "bytes_per_node", "nx", "ny"]
         return dict(zip(keys, out))
+
+    def set_launch(self, waves_per_cu):
+        _check(lib().goc_lbm_set_launch(self.h, float(waves_per_cu)))
+        return self
+
+    def launch_info(self):
+        out = np.zeros(4)
+        _check(lib().goc_lbm_launch_info(self.h, _dptr(out)))
+        return dict(waves_per_cu=out[0], blocks=int(out[1]), rows_per_segment=out[2], strips=int(out[3]))
+
+    def tune(self, trial_steps=20):
+        """Autotune the launch plan (the state does not change)."""
+        out = np.zeros(4)
+        _check(lib().goc_lbm_tune(self.h, int(trial_steps), _dptr(out)))
+        return dict(waves_per_cu=out[0], us_per_step=out[1], us_before=out[2], candidates=int(out[3]))
 
     def metric_arrays(self):
         h1, t1 = np.zeros(self.nx), np.zeros(self.nx)

@@ -176,6 +176,9 @@ struct goc_lbm {
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int rows_per_seg = 0;
     uint32_t* step_ctr = nullptr;   // device: index of the next step's rounding draws
+    int ncu = 256;                  // compute units of the device
+    double waves_per_cu = 16.0;     // launch plan: work-groups per CU over the whole launch
+    int block_cap = 0;              // capacity of block_run_d (entries)
 };
 
 namespace {
@@ -293,6 +296,52 @@ int choose_rows(int ny, int strips, int target_waves)
     return rows;
 }
 
+// Launch plan: each run gets work-groups (62-column strips x row segments)
+// in proportion to its nodes, about waves_per_cu per CU over the launch;
+// fills segs / first_block of the runs and the work-group -> run list.
+void plan_rows(goc_lbm* h, std::vector<int32_t>& block_run)
+{
+    int64_t total_nodes = 0;
+    for (const RunDesc& d : h->runs) total_nodes += (int64_t)d.nx * d.ny;
+    block_run.clear();
+    for (int r = 0; r < h->nruns; ++r) {
+        RunDesc& d = h->runs[r];
+        const double share = double((int64_t)d.nx * d.ny) / double(total_nodes);
+        const int target = std::max(1, int(share * h->waves_per_cu * h->ncu));
+        const int rows = choose_rows(d.ny, d.strips, target);
+        d.segs = std::max(1, std::min(d.ny / 2, (d.ny + rows - 1) / rows));
+        d.first_block = (int)block_run.size();
+        for (int b = 0; b < d.strips * d.segs; ++b) block_run.push_back(r);
+    }
+    h->total_blocks = (int)block_run.size();
+}
+
+// Apply a launch plan on the device: run table and work list (synchronous;
+// captured step graphs are dropped, as their grid changes).
+int apply_plan(goc_lbm* h, double waves_per_cu)
+{
+    h->waves_per_cu = waves_per_cu;
+    std::vector<int32_t> block_run;
+    plan_rows(h, block_run);
+    if ((int)block_run.size() > h->block_cap) {
+        (void)hipFree(h->block_run_d);
+        h->block_run_d = nullptr;
+        h->block_cap = 0;
+        if (hipMalloc(&h->block_run_d, block_run.size() * 4) != hipSuccess)
+            return fail(GOC_ENOMEM, "hipMalloc of the work list failed");
+        h->block_cap = (int)block_run.size();
+    }
+    HIPOK(hipStreamSynchronize(h->stream));
+    for (int k = 0; k < 2; ++k)
+        if (h->graph[k]) {
+            (void)hipGraphExecDestroy(h->graph[k]);
+            h->graph[k] = nullptr;
+        }
+    HIPOK(hipMemcpy(h->runs_d, h->runs.data(), h->nruns * sizeof(RunDesc), hipMemcpyHostToDevice));
+    HIPOK(hipMemcpy(h->block_run_d, block_run.data(), block_run.size() * 4, hipMemcpyHostToDevice));
+    return GOC_OK;
+}
+
 int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metric* metric,
                 const goc_params* params, int32_t storage, void* stream)
 {
@@ -334,8 +383,6 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
     h->q.resize(nruns);
     int64_t sum_nx = 0, sum_ny = 0, f_elems = 0, F_elems = 0, g_elems = 0;
     // one wave per work-group; aim for ~16 waves per CU over the whole batch
-    int64_t total_nodes = 0;
-    for (int r = 0; r < nruns; ++r) total_nodes += (int64_t)grid[r].nx * grid[r].ny;
     std::vector<int32_t> block_run;
     for (int r = 0; r < nruns; ++r) {
         if ((rc = check_grid(&grid[r])) != GOC_OK) return bail(rc);
@@ -383,15 +430,10 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
         d.inv_mu = p.mhd ? 1.0 / p.mu_m : 1.0;
         d.B0 = p.mhd ? p.B0 : 0.0;
         d.strips = (g.nx + goc::kOwn - 1) / goc::kOwn;
-        // share of the chip in proportion to the run's nodes
-        const double share = double((int64_t)g.nx * g.ny) / double(total_nodes);
-        const int target = std::max(1, int(share * 16.0 * ncu));
-        const int rows = choose_rows(g.ny, d.strips, target);
-        d.segs = std::max(1, std::min(g.ny / 2, (g.ny + rows - 1) / rows));
-        d.first_block = (int)block_run.size();
-        for (int b = 0; b < d.strips * d.segs; ++b) block_run.push_back(r);
     }
-    h->total_blocks = (int)block_run.size();
+    h->ncu = ncu;
+    plan_rows(h, block_run);
+    h->block_cap = (int)block_run.size();
     h->f_elems = f_elems;
     h->F_elems = F_elems;
     h->g_elems = g_elems;
@@ -861,6 +903,73 @@ int goc_lbm_step(goc_lbm_t* h, int64_t n)
             }
         }
     }
+    return GOC_OK;
+}
+
+int goc_lbm_set_launch(goc_lbm_t* h, double waves_per_cu)
+{
+    if (!check_handle(h)) return GOC_EINVAL;
+    if (!(waves_per_cu >= 0.5 && waves_per_cu <= 256.0))
+        return fail(GOC_EINVAL, "waves_per_cu %g outside [0.5, 256]", waves_per_cu);
+    return apply_plan(h, waves_per_cu);
+}
+
+int goc_lbm_launch_info(const goc_lbm_t* h, double out[4])
+{
+    if (!h || !out) return fail(GOC_EINVAL, "NULL handle or output");
+    int64_t rows = 0, segs = 0, strips = 0;
+    for (const RunDesc& d : h->runs) {
+        rows += (int64_t)d.ny * d.strips;
+        segs += (int64_t)d.segs * d.strips;
+        strips += d.strips;
+    }
+    out[0] = h->waves_per_cu;
+    out[1] = h->total_blocks;
+    out[2] = segs ? double(rows) / double(segs) : 0.0;
+    out[3] = (double)strips;
+    return GOC_OK;
+}
+
+int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
+{
+    if (!check_handle(h)) return GOC_EINVAL;
+    if (!out) return fail(GOC_EINVAL, "out is NULL");
+    if (trial_steps < 1 || trial_steps > 10000) return fail(GOC_EINVAL, "trial_steps %d outside [1, 10000]", trial_steps);
+    static const double cand[] = {2, 3, 4, 6, 8, 12, 16, 24, 32, 48};
+    const int ncand = (int)(sizeof(cand) / sizeof(cand[0]));
+    struct Ev {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Ev() { for (auto x : e) if (x) (void)hipEventDestroy(x); }
+    } ev;
+    HIPOK(hipEventCreate(&ev.e[0]));
+    HIPOK(hipEventCreate(&ev.e[1]));
+    const double prev = h->waves_per_cu;
+    double best_us = 1e300, best_w = prev, prev_us = -1.0;
+    // every trial launch reads the current buffers and writes the others,
+    // which the next real step overwrites: the state does not change
+    for (int c = 0; c < ncand; ++c) {
+        int rc = apply_plan(h, cand[c]);
+        if (rc) return rc;
+        if ((rc = launch_step(h, 0))) return rc;
+        HIPOK(hipEventRecord(ev.e[0], h->stream));
+        for (int s = 0; s < trial_steps; ++s)
+            if ((rc = launch_step(h, s))) return rc;
+        HIPOK(hipEventRecord(ev.e[1], h->stream));
+        HIPOK(hipEventSynchronize(ev.e[1]));
+        float ms = 0.0f;
+        HIPOK(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
+        const double us = 1e3 * ms / trial_steps;
+        if (cand[c] == prev) prev_us = us;
+        if (us < best_us) {
+            best_us = us;
+            best_w = cand[c];
+        }
+    }
+    if (int rc = apply_plan(h, best_w)) return rc;
+    out[0] = best_w;
+    out[1] = best_us;
+    out[2] = prev_us;
+    out[3] = ncand;
     return GOC_OK;
 }
 

@@ -332,6 +332,41 @@ def test_determinism_and_graph_blocks(oracle_lib):
     assert np.array_equal(fa, fb)
 
 
+def test_autotuner_keeps_state_and_results():
+    """The launch-plan autotuner leaves the state untouched and any plan gives
+    bitwise the same steps (the rounding draws depend on node, population
+    and step only): a run tuned half-way equals an untuned one, for a
+    single run and for a batch of uneven runs."""
+    case = W.hartmann_4096().replace(name="tune", nx=300, ny=130)
+    a, b = B.Run(case), B.Run(case)
+    a.step(50)
+    before = a.populations()
+    info = a.tune(5)
+    assert info["candidates"] >= 5 and info["us_per_step"] > 0
+    after = a.populations()
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)
+    a.step(50)
+    b.step(100)
+    for x, y in zip(a.populations(), b.populations()):
+        assert np.array_equal(x, y)
+    a.set_launch(3)
+    assert a.launch_info()["waves_per_cu"] == 3
+    a.step(7)
+    b.step(7)
+    for x, y in zip(a.populations(), b.populations()):
+        assert np.array_equal(x, y)
+    runs = W.batch_256(n=6)
+    c, e = B.Run(batch=runs), B.Run(batch=runs)
+    c.step(20)
+    c.tune(3)
+    c.step(20)
+    e.step(40)
+    for r in range(len(runs)):
+        for x, y in zip(c.populations(run=r), e.populations(run=r)):
+            assert np.array_equal(x, y)
+
+
 def test_watchdog_reports_non_finite_state(oracle_lib):
     case = W.Case("wd", 40, 30, "periodic", "wall", ("uniform", 0.0), ("tanh", 1.5), flow="channel",
                   Re=10.0, tau=0.8, storage="f32")
