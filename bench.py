@@ -15,7 +15,10 @@ Prints ONE JSON line:
   cpu_baseline               the FP64 oracle on the host cores, on a bounded
                              sample of the same workload
   forms                      the same GPU on the 4096x1024 MHD workload in
-                             FP32 and the FP16 / BF16 deviation-storage forms
+                             FP32 and the FP16 / BF16 deviation-storage forms,
+                             with their field errors against the FP32 run
+  batched                    the seeded 256-run batch in one launch per step
+                             against the same runs one after another
 """
 from __future__ import annotations
 
@@ -139,6 +142,54 @@ def storage_forms(steps: int):
     return forms
 
 
+def batched_form(steps: int):
+    """The seeded batch of 256 stretched Hartmann channels (uneven grids,
+    beta, Re, Ha; FP32) from their developed flows: one launch per step for
+    the whole batch (100-step graphs, tuned plan) against the same runs
+    stepped one after another with their own launches (each tuned)."""
+    from paper_2607_15362_amd import binding as B
+    from paper_2607_15362_amd import workloads as W
+    runs = W.batch_256()
+    nodes = sum(c.nx * c.ny for c in runs)
+    n = max(100, (steps // 30) // 100 * 100)
+
+    def start(r, c, run=None):
+        d = r.derived(run=run or 0)
+        init = W.hartmann_start(c, d["nu"], d["F1"], d["eta"], d["B0"])
+        if run is None:
+            r.init(*init)
+        else:
+            r.init_run(run, *init)
+
+    b = B.Run(batch=runs)
+    for k, c in enumerate(runs):
+        start(b, c, k)
+    tuned = b.tune(5)
+    w, _ = time_run(b, n, 100)
+    out = {"runs": len(runs), "nodes": nodes, "steps": n, "MLUPS": round(nodes * n / w / 1e6, 1),
+           "waves_per_cu": tuned["waves_per_cu"]}
+    b.close()
+    singles = []
+    for c in runs:
+        r = B.Run(c)
+        start(r, c)
+        r.tune(3)
+        r.step(100)
+        singles.append(r)
+    for r in singles:
+        r.synchronize()
+    t0 = time.perf_counter()
+    for r in singles:
+        r.step(n)
+        r.synchronize()
+    dt = time.perf_counter() - t0
+    for r in singles:
+        r.close()
+    out["one_after_another_MLUPS"] = round(nodes * n / dt / 1e6, 1)
+    out["speedup"] = round(out["MLUPS"] / out["one_after_another_MLUPS"], 2)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +199,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB mebibytes (counter calibration)")
     args = ap.parse_args()
@@ -208,6 +260,10 @@ def main():
 
     if not args.no_forms:
         out["forms"] = storage_forms(args.steps)
+    if not args.no_batch:
+        out["batched"] = batched_form(args.steps)
+        if "forms" in out:
+            out["batched"]["vs_plain_fp32_4096x1024"] = round(out["batched"]["MLUPS"] / out["forms"]["f32"]["MLUPS"], 3)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     print(json.dumps(out), flush=True)

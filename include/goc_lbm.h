@@ -164,6 +164,13 @@ int goc_lbm_init(goc_lbm_t *h, const double *rho, const double *u1, const double
 int goc_lbm_init_mhd(goc_lbm_t *h, const double *rho, const double *u1, const double *u2,
                      const double *b1, const double *b2, int32_t on_device);
 
+/* Initial state of one run of a batch from its node fields (as
+   goc_lbm_init_mhd; b1, b2 may be NULL): rho, u1, u2 [ny*nx] of that run.
+   The other runs and the handle's step count are unchanged.  GOC_EINVAL for
+   a run outside [0, num_runs) or missing fields. */
+int goc_lbm_init_run(goc_lbm_t *h, int32_t run, const double *rho, const double *u1, const double *u2,
+                     const double *b1, const double *b2, int32_t on_device);
+
 /* Advance n >= 0 time steps (App. E steps 1-7 and App. G steps 1-6 per
    step, one fused kernel launch each).  Asynchronous on the stream unless
    the watchdog interval is due (goc_lbm_set_watchdog). */
@@ -228,6 +235,8 @@ int goc_lbm_set_state(goc_lbm_t *h, const void *buf, size_t bytes);
    [10] h2 on the xi2 = 0 face, [11] on the xi2 = ny face, [12] step count,
    [13] storage bytes per node per step (algorithmic), [14] nx, [15] ny. */
 int goc_lbm_derived(const goc_lbm_t *h, double out[16]);
+/* The same for run `run` of a batch (GOC_EINVAL outside [0, num_runs)). */
+int goc_lbm_derived_run(const goc_lbm_t *h, int32_t run, double out[16]);
 
 /* Metric arrays as used by the kernels (FP64 host): h1, theta11 [nx],
    h2, theta22 [ny]; any pointer may be NULL. */

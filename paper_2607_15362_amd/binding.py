@@ -67,6 +67,8 @@ SIGNATURES = {
                                        C.POINTER(Params), C.c_int32, VP]),
     "goc_lbm_init": (C.c_int, [VP, VP, VP, VP, C.c_int32]),
     "goc_lbm_init_mhd": (C.c_int, [VP, VP, VP, VP, VP, VP, C.c_int32]),
+    "goc_lbm_init_run": (C.c_int, [VP, C.c_int32, VP, VP, VP, VP, VP, C.c_int32]),
+    "goc_lbm_derived_run": (C.c_int, [VP, C.c_int32, P_D]),
     "goc_lbm_step": (C.c_int, [VP, C.c_int64]),
     "goc_lbm_moments": (C.c_int, [VP, VP, VP, VP, C.c_int32]),
     "goc_lbm_moments_run": (C.c_int, [VP, C.c_int32, VP, VP, VP, C.c_int32]),
@@ -265,6 +267,14 @@ class Run:
             pass
 
     # ---- calls ---------------------------------------------------------
+    def init_run(self, run, rho, u1, u2, b1=None, b2=None):
+        """Initial fields of one run of a batch (the others are unchanged)."""
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (rho, u1, u2)]
+        bs = [None, None] if b1 is None else [np.ascontiguousarray(a, dtype=np.float64) for a in (b1, b2)]
+        ptr = [a.ctypes.data for a in arrs] + [None if b is None else b.ctypes.data for b in bs]
+        _check(lib().goc_lbm_init_run(self.h, int(run), *ptr, 0))
+        return self
+
     def init(self, rho=None, u1=None, u2=None, b1=None, b2=None):
         if rho is None:
             _check(lib().goc_lbm_init(self.h, None, None, None, 0))
@@ -337,12 +347,15 @@ class Run:
         buf = C.create_string_buffer(blob, len(blob))
         _check(lib().goc_lbm_set_state(self.h, C.cast(buf, VP), len(blob)))
 
-    def derived(self):
+    def derived(self, run=0):
         out = np.zeros(16)
-        _check(lib().goc_lbm_derived(self.h, _dptr(out)))
+        _check(lib().goc_lbm_derived_run(self.h, int(run), _dptr(out)))
         keys = ["cs2", "nu", "zeta", "q", "csm2", "eta", "tau_m", "B0", "F1", "F2", "hw_lo", "hw_hi",
                 "step", "bytes_per_node", "nx", "ny"]
         return dict(zip(keys, out))
+
+    def num_runs(self):
+        return int(lib().goc_lbm_num_runs(self.h))
 
     def set_launch(self, waves_per_cu):
         _check(lib().goc_lbm_set_launch(self.h, float(waves_per_cu)))

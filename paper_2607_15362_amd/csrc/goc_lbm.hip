@@ -818,16 +818,59 @@ void goc_lbm_destroy(goc_lbm_t* h)
     delete h;
 }
 
+namespace {
+// Fields of one run (all five given or B NULL); the caller resets the step.
+int init_fields(goc_lbm* h, int run, const double* rho, const double* u1, const double* u2, const double* b1,
+                const double* b2, int32_t on_device)
+{
+    const RunDesc& d = h->runs[run];
+    const size_t N = (size_t)d.nx * d.ny;
+    const double* src[5] = {rho, u1, u2, b1, b2};
+    const double* dev[5] = {rho, u1, u2, b1, b2};
+    DevBuf buf[5];
+    if (!on_device) {
+        for (int k = 0; k < 5; ++k) {
+            if (!src[k]) continue;
+            if (int rc = buf[k].alloc(N)) return rc;
+            HIPOK(hipMemcpyAsync(buf[k].p, src[k], N * 8, hipMemcpyHostToDevice, h->stream));
+            dev[k] = buf[k].p;
+        }
+    }
+    int rc = init_run(h, run, dev[0], dev[1], dev[2], dev[3], dev[4]);
+    if (rc) return rc;
+    HIPOK(hipStreamSynchronize(h->stream));
+    return GOC_OK;
+}
+
+int check_fields(const goc_lbm* h, int run, const double* rho, const double* u1, const double* u2,
+                 const double* b1, const double* b2)
+{
+    if (!(rho && u1 && u2)) return fail(GOC_EINVAL, "init needs all of rho, u1, u2");
+    if ((b1 != nullptr) != (b2 != nullptr)) return fail(GOC_EINVAL, "init needs both of b1, b2 or neither");
+    if (b1 && !h->runs[run].mhd) return fail(GOC_EINVAL, "b1, b2 given for a run without MHD");
+    return GOC_OK;
+}
+}  // namespace
+
+int goc_lbm_init_run(goc_lbm_t* h, int32_t run, const double* rho, const double* u1, const double* u2,
+                     const double* b1, const double* b2, int32_t on_device)
+{
+    if (!check_handle(h)) return GOC_EINVAL;
+    if (run < 0 || run >= h->nruns) return fail(GOC_EINVAL, "run %d outside [0, %d)", run, h->nruns);
+    if (int rc = check_fields(h, run, rho, u1, u2, b1, b2)) return rc;
+    return init_fields(h, run, rho, u1, u2, b1, b2, on_device);
+}
+
 int goc_lbm_init_mhd(goc_lbm_t* h, const double* rho, const double* u1, const double* u2, const double* b1,
                      const double* b2, int32_t on_device)
 {
     if (!check_handle(h)) return GOC_EINVAL;
     const bool given = rho || u1 || u2;
-    if (given && !(rho && u1 && u2)) return fail(GOC_EINVAL, "init needs all of rho, u1, u2 or none");
-    if ((b1 != nullptr) != (b2 != nullptr)) return fail(GOC_EINVAL, "init needs both of b1, b2 or neither");
-    if (b1 && !given) return fail(GOC_EINVAL, "b1, b2 need rho, u1, u2 too");
-    if (b1 && !h->runs[0].mhd) return fail(GOC_EINVAL, "b1, b2 given for a run without MHD");
-    if (given && h->nruns != 1) return fail(GOC_EINVAL, "field initialisation is per single run");
+    if (!given && (b1 || b2)) return fail(GOC_EINVAL, "b1, b2 need rho, u1, u2 too");
+    if (given) {
+        if (int rc = check_fields(h, 0, rho, u1, u2, b1, b2)) return rc;
+        if (h->nruns != 1) return fail(GOC_EINVAL, "field initialisation of a batch is per run (goc_lbm_init_run)");
+    }
     // write into the input buffer: kernels write to "out" of pools(1 - cur)
     if (!given) {
         for (int r = 0; r < h->nruns; ++r) {
@@ -835,22 +878,7 @@ int goc_lbm_init_mhd(goc_lbm_t* h, const double* rho, const double* u1, const do
             if (rc) return rc;
         }
     } else {
-        const RunDesc& d = h->runs[0];
-        const size_t N = (size_t)d.nx * d.ny;
-        const double* src[5] = {rho, u1, u2, b1, b2};
-        const double* dev[5] = {rho, u1, u2, b1, b2};
-        DevBuf buf[5];
-        if (!on_device) {
-            for (int k = 0; k < 5; ++k) {
-                if (!src[k]) continue;
-                if (int rc = buf[k].alloc(N)) return rc;
-                HIPOK(hipMemcpyAsync(buf[k].p, src[k], N * 8, hipMemcpyHostToDevice, h->stream));
-                dev[k] = buf[k].p;
-            }
-        }
-        int rc = init_run(h, 0, dev[0], dev[1], dev[2], dev[3], dev[4]);
-        if (rc) return rc;
-        HIPOK(hipStreamSynchronize(h->stream));
+        if (int rc = init_fields(h, 0, rho, u1, u2, b1, b2, on_device)) return rc;
     }
     h->step = 0;
     if (int rc = counter_op(h, 0, 0)) return rc;
@@ -1127,16 +1155,17 @@ int goc_lbm_set_state(goc_lbm_t* h, const void* buf, size_t bytes)
     return GOC_OK;
 }
 
-int goc_lbm_derived(const goc_lbm_t* h, double out[16])
+int goc_lbm_derived_run(const goc_lbm_t* h, int32_t run, double out[16])
 {
     if (!h) return fail(GOC_EINVAL, "handle is NULL");
     if (!out) return fail(GOC_EINVAL, "out is NULL");
-    const RunDesc& d = h->runs[0];
+    if (run < 0 || run >= h->nruns) return fail(GOC_EINVAL, "run %d outside [0, %d)", run, h->nruns);
+    const RunDesc& d = h->runs[run];
     const double sb = (double)storage_bytes(h->storage), fb = (double)force_bytes(h->storage);
     out[0] = d.cs2;
     out[1] = d.nu;
     out[2] = d.zeta;
-    out[3] = h->q[0];
+    out[3] = h->q[run];
     out[4] = d.csm2;
     out[5] = d.eta;
     out[6] = d.tau_m;
@@ -1151,6 +1180,8 @@ int goc_lbm_derived(const goc_lbm_t* h, double out[16])
     out[15] = d.ny;
     return GOC_OK;
 }
+
+int goc_lbm_derived(const goc_lbm_t* h, double out[16]) { return goc_lbm_derived_run(h, 0, out); }
 
 int goc_lbm_metric(const goc_lbm_t* h, double* h1, double* th11, double* h2, double* th22)
 {
