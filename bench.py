@@ -200,6 +200,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--waves", type=float, default=0.0, metavar="W",
+                    help="fixed launch plan of W waves per CU instead of the autotuner "
+                         "(for profiler runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB mebibytes (counter calibration)")
     args = ap.parse_args()
@@ -217,7 +220,11 @@ def main():
 
     case = W.cavity_1024() if args.workload == "cavity_1024" else W.hartmann_4096()
     run = B.Run(case)
-    tuned = run.tune(20)          # launch-plan autotuner (state unchanged)
+    if args.waves > 0:
+        run.set_launch(args.waves)
+        tuned = {"us_before": float("nan")}
+    else:
+        tuned = run.tune(20)      # launch-plan autotuner (state unchanged)
     launch = run.launch_info()
     wall, ev = time_run(run, args.steps, args.warmup)
     d = run.derived()
@@ -254,7 +261,8 @@ def main():
                      "kernel": "goc::step_kernel",
                      "launch_plan": {"waves_per_cu": launch["waves_per_cu"], "work_groups": launch["blocks"],
                                      "rows_per_segment": round(launch["rows_per_segment"], 2),
-                                     "untuned_us": round(tuned["us_before"], 2)}},
+                                     "untuned_us": (round(tuned["us_before"], 2)
+                                                    if tuned["us_before"] == tuned["us_before"] else None)}},
     }
     run.close()
 

@@ -173,33 +173,32 @@ __host__ __device__ inline uint32_t mix32(uint32_t x)
     return x;
 }
 
-// Uniform draw in [-1/2, 1/2) from the top 24 bits of r.
-__device__ inline float dither_u(uint32_t r) { return float(r >> 8) * 0x1p-24f - 0.5f; }
-
-// Power of two of the binade of x (0 for zero and subnormals).
-__device__ inline float binade(float x) { return __uint_as_float(__float_as_uint(x) & 0x7f800000u); }
-
-// a + b rounded stochastically to FP32: s = RN(a + b), e its exact
-// residual (TwoSum, for any magnitudes of a and b), then RN(s + e + u ulp(s))
-// lands on the upper neighbour with probability e / ulp(s).
+// a + b rounded stochastically to FP32.  The sum is formed in FP64, where it
+// is exact (two FP32 values; b more than 29 binades below a is far below an
+// FP32 ulp of the result anyway); adding 29 random bits below the FP32
+// rounding point of the FP64 significand and truncating them lands on the
+// upper neighbour (in magnitude, so for either sign) with probability equal
+// to the discarded fraction: unbiased stochastic rounding.
 __device__ inline float sr_add(float a, float b, uint32_t r)
 {
-    const float s = a + b;
-    const float bb = s - a;
-    const float e = (a - (s - bb)) + (b - bb);
-    return s + __builtin_fmaf(dither_u(r), binade(s) * 0x1p-23f, e);
+    const double s = double(a) + double(b);
+    const uint64_t u = (uint64_t(__double_as_longlong(s)) + (r >> 3)) & ~uint64_t(0x1FFFFFFF);
+    return float(__longlong_as_double(int64_t(u)));
 }
 
 // ---------------------------------------------------------------------------
 // Storage codecs: FP64 and FP32 store the deviation itself, the 16-bit forms
-// store s * deviation with one scale s per direction class.  st_sr stores
-// base + inc with the unbiased rounding above (FP64: rounded to nearest).
+// store s * deviation with one scale s per direction class.  put / st_sr
+// store base + inc with the unbiased rounding above (FP64: rounded to
+// nearest) at an address / at an element index.
 template <class S> struct Store;
 template <> struct Store<double> {
     static constexpr bool scaled = false;
     __device__ static double dec(double v, double) { return v; }
     __device__ static double ld(const double* p, int64_t i, double) { return p[i]; }
     __device__ static void st(double* p, int64_t i, double v, double) { p[i] = v; }
+    __device__ static double enc(double b, double inc, double, uint32_t) { return b + inc; }
+    __device__ static void put(double* q, double b, double inc, double, uint32_t) { *q = b + inc; }
     __device__ static void st_sr(double* p, int64_t i, double b, double inc, double, uint32_t) { p[i] = b + inc; }
 };
 template <> struct Store<float> {
@@ -207,6 +206,8 @@ template <> struct Store<float> {
     __device__ static float dec(float v, float) { return v; }
     __device__ static float ld(const float* p, int64_t i, float) { return p[i]; }
     __device__ static void st(float* p, int64_t i, float v, float) { p[i] = v; }
+    __device__ static float enc(float b, float inc, float, uint32_t r) { return sr_add(b, inc, r); }
+    __device__ static void put(float* q, float b, float inc, float, uint32_t r) { *q = sr_add(b, inc, r); }
     __device__ static void st_sr(float* p, int64_t i, float b, float inc, float, uint32_t r)
     {
         p[i] = sr_add(b, inc, r);
@@ -222,11 +223,16 @@ template <> struct Store<__half> {
     __device__ static float dec(__half v, float inv_s) { return __half2float(v) * inv_s; }
     __device__ static float ld(const __half* p, int64_t i, float inv_s) { return __half2float(p[i]) * inv_s; }
     __device__ static void st(__half* p, int64_t i, float v, float s) { p[i] = __float2half_rn(v * s); }
-    __device__ static void st_sr(__half* p, int64_t i, float b, float inc, float s, uint32_t r)
+    __device__ static __half enc(float b, float inc, float s, uint32_t r)
     {
         goc_f16x2 h = {};
         h = __builtin_amdgcn_cvt_sr_f16_f32(h, (b + inc) * s, r, false);
-        reinterpret_cast<uint16_t*>(p)[i] = uint16_t(__builtin_bit_cast(uint32_t, h));
+        return __builtin_bit_cast(__half, uint16_t(__builtin_bit_cast(uint32_t, h)));
+    }
+    __device__ static void put(__half* q, float b, float inc, float s, uint32_t r) { *q = enc(b, inc, s, r); }
+    __device__ static void st_sr(__half* p, int64_t i, float b, float inc, float s, uint32_t r)
+    {
+        put(p + i, b, inc, s, r);
     }
 };
 template <> struct Store<__hip_bfloat16> {
@@ -236,11 +242,19 @@ template <> struct Store<__hip_bfloat16> {
         return __bfloat162float(p[i]) * inv_s;
     }
     __device__ static void st(__hip_bfloat16* p, int64_t i, float v, float s) { p[i] = __float2bfloat16(v * s); }
-    __device__ static void st_sr(__hip_bfloat16* p, int64_t i, float b, float inc, float s, uint32_t r)
+    __device__ static __hip_bfloat16 enc(float b, float inc, float s, uint32_t r)
     {
         goc_bf16x2 h = {};
         h = __builtin_amdgcn_cvt_sr_bf16_f32(h, (b + inc) * s, r, false);
-        reinterpret_cast<uint16_t*>(p)[i] = uint16_t(__builtin_bit_cast(uint32_t, h));
+        return __builtin_bit_cast(__hip_bfloat16, uint16_t(__builtin_bit_cast(uint32_t, h)));
+    }
+    __device__ static void put(__hip_bfloat16* q, float b, float inc, float s, uint32_t r)
+    {
+        *q = enc(b, inc, s, r);
+    }
+    __device__ static void st_sr(__hip_bfloat16* p, int64_t i, float b, float inc, float s, uint32_t r)
+    {
+        put(p + i, b, inc, s, r);
     }
 };
 
@@ -325,6 +339,7 @@ __device__ inline NodeParams<T> node_params(const RunDesc& d)
 __device__ inline void opaque_v(float& x) { asm volatile("" : "+v"(x)); }
 __device__ inline void opaque_v(double& x) { asm volatile("" : "+v"(x)); }
 __device__ inline void opaque_v(int32_t& x) { asm volatile("" : "+v"(x)); }
+__device__ inline void opaque_v(uint32_t& x) { asm volatile("" : "+v"(x)); }
 
 // Metric at one node.
 template <class T>
@@ -440,17 +455,25 @@ __device__ inline void cm_collide(const NodeParams<T>& p, const NodeMetric<T>& g
     const T h1 = g.h1, h2 = g.h2;
     const T r21 = h2 * g.ih1, r12 = h1 * g.ih2;
     const T M0 = h1 * h2 * p.rho0, A = r21 * p.P0, Bm = r12 * p.P0;
-    const T c00 = M0 + m.m00, c20 = A + m.m20, c02 = Bm + m.m02;   // full moments
+    const T c00 = M0 + m.m00, c02 = Bm + m.m02;   // full moments
     // step 2: central moments (deviations from the rest central moments;
-    // the first-order ones enter only through the identity below)
+    // the first-order ones enter only through the identity below).  The
+    // shift to central moments factors into a shift by U1 along xi1 and one
+    // by U2 along xi2, each the binomial recurrence
+    //   k0 = m0, k1 = m1 - U m0, k2 = m2 - U (m1 + k1);
+    // the rest moments enter where they do not cancel (c00, c02 and, in the
+    // second shift, A + a20).
     const T U11 = U1 * U1, U22 = U2 * U2, U12 = U1 * U2;
-    const T k20 = m.m20 - T(2) * U1 * m.m10 + U11 * c00;
-    const T k02 = m.m02 - T(2) * U2 * m.m01 + U22 * c00;
-    const T k11 = m.m11 - U2 * m.m10 - U1 * m.m01 + U12 * c00;
-    const T k21 = m.m21 - T(2) * U1 * m.m11 + U11 * m.m01 - U2 * c20 + T(2) * U12 * m.m10 - U11 * U2 * c00;
-    const T k12 = m.m12 - T(2) * U2 * m.m11 + U22 * m.m10 - U1 * c02 + T(2) * U12 * m.m01 - U1 * U22 * c00;
-    const T k22 = m.m22 - T(2) * U1 * m.m12 + U11 * c02 - T(2) * U2 * m.m21 + T(4) * U12 * m.m11
-                - T(2) * U11 * U2 * m.m01 + U22 * c20 - T(2) * U1 * U22 * m.m10 + U11 * U22 * c00;
+    const T a10 = m.m10 - U1 * c00, a20 = m.m20 - U1 * (m.m10 + a10);
+    const T a11 = m.m11 - U1 * m.m01, a21 = m.m21 - U1 * (m.m11 + a11);
+    const T a12 = m.m12 - U1 * c02, a22 = m.m22 - U1 * (m.m12 + a12);
+    const T k01 = m.m01 - U2 * c00;
+    const T k20 = a20;
+    const T k02 = m.m02 - U2 * (m.m01 + k01);
+    const T k11 = a11 - U2 * a10;
+    const T k12 = a12 - U2 * (a11 + k11);
+    const T k21 = a21 - U2 * (A + a20);
+    const T k22 = a22 - U2 * (a21 + k21);
     // step 3: deviations of the central equilibria (binomial transform of the
     // Sec. 3 equilibria) with the corrections of Sec. 5
     const T h1m = h1 - T(1), h2m = h2 - T(1);
@@ -484,15 +507,19 @@ __device__ inline void cm_collide(const NodeParams<T>& p, const NodeMetric<T>& g
     const T d12 = w[7] * (e12 - k12);
     const T d22 = w[8] * (e22 - k22);
     const T d20 = T(0.5) * (d2s + d2d), d02 = T(0.5) * (d2s - d2d);
-    // step 4: raw-moment increments, F(U) applied to dk (dk00 = 0)
+    // step 4: raw-moment increments, F(U) applied to dk (dk00 = 0): the
+    // inverse shifts, by U2 along xi2 and then by U1 along xi1, each
+    //   n0 = d0, n1 = d1 + U d0, n2 = d2 + U (d1 + n1)
+    const T b11 = d11 + U2 * d10, b21 = d21 + U2 * d20;
+    const T b02 = d02 + T(2) * U2 * d01;
+    const T b12 = d12 + U2 * (d11 + b11), b22 = d22 + U2 * (d21 + b21);
     const T n10 = d10, n01 = d01;
     const T n20 = d20 + T(2) * U1 * d10;
-    const T n02 = d02 + T(2) * U2 * d01;
-    const T n11 = d11 + U2 * d10 + U1 * d01;
-    const T n21 = d21 + T(2) * U1 * d11 + U11 * d01 + U2 * d20 + T(2) * U12 * d10;
-    const T n12 = d12 + T(2) * U2 * d11 + U22 * d10 + U1 * d02 + T(2) * U12 * d01;
-    const T n22 = d22 + T(2) * U1 * d12 + U11 * d02 + T(2) * U2 * d21 + T(4) * U12 * d11
-                + T(2) * U11 * U2 * d01 + U22 * d20 + T(2) * U1 * U22 * d10;
+    const T n02 = b02;
+    const T n11 = b11 + U1 * d01;
+    const T n21 = b21 + U1 * (b11 + n11);
+    const T n12 = b12 + U1 * b02;
+    const T n22 = b22 + U1 * (b12 + n12);
     // step 5: population increments P^-1 dn
     const T hx = T(0.5) * (n20 - n22), hy = T(0.5) * (n02 - n22);
     const T gx = T(0.5) * (n10 - n12), gy = T(0.5) * (n01 - n21);
@@ -570,10 +597,16 @@ __device__ inline void mie_node(const NodeParams<T>& p, const NodeMetric<T>& g, 
 // Geometry helpers of the strip / segment decomposition.
 
 // Balanced split of ny rows into segs segments of at least two rows.
-__device__ inline void seg_rows(int ny, int segs, int s, int& y0, int& y1)
+// Rows [y0, y1) of segment s of segs: whole groups of kRowGroup rows (the
+// step kernel marches a group per loop pass), the last one clipped at ny.
+// segs <= ceil(ny / kRowGroup), so no segment is empty.
+constexpr int kRowGroup = 4;
+__host__ __device__ inline void seg_rows(int ny, int segs, int s, int& y0, int& y1)
 {
-    y0 = (int)(((int64_t)ny * s) / segs);
-    y1 = (int)(((int64_t)ny * (s + 1)) / segs);
+    const int64_t groups = (ny + kRowGroup - 1) / kRowGroup;
+    y0 = kRowGroup * (int)((groups * s) / segs);
+    y1 = kRowGroup * (int)((groups * (s + 1)) / segs);
+    if (y1 > ny) y1 = ny;
 }
 
 // First column covered by lane 0 of strip k.  With x-walls the last strip

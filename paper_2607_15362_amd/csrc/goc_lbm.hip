@@ -309,7 +309,7 @@ void plan_rows(goc_lbm* h, std::vector<int32_t>& block_run)
         const double share = double((int64_t)d.nx * d.ny) / double(total_nodes);
         const int target = std::max(1, int(share * h->waves_per_cu * h->ncu));
         const int rows = choose_rows(d.ny, d.strips, target);
-        d.segs = std::max(1, std::min(d.ny / 2, (d.ny + rows - 1) / rows));
+        d.segs = std::max(1, std::min((d.ny + goc::kRowGroup - 1) / goc::kRowGroup, (d.ny + rows - 1) / rows));
         d.first_block = (int)block_run.size();
         for (int b = 0; b < d.strips * d.segs; ++b) block_run.push_back(r);
     }
@@ -398,6 +398,11 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
         d.bc_x = g.bc_x;
         d.bc_y = g.bc_y;
         d.plane = (int64_t)d.pitch * g.ny + 256;
+        // the step kernel addresses a run's slot pool (ten planes at most)
+        // with 32-bit byte offsets
+        if ((int64_t)(p.mhd ? 10 : 9) * d.plane * (int64_t)sb > (int64_t)UINT32_MAX)
+            return bail(fail(GOC_EINVAL, "run %d: grid %d x %d too large for this storage "
+                             "(slot pool of one run above 4 GiB)", r, g.nx, g.ny));
         d.f_off = f_elems;
         d.F_off = F_elems;
         d.g_off = g_elems;
@@ -963,7 +968,7 @@ int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
     if (!check_handle(h)) return GOC_EINVAL;
     if (!out) return fail(GOC_EINVAL, "out is NULL");
     if (trial_steps < 1 || trial_steps > 10000) return fail(GOC_EINVAL, "trial_steps %d outside [1, 10000]", trial_steps);
-    static const double cand[] = {2, 3, 4, 6, 8, 12, 16, 24, 32, 48};
+    static const double cand[] = {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96};
     const int ncand = (int)(sizeof(cand) / sizeof(cand[0]));
     struct Ev {
         hipEvent_t e[2] = {nullptr, nullptr};

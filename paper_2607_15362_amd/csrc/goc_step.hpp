@@ -63,8 +63,15 @@ __device__ inline RowGeo row_geo(const RunDesc& d, int r)
     return G;
 }
 
-__device__ inline bool row_ok(const RunDesc& d, int r) { return d.bc_y == 0 || (r >= 0 && r < d.ny); }
-__device__ inline int row_wrap(const RunDesc& d, int r) { return d.bc_y == 0 ? (r % d.ny + d.ny) % d.ny : r; }
+// (written with selects, no branches: the step kernel calls these for every
+// row on scalar values)
+__device__ inline bool row_ok(const RunDesc& d, int r) { return (d.bc_y == 0) | (uint32_t(r) < uint32_t(d.ny)); }
+// Rows within two of the domain (all the step asks for), wrapped when periodic.
+__device__ inline int row_wrap(const RunDesc& d, int r)
+{
+    const int w = r < 0 ? r + d.ny : (r >= d.ny ? r - d.ny : r);
+    return d.bc_y != 0 ? r : w;
+}
 
 // Element offset (within a run's pool region) of the slot pulled by
 // direction a into node (L.col, G.r): slot(a, x - e_a) in the interior,
@@ -120,12 +127,20 @@ __device__ inline void row_moments(const RunDesc& d, const FT* __restrict__ Fin,
     U2 = (m01 + T(0.5) * Fp2) * ih1 * irho;
 }
 
-// Rounding draws of a node's populations: the node hash hn times distinct
-// odd multipliers (D2Q9 populations 0-8, then the ten D2Q5 populations).
-__device__ inline uint32_t pop_draw(uint32_t hn, int a) { return hn * (0x9E3779B1u * uint32_t(2 * a + 1)); }
+// Rounding draws of a node's populations (D2Q9 populations 0-8, then the
+// ten D2Q5 populations): the low 24 bits of the node hash hn times distinct
+// odd 24-bit multipliers (a full-rate 24-bit multiply), whose high result
+// bits are the dither.
+__device__ inline uint32_t pop_draw(uint32_t hn, int a)
+{
+    return __umul24(hn, (0x9E3779u * uint32_t(2 * a + 1)) & 0xFFFFFFu | 1u);
+}
 
 // Metric table of the compute type: the FP64 tables for FP64 arithmetic,
 // their FP32 copy otherwise.
+// Read-only memory read at wave-uniform addresses (constant address space).
+template <class T> using CPtr = const __attribute__((address_space(4))) T*;
+
 template <class T> __device__ inline const T* table_of(const double* d, const float* f);
 template <> __device__ inline const double* table_of<double>(const double* d, const float*) { return d; }
 template <> __device__ inline const float* table_of<float>(const double*, const float* f) { return f; }
@@ -147,6 +162,47 @@ __device__ inline double from_next(double v)
     return __hiloint2double(hi, lo);
 }
 
+// Buffer resource over `bytes` bytes from `base` (raw 32-bit format).  The
+// hardware range-checks every lane's byte offset against `bytes`: beyond it
+// a load returns zero and a store writes nothing.  The step kernel issues
+// all its loads and stores unconditionally and turns the unneeded ones off
+// this way (bytes = 0 for a row it does not need, an offset of kOff for a
+// lane that owns no node): with no branch around any memory instruction,
+// the waits for a row's loads never include the loads issued after them.
+// bytes < 2^32: the library refuses larger runs at creation, so kOff lies
+// beyond every resource.
+constexpr uint32_t kOff = 0xFFFFFFFFu;
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, __builtin_bit_cast(int, bytes),
+                                             0x00020000);
+}
+template <class S>
+__device__ inline S buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    const int o = __builtin_bit_cast(int, off);
+    if constexpr (sizeof(S) == 2) {
+        return __builtin_bit_cast(S, (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, o, 0, 0));
+    } else if constexpr (sizeof(S) == 4) {
+        return __builtin_bit_cast(S, (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0));
+    } else {
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, o, 0, 0));
+    }
+}
+template <class S>
+__device__ inline void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t off, S v)
+{
+    const int o = __builtin_bit_cast(int, off);
+    if constexpr (sizeof(S) == 2) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, o, 0, 0);
+    } else if constexpr (sizeof(S) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, o, 0, 0);
+    } else {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, o, 0, 0);
+    }
+}
+
 // State of one pulled row in the marching window: the raw slots (storage
 // type, possibly still in flight), the decoded deviations and the moments.
 template <class S, class T, class FT>
@@ -158,48 +214,90 @@ struct RowSlot {
     T dr, U1, U2, Fp1, Fp2;
 };
 
-// Issue the loads of the nine slots pulled into row r (and its lagged
-// force).  Interior rows (0 < r < ny - 1): every direction's source row is
-// uniform, so the address is a per-(plane, row) base plus the lane's
-// constant offset off[a].  Rows 0 and ny - 1 (walls or periodic wrap) take
-// the general index.
+// Byte addressing of one run's pool regions, computed once per wave (a
+// region is below 4 GiB, so every offset within it fits in 32 bits).
+struct RunBytes {
+    const char *f, *F, *g;           // input regions (slots, lagged force, D2Q5)
+    char *fo, *Fo, *go;              // output regions
+    uint32_t pitch_s, pitch_F;       // one row of a slot / force plane
+    uint32_t f_all, F_all, g_all;    // region sizes: 9, 2 and 10 planes
+    uint32_t g_comp;                 // one D2Q5 component: 5 planes
+    int ny;
+};
+
 template <class S, class FT>
-__device__ inline void issue_row(const RunDesc& d, const S* __restrict__ fin, const FT* __restrict__ Fin,
-                                 const LaneCol& Ls, const int32_t* off, int r, S* raw, FT* Fr)
+__device__ inline RunBytes run_bytes(const RunDesc& d, const Pools<S, FT>& pl)
 {
-    const S* fb = fin + d.f_off;
-    if (r > 0 && r < d.ny - 1) {
-#pragma unroll
-        for (int a = 0; a < kQ; ++a)
-            raw[a] = (fb + (int64_t)a * d.plane + (int64_t)(r - ey_(a)) * d.pitch)[off[a]];
-    } else {
-        const RowGeo G = row_geo(d, r);
-#pragma unroll
-        for (int a = 0; a < kQ; ++a) raw[a] = fb[pull_index(d, Ls, G, a)];
-    }
-    const FT* Fb = Fin + d.F_off + (int64_t)r * d.pitch;
-    Fr[0] = Fb[Ls.col];
-    Fr[1] = Fb[Ls.col + d.plane];
+    RunBytes b;
+    b.f = reinterpret_cast<const char*>(pl.fin + d.f_off);
+    b.F = reinterpret_cast<const char*>(pl.Fin + d.F_off);
+    b.g = reinterpret_cast<const char*>(pl.gin + d.g_off);
+    b.fo = reinterpret_cast<char*>(pl.fout + d.f_off);
+    b.Fo = reinterpret_cast<char*>(pl.Fout + d.F_off);
+    b.go = reinterpret_cast<char*>(pl.gout + d.g_off);
+    b.pitch_s = uint32_t(d.pitch * sizeof(S));
+    b.pitch_F = uint32_t(d.pitch * sizeof(FT));
+    b.f_all = uint32_t(9 * d.plane * sizeof(S));
+    b.F_all = uint32_t(2 * d.plane * sizeof(FT));
+    b.g_all = uint32_t(10 * d.plane * sizeof(S));
+    b.g_comp = uint32_t(kM * d.plane * sizeof(S));
+    b.ny = d.ny;
+    return b;
 }
 
-// The same for the ten D2Q5 slots of row r.
-template <class S>
-__device__ inline void issue_row_g(const RunDesc& d, const S* __restrict__ gin, const LaneCol& Ls,
-                                   const int32_t* off, int r, S (*graw)[kM])
+// Issue the loads of the nine slots pulled into row r and of its lagged
+// force (byte offsets offF[2] of the lane's node in the two force planes);
+// valid = false issues them with an empty resource (zeros, no memory
+// access).  Interior rows (0 < r < ny - 1): every direction's source row is
+// uniform, so a slot is the lane's constant byte offset off[a] (plane,
+// source row relative to row r - 1, column; see the kernel) from the base of
+// row r - 1.  Rows 0 and ny - 1 (walls or periodic wrap) take the general
+// index.
+template <class S, class FT>
+__device__ inline void issue_row(const RunDesc& d, const RunBytes& b, const LaneCol& Ls, const uint32_t* off,
+                                 const uint32_t* offF, int r, bool valid, S* raw, FT* Fr)
 {
-    const S* gb = gin + d.g_off;
-    if (r > 0 && r < d.ny - 1) {
+    const int rv = valid ? r : 1;
+    if (rv > 0 && rv < b.ny - 1) {
+        const uint32_t e0 = uint32_t(rv - 1) * b.pitch_s;
+        const __amdgpu_buffer_rsrc_t rs = rsrc(b.f + e0, valid ? b.f_all - e0 : 0u);
+#pragma unroll
+        for (int a = 0; a < kQ; ++a) raw[a] = buf_ld<S>(rs, off[a]);
+    } else {
+        const RowGeo G = row_geo(d, rv);
+        const __amdgpu_buffer_rsrc_t rs = rsrc(b.f, valid ? b.f_all : 0u);
+#pragma unroll
+        for (int a = 0; a < kQ; ++a) raw[a] = buf_ld<S>(rs, uint32_t(pull_index(d, Ls, G, a)) * uint32_t(sizeof(S)));
+    }
+    const uint32_t eF = uint32_t(rv) * b.pitch_F;
+    const __amdgpu_buffer_rsrc_t rF = rsrc(b.F + eF, valid ? b.F_all - eF : 0u);
+    Fr[0] = buf_ld<FT>(rF, offF[0]);
+    Fr[1] = buf_ld<FT>(rF, offF[1]);
+}
+
+// The same for the ten D2Q5 slots of row r (component planes ci kM + a).
+template <class S>
+__device__ inline void issue_row_g(const RunDesc& d, const RunBytes& b, const LaneCol& Ls, const uint32_t* off,
+                                   int r, bool valid, S (*graw)[kM])
+{
+    const int rv = valid ? r : 1;
+    if (rv > 0 && rv < b.ny - 1) {
+        const uint32_t e0 = uint32_t(rv - 1) * b.pitch_s;
+#pragma unroll
+        for (int ci = 0; ci < 2; ++ci) {
+            const uint32_t e = ci * b.g_comp + e0;
+            const __amdgpu_buffer_rsrc_t rs = rsrc(b.g + e, valid ? b.g_all - e : 0u);
+#pragma unroll
+            for (int a = 0; a < kM; ++a) graw[ci][a] = buf_ld<S>(rs, off[a]);
+        }
+    } else {
+        const RowGeo G = row_geo(d, rv);
+        const __amdgpu_buffer_rsrc_t rs = rsrc(b.g, valid ? b.g_all : 0u);
 #pragma unroll
         for (int ci = 0; ci < 2; ++ci)
 #pragma unroll
             for (int a = 0; a < kM; ++a)
-                graw[ci][a] = (gb + (int64_t)(ci * kM + a) * d.plane + (int64_t)(r - ey_(a)) * d.pitch)[off[a]];
-    } else {
-        const RowGeo G = row_geo(d, r);
-#pragma unroll
-        for (int ci = 0; ci < 2; ++ci)
-#pragma unroll
-            for (int a = 0; a < kM; ++a) graw[ci][a] = gb[(int64_t)ci * kM * d.plane + pull_index(d, Ls, G, a)];
+                graw[ci][a] = buf_ld<S>(rs, ci * b.g_comp + uint32_t(pull_index(d, Ls, G, a)) * uint32_t(sizeof(S)));
     }
 }
 
@@ -242,8 +340,9 @@ __device__ inline void tile_of(const RunDesc& d, int local, int& strip, int& seg
 //   block_run[b]: run of work-group b.
 //   step_ctr[0] + k: the step's index in the sequence of rounding draws.
 // A wave owns 62 columns (lanes 1..62; lanes 0 and 63 are the x-halo) and a
-// segment of rows, and marches up the rows with three row slots (rows j-1,
-// j, j+1); the loads of row j+2 are in flight while row j is collided.
+// segment of rows, and marches up the rows with four row slots (rows j-1,
+// j, j+1, j+2); the loads of rows j+2 and j+3 are in flight while row j is
+// collided.
 template <class S, bool MHD>
 __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__ runs,
                                                      const int32_t* __restrict__ block_run,
@@ -278,22 +377,43 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
     const bool xwall_lo = d.bc_x != 0 && L.col == 0;
     const bool xwall_hi = d.bc_x != 0 && L.col == d.nx - 1;
     const T* ctab = table_of<T>(pl.col, pl.colf) + (int64_t)(d.col_off + Ls.col) * kTab;
-    const T* rtab = table_of<T>(pl.row, pl.rowf) + (int64_t)d.row_off * kTab;
+    // the row tables are read at wave-uniform indices through the constant
+    // address space: scalar loads, which the wave waits for on their own
+    // counter instead of behind the population loads in flight
+    const CPtr<T> rtab = (CPtr<T>)(table_of<T>(pl.row, pl.rowf) + (int64_t)d.row_off * kTab);
     const T h1_0 = ctab[T_H], ih1_0 = ctab[T_IH], th11_0 = ctab[T_TH];
     const T a1p_0 = ctab[T_AP], a1m_0 = ctab[T_AM], b1p_0 = ctab[T_BP], b1m_0 = ctab[T_BM];
-    // per-lane pull offsets of interior rows, relative to the (plane a,
-    // row r - ey) base: the source column, or through an x-wall the lane's
-    // own node in the opposite plane
-    int32_t off[kQ];
+    // per-lane pull offsets of interior rows in bytes, relative to the base
+    // of row r - 1: plane a, the source row r - ey and the source column, or
+    // through an x-wall the lane's own node (row r) in the opposite plane.
+    // All are non-negative and below 2^32.
+    uint32_t off[kQ];
 #pragma unroll
     for (int a = 0; a < kQ; ++a) {
         const int ex = ex_(a), ey = ey_(a);
+        int64_t e;
         if (ex == 0) {
-            off[a] = Ls.col;
+            e = (int64_t)a * d.plane + (1 - ey) * d.pitch + Ls.col;
         } else {
             const bool wx = ex > 0 ? Ls.wm : Ls.wp;
-            off[a] = wx ? (opp_(a) - a) * (int32_t)d.plane + ey * d.pitch + Ls.col : (ex > 0 ? Ls.cm : Ls.cp);
+            e = wx ? (int64_t)opp_(a) * d.plane + d.pitch + Ls.col
+                   : (int64_t)a * d.plane + (1 - ey) * d.pitch + (ex > 0 ? Ls.cm : Ls.cp);
         }
+        off[a] = uint32_t(e * (int64_t)sizeof(S));
+    }
+    const uint32_t offF[2] = {uint32_t(Ls.col * sizeof(FT)),     // the two force planes
+                              uint32_t((d.plane + Ls.col) * sizeof(FT))};
+    const RunBytes rb = run_bytes(d, pl);
+    // byte offsets of the writes from the base of output row j: plane and own
+    // column; kOff (discarded) for lanes that own no node
+    uint32_t wf[kQ], wF[2], wg[MHD ? 2 * kM : 1];
+#pragma unroll
+    for (int a = 0; a < kQ; ++a) wf[a] = own ? uint32_t(((int64_t)a * d.plane + L.col) * sizeof(S)) : kOff;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) wF[c] = own ? uint32_t(((int64_t)c * d.plane + L.col) * sizeof(FT)) : kOff;
+    if constexpr (MHD) {
+#pragma unroll
+        for (int a = 0; a < 2 * kM; ++a) wg[a] = own ? uint32_t(((int64_t)a * d.plane + L.col) * sizeof(S)) : kOff;
     }
     const T* sp = step_params<T>(d);
     T sinv[4], sfw[4], sginv = T(1), sgw = T(1);
@@ -307,32 +427,73 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
         sgw = sp[P_SCG];
     }
     auto ih2_of = [&](int r) { return rtab[(int64_t)r * kTab + T_IH]; };
+    // one resource per plane of output row j: the row's bytes (0: none)
+    // resource over a pool from output row j to its end (nplanes planes); no
+    // bytes when off
+    auto out_row = [&](char* region, uint32_t pitch, uint32_t all, int j, bool on) {
+        const uint32_t e = uint32_t(j) * pitch;
+        return rsrc(region + e, on ? all - e : 0u);
+    };
 
     int y0, y1;
     seg_rows(d.ny, d.segs, seg, y0, y1);
 
-    // window: A = row y0 - 1, B = row y0, C = row y0 + 1 (loads in flight)
-    Slot A, B, C;
-    A.dr = A.U2 = T(0);
-    if (row_ok(d, y0 - 1)) {
-        const int r = row_wrap(d, y0 - 1);
-        issue_row<S, FT>(d, pl.fin, pl.Fin, Ls, off, r, A.raw, A.Fr);
-        decode_row<S, T, FT>(A, sinv, p0.rho0, ih1_0, ih2_of(r));
+    // window: A = row y0 - 1, B = row y0, C = row y0 + 1 and D = row y0 + 2
+    // (loads in flight)
+    // (a row outside a walled domain is loaded as zeros and never used)
+    Slot A, B, C, D;
+    const bool ok_a = row_ok(d, y0 - 1);
+    const int ra = ok_a ? row_wrap(d, y0 - 1) : y0;
+    issue_row<S, FT>(d, rb, Ls, off, offF, ra, ok_a, A.raw, A.Fr);
+    issue_row<S, FT>(d, rb, Ls, off, offF, y0, true, B.raw, B.Fr);
+    issue_row<S, FT>(d, rb, Ls, off, offF, row_wrap(d, y0 + 1), row_ok(d, y0 + 1), C.raw, C.Fr);
+    issue_row<S, FT>(d, rb, Ls, off, offF, row_wrap(d, y0 + 2), y0 + 2 <= y1 && row_ok(d, y0 + 2),
+                     D.raw, D.Fr);
+    // D2Q5 slots of the segment's rows only (each row reads its own)
+    if constexpr (MHD) {
+        issue_row_g<S>(d, rb, Ls, off, y0, mhd_run, B.graw);
+        issue_row_g<S>(d, rb, Ls, off, row_wrap(d, y0 + 1), mhd_run && y0 + 1 < y1, C.graw);
+        issue_row_g<S>(d, rb, Ls, off, row_wrap(d, y0 + 2), mhd_run && y0 + 2 < y1, D.graw);
     }
-    issue_row<S, FT>(d, pl.fin, pl.Fin, Ls, off, y0, B.raw, B.Fr);
-    if (mhd_run) issue_row_g<S>(d, pl.gin, Ls, off, y0, B.graw);
-    if (row_ok(d, y0 + 1)) issue_row<S, FT>(d, pl.fin, pl.Fin, Ls, off, row_wrap(d, y0 + 1), C.raw, C.Fr);
+    // All four rows are in flight together; draining them here, once per
+    // segment, leaves nothing of the set-up pending at the loop entry, so the
+    // compiler's waits inside the loop follow the steady state (each row's
+    // loads waited for two rows after their issue) instead of the set-up's
+    // more recent loads.
+    __builtin_amdgcn_s_waitcnt(0);
+    decode_row<S, T, FT>(A, sinv, p0.rho0, ih1_0, ih2_of(ra));
     decode_row<S, T, FT>(B, sinv, p0.rho0, ih1_0, ih2_of(y0));
 
     const int64_t plane = d.plane;
-    // one row: P = row j - 1, Cs = row j, N = row j + 1
+    // one row: P = row j - 1, Cs = row j, N = row j + 1 (Q = row j + 2 has
+    // its loads in flight)
     auto row_step = [&](Slot& P, Slot& Cs, Slot& N, int j) {
         // the scheduler keeps each row to itself (interleaving the unrolled
         // rows only lengthens live ranges); the loads issued here complete
         // during the row's arithmetic
         __builtin_amdgcn_sched_barrier(0);
+        // The run's scalars (parameters, byte sizes, scales) are read again
+        // for every row, through a pointer the compiler cannot follow from
+        // one row to the next: they come from the scalar cache instead of
+        // occupying scalar registers through the whole march, which made the
+        // compiler spill them into vector lanes.
+        CPtr<RunDesc> drow = (CPtr<RunDesc>)&d;
+        asm volatile("" : "+s"(drow));
+        const RunDesc& d = *(const RunDesc*)drow;
+        const NodeParams<T> p = node_params<T>(d);
+        const RunBytes rb = run_bytes(d, pl);
+        const T* sp = step_params<T>(d);
+        T sinv[4], sfw[4], sginv = T(1), sgw = T(1);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            sinv[c] = Store<S>::scaled ? sp[P_ISC + c] : T(1);
+            sfw[c] = Store<S>::scaled ? sp[P_SC + c] : T(1);
+        }
+        if (Store<S>::scaled) {
+            sginv = sp[P_ISCG];
+            sgw = sp[P_SCG];
+        }
         // per-row opaque copies of the lane constants
-        const NodeParams<T>& p = p0;
         T h1 = h1_0, ih1 = ih1_0, th11 = th11_0, a1p = a1p_0, a1m = a1m_0, b1p = b1p_0, b1m = b1m_0;
         opaque_v(h1);
         opaque_v(ih1);
@@ -341,18 +502,34 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
         opaque_v(a1m);
         opaque_v(b1p);
         opaque_v(b1m);
-        // 1. loads of row j + 2 (into P, whose populations are done)
+        // the lane's byte offsets, also made opaque per row: their zero
+        // extension then stays in the row, where the loads and stores can
+        // take the scalar-base form (base in scalar registers + 32-bit lane
+        // offset) instead of a 64-bit vector address each
+        uint32_t off_r[kQ], offF_r[2] = {offF[0], offF[1]};
+#pragma unroll
+        for (int a = 0; a < kQ; ++a) {
+            off_r[a] = off[a];
+            opaque_v(off_r[a]);
+        }
+        opaque_v(offF_r[0]);
+        opaque_v(offF_r[1]);
+        const bool act = j < y1;             // a row of this segment (else stores off)
+        const int jt = min(j, d.ny - 1);     // table row (rows beyond the domain read the last)
+        // 1. loads of row j + 3 (into P, whose populations are done)
         const bool have_next = row_ok(d, j + 1);
-        const bool load2 = j + 2 <= y1 && row_ok(d, j + 2);
-        if (load2) issue_row<S, FT>(d, pl.fin, pl.Fin, Ls, off, row_wrap(d, j + 2), P.raw, P.Fr);
+        issue_row<S, FT>(d, rb, Ls, off_r, offF_r, row_wrap(d, j + 3), j + 3 <= y1 && row_ok(d, j + 3),
+                         P.raw, P.Fr);
+        if constexpr (MHD)
+            issue_row_g<S>(d, rb, Ls, off_r, row_wrap(d, j + 3), mhd_run && j + 3 < y1, P.graw);
         // 2. moments of row j + 1
-        if (have_next) decode_row<S, T, FT>(N, sinv, p.rho0, ih1, ih2_of(row_wrap(d, j + 1)));
+        decode_row<S, T, FT>(N, sinv, p.rho0, ih1, ih2_of(have_next ? min(row_wrap(d, j + 1), d.ny - 1) : jt));
 
         NodeMetric<T> g;
         g.h1 = h1;
         g.ih1 = ih1;
         g.th11 = th11;
-        const T* rt = rtab + (int64_t)j * kTab;
+        const CPtr<T> rt = rtab + (int64_t)jt * kTab;
         g.h2 = rt[T_H];
         g.ih2 = rt[T_IH];
         g.th22 = rt[T_TH];
@@ -360,13 +537,13 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
         T d2U2, d2r;
         if (d.bc_y != 0 && j == 0) {
             Slot W;
-            issue_row<S, FT>(d, pl.fin, pl.Fin, Ls, off, 2, W.raw, W.Fr);
+            issue_row<S, FT>(d, rb, Ls, off_r, offF_r, 2, true, W.raw, W.Fr);
             decode_row<S, T, FT>(W, sinv, p.rho0, ih1, ih2_of(2));
             d2U2 = T(0.5) * (T(-3) * Cs.U2 + T(4) * N.U2 - W.U2);
             d2r = T(0.5) * (T(-3) * Cs.dr + T(4) * N.dr - W.dr);
         } else if (d.bc_y != 0 && j == d.ny - 1) {
             Slot W;
-            issue_row<S, FT>(d, pl.fin, pl.Fin, Ls, off, j - 2, W.raw, W.Fr);
+            issue_row<S, FT>(d, rb, Ls, off_r, offF_r, j - 2, true, W.raw, W.Fr);
             decode_row<S, T, FT>(W, sinv, p.rho0, ih1, ih2_of(j - 2));
             d2U2 = T(0.5) * (T(3) * Cs.U2 - T(4) * P.U2 + W.U2);
             d2r = T(0.5) * (T(3) * Cs.dr - T(4) * P.dr + W.dr);
@@ -395,13 +572,12 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
 
         // 4. App. G: magnetic field, local derivatives, Lorentz force,
         //    collision and the D2Q5 writes (stored value = base + increment;
-        //    anti-bounce-back slots negate the post-collision value); then the
-        //    D2Q5 loads of row j + 1, in flight during the fluid collision
+        //    anti-bounce-back slots negate the post-collision value)
         T Fx1 = p.Fx1, Fx2 = p.Fx2;
         const RowGeo Gj = row_geo(d, j);
         const int64_t nn = (int64_t)j * d.pitch + L.col;
         const uint32_t hn = mix32(uint32_t(d.f_off + nn) ^ seed);
-        if (mhd_run) {
+        if constexpr (MHD) {   // (a plain run of a mixed batch: no D2Q5 memory access, no force)
             T dg[2][kM], dgi[2][kM];
 #pragma unroll
             for (int ci = 0; ci < 2; ++ci)
@@ -409,9 +585,11 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
                 for (int a = 0; a < kM; ++a) dg[ci][a] = T(Store<S>::dec(Cs.graw[ci][a], sginv));
             T B1, B2, FL1, FL2;
             mie_node<T>(p, g, dg, U1, U2, B1, B2, FL1, FL2, dgi);
-            Fx1 += FL1;
-            Fx2 += FL2;
-            if (own) {
+            if (mhd_run) {
+                Fx1 += FL1;
+                Fx2 += FL2;
+            }
+            {
                 const T b2p = rt[T_BP], b2m = rt[T_BM];
                 const T hh = g.h1 * g.h2;
 #pragma unroll
@@ -432,15 +610,14 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
                         dgi[1][a] += a == 1 ? g.h2 * b1p : a == 3 ? g.h2 * b1m : a == 2 ? g.h1 * b2p : g.h1 * b2m;
                     }
                 }
-                S* go = pl.gout + d.g_off + nn;
+                const __amdgpu_buffer_rsrc_t rg = out_row(rb.go, rb.pitch_s, rb.g_all, j, mhd_run && act);
 #pragma unroll
                 for (int ci = 0; ci < 2; ++ci)
 #pragma unroll
                     for (int a = 0; a < kM; ++a)
-                        Store<S>::st_sr(go, (ci * kM + a) * plane, dg[ci][a], dgi[ci][a], sgw,
-                                        pop_draw(hn, kQ + ci * kM + a));
+                        buf_st<S>(rg, wg[ci * kM + a],
+                                  Store<S>::enc(dg[ci][a], dgi[ci][a], sgw, pop_draw(hn, kQ + ci * kM + a)));
             }
-            if (j + 1 < y1) issue_row_g<S>(d, pl.gin, Ls, off, row_wrap(d, j + 1), N.graw);
         }
 
         // 5. effective force, corrections, central-moment collision
@@ -452,7 +629,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
         //    rest-state offsets of the interior axis slots (the reader is the
         //    neighbour; its rest state differs through the metric) and the
         //    reader's wall terms
-        if (own) {
+        {
             const T a2p = rt[T_AP], a2m = rt[T_AM];
             inc[1] += g.h2 * a1p;
             inc[3] += g.h2 * a1m;
@@ -472,23 +649,30 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
                 if (d.lid_corners || !xwall_lo) inc[7] += cw;
                 if (d.lid_corners || !xwall_hi) inc[8] -= cw;
             }
-            S* fo = pl.fout + d.f_off + nn;
+            const __amdgpu_buffer_rsrc_t rf = out_row(rb.fo, rb.pitch_s, rb.f_all, j, act);
 #pragma unroll
             for (int a = 0; a < kQ; ++a)
-                Store<S>::st_sr(fo, a * plane, Cs.f[a], inc[a], sfw[cls_(a)], pop_draw(hn, a));
-            pl.Fout[d.F_off + nn] = FT(F1);
-            pl.Fout[d.F_off + nn + plane] = FT(F2);
+                buf_st<S>(rf, wf[a], Store<S>::enc(Cs.f[a], inc[a], sfw[cls_(a)], pop_draw(hn, a)));
+            const __amdgpu_buffer_rsrc_t rF = out_row(rb.Fo, rb.pitch_F, rb.F_all, j, act);
+            buf_st<FT>(rF, wF[0], FT(F1));
+            buf_st<FT>(rF, wF[1], FT(F2));
         }
         __builtin_amdgcn_sched_barrier(0);
     };
 
-    // march with the three slots rotating roles (no moves between rows)
-    for (int j = y0; j < y1; j += 3) {
+    // march with the four slots rotating roles (no moves between rows), a
+    // group of four rows per pass.  The loop has a single exit and no code
+    // after it that reads the slots: an exit from inside the body, or slots
+    // live after the loop, would make the compiler join states at the loop
+    // entry or copy the slots there, and every wait would then include the
+    // loads in flight.  A segment is whole groups except at the top of the
+    // domain; rows of a group beyond the segment run with their stores off.
+    static_assert(kRowGroup == 4, "the march below unrolls four rows");
+    for (int j = y0; j < y1; j += 4) {
         row_step(A, B, C, j);
-        if (j + 1 >= y1) break;
-        row_step(B, C, A, j + 1);
-        if (j + 2 >= y1) break;
-        row_step(C, A, B, j + 2);
+        row_step(B, C, D, j + 1);
+        row_step(C, D, A, j + 2);
+        row_step(D, A, B, j + 3);
     }
 }
 
