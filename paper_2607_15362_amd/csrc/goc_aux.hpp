@@ -169,7 +169,7 @@ __global__ void init_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, 
     f[8] = T(0.25) * (-m11 - m21 + m12 + m22);
     for (int a = 0; a < kQ; ++a)
         Store<S>::st(pl.fout + d.f_off, slot_index(d, i, j, a), f[a], T(sc_of(d, a, Store<S>::scaled)));
-    const int64_t n = (int64_t)j * d.pitch + i;
+    const int64_t n = (int64_t)j * d.pitchF + i;   // force pool
     pl.Fout[d.F_off + n] = FT(0);
     pl.Fout[d.F_off + n + d.plane] = FT(0);
     if (d.mhd) {
@@ -211,7 +211,7 @@ __global__ void gather_kernel(const RunDesc* __restrict__ runs, int run, Pools<S
         const double dv = double(Store<S>::ld(pl.fin + d.f_off, slot_index(d, i, j, a), 1.0f)) / sc_of(d, a, sc);
         f[a * N + o] = dv + rest_pop(a, m.h1, m.h2, d.rho0, d.cs2);
     }
-    const int64_t n = (int64_t)j * d.pitch + i;
+    const int64_t n = (int64_t)j * d.pitchF + i;   // force pool
     F[o] = double(pl.Fin[d.F_off + n]);
     F[N + o] = double(pl.Fin[d.F_off + n + d.plane]);
     if (d.mhd && g) {
@@ -244,7 +244,7 @@ __global__ void scatter_kernel(const RunDesc* __restrict__ runs, int run, Pools<
         const double dv = f[a * N + o] - rest_pop(a, m.h1, m.h2, d.rho0, d.cs2);
         Store<S>::st(pl.fout + d.f_off, slot_index(d, i, j, a), T(dv), T(sc_of(d, a, sc)));
     }
-    const int64_t n = (int64_t)j * d.pitch + i;
+    const int64_t n = (int64_t)j * d.pitchF + i;   // force pool
     pl.Fout[d.F_off + n] = FT(F[o]);
     pl.Fout[d.F_off + n + d.plane] = FT(F[N + o]);
     if (d.mhd && g) {

@@ -9,7 +9,13 @@
 // removes every theta12 / theta21 term and makes the effective force equal
 // to its reduced form F~ (tau12 is not needed).
 //
-// State layout in HBM (structure of arrays, one plane per direction):
+// State layout in HBM (one plane per direction, rows interleaved): the
+// element of plane a at node (i, j) is at a * plane + j * pitch + i, with
+// plane the padded row length (nx rounded up to 64) and pitch the row
+// stride, Q * plane for the Q planes of a pool (9 for the populations; 10
+// for both the populations and the D2Q5 slots of an MHD run), so that the
+// planes of one row lie together; the two force planes have the row stride
+// pitchF = 2 * plane.
 //   slot(a, x) in plane a at the writer node x holds the population that
 //   leaves x along e_a after collision, minus the rest-state population of
 //   its reader (the node that pulls it), with the reader's wall condition
@@ -69,13 +75,13 @@ enum {
 };
 
 struct RunDesc {
-    int32_t nx, ny, pitch;
+    int32_t nx, ny, pitch;         // pitch: row stride of the slot pools (elements)
     int32_t bc_x, bc_y;            // 0 periodic, 1 wall
     int32_t strips, segs;          // launch geometry of this run
     int32_t first_block;           // first work-group of this run
     int32_t gi_terms, q3_sign, rho_terms, lid_corners, mhd;
-    int32_t pad_;
-    int64_t plane;                 // elements per plane (row pitch * ny + padding)
+    int32_t pitchF;                // row stride of the force pool
+    int64_t plane;                 // offset between planes within a row (the padded row length)
     int64_t f_off, F_off, g_off;   // element offsets of plane 0 in the f, force, g pools
     int64_t col_off, row_off;      // entry offsets into the column / row tables
     double cs2, nu, zeta;

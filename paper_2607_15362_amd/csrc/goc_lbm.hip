@@ -394,22 +394,26 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
         std::memset(&d, 0, sizeof(d));
         d.nx = g.nx;
         d.ny = g.ny;
-        d.pitch = (g.nx + 63) / 64 * 64;
+        const int32_t row = (g.nx + 63) / 64 * 64;
         d.bc_x = g.bc_x;
         d.bc_y = g.bc_y;
-        d.plane = (int64_t)d.pitch * g.ny + 256;
-        // the step kernel addresses a run's slot pool (ten planes at most)
-        // with 32-bit byte offsets
-        if ((int64_t)(p.mhd ? 10 : 9) * d.plane * (int64_t)sb > (int64_t)UINT32_MAX)
+        // rows interleaved: the planes of a row lie together (row stride
+        // Q * plane, Q = 9 planes, or 10 with the D2Q5 slots, which share it)
+        d.plane = row;
+        d.pitch = (p.mhd ? 10 : 9) * row;
+        d.pitchF = 2 * row;
+        const int64_t region = (int64_t)d.pitch * g.ny + 256, regionF = (int64_t)d.pitchF * g.ny + 256;
+        // the step kernel addresses a run's regions with 32-bit byte offsets
+        if (region * (int64_t)sb > (int64_t)UINT32_MAX)
             return bail(fail(GOC_EINVAL, "run %d: grid %d x %d too large for this storage "
-                             "(slot pool of one run above 4 GiB)", r, g.nx, g.ny));
+                             "(slot region of one run above 4 GiB)", r, g.nx, g.ny));
         d.f_off = f_elems;
         d.F_off = F_elems;
         d.g_off = g_elems;
-        f_elems += 9 * d.plane;
-        F_elems += 2 * d.plane;
+        f_elems += region;
+        F_elems += regionF;
         if (p.mhd) {
-            g_elems += 10 * d.plane;
+            g_elems += region;
             h->any_mhd = true;
         }
         d.col_off = sum_nx;

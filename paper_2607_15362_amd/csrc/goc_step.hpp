@@ -117,7 +117,7 @@ __device__ inline void row_moments(const RunDesc& d, const FT* __restrict__ Fin,
     Fp1 = T(0);
     Fp2 = T(0);
     if (L.valid) {
-        const int64_t n = d.F_off + (int64_t)r * d.pitch + L.col;
+        const int64_t n = d.F_off + (int64_t)r * d.pitchF + L.col;
         Fp1 = T(Fin[n]);
         Fp2 = T(Fin[n + d.plane]);
     }
@@ -220,8 +220,8 @@ struct RunBytes {
     const char *f, *F, *g;           // input regions (slots, lagged force, D2Q5)
     char *fo, *Fo, *go;              // output regions
     uint32_t pitch_s, pitch_F;       // one row of a slot / force plane
-    uint32_t f_all, F_all, g_all;    // region sizes: 9, 2 and 10 planes
-    uint32_t g_comp;                 // one D2Q5 component: 5 planes
+    uint32_t f_all, F_all, g_all;    // region sizes (ny rows each)
+    uint32_t g_comp;                 // one D2Q5 component: 5 planes of a row
     int ny;
 };
 
@@ -236,10 +236,10 @@ __device__ inline RunBytes run_bytes(const RunDesc& d, const Pools<S, FT>& pl)
     b.Fo = reinterpret_cast<char*>(pl.Fout + d.F_off);
     b.go = reinterpret_cast<char*>(pl.gout + d.g_off);
     b.pitch_s = uint32_t(d.pitch * sizeof(S));
-    b.pitch_F = uint32_t(d.pitch * sizeof(FT));
-    b.f_all = uint32_t(9 * d.plane * sizeof(S));
-    b.F_all = uint32_t(2 * d.plane * sizeof(FT));
-    b.g_all = uint32_t(10 * d.plane * sizeof(S));
+    b.pitch_F = uint32_t(d.pitchF * sizeof(FT));
+    b.f_all = uint32_t((int64_t)d.pitch * d.ny * sizeof(S));
+    b.F_all = uint32_t((int64_t)d.pitchF * d.ny * sizeof(FT));
+    b.g_all = b.f_all;
     b.g_comp = uint32_t(kM * d.plane * sizeof(S));
     b.ny = d.ny;
     return b;
@@ -502,26 +502,14 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
         opaque_v(a1m);
         opaque_v(b1p);
         opaque_v(b1m);
-        // the lane's byte offsets, also made opaque per row: their zero
-        // extension then stays in the row, where the loads and stores can
-        // take the scalar-base form (base in scalar registers + 32-bit lane
-        // offset) instead of a 64-bit vector address each
-        uint32_t off_r[kQ], offF_r[2] = {offF[0], offF[1]};
-#pragma unroll
-        for (int a = 0; a < kQ; ++a) {
-            off_r[a] = off[a];
-            opaque_v(off_r[a]);
-        }
-        opaque_v(offF_r[0]);
-        opaque_v(offF_r[1]);
         const bool act = j < y1;             // a row of this segment (else stores off)
         const int jt = min(j, d.ny - 1);     // table row (rows beyond the domain read the last)
         // 1. loads of row j + 3 (into P, whose populations are done)
         const bool have_next = row_ok(d, j + 1);
-        issue_row<S, FT>(d, rb, Ls, off_r, offF_r, row_wrap(d, j + 3), j + 3 <= y1 && row_ok(d, j + 3),
+        issue_row<S, FT>(d, rb, Ls, off, offF, row_wrap(d, j + 3), j + 3 <= y1 && row_ok(d, j + 3),
                          P.raw, P.Fr);
         if constexpr (MHD)
-            issue_row_g<S>(d, rb, Ls, off_r, row_wrap(d, j + 3), mhd_run && j + 3 < y1, P.graw);
+            issue_row_g<S>(d, rb, Ls, off, row_wrap(d, j + 3), mhd_run && j + 3 < y1, P.graw);
         // 2. moments of row j + 1
         decode_row<S, T, FT>(N, sinv, p.rho0, ih1, ih2_of(have_next ? min(row_wrap(d, j + 1), d.ny - 1) : jt));
 
@@ -537,13 +525,13 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
         T d2U2, d2r;
         if (d.bc_y != 0 && j == 0) {
             Slot W;
-            issue_row<S, FT>(d, rb, Ls, off_r, offF_r, 2, true, W.raw, W.Fr);
+            issue_row<S, FT>(d, rb, Ls, off, offF, 2, true, W.raw, W.Fr);
             decode_row<S, T, FT>(W, sinv, p.rho0, ih1, ih2_of(2));
             d2U2 = T(0.5) * (T(-3) * Cs.U2 + T(4) * N.U2 - W.U2);
             d2r = T(0.5) * (T(-3) * Cs.dr + T(4) * N.dr - W.dr);
         } else if (d.bc_y != 0 && j == d.ny - 1) {
             Slot W;
-            issue_row<S, FT>(d, rb, Ls, off_r, offF_r, j - 2, true, W.raw, W.Fr);
+            issue_row<S, FT>(d, rb, Ls, off, offF, j - 2, true, W.raw, W.Fr);
             decode_row<S, T, FT>(W, sinv, p.rho0, ih1, ih2_of(j - 2));
             d2U2 = T(0.5) * (T(3) * Cs.U2 - T(4) * P.U2 + W.U2);
             d2r = T(0.5) * (T(3) * Cs.dr - T(4) * P.dr + W.dr);
