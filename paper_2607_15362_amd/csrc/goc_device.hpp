@@ -30,11 +30,13 @@
 //   Lagged effective force: two planes per node (no streaming).
 //
 // Work decomposition: one wave64 work-group per (x-strip, y-segment).  The
-// 64 lanes cover 64 consecutive columns, of which the inner 62 are owned;
-// the wave marches up the rows of its segment keeping the moments of rows
-// j-2 .. j+1 in registers, so the finite differences of App. E step 3(a)
-// need no second pass: halo columns come from neighbouring lanes, halo rows
-// from the march (recomputed at segment ends from the pulled populations).
+// 64 lanes own 64 consecutive columns starting at a multiple of 64 (so that
+// every row access of a wave is line-aligned); the wave marches up the rows
+// of its segment keeping the moments of neighbouring rows in registers, so
+// the finite differences of App. E step 3(a) need no second pass: the
+// neighbouring columns come from neighbouring lanes, the two beyond the
+// strip from lanes 0 and 63, which also pull and decode those halo nodes,
+// and the halo rows from the march.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -47,7 +49,7 @@ namespace goc {
 constexpr int kQ = 9;
 constexpr int kM = 5;
 constexpr int kWave = 64;
-constexpr int kOwn = kWave - 2;
+constexpr int kOwn = kWave;   // columns owned per strip
 constexpr int kTab = 8;   // doubles per column / row table entry
 
 __host__ __device__ constexpr int ex_(int a) { return (a == 1 || a == 5 || a == 8) ? 1 : (a == 3 || a == 6 || a == 7) ? -1 : 0; }
@@ -604,15 +606,17 @@ __device__ inline void mie_node(const NodeParams<T>& p, const NodeMetric<T>& g, 
 
 // Balanced split of ny rows into segs segments of at least two rows.
 // Rows [y0, y1) of segment s of segs: whole groups of kRowGroup rows (the
-// step kernel marches a group per loop pass), the last one clipped at ny.
-// segs <= ceil(ny / kRowGroup), so no segment is empty.
+// step kernel marches a group per loop pass); the last segment also takes
+// the ny mod kRowGroup rows left over, so that every segment of a run with
+// ny >= kRowGroup has at least kRowGroup rows (the one-sided difference at
+// the top wall then finds row ny - 3 in the march).  segs <= row_groups(ny).
 constexpr int kRowGroup = 4;
+__host__ __device__ inline int row_groups(int ny) { return ny / kRowGroup > 1 ? ny / kRowGroup : 1; }
 __host__ __device__ inline void seg_rows(int ny, int segs, int s, int& y0, int& y1)
 {
-    const int64_t groups = (ny + kRowGroup - 1) / kRowGroup;
+    const int64_t groups = row_groups(ny);
     y0 = kRowGroup * (int)((groups * s) / segs);
-    y1 = kRowGroup * (int)((groups * (s + 1)) / segs);
-    if (y1 > ny) y1 = ny;
+    y1 = s == segs - 1 ? ny : kRowGroup * (int)((groups * (s + 1)) / segs);
 }
 
 // First column covered by lane 0 of strip k.  With x-walls the last strip
@@ -621,8 +625,11 @@ __host__ __device__ inline void seg_rows(int ny, int segs, int s, int& y0, int& 
 __host__ __device__ inline int lane_base(int nx, int bc_x, int k)
 {
     const int x0 = k * kOwn;
-    if (bc_x && nx - x0 < 2 && nx >= kWave - 1) return nx - (kWave - 1);
-    return x0 - 1;
+    // with x-walls a last strip holding only the wall column starts one
+    // column early: the one-sided difference there needs the two columns
+    // before it, which lane 0 and lane 0's halo then provide
+    if (bc_x && nx - x0 == 1) return x0 - 1;
+    return x0;
 }
 
 template <class T>

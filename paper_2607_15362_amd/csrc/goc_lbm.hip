@@ -309,7 +309,7 @@ void plan_rows(goc_lbm* h, std::vector<int32_t>& block_run)
         const double share = double((int64_t)d.nx * d.ny) / double(total_nodes);
         const int target = std::max(1, int(share * h->waves_per_cu * h->ncu));
         const int rows = choose_rows(d.ny, d.strips, target);
-        d.segs = std::max(1, std::min((d.ny + goc::kRowGroup - 1) / goc::kRowGroup, (d.ny + rows - 1) / rows));
+        d.segs = std::max(1, std::min(goc::row_groups(d.ny), (d.ny + rows - 1) / rows));
         d.first_block = (int)block_run.size();
         for (int b = 0; b < d.strips * d.segs; ++b) block_run.push_back(r);
     }

@@ -301,6 +301,35 @@ __device__ inline void issue_row_g(const RunDesc& d, const RunBytes& b, const La
     }
 }
 
+// Issue the loads of the halo node of lanes 0 and 63 in row r (the node
+// beside the strip that the differences along xi1 need): its nine pulled
+// slots and the first component of its lagged force.  hoff / hoffF are the
+// interior-row offsets from the kernel, kOff (off) for every other lane and
+// where no halo node is needed; valid = false issues none.
+template <class S, class FT>
+__device__ inline void issue_halo(const RunDesc& d, const RunBytes& b, const LaneCol& Lh, bool hneed,
+                                  const uint32_t* hoff, uint32_t hoffF, int r, bool valid, S* hraw, FT& hF)
+{
+    const int rv = valid ? r : 1;
+    if (rv > 0 && rv < b.ny - 1) {
+        const uint32_t e0 = uint32_t(rv - 1) * b.pitch_s;
+        const __amdgpu_buffer_rsrc_t rs = rsrc(b.f + e0, valid ? b.f_all - e0 : 0u);
+#pragma unroll
+        for (int a = 0; a < kQ; ++a) hraw[a] = buf_ld<S>(rs, hoff[a]);
+    } else {
+        const RowGeo G = row_geo(d, rv);
+        const __amdgpu_buffer_rsrc_t rs = rsrc(b.f, valid ? b.f_all : 0u);
+        // (or-ing kOff into the offsets of the other lanes, rather than a
+        // select, keeps the compiler from branching around each load)
+        const uint32_t hmask = hneed ? 0u : kOff;
+#pragma unroll
+        for (int a = 0; a < kQ; ++a)
+            hraw[a] = buf_ld<S>(rs, (uint32_t(pull_index(d, Lh, G, a)) * uint32_t(sizeof(S))) | hmask);
+    }
+    const uint32_t eF = uint32_t(rv) * b.pitch_F;
+    hF = buf_ld<FT>(rsrc(b.F + eF, valid ? b.F_all - eF : 0u), hoffF);
+}
+
 // Decode a pulled row and form its moments: dr = rho - rho0 = dm00/(h1 h2),
 // U1 = (dm10 + F1/2)/(rho h2), U2 = (dm01 + F2/2)/(rho h1) with the lagged
 // effective force (App. E step 7).
@@ -339,10 +368,11 @@ __device__ inline void tile_of(const RunDesc& d, int local, int& strip, int& seg
 //   grid.x = total work-groups, block = 64 (one wave).
 //   block_run[b]: run of work-group b.
 //   step_ctr[0] + k: the step's index in the sequence of rounding draws.
-// A wave owns 62 columns (lanes 1..62; lanes 0 and 63 are the x-halo) and a
+// A wave owns 64 columns (one per lane, starting at a multiple of 64) and a
 // segment of rows, and marches up the rows with four row slots (rows j-1,
 // j, j+1, j+2); the loads of rows j+2 and j+3 are in flight while row j is
-// collided.
+// collided.  Lanes 0 and 63 also pull the node beside the strip, one row
+// ahead, for the differences along xi1.
 template <class S, bool MHD>
 __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__ runs,
                                                      const int32_t* __restrict__ block_run,
@@ -373,7 +403,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
     }
     const int x0 = strip * kOwn;
     const int x1 = min(x0 + kOwn, d.nx);
-    const bool own = lane >= 1 && lane <= kWave - 2 && craw >= x0 && craw < x1;
+    const bool own = craw >= x0 && craw < x1;
     const bool xwall_lo = d.bc_x != 0 && L.col == 0;
     const bool xwall_hi = d.bc_x != 0 && L.col == d.nx - 1;
     const T* ctab = table_of<T>(pl.col, pl.colf) + (int64_t)(d.col_off + Ls.col) * kTab;
@@ -403,6 +433,28 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
     }
     const uint32_t offF[2] = {uint32_t(Ls.col * sizeof(FT)),     // the two force planes
                               uint32_t((d.plane + Ls.col) * sizeof(FT))};
+    // halo nodes of the differences along xi1: the column left of lane 0 and
+    // right of lane 63 (wrapped when periodic; none beyond a wall, where the
+    // one-sided difference is used), pulled like an own node by that lane
+    const bool hl = lane == 0, hr = lane == kWave - 1;
+    const LaneCol Lh = lane_col(d, hl ? craw - 1 : craw + 1);
+    const bool hneed = (hl || hr) && Lh.valid;
+    uint32_t hoff[kQ];
+#pragma unroll
+    for (int a = 0; a < kQ; ++a) {
+        const int ex = ex_(a), ey = ey_(a);
+        int64_t e;
+        if (ex == 0) {
+            e = (int64_t)a * d.plane + (1 - ey) * d.pitch + Lh.col;
+        } else {
+            const bool wx = ex > 0 ? Lh.wm : Lh.wp;
+            e = wx ? (int64_t)opp_(a) * d.plane + d.pitch + Lh.col
+                   : (int64_t)a * d.plane + (1 - ey) * d.pitch + (ex > 0 ? Lh.cm : Lh.cp);
+        }
+        hoff[a] = hneed ? uint32_t(e * (int64_t)sizeof(S)) : kOff;
+    }
+    const uint32_t hoffF = hneed ? uint32_t(Lh.col * sizeof(FT)) : kOff;
+    const T ih1h = table_of<T>(pl.col, pl.colf)[(int64_t)(d.col_off + (hneed ? Lh.col : Ls.col)) * kTab + T_IH];
     const RunBytes rb = run_bytes(d, pl);
     // byte offsets of the writes from the base of output row j: plane and own
     // column; kOff (discarded) for lanes that own no node
@@ -455,6 +507,9 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
         issue_row_g<S>(d, rb, Ls, off, row_wrap(d, y0 + 1), mhd_run && y0 + 1 < y1, C.graw);
         issue_row_g<S>(d, rb, Ls, off, row_wrap(d, y0 + 2), mhd_run && y0 + 2 < y1, D.graw);
     }
+    S hraw[kQ];   // halo node of the next row (lanes 0 and 63)
+    FT hF;
+    issue_halo<S, FT>(d, rb, Lh, hneed, hoff, hoffF, y0, true, hraw, hF);
     // All four rows are in flight together; draining them here, once per
     // segment, leaves nothing of the set-up pending at the loop entry, so the
     // compiler's waits inside the loop follow the steady state (each row's
@@ -465,9 +520,9 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
     decode_row<S, T, FT>(B, sinv, p0.rho0, ih1_0, ih2_of(y0));
 
     const int64_t plane = d.plane;
-    // one row: P = row j - 1, Cs = row j, N = row j + 1 (Q = row j + 2 has
-    // its loads in flight)
-    auto row_step = [&](Slot& P, Slot& Cs, Slot& N, int j) {
+    // one row: P = row j - 1, Cs = row j, N = row j + 1, Q = row j + 2 (its
+    // loads in flight; its moments still those of row j - 2)
+    auto row_step = [&](Slot& P, Slot& Cs, Slot& N, Slot& Q, int j) {
         // the scheduler keeps each row to itself (interleaving the unrolled
         // rows only lengthens live ranges); the loads issued here complete
         // during the row's arithmetic
@@ -504,6 +559,31 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
         opaque_v(b1m);
         const bool act = j < y1;             // a row of this segment (else stores off)
         const int jt = min(j, d.ny - 1);     // table row (rows beyond the domain read the last)
+        // 0. the halo node of row j (its loads were issued one row earlier,
+        //    before those of row j + 2), decoded as decode_row does; then
+        //    the halo loads of row j + 1
+        T hU, hR;
+        {
+            const T ih2j = rtab[(int64_t)jt * kTab + T_IH];
+            T hf[kQ];
+#pragma unroll
+            for (int a = 0; a < kQ; ++a) hf[a] = Store<S>::dec(hraw[a], sinv[cls_(a)]);
+            const T m00 = ((hf[0] + hf[1]) + (hf[2] + hf[3])) + ((hf[4] + hf[5]) + (hf[6] + hf[7])) + hf[8];
+            const T m10 = (hf[1] - hf[3]) + ((hf[5] - hf[6]) + (hf[8] - hf[7]));
+            hR = m00 * ih1h * ih2j;
+            const T irho = recip_sum(p.rho0, hR);
+            hU = (m10 + T(0.5) * T(hF)) * ih2j * irho;
+        }
+        // (kept here: decoded later, the halo registers would have to be
+        // duplicated while the next row's halo is in flight)
+        opaque_v(hU);
+        opaque_v(hR);
+        __builtin_amdgcn_sched_barrier(0);
+        issue_halo<S, FT>(d, rb, Lh, hneed, hoff, hoffF, row_wrap(d, j + 1), j + 1 < y1 && row_ok(d, j + 1), hraw,
+                          hF);
+        // (the halo loads go out first: the wait for them one row later then
+        // leaves the loads of row j + 3 in flight)
+        __builtin_amdgcn_sched_barrier(0);
         // 1. loads of row j + 3 (into P, whose populations are done)
         const bool have_next = row_ok(d, j + 1);
         issue_row<S, FT>(d, rb, Ls, off, offF, row_wrap(d, j + 3), j + 3 <= y1 && row_ok(d, j + 3),
@@ -523,18 +603,24 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
         g.th22 = rt[T_TH];
         // 3. differences along xi2 (one-sided next to walls)
         T d2U2, d2r;
+        // (the rows these need are in the march: no load here, as a load in
+        // a branch would make the compiler's later waits conservative)
         if (d.bc_y != 0 && j == 0) {
+            // row 2: the raw slots of Q (the segment starts at row 0, so
+            // they were loaded, and waited for, at its set-up)
             Slot W;
-            issue_row<S, FT>(d, rb, Ls, off, offF, 2, true, W.raw, W.Fr);
+#pragma unroll
+            for (int a = 0; a < kQ; ++a) W.raw[a] = Q.raw[a];
+            W.Fr[0] = Q.Fr[0];
+            W.Fr[1] = Q.Fr[1];
             decode_row<S, T, FT>(W, sinv, p.rho0, ih1, ih2_of(2));
             d2U2 = T(0.5) * (T(-3) * Cs.U2 + T(4) * N.U2 - W.U2);
             d2r = T(0.5) * (T(-3) * Cs.dr + T(4) * N.dr - W.dr);
         } else if (d.bc_y != 0 && j == d.ny - 1) {
-            Slot W;
-            issue_row<S, FT>(d, rb, Ls, off, offF, j - 2, true, W.raw, W.Fr);
-            decode_row<S, T, FT>(W, sinv, p.rho0, ih1, ih2_of(j - 2));
-            d2U2 = T(0.5) * (T(3) * Cs.U2 - T(4) * P.U2 + W.U2);
-            d2r = T(0.5) * (T(3) * Cs.dr - T(4) * P.dr + W.dr);
+            // row ny - 3: the moments Q still holds (the top segment has at
+            // least four rows, or starts at row 0 when ny = 3)
+            d2U2 = T(0.5) * (T(3) * Cs.U2 - T(4) * P.U2 + Q.U2);
+            d2r = T(0.5) * (T(3) * Cs.dr - T(4) * P.dr + Q.dr);
         } else {
             d2U2 = T(0.5) * (N.U2 - P.U2);
             d2r = T(0.5) * (N.dr - P.dr);
@@ -543,8 +629,19 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
         const T drho = Cs.dr, rho = p.rho0 + drho, U1 = Cs.U1, U2 = Cs.U2;
         // (the lane shifts run with every lane active: a shift inside a
         // lane-divergent branch would read inactive lanes)
-        const T Um1 = from_prev(U1), Up1 = from_next(U1);
-        const T rm1 = from_prev(drho), rp1 = from_next(drho);
+        // (the shifts are pinned before the halo values replace them in lanes
+        // 0 and 63: folded into the selects, the compiler would shift under a
+        // mask without lanes 0 / 63, and their neighbours would then read the
+        // halo value instead of the lane's own)
+        T Um1 = from_prev(U1), Up1 = from_next(U1), rm1 = from_prev(drho), rp1 = from_next(drho);
+        opaque_v(Um1);
+        opaque_v(Up1);
+        opaque_v(rm1);
+        opaque_v(rp1);
+        Um1 = hl ? hU : Um1;
+        Up1 = hr ? hU : Up1;
+        rm1 = hl ? hR : rm1;
+        rp1 = hr ? hR : rp1;
         T d1U1 = T(0.5) * (Up1 - Um1), d1r = T(0.5) * (rp1 - rm1);
         if (d.bc_x != 0) {   // one-sided next to x-walls
             const T Up2 = from_next(Up1), rp2 = from_next(rp1);
@@ -657,10 +754,10 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
     // domain; rows of a group beyond the segment run with their stores off.
     static_assert(kRowGroup == 4, "the march below unrolls four rows");
     for (int j = y0; j < y1; j += 4) {
-        row_step(A, B, C, j);
-        row_step(B, C, D, j + 1);
-        row_step(C, D, A, j + 2);
-        row_step(D, A, B, j + 3);
+        row_step(A, B, C, D, j);
+        row_step(B, C, D, A, j + 1);
+        row_step(C, D, A, B, j + 2);
+        row_step(D, A, B, C, j + 3);
     }
 }
 
