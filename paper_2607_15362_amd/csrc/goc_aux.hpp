@@ -73,6 +73,34 @@ __device__ inline int64_t slot_index(const RunDesc& d, int i, int j, int a)
     return (int64_t)pa * d.plane + (int64_t)sj * d.pitch + si;
 }
 
+// The ghost slot (row -1 or ny of the slot region) from which the step kernel
+// pulls direction a into node (i, j), when that pull leaves the domain in y
+// and does not bounce back through an x-wall first; false otherwise.  For
+// a y-wall it holds what slot_index gives (the bounced value), for periodic y
+// a copy of the wrapped slot.
+__device__ inline bool ghost_index(const RunDesc& d, int i, int j, int a, int64_t& idx)
+{
+    const int sj = j - ey_(a);
+    if (sj >= 0 && sj < d.ny) return false;
+    int si = i - ex_(a);
+    if (si < 0 || si >= d.nx) {
+        if (d.bc_x != 0) return false;
+        si = si < 0 ? si + d.nx : si - d.nx;
+    }
+    idx = (int64_t)a * d.plane + (int64_t)sj * d.pitch + si;
+    return true;
+}
+
+// Store the deviation of population a of node (i, j) at the slot its pull
+// reads (and at the step kernel's ghost copy of it).
+template <class S, class T>
+__device__ inline void put_slot(S* base, const RunDesc& d, int i, int j, int a, T v, T s)
+{
+    Store<S>::st(base, slot_index(d, i, j, a), v, s);
+    int64_t gi;
+    if (ghost_index(d, i, j, a, gi)) Store<S>::st(base, gi, v, s);
+}
+
 __device__ inline double sc_of(const RunDesc& d, int a, bool scaled) { return scaled ? d.sc[cls_(a)] : 1.0; }
 
 // Per-node metric of run d (FP64).
@@ -168,7 +196,7 @@ __global__ void init_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, 
     f[7] = T(0.25) * (m11 - m21 - m12 + m22);
     f[8] = T(0.25) * (-m11 - m21 + m12 + m22);
     for (int a = 0; a < kQ; ++a)
-        Store<S>::st(pl.fout + d.f_off, slot_index(d, i, j, a), f[a], T(sc_of(d, a, Store<S>::scaled)));
+        put_slot<S, T>(pl.fout + d.f_off, d, i, j, a, f[a], T(sc_of(d, a, Store<S>::scaled)));
     const int64_t n = (int64_t)j * d.pitchF + i;   // force pool
     pl.Fout[d.F_off + n] = FT(0);
     pl.Fout[d.F_off + n + d.plane] = FT(0);
@@ -188,7 +216,7 @@ __global__ void init_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, 
                 const T W = a == 0 ? p.W0 : p.W1;
                 // g^eq(0) minus the rest state W h1 h2 B_rest
                 const T dg = W * (g.h1 * g.h2 * dB[ci] + (T(ex_(a)) * g.h2 * A1 + T(ey_(a)) * g.h1 * A2) * p.inv_csm2);
-                Store<S>::st(pl.gout + d.g_off + ci * kM * d.plane, slot_index(d, i, j, a), dg, sg);
+                put_slot<S, T>(pl.gout + d.g_off + ci * kM * d.plane, d, i, j, a, dg, sg);
             }
         }
     }
@@ -242,7 +270,7 @@ __global__ void scatter_kernel(const RunDesc* __restrict__ runs, int run, Pools<
     const bool sc = Store<S>::scaled;
     for (int a = 0; a < kQ; ++a) {
         const double dv = f[a * N + o] - rest_pop(a, m.h1, m.h2, d.rho0, d.cs2);
-        Store<S>::st(pl.fout + d.f_off, slot_index(d, i, j, a), T(dv), T(sc_of(d, a, sc)));
+        put_slot<S, T>(pl.fout + d.f_off, d, i, j, a, T(dv), T(sc_of(d, a, sc)));
     }
     const int64_t n = (int64_t)j * d.pitchF + i;   // force pool
     pl.Fout[d.F_off + n] = FT(F[o]);
@@ -252,8 +280,7 @@ __global__ void scatter_kernel(const RunDesc* __restrict__ runs, int run, Pools<
             for (int a = 0; a < kM; ++a) {
                 const double W = a == 0 ? 1.0 - 2.0 * d.csm2 : 0.5 * d.csm2;
                 const double dv = g[(ci * kM + a) * N + o] - (ci == 1 ? W * m.h1 * m.h2 * d.B0 : 0.0);
-                Store<S>::st(pl.gout + d.g_off + ci * kM * d.plane, slot_index(d, i, j, a), T(dv),
-                             T(sc ? d.scg : 1.0));
+                put_slot<S, T>(pl.gout + d.g_off + ci * kM * d.plane, d, i, j, a, T(dv), T(sc ? d.scg : 1.0));
             }
     }
 }

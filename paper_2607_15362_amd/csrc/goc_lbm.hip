@@ -402,14 +402,16 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
         d.plane = row;
         d.pitch = (p.mhd ? 10 : 9) * row;
         d.pitchF = 2 * row;
-        const int64_t region = (int64_t)d.pitch * g.ny + 256, regionF = (int64_t)d.pitchF * g.ny + 256;
+        // slot regions (populations, D2Q5) hold two ghost rows, -1 and ny, for
+        // the step kernel's pulls beyond the domain in y
+        const int64_t region = (int64_t)d.pitch * (g.ny + 2) + 256, regionF = (int64_t)d.pitchF * g.ny + 256;
         // the step kernel addresses a run's regions with 32-bit byte offsets
         if (region * (int64_t)sb > (int64_t)UINT32_MAX)
             return bail(fail(GOC_EINVAL, "run %d: grid %d x %d too large for this storage "
                              "(slot region of one run above 4 GiB)", r, g.nx, g.ny));
-        d.f_off = f_elems;
+        d.f_off = f_elems + d.pitch;   // row 0 (row -1 before it)
         d.F_off = F_elems;
-        d.g_off = g_elems;
+        d.g_off = g_elems + d.pitch;
         f_elems += region;
         F_elems += regionF;
         if (p.mhd) {

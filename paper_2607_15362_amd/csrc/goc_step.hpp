@@ -214,13 +214,17 @@ struct RowSlot {
     T dr, U1, U2, Fp1, Fp2;
 };
 
-// Byte addressing of one run's pool regions, computed once per wave (a
-// region is below 4 GiB, so every offset within it fits in 32 bits).
+// Byte addressing of one run's pool regions (a region is below 4 GiB, so
+// every offset within it fits in 32 bits).  The slot regions (f, g) start at
+// ghost row -1: row r begins (r + 1) rows in, and rows -1 and ny hold the
+// slots the pulls of rows 0 and ny - 1 take from beyond the domain in y
+// (the writers of those rows fill them).
 struct RunBytes {
-    const char *f, *F, *g;           // input regions (slots, lagged force, D2Q5)
+    const char *f, *F, *g;           // input regions (slots from row -1, lagged force, D2Q5 from row -1)
     char *fo, *Fo, *go;              // output regions
-    uint32_t pitch_s, pitch_F;       // one row of a slot / force plane
-    uint32_t f_all, F_all, g_all;    // region sizes (ny rows each)
+    uint32_t pitch_s, pitch_F;       // one row of the slot / force regions
+    uint32_t plane_s;                // one plane within a row
+    uint32_t f_all, F_all, g_all;    // region sizes (ny + 2, ny and ny + 2 rows)
     uint32_t g_comp;                 // one D2Q5 component: 5 planes of a row
     int ny;
 };
@@ -229,15 +233,16 @@ template <class S, class FT>
 __device__ inline RunBytes run_bytes(const RunDesc& d, const Pools<S, FT>& pl)
 {
     RunBytes b;
-    b.f = reinterpret_cast<const char*>(pl.fin + d.f_off);
+    b.f = reinterpret_cast<const char*>(pl.fin + (d.f_off - d.pitch));
     b.F = reinterpret_cast<const char*>(pl.Fin + d.F_off);
-    b.g = reinterpret_cast<const char*>(pl.gin + d.g_off);
-    b.fo = reinterpret_cast<char*>(pl.fout + d.f_off);
+    b.g = reinterpret_cast<const char*>(pl.gin + (d.g_off - d.pitch));
+    b.fo = reinterpret_cast<char*>(pl.fout + (d.f_off - d.pitch));
     b.Fo = reinterpret_cast<char*>(pl.Fout + d.F_off);
-    b.go = reinterpret_cast<char*>(pl.gout + d.g_off);
+    b.go = reinterpret_cast<char*>(pl.gout + (d.g_off - d.pitch));
     b.pitch_s = uint32_t(d.pitch * sizeof(S));
     b.pitch_F = uint32_t(d.pitchF * sizeof(FT));
-    b.f_all = uint32_t((int64_t)d.pitch * d.ny * sizeof(S));
+    b.plane_s = uint32_t(d.plane * sizeof(S));
+    b.f_all = uint32_t((int64_t)d.pitch * (d.ny + 2) * sizeof(S));
     b.F_all = uint32_t((int64_t)d.pitchF * d.ny * sizeof(FT));
     b.g_all = b.f_all;
     b.g_comp = uint32_t(kM * d.plane * sizeof(S));
@@ -248,27 +253,19 @@ __device__ inline RunBytes run_bytes(const RunDesc& d, const Pools<S, FT>& pl)
 // Issue the loads of the nine slots pulled into row r and of its lagged
 // force (byte offsets offF[2] of the lane's node in the two force planes);
 // valid = false issues them with an empty resource (zeros, no memory
-// access).  Interior rows (0 < r < ny - 1): every direction's source row is
-// uniform, so a slot is the lane's constant byte offset off[a] (plane,
-// source row relative to row r - 1, column; see the kernel) from the base of
-// row r - 1.  Rows 0 and ny - 1 (walls or periodic wrap) take the general
-// index.
+// access).  Every direction's source row is uniform (rows -1 and ny are the
+// ghost rows), so a slot is the lane's constant byte offset off[a] (plane,
+// source row relative to row r - 1, column; see the kernel) from the base
+// of row r - 1: one code path for every row.
 template <class S, class FT>
-__device__ inline void issue_row(const RunDesc& d, const RunBytes& b, const LaneCol& Ls, const uint32_t* off,
-                                 const uint32_t* offF, int r, bool valid, S* raw, FT* Fr)
+__device__ inline void issue_row(const RunBytes& b, const uint32_t* off, const uint32_t* offF, int r, bool valid,
+                                 S* raw, FT* Fr)
 {
-    const int rv = valid ? r : 1;
-    if (rv > 0 && rv < b.ny - 1) {
-        const uint32_t e0 = uint32_t(rv - 1) * b.pitch_s;
-        const __amdgpu_buffer_rsrc_t rs = rsrc(b.f + e0, valid ? b.f_all - e0 : 0u);
+    const int rv = valid ? r : 0;
+    const uint32_t e0 = uint32_t(rv) * b.pitch_s;   // row r - 1 (regions start at row -1)
+    const __amdgpu_buffer_rsrc_t rs = rsrc(b.f + e0, valid ? b.f_all - e0 : 0u);
 #pragma unroll
-        for (int a = 0; a < kQ; ++a) raw[a] = buf_ld<S>(rs, off[a]);
-    } else {
-        const RowGeo G = row_geo(d, rv);
-        const __amdgpu_buffer_rsrc_t rs = rsrc(b.f, valid ? b.f_all : 0u);
-#pragma unroll
-        for (int a = 0; a < kQ; ++a) raw[a] = buf_ld<S>(rs, uint32_t(pull_index(d, Ls, G, a)) * uint32_t(sizeof(S)));
-    }
+    for (int a = 0; a < kQ; ++a) raw[a] = buf_ld<S>(rs, off[a]);
     const uint32_t eF = uint32_t(rv) * b.pitch_F;
     const __amdgpu_buffer_rsrc_t rF = rsrc(b.F + eF, valid ? b.F_all - eF : 0u);
     Fr[0] = buf_ld<FT>(rF, offF[0]);
@@ -277,55 +274,33 @@ __device__ inline void issue_row(const RunDesc& d, const RunBytes& b, const Lane
 
 // The same for the ten D2Q5 slots of row r (component planes ci kM + a).
 template <class S>
-__device__ inline void issue_row_g(const RunDesc& d, const RunBytes& b, const LaneCol& Ls, const uint32_t* off,
-                                   int r, bool valid, S (*graw)[kM])
+__device__ inline void issue_row_g(const RunBytes& b, const uint32_t* off, int r, bool valid, S (*graw)[kM])
 {
-    const int rv = valid ? r : 1;
-    if (rv > 0 && rv < b.ny - 1) {
-        const uint32_t e0 = uint32_t(rv - 1) * b.pitch_s;
+    const int rv = valid ? r : 0;
+    const uint32_t e0 = uint32_t(rv) * b.pitch_s;
 #pragma unroll
-        for (int ci = 0; ci < 2; ++ci) {
-            const uint32_t e = ci * b.g_comp + e0;
-            const __amdgpu_buffer_rsrc_t rs = rsrc(b.g + e, valid ? b.g_all - e : 0u);
+    for (int ci = 0; ci < 2; ++ci) {
+        const uint32_t e = ci * b.g_comp + e0;
+        const __amdgpu_buffer_rsrc_t rs = rsrc(b.g + e, valid ? b.g_all - e : 0u);
 #pragma unroll
-            for (int a = 0; a < kM; ++a) graw[ci][a] = buf_ld<S>(rs, off[a]);
-        }
-    } else {
-        const RowGeo G = row_geo(d, rv);
-        const __amdgpu_buffer_rsrc_t rs = rsrc(b.g, valid ? b.g_all : 0u);
-#pragma unroll
-        for (int ci = 0; ci < 2; ++ci)
-#pragma unroll
-            for (int a = 0; a < kM; ++a)
-                graw[ci][a] = buf_ld<S>(rs, ci * b.g_comp + uint32_t(pull_index(d, Ls, G, a)) * uint32_t(sizeof(S)));
+        for (int a = 0; a < kM; ++a) graw[ci][a] = buf_ld<S>(rs, off[a]);
     }
 }
 
 // Issue the loads of the halo node of lanes 0 and 63 in row r (the node
 // beside the strip that the differences along xi1 need): its nine pulled
 // slots and the first component of its lagged force.  hoff / hoffF are the
-// interior-row offsets from the kernel, kOff (off) for every other lane and
-// where no halo node is needed; valid = false issues none.
+// offsets from the kernel, kOff (off) for every other lane and where no halo
+// node is needed; valid = false issues none.
 template <class S, class FT>
-__device__ inline void issue_halo(const RunDesc& d, const RunBytes& b, const LaneCol& Lh, bool hneed,
-                                  const uint32_t* hoff, uint32_t hoffF, int r, bool valid, S* hraw, FT& hF)
+__device__ inline void issue_halo(const RunBytes& b, const uint32_t* hoff, uint32_t hoffF, int r, bool valid,
+                                  S* hraw, FT& hF)
 {
-    const int rv = valid ? r : 1;
-    if (rv > 0 && rv < b.ny - 1) {
-        const uint32_t e0 = uint32_t(rv - 1) * b.pitch_s;
-        const __amdgpu_buffer_rsrc_t rs = rsrc(b.f + e0, valid ? b.f_all - e0 : 0u);
+    const int rv = valid ? r : 0;
+    const uint32_t e0 = uint32_t(rv) * b.pitch_s;
+    const __amdgpu_buffer_rsrc_t rs = rsrc(b.f + e0, valid ? b.f_all - e0 : 0u);
 #pragma unroll
-        for (int a = 0; a < kQ; ++a) hraw[a] = buf_ld<S>(rs, hoff[a]);
-    } else {
-        const RowGeo G = row_geo(d, rv);
-        const __amdgpu_buffer_rsrc_t rs = rsrc(b.f, valid ? b.f_all : 0u);
-        // (or-ing kOff into the offsets of the other lanes, rather than a
-        // select, keeps the compiler from branching around each load)
-        const uint32_t hmask = hneed ? 0u : kOff;
-#pragma unroll
-        for (int a = 0; a < kQ; ++a)
-            hraw[a] = buf_ld<S>(rs, (uint32_t(pull_index(d, Lh, G, a)) * uint32_t(sizeof(S))) | hmask);
-    }
+    for (int a = 0; a < kQ; ++a) hraw[a] = buf_ld<S>(rs, hoff[a]);
     const uint32_t eF = uint32_t(rv) * b.pitch_F;
     hF = buf_ld<FT>(rsrc(b.F + eF, valid ? b.F_all - eF : 0u), hoffF);
 }
@@ -467,6 +442,13 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
 #pragma unroll
         for (int a = 0; a < 2 * kM; ++a) wg[a] = own ? uint32_t(((int64_t)a * d.plane + L.col) * sizeof(S)) : kOff;
     }
+    // ghost-row writes of rows 0 and ny - 1: offsets within a plane row.
+    // Walls: the source column of the reader's pull (own column, or for the
+    // diagonal slots the neighbour's; none where the reader bounces in x
+    // instead); periodic: the own column (copies).
+    const uint32_t gw0 = own ? uint32_t(L.col * sizeof(S)) : kOff;
+    const uint32_t gw1 = !own ? kOff : d.bc_y != 0 ? (L.wm ? kOff : uint32_t(L.cm * sizeof(S))) : gw0;
+    const uint32_t gw2 = !own ? kOff : d.bc_y != 0 ? (L.wp ? kOff : uint32_t(L.cp * sizeof(S))) : gw0;
     const T* sp = step_params<T>(d);
     T sinv[4], sfw[4], sginv = T(1), sgw = T(1);
 #pragma unroll
@@ -482,8 +464,9 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
     // one resource per plane of output row j: the row's bytes (0: none)
     // resource over a pool from output row j to its end (nplanes planes); no
     // bytes when off
-    auto out_row = [&](char* region, uint32_t pitch, uint32_t all, int j, bool on) {
-        const uint32_t e = uint32_t(j) * pitch;
+    // (slot regions start at ghost row -1: row j is j + 1 rows in)
+    auto out_row = [&](char* region, uint32_t pitch, uint32_t all, int row_in, bool on) {
+        const uint32_t e = uint32_t(row_in) * pitch;
         return rsrc(region + e, on ? all - e : 0u);
     };
 
@@ -496,20 +479,20 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
     Slot A, B, C, D;
     const bool ok_a = row_ok(d, y0 - 1);
     const int ra = ok_a ? row_wrap(d, y0 - 1) : y0;
-    issue_row<S, FT>(d, rb, Ls, off, offF, ra, ok_a, A.raw, A.Fr);
-    issue_row<S, FT>(d, rb, Ls, off, offF, y0, true, B.raw, B.Fr);
-    issue_row<S, FT>(d, rb, Ls, off, offF, row_wrap(d, y0 + 1), row_ok(d, y0 + 1), C.raw, C.Fr);
-    issue_row<S, FT>(d, rb, Ls, off, offF, row_wrap(d, y0 + 2), y0 + 2 <= y1 && row_ok(d, y0 + 2),
+    issue_row<S, FT>(rb, off, offF, ra, ok_a, A.raw, A.Fr);
+    issue_row<S, FT>(rb, off, offF, y0, true, B.raw, B.Fr);
+    issue_row<S, FT>(rb, off, offF, row_wrap(d, y0 + 1), row_ok(d, y0 + 1), C.raw, C.Fr);
+    issue_row<S, FT>(rb, off, offF, row_wrap(d, y0 + 2), y0 + 2 <= y1 && row_ok(d, y0 + 2),
                      D.raw, D.Fr);
     // D2Q5 slots of the segment's rows only (each row reads its own)
     if constexpr (MHD) {
-        issue_row_g<S>(d, rb, Ls, off, y0, mhd_run, B.graw);
-        issue_row_g<S>(d, rb, Ls, off, row_wrap(d, y0 + 1), mhd_run && y0 + 1 < y1, C.graw);
-        issue_row_g<S>(d, rb, Ls, off, row_wrap(d, y0 + 2), mhd_run && y0 + 2 < y1, D.graw);
+        issue_row_g<S>(rb, off, y0, mhd_run, B.graw);
+        issue_row_g<S>(rb, off, row_wrap(d, y0 + 1), mhd_run && y0 + 1 < y1, C.graw);
+        issue_row_g<S>(rb, off, row_wrap(d, y0 + 2), mhd_run && y0 + 2 < y1, D.graw);
     }
     S hraw[kQ];   // halo node of the next row (lanes 0 and 63)
     FT hF;
-    issue_halo<S, FT>(d, rb, Lh, hneed, hoff, hoffF, y0, true, hraw, hF);
+    issue_halo<S, FT>(rb, hoff, hoffF, y0, true, hraw, hF);
     // All four rows are in flight together; draining them here, once per
     // segment, leaves nothing of the set-up pending at the loop entry, so the
     // compiler's waits inside the loop follow the steady state (each row's
@@ -579,17 +562,17 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
         opaque_v(hU);
         opaque_v(hR);
         __builtin_amdgcn_sched_barrier(0);
-        issue_halo<S, FT>(d, rb, Lh, hneed, hoff, hoffF, row_wrap(d, j + 1), j + 1 < y1 && row_ok(d, j + 1), hraw,
+        issue_halo<S, FT>(rb, hoff, hoffF, row_wrap(d, j + 1), j + 1 < y1 && row_ok(d, j + 1), hraw,
                           hF);
         // (the halo loads go out first: the wait for them one row later then
         // leaves the loads of row j + 3 in flight)
         __builtin_amdgcn_sched_barrier(0);
         // 1. loads of row j + 3 (into P, whose populations are done)
         const bool have_next = row_ok(d, j + 1);
-        issue_row<S, FT>(d, rb, Ls, off, offF, row_wrap(d, j + 3), j + 3 <= y1 && row_ok(d, j + 3),
+        issue_row<S, FT>(rb, off, offF, row_wrap(d, j + 3), j + 3 <= y1 && row_ok(d, j + 3),
                          P.raw, P.Fr);
         if constexpr (MHD)
-            issue_row_g<S>(d, rb, Ls, off, row_wrap(d, j + 3), mhd_run && j + 3 < y1, P.graw);
+            issue_row_g<S>(rb, off, row_wrap(d, j + 3), mhd_run && j + 3 < y1, P.graw);
         // 2. moments of row j + 1
         decode_row<S, T, FT>(N, sinv, p.rho0, ih1, ih2_of(have_next ? min(row_wrap(d, j + 1), d.ny - 1) : jt));
 
@@ -695,13 +678,25 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
                         dgi[1][a] += a == 1 ? g.h2 * b1p : a == 3 ? g.h2 * b1m : a == 2 ? g.h1 * b2p : g.h1 * b2m;
                     }
                 }
-                const __amdgpu_buffer_rsrc_t rg = out_row(rb.go, rb.pitch_s, rb.g_all, j, mhd_run && act);
+                const __amdgpu_buffer_rsrc_t rg = out_row(rb.go, rb.pitch_s, rb.g_all, j + 1, mhd_run && act);
+                S eg[2][kM];
 #pragma unroll
                 for (int ci = 0; ci < 2; ++ci)
 #pragma unroll
-                    for (int a = 0; a < kM; ++a)
-                        buf_st<S>(rg, wg[ci * kM + a],
-                                  Store<S>::enc(dg[ci][a], dgi[ci][a], sgw, pop_draw(hn, kQ + ci * kM + a)));
+                    for (int a = 0; a < kM; ++a) {
+                        eg[ci][a] = Store<S>::enc(dg[ci][a], dgi[ci][a], sgw, pop_draw(hn, kQ + ci * kM + a));
+                        buf_st<S>(rg, wg[ci * kM + a], eg[ci][a]);
+                    }
+                // ghost rows (as for the populations below): plane 2 / 4 of
+                // each component, own column
+                const bool bot = j == 0, top = j == d.ny - 1, wall = d.bc_y != 0;
+                const bool on = mhd_run && act && (bot || top);
+                const uint32_t eg_row = (wall ? bot : top) ? 0u : uint32_t(d.ny + 1) * rb.pitch_s;
+                const uint32_t pg = (wall == bot) ? 2u : 4u;
+#pragma unroll
+                for (int ci = 0; ci < 2; ++ci)
+                    buf_st<S>(rsrc(rb.go + eg_row + (ci * kM + pg) * rb.plane_s, on ? rb.plane_s : 0u), gw0,
+                              bot ? eg[ci][4] : eg[ci][2]);
             }
         }
 
@@ -734,10 +729,33 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
                 if (d.lid_corners || !xwall_lo) inc[7] += cw;
                 if (d.lid_corners || !xwall_hi) inc[8] -= cw;
             }
-            const __amdgpu_buffer_rsrc_t rf = out_row(rb.fo, rb.pitch_s, rb.f_all, j, act);
+            const __amdgpu_buffer_rsrc_t rf = out_row(rb.fo, rb.pitch_s, rb.f_all, j + 1, act);
+            S e[kQ];
 #pragma unroll
-            for (int a = 0; a < kQ; ++a)
-                buf_st<S>(rf, wf[a], Store<S>::enc(Cs.f[a], inc[a], sfw[cls_(a)], pop_draw(hn, a)));
+            for (int a = 0; a < kQ; ++a) {
+                e[a] = Store<S>::enc(Cs.f[a], inc[a], sfw[cls_(a)], pop_draw(hn, a));
+                buf_st<S>(rf, wf[a], e[a]);
+            }
+            // ghost rows: the writers of rows 0 and ny - 1 also store, into
+            // row -1 or ny, the three slots their own row's pulls take from
+            // beyond the domain in y.  Walls: the bounced value (the slot of
+            // the opposite direction, which already holds the reader's wall
+            // terms) at the reader's source column, into the row beyond the
+            // wall; periodic: copies of the slots the opposite edge row pulls,
+            // into the ghost row beyond that edge.  Planes: walls bottom
+            // {2, 5, 6}, top {4, 8, 7}; periodic bottom {4, 7, 8}, top {2, 6, 5}.
+            {
+                const bool bot = j == 0, top = j == d.ny - 1, wall = d.bc_y != 0;
+                const bool on = act && (bot || top);
+                const uint32_t eg_row = (wall ? bot : top) ? 0u : uint32_t(d.ny + 1) * rb.pitch_s;
+                const uint32_t p0 = (wall == bot) ? 2u : 4u;
+                const uint32_t p1 = wall ? (bot ? 5u : 8u) : (bot ? 7u : 6u);
+                const uint32_t p2 = wall ? (bot ? 6u : 7u) : (bot ? 8u : 5u);
+                const uint32_t nb = on ? rb.plane_s : 0u;
+                buf_st<S>(rsrc(rb.fo + eg_row + p0 * rb.plane_s, nb), gw0, bot ? e[4] : e[2]);
+                buf_st<S>(rsrc(rb.fo + eg_row + p1 * rb.plane_s, nb), gw1, bot ? e[7] : e[6]);
+                buf_st<S>(rsrc(rb.fo + eg_row + p2 * rb.plane_s, nb), gw2, bot ? e[8] : e[5]);
+            }
             const __amdgpu_buffer_rsrc_t rF = out_row(rb.Fo, rb.pitch_F, rb.F_all, j, act);
             buf_st<FT>(rF, wF[0], FT(F1));
             buf_st<FT>(rF, wF[1], FT(F2));
