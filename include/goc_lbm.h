@@ -198,11 +198,13 @@ int goc_lbm_diagnostics(goc_lbm_t *h, double out[8]);
 int goc_lbm_set_watchdog(goc_lbm_t *h, int64_t every);
 
 /* Launch plan of the step kernel.  One work-group (a wave of 64 lanes)
-   owns 62 columns of a run and a segment of rows; every run gets segments
+   owns 64 columns of a run and a segment of rows (whole groups of 4 rows,
+   the last segment of a run taking the remainder); every run gets segments
    in proportion to its nodes so that the launch holds about waves_per_cu
-   work-groups per compute unit (default 16).  Fewer, longer segments re-read
-   fewer halo rows; more segments fill the chip.  goc_lbm_set_launch applies
-   waves_per_cu in [0.5, 256] (synchronous; GOC_EINVAL outside).
+   work-groups per compute unit (default 16; fewer where a run has too few
+   row groups).  Fewer, longer segments re-read fewer halo rows; more
+   segments fill the chip and balance uneven batches.  goc_lbm_set_launch
+   applies waves_per_cu in [0.5, 1024] (synchronous; GOC_EINVAL outside).
    goc_lbm_launch_info writes out[0] = waves_per_cu, out[1] = work-groups
    per step, out[2] = mean rows per segment, out[3] = strips (all runs). */
 int goc_lbm_set_launch(goc_lbm_t *h, double waves_per_cu);
@@ -210,7 +212,8 @@ int goc_lbm_launch_info(const goc_lbm_t *h, double out[4]);
 
 /* Autotuner of the launch plan: times trial_steps step launches (1..10000,
    plus one warm-up) for each waves_per_cu in {2, 3, 4, 6, 8, 12, 16, 24, 32,
-   48} on the handle's stream and keeps the fastest.  The state does not
+   48, 64, 96, 128, 192, 256, 384, 512} on the handle's stream and keeps the
+   fastest.  The state does not
    change: trial launches read the current buffers and write the spare ones.
    out[0] = chosen waves_per_cu, out[1] = its microseconds per step,
    out[2] = microseconds per step of the plan in use before (-1 if it was not

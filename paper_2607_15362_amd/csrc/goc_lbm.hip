@@ -948,8 +948,8 @@ int goc_lbm_step(goc_lbm_t* h, int64_t n)
 int goc_lbm_set_launch(goc_lbm_t* h, double waves_per_cu)
 {
     if (!check_handle(h)) return GOC_EINVAL;
-    if (!(waves_per_cu >= 0.5 && waves_per_cu <= 256.0))
-        return fail(GOC_EINVAL, "waves_per_cu %g outside [0.5, 256]", waves_per_cu);
+    if (!(waves_per_cu >= 0.5 && waves_per_cu <= 1024.0))
+        return fail(GOC_EINVAL, "waves_per_cu %g outside [0.5, 1024]", waves_per_cu);
     return apply_plan(h, waves_per_cu);
 }
 
@@ -974,7 +974,7 @@ int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
     if (!check_handle(h)) return GOC_EINVAL;
     if (!out) return fail(GOC_EINVAL, "out is NULL");
     if (trial_steps < 1 || trial_steps > 10000) return fail(GOC_EINVAL, "trial_steps %d outside [1, 10000]", trial_steps);
-    static const double cand[] = {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96};
+    static const double cand[] = {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512};
     const int ncand = (int)(sizeof(cand) / sizeof(cand[0]));
     struct Ev {
         hipEvent_t e[2] = {nullptr, nullptr};
