@@ -80,7 +80,11 @@ class OracleCfg(C.Structure):
         ("h1_face_ylo", C.POINTER(C.c_double)), ("h1_face_yhi", C.POINTER(C.c_double)),
         ("h1_face_lo", C.POINTER(C.c_double)), ("h1_face_hi", C.POINTER(C.c_double)),
         ("h2_face_xlo", C.POINTER(C.c_double)), ("h2_face_xhi", C.POINTER(C.c_double)),
+        ("collision", C.c_int32),
     ]
+
+
+COLLISIONS = {"central": 0, "raw": 1, "srt": 2}
 
 
 def _ptr(a):
@@ -123,7 +127,8 @@ def derive(case, h1, h2) -> Lattice:
     """Lattice parameters of a workload (Sec. 3.2.1, Sec. 5, App. G, Sec. 8).
 
     reading: omega_0,1,2,6,7,8 = 1 and omega_3 = 1 (bulk viscosity
-    zeta = c_s^2/2); omega_4 = omega_5 from the shear viscosity.
+    zeta = c_s^2/2); omega_4 = omega_5 from the shear viscosity.  The SRT
+    model relaxes every moment at omega = 1/tau, so zeta = nu.
     """
     cs2 = params.sound_speed_sq(h1, h2)
     rho0 = case.rho0
@@ -165,6 +170,8 @@ def derive(case, h1, h2) -> Lattice:
     w45 = params.omega_from_viscosity(cs2, nu)
     omega = np.ones(9)
     omega[4] = omega[5] = w45
+    if getattr(case, "collision", "central") == "srt":
+        omega[:] = w45
     zeta = cs2 * (1.0 / omega[3] - 0.5)
     csm2 = cs2
     if case.mhd:
@@ -214,6 +221,7 @@ class Model:
         c.bc_y = 0 if case.bc_y == "periodic" else 1
         c.gi_terms, c.q3_sign, c.lid_corners = case.gi_terms, case.q3_sign, case.lid_corners
         c.rho_terms = getattr(case, "rho_terms", 0)
+        c.collision = COLLISIONS[getattr(case, "collision", "central")]
         c.mhd = 1 if lat.mhd else 0
         c.u_wall_lo, c.u_wall_hi = lat.u_wall_lo, lat.u_wall_hi
         c.cs2 = lat.cs2
@@ -332,9 +340,10 @@ def mie_node(cfg, gb, U, metric):
 
 
 def bare_cfg(cs2=1.0 / 3.0, omega=None, nu=0.1, zeta=None, gi_terms=1, q3_sign=0, csm2=None,
-             tau_m=1.0, eta=None, mu_m=1.0, B0=0.0, rho_terms=0):
+             tau_m=1.0, eta=None, mu_m=1.0, B0=0.0, rho_terms=0, collision="central"):
     """A configuration for single-node calls (no grid pointers)."""
     c = OracleCfg()
+    c.collision = COLLISIONS[collision]
     c.cs2 = cs2
     om = np.ones(9) if omega is None else np.asarray(omega, float)
     for k in range(9):

@@ -10,8 +10,12 @@
  *
  * Scope: the central-moment MRT GOC-LBM for the Navier-Stokes equations
  * (Appendix E of the paper, with the shear stress of Appendix A and the
- * initial / boundary conditions of Appendix C) and the D2Q5 vector
- * distribution GOC-LBM for the magnetic induction equation (Appendix G).
+ * initial / boundary conditions of Appendix C), its two simpler collision
+ * variants on the same grid and streaming -- the raw-moment MRT model (the
+ * appendix summarising the raw-moment algorithm) and the single-relaxation-
+ * time model in velocity space (the appendix on collisions in velocity
+ * space) -- and the D2Q5 vector distribution GOC-LBM for the magnetic
+ * induction equation (Appendix G).
  * The metric is a general 2-D orthogonal one (h1, h2 and all four theta_ij
  * per node); straight clustered grids are the special case theta12 =
  * theta21 = 0.
@@ -41,7 +45,11 @@
  * form P^-1 F^-1 [...] of App. E, the binomial definitions of the central
  * moments, the symbolic Chapman-Enskog constraints of Sec. 4-5, the h = 1
  * reduction to a textbook central-moment LBM, mass conservation and the
- * Poiseuille / Couette / Hartmann closed forms.
+ * Poiseuille / Couette / Hartmann closed forms.  The raw-moment collision is
+ * pinned against its matrix form P^-1 [m + B^-1 L (...)], the SRT collision
+ * against the raw-moment one with equal rates (the identity of the two
+ * formulations through the linear map P), both against the h = 1 textbook
+ * product-form BGK scheme and the Poiseuille closed form.
  */
 #include <math.h>
 #ifdef _OPENMP
@@ -85,6 +93,8 @@ typedef struct {
        and h2 beside the x-wall faces (per row) */
     const double *h2_face_lo, *h2_face_hi, *h1_face_ylo, *h1_face_yhi;  /* [nx] */
     const double *h1_face_lo, *h1_face_hi, *h2_face_xlo, *h2_face_xhi;  /* [ny] */
+    int32_t collision;           /* 0 central-moment MRT, 1 raw-moment MRT,
+                                    2 SRT with tau = 1/omega_4              */
 } OracleCfg;
 
 /* ------------------------------------------------------------------ */
@@ -178,19 +188,26 @@ typedef struct {
 } ForceTerms;
 
 /* Sec. 2: normal viscous stresses tau11, tau22 with their curvature parts
-   tau^c; App. A: reduced effective force F~ (tau12 set to zero), the local
-   implicit solution for tau12 from the non-equilibrium raw moment k'11, and
-   the full effective force F = F~ + 2 h theta tau12. */
-static void force_terms(const OracleCfg *c, const Metric *g, const NodeFlow *n,
-                        double k11raw, ForceTerms *t)
+   tau^c (bulk viscosity zeta, shear viscosity nu). */
+static void normal_stresses(const OracleCfg *c, const Metric *g, const NodeFlow *n, ForceTerms *t)
 {
     const double rho = n->rho, U1 = n->U1, U2 = n->U2;
     const double nu = c->nu, zeta = c->zeta;
-    const double P = rho * c->cs2;
     t->tc11 = rho * (zeta + nu) * U2 * g->th12 + rho * (zeta - nu) * U1 * g->th21;
     t->tc22 = rho * (zeta + nu) * U1 * g->th21 + rho * (zeta - nu) * U2 * g->th12;
     t->t11 = rho * (zeta + nu) * n->d1U1 / g->h1 + rho * (zeta - nu) * n->d2U2 / g->h2 + t->tc11;
     t->t22 = rho * (zeta + nu) * n->d2U2 / g->h2 + rho * (zeta - nu) * n->d1U1 / g->h1 + t->tc22;
+}
+
+/* App. A: reduced effective force F~ (tau12 set to zero) from the normal
+   stresses, the local implicit solution for tau12 from the non-equilibrium
+   raw moment k'11 (relaxed at rate w5), and the full effective force
+   F = F~ + 2 h theta tau12.  The same for every collision model. */
+static void effective_force(const OracleCfg *c, const Metric *g, const NodeFlow *n, double k11raw,
+                            double w5, ForceTerms *t)
+{
+    const double rho = n->rho, U1 = n->U1, U2 = n->U2;
+    const double P = rho * c->cs2;
     t->Ft1 = g->h2 * (n->Fx1 + (g->th21 - g->th11) * P
                       + g->th11 * (t->t11 - rho * U1 * U1)
                       + 2.0 * g->th12 * (0.0 - rho * U1 * U2)
@@ -199,11 +216,19 @@ static void force_terms(const OracleCfg *c, const Metric *g, const NodeFlow *n,
                       + g->th22 * (t->t22 - rho * U2 * U2)
                       + 2.0 * g->th21 * (0.0 - rho * U1 * U2)
                       - g->th12 * (t->t11 - rho * U1 * U1));
-    const double a = 1.0 - 0.5 * c->omega[5];
+    const double a = 1.0 - 0.5 * w5;
     const double num = k11raw + 0.5 * (t->Ft1 * U2 / g->h2 + t->Ft2 * U1 / g->h1) - rho * U1 * U2;
     t->t12 = -a * num / (1.0 + a * (g->th12 * U2 + g->th21 * U1));
     t->F1 = t->Ft1 + 2.0 * g->h2 * g->th12 * t->t12;
     t->F2 = t->Ft2 + 2.0 * g->h1 * g->th21 * t->t12;
+}
+
+/* Stresses and effective force of the MRT models. */
+static void force_terms(const OracleCfg *c, const Metric *g, const NodeFlow *n,
+                        double k11raw, ForceTerms *t)
+{
+    normal_stresses(c, g, n, t);
+    effective_force(c, g, n, k11raw, c->omega[5], t);
 }
 
 /* Sec. 5: equilibrium corrections n3^eq(1) (combined k2s) and n4^eq(1)
@@ -359,6 +384,177 @@ static void cm_collide(const OracleCfg *c, const Metric *g, const double f[NQ],
     pops_from_raw(mt, ft);
     Fout[0] = t.F1;
     Fout[1] = t.F2;
+}
+
+/* ------------------------------------------------------------------ */
+/* Raw-moment MRT GOC-LBM (appendix summarising the raw-moment model)    */
+/* ------------------------------------------------------------------ */
+
+/* Sec. 3, base raw-moment equilibria in the combined basis n^eq = B m^eq:
+   slot K20 holds n3 = k20 + k02, slot K02 holds n4 = k20 - k02. */
+static void raw_equilibria(const OracleCfg *c, const Metric *g, double rho, double U1, double U2,
+                           double eq[NQ])
+{
+    const double h1 = g->h1, h2 = g->h2, cs2 = c->cs2;
+    const double P = rho * cs2;
+    eq[K00] = h1 * h2 * rho;
+    eq[K10] = h2 * rho * U1;
+    eq[K01] = h1 * rho * U2;
+    eq[K20] = h2 / h1 * rho * U1 * U1 + h1 / h2 * rho * U2 * U2 + (h2 / h1 + h1 / h2) * P;
+    eq[K02] = h2 / h1 * rho * U1 * U1 - h1 / h2 * rho * U2 * U2 + (h2 / h1 - h1 / h2) * P;
+    eq[K11] = rho * U1 * U2;
+    eq[K21] = rho * (cs2 + U1 * U1) * U2 / h1;
+    eq[K12] = rho * (cs2 + U2 * U2) * U1 / h2;
+    eq[K22] = rho * cs2 * cs2 + rho * cs2 * (U1 * U1 + U2 * U2) + rho * U1 * U1 * U2 * U2;
+}
+
+/* Sec. 3, raw source moments in the combined basis Psi = B sigma. */
+static void raw_sources(const Metric *g, double U1, double U2, double F1, double F2, double s[NQ])
+{
+    const double h1 = g->h1, h2 = g->h2;
+    s[K00] = 0.0;
+    s[K10] = F1;
+    s[K01] = F2;
+    s[K20] = 2.0 * (F1 * U1 / h1 + F2 * U2 / h2);   /* sigma2s */
+    s[K02] = 2.0 * (F1 * U1 / h1 - F2 * U2 / h2);   /* sigma2d */
+    s[K11] = F1 * U2 / h2 + F2 * U1 / h1;
+    s[K21] = 0.0;
+    s[K12] = 0.0;
+    s[K22] = 0.0;
+}
+
+/* Raw-moment collision at one node: step 1 (m = P f), step 2 (stresses,
+   local tau12, effective force, sources, base equilibria plus the Sec. 5
+   corrections on the combined diagonal moments, relaxation of the nine
+   combined moments, split back to k20, k02) and step 3 (f~ = P^-1 m~). */
+static void raw_collide(const OracleCfg *c, const Metric *g, const double f[NQ],
+                        const NodeFlow *n, double ft[NQ], double Fout[2])
+{
+    double m[NQ], eq[NQ], s[NQ], mt[NQ];
+    ForceTerms t;
+    double n3, n4;
+    raw_moments(f, m);
+    force_terms(c, g, n, m[K11], &t);
+    raw_sources(g, n->U1, n->U2, t.F1, t.F2, s);
+    raw_equilibria(c, g, n->rho, n->U1, n->U2, eq);
+    eq_corrections(c, g, n, &t, &n3, &n4);
+    eq[K20] += n3;   /* k2s^eq */
+    eq[K02] += n4;   /* k2d^eq */
+    const double k2s = m[K20] + m[K02];
+    const double k2d = m[K20] - m[K02];
+    const double *w = c->omega;
+    /* reading: as in the central-moment model, the conserved k'00 relaxes
+       to h1 h2 rho = k'00 and is kept exactly. */
+    mt[K00] = m[K00];
+    mt[K10] = m[K10] + w[1] * (eq[K10] - m[K10]) + (1.0 - 0.5 * w[1]) * s[K10];
+    mt[K01] = m[K01] + w[2] * (eq[K01] - m[K01]) + (1.0 - 0.5 * w[2]) * s[K01];
+    const double mt2s = k2s + w[3] * (eq[K20] - k2s) + (1.0 - 0.5 * w[3]) * s[K20];
+    const double mt2d = k2d + w[4] * (eq[K02] - k2d) + (1.0 - 0.5 * w[4]) * s[K02];
+    mt[K11] = m[K11] + w[5] * (eq[K11] - m[K11]) + (1.0 - 0.5 * w[5]) * s[K11];
+    mt[K21] = m[K21] + w[6] * (eq[K21] - m[K21]) + (1.0 - 0.5 * w[6]) * s[K21];
+    mt[K12] = m[K12] + w[7] * (eq[K12] - m[K12]) + (1.0 - 0.5 * w[7]) * s[K12];
+    mt[K22] = m[K22] + w[8] * (eq[K22] - m[K22]) + (1.0 - 0.5 * w[8]) * s[K22];
+    mt[K20] = 0.5 * (mt2s + mt2d);
+    mt[K02] = 0.5 * (mt2s - mt2d);
+    pops_from_raw(mt, ft);
+    Fout[0] = t.F1;
+    Fout[1] = t.F2;
+}
+
+/* ------------------------------------------------------------------ */
+/* SRT GOC-LBM in velocity space (appendix on velocity-space collisions) */
+/* ------------------------------------------------------------------ */
+
+/* SRT collision at one node with the single relaxation time tau =
+   1/omega_4; bulk and shear viscosity coincide, nu = zeta = c_s^2 (tau - 1/2).
+   The normal stresses take their reduced forms tau11 = 2 rho nu d1U1/h1 +
+   tau^c11 with tau^c11 = 2 rho nu U2 theta12 (and symmetrically); the shear
+   stress and the effective force are those of every model (App. A, relaxed
+   at 1/tau).  The bare second-order equilibria carry the corrections through
+   the coefficients G_j, H_j; f^eq = P^-1 m^eq and S = P^-1 sigma, then
+   f~ = f + (f^eq - f)/tau + (1 - 1/(2 tau)) S. */
+static void srt_collide(const OracleCfg *c, const Metric *g, const double f[NQ],
+                        const NodeFlow *n, double ft[NQ], double Fout[2])
+{
+    const double tau = 1.0 / c->omega[4];
+    const double cs2 = c->cs2, nu = cs2 * (tau - 0.5);
+    const double rho = n->rho, U1 = n->U1, U2 = n->U2;
+    const double h1 = g->h1, h2 = g->h2;
+    double m[NQ];
+    raw_moments(f, m);            /* k'11 for the local shear stress */
+    ForceTerms t;
+    t.tc11 = 2.0 * rho * nu * U2 * g->th12;
+    t.tc22 = 2.0 * rho * nu * U1 * g->th21;
+    t.t11 = 2.0 * rho * nu / h1 * n->d1U1 + t.tc11;
+    t.t22 = 2.0 * rho * nu / h2 * n->d2U2 + t.tc22;
+    effective_force(c, g, n, m[K11], 1.0 / tau, &t);
+    const double u1s = U1 * U1 / cs2, u2s = U2 * U2 / cs2;
+    double G1, G3, G5, H2, H4, H5;
+    if (c->gi_terms) {
+        G1 = rho * nu * (h2 / cs2 - 3.0 * (1.0 + u1s) * h2 / (h1 * h1));
+        /* reading: the H2 bracket carries h1/h2^2 (as D3,2 it is half of),
+           not the printed h1/h1^2. */
+        H2 = rho * nu * (h1 / cs2 - 3.0 * (1.0 + u2s) * h1 / (h2 * h2));
+        /* reading: G3, H4 keep the cubic U^2/c_s^2 part of the Chapman-Enskog
+           density coefficients D3,3 and D4,3 at zeta = nu, from which the
+           coefficients are stated to reduce (the printed G3, H4 drop it while
+           G1, H2 keep the analogous term). */
+        G3 = -nu * ((3.0 + u1s) * h2 / (h1 * h1) - h2 / cs2) * U1;
+        H4 = -nu * ((3.0 + u2s) * h1 / (h2 * h2) - h1 / cs2) * U2;
+        G5 = -h2 / h1 * t.tc11
+             - rho * nu * (-2.0 * U1 * (u1s + 1.0) * h2 / h1 * g->th11
+                           + U1 * ((3.0 + u1s) * h2 / h1 - h1 * h2 / cs2) * g->th21
+                           + 2.0 * U2 * h2 / h1 * g->th12);
+        H5 = -h1 / h2 * t.tc22
+             - rho * nu * (-2.0 * U2 * (u2s + 1.0) * h1 / h2 * g->th22
+                           + U2 * ((3.0 + u2s) * h1 / h2 - h1 * h2 / cs2) * g->th12
+                           + 2.0 * U1 * h1 / h2 * g->th21);
+    } else {
+        /* App. B(ii) low-Mach straight-grid limit of the same coefficients:
+           no cubic velocity terms, theta12 = theta21 = 0. */
+        G1 = rho * nu * (h2 / cs2 - 3.0 * h2 / (h1 * h1));
+        H2 = rho * nu * (h1 / cs2 - 3.0 * h1 / (h2 * h2));
+        G3 = 0.0;
+        H4 = 0.0;
+        G5 = 2.0 * rho * nu * U1 * h2 / h1 * g->th11;
+        H5 = 2.0 * rho * nu * U2 * h1 / h2 * g->th22;
+    }
+    double meq[NQ], sig[NQ], feq[NQ], S[NQ];
+    meq[K00] = rho * h1 * h2;
+    meq[K10] = rho * U1 * h2;
+    meq[K01] = rho * U2 * h1;
+    meq[K20] = h2 / h1 * rho * (U1 * U1 + cs2) + G1 * n->d1U1 + G3 * n->d1rho + G5;
+    meq[K02] = h1 / h2 * rho * (U2 * U2 + cs2) + H2 * n->d2U2 + H4 * n->d2rho + H5;
+    meq[K11] = rho * U1 * U2;
+    meq[K21] = rho * U2 / h1 * (cs2 + U1 * U1);
+    meq[K12] = rho * U1 / h2 * (cs2 + U2 * U2);
+    meq[K22] = rho * cs2 * cs2 + rho * cs2 * (U1 * U1 + U2 * U2) + rho * U1 * U1 * U2 * U2;
+    sig[K00] = 0.0;
+    sig[K10] = t.F1;
+    sig[K01] = t.F2;
+    sig[K20] = 2.0 * t.F1 * U1 / h1;
+    sig[K02] = 2.0 * t.F2 * U2 / h2;
+    /* reading: sigma'11 without the printed extra factor 2 on F1 U2/h2, as in
+       the raw-moment sources of Sec. 3 it restates. */
+    sig[K11] = t.F1 * U2 / h2 + t.F2 * U1 / h1;
+    sig[K21] = 0.0;
+    sig[K12] = 0.0;
+    sig[K22] = 0.0;
+    pops_from_raw(meq, feq);
+    pops_from_raw(sig, S);
+    for (int a = 0; a < NQ; ++a)
+        ft[a] = f[a] + (feq[a] - f[a]) / tau + (1.0 - 0.5 / tau) * S[a];
+    Fout[0] = t.F1;
+    Fout[1] = t.F2;
+}
+
+/* Collision of the selected model. */
+static void collide_node(const OracleCfg *c, const Metric *g, const double f[NQ],
+                         const NodeFlow *n, double ft[NQ], double Fout[2])
+{
+    if (c->collision == 1) raw_collide(c, g, f, n, ft, Fout);
+    else if (c->collision == 2) srt_collide(c, g, f, n, ft, Fout);
+    else cm_collide(c, g, f, n, ft, Fout);
 }
 
 /* ------------------------------------------------------------------ */
@@ -616,7 +812,7 @@ static void collide_at(const OracleCfg *c, const double *f, const double *g, Wor
     }
     double fl[NQ], ft[NQ], F[2];
     for (int a = 0; a < NQ; ++a) fl[a] = f[a * N + n];
-    cm_collide(c, &gm, fl, &nf, ft, F);
+    collide_node(c, &gm, fl, &nf, ft, F);
     for (int a = 0; a < NQ; ++a) w->ft[a * N + n] = ft[a];
     w->Fn[n] = F[0];
     w->Fn[N + n] = F[1];
@@ -873,14 +1069,15 @@ int oracle_init(const OracleCfg *c, const double *rho_i, const double *U1_i, con
 /* Collision of one node from explicit inputs:
    in[0..8] f, in[9..14] h1 h2 th11 th12 th21 th22, in[15..17] rho U1 U2,
    in[18..21] d1U1 d2U2 d1rho d2rho, in[22..23] external force.
-   out[0..8] ft, out[9..10] F, out[11] tau12, out[12] n3eq1, out[13] n4eq1,
-   out[14..15] F~ */
+   out[0..8] ft, out[9..10] F of the selected collision model; out[11]
+   tau12, out[12] n3eq1, out[13] n4eq1, out[14..15] F~ of the MRT models'
+   stresses. */
 int oracle_collide_node(const OracleCfg *c, const double *in, double *out)
 {
     Metric g = {in[9], in[10], in[11], in[12], in[13], in[14]};
     NodeFlow n = {in[15], in[16], in[17], in[18], in[19], in[20], in[21], in[22], in[23]};
     double ft[NQ], F[2], m[NQ];
-    cm_collide(c, &g, in, &n, ft, F);
+    collide_node(c, &g, in, &n, ft, F);
     for (int a = 0; a < NQ; ++a) out[a] = ft[a];
     out[9] = F[0];
     out[10] = F[1];

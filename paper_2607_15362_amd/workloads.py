@@ -47,6 +47,7 @@ class Case:
     q3_sign: int = 0
     lid_corners: int = 1
     rho_terms: int = 0
+    collision: str = "central"        # "central" | "raw" (moment MRT) | "srt"
     body_force: tuple = (0.0, 0.0)    # "free" flows: explicit force density
     init_seed: int | None = None      # smooth random initial fields when set
     init_amp: float = 0.0

@@ -197,3 +197,76 @@ def textbook_mhd_step(f, g, Fprev, omega, cs2, Fext, tau_m, mu_m=1.0):
             gn[c, a] = np.roll(np.roll(gt[c, a], int(E5Y[a]), axis=0), int(E5X[a]), axis=1)
     Fused = np.stack([Fext[0] + FL1, Fext[1] + FL2])
     return fn, gn.reshape(10, ny, nx), Fused
+
+
+# ------------------------------------------------------- collision variants ----
+
+def raw_collision_matrix_form(f, rho, U1, U2, h1, h2, cs2, omega, F1, F2, n3, n4):
+    """Raw-moment MRT collision as the explicit matrix product
+    f~ = P^-1 [m + B^-1 L (B m^eq + c - B m) + B^-1 (I - L/2) B sigma]
+    with the Sec. 3 raw equilibria and sources and the corrections
+    c = (0, 0, 0, n3, n4, 0, 0, 0, 0) on the combined diagonal slots."""
+    P = P_matrix()
+    Pinv = np.linalg.inv(P)
+    B = B_matrix()
+    Binv = np.linalg.inv(B)
+    L = np.diag(omega)
+    m = P @ f
+    Beq = B @ raw_eq_sec3(rho, U1, U2, h1, h2, cs2)
+    Beq[3] += n3
+    Beq[4] += n4
+    sig = raw_src_sec3(F1, F2, U1, U2, h1, h2)
+    mt = m + Binv @ (L @ (Beq - B @ m)) + Binv @ ((np.eye(9) - L / 2) @ (B @ sig))
+    return Pinv @ mt
+
+
+def product_equilibrium(rho, U1, U2, cs2):
+    """Factorised D2Q9 equilibrium: rho times the product over both axes of
+    the one-dimensional three-velocity populations that carry the moments
+    1, u, cs2 + u^2 of a Maxwellian (phi_0 = 1 - cs2 - u^2,
+    phi_+-1 = (cs2 + u^2 +- u)/2).  Arrays of any common shape."""
+    def phi(e, u):
+        if e == 0:
+            return 1.0 - cs2 - u * u
+        return 0.5 * (cs2 + u * u + e * u)
+    return np.stack([rho * phi(int(EX[a]), U1) * phi(int(EY[a]), U2) for a in range(9)])
+
+
+def _stream_periodic(ft):
+    fn = np.empty_like(ft)
+    for a in range(9):
+        fn[a] = np.roll(np.roll(ft[a], int(EY[a]), axis=0), int(EX[a]), axis=1)
+    return fn
+
+
+def textbook_product_bgk_step(f, tau, cs2):
+    """One step of a uniform periodic D2Q9 BGK LBM with the factorised
+    equilibrium and no force."""
+    rho = f.sum(axis=0)
+    U1 = (f * EX[:, None, None]).sum(axis=0) / rho
+    U2 = (f * EY[:, None, None]).sum(axis=0) / rho
+    feq = product_equilibrium(rho, U1, U2, cs2)
+    return _stream_periodic(f + (feq - f) / tau)
+
+
+def textbook_raw_mrt_step(f, omega, cs2):
+    """One step of a uniform periodic D2Q9 raw-moment MRT LBM (moments of
+    the monomial basis, diagonal second moments combined as k20 +- k02) with
+    the factorised equilibrium and no force."""
+    nine, ny, nx = f.shape
+    rho = f.sum(axis=0)
+    U1 = (f * EX[:, None, None]).sum(axis=0) / rho
+    U2 = (f * EY[:, None, None]).sum(axis=0) / rho
+    feq = product_equilibrium(rho, U1, U2, cs2)
+    P = P_matrix()
+    B = B_matrix()
+    Binv = np.linalg.inv(B)
+    L = np.diag(omega)
+    Pinv = np.linalg.inv(P)
+    ft = np.empty_like(f)
+    for j in range(ny):
+        for i in range(nx):
+            m = P @ f[:, j, i]
+            meq = P @ feq[:, j, i]
+            ft[:, j, i] = Pinv @ (m + Binv @ (L @ (B @ meq - B @ m)))
+    return _stream_periodic(ft)

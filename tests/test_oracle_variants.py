@@ -1,0 +1,202 @@
+"""Pins of the oracle's two collision variants: the raw-moment MRT model and
+the single-relaxation-time (SRT) model in velocity space.
+
+Each is checked against its explicit matrix form, against each other (equal
+rates make them the same scheme through the linear map P), against textbook
+uniform-grid schemes at h = 1 built from the factorised equilibrium, and
+through the grid-level invariants and closed forms shared with the
+central-moment model.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import refimpl as R
+from paper_2607_15362_amd import workloads as W
+
+
+def _node(r, straight=False):
+    h1, h2 = r.uniform(0.3, 2.5, size=2)
+    th = r.normal(scale=0.05, size=4)
+    if straight:
+        th[1] = th[2] = 0.0
+    metric = np.array([h1, h2, *th])
+    cs2 = r.uniform(0.02, 0.3)
+    rho = r.uniform(0.9, 1.1)
+    U1, U2 = r.normal(scale=0.03, size=2)
+    feq = np.linalg.inv(R.P_matrix()) @ R.raw_eq_sec3(rho, U1, U2, h1, h2, cs2)
+    f = feq * (1 + r.normal(scale=0.02, size=9))
+    Fp = r.normal(scale=1e-5, size=2)
+    m = R.P_matrix() @ f
+    rho = m[0] / (h1 * h2)
+    U1 = (m[1] + Fp[0] / 2) / (rho * h2)
+    U2 = (m[2] + Fp[1] / 2) / (rho * h1)
+    grads = r.normal(scale=1e-3, size=4)
+    force = r.normal(scale=1e-5, size=2)
+    return metric, cs2, f, [rho, U1, U2, *grads], force
+
+
+@pytest.mark.parametrize("gi_terms", [1, 0])
+def test_raw_collision_equals_matrix_form(oracle_lib, gi_terms):
+    """Raw-moment MRT (relaxation of the nine combined raw moments) equals
+    P^-1 [m + B^-1 L (B m^eq + c - B m) + B^-1 (I - L/2) B sigma] with
+    matrices from their definitions; k'00 is conserved."""
+    o = oracle_lib
+    r = np.random.default_rng(11)
+    for _ in range(200):
+        metric, cs2, f, flow, force = _node(r)
+        omega = r.uniform(0.5, 1.8, size=9)
+        nu = cs2 * (1 / omega[4] - 0.5)
+        cfg = o.bare_cfg(cs2=cs2, omega=omega, nu=nu, gi_terms=gi_terms, collision="raw")
+        out = o.collide_node(cfg, f, metric, flow, force)
+        ref = R.raw_collision_matrix_form(f, flow[0], flow[1], flow[2], metric[0], metric[1], cs2,
+                                          omega, out["F"][0], out["F"][1], out["n3"], out["n4"])
+        assert np.max(np.abs(out["ft"] - ref)) < 1e-13 * np.max(np.abs(f))
+        assert abs(out["ft"].sum() - f.sum()) < 1e-14 * abs(f.sum())
+        # the force of the raw model is the central model's (App. A is shared)
+        cm = o.collide_node(o.bare_cfg(cs2=cs2, omega=omega, nu=nu, gi_terms=gi_terms), f,
+                            metric, flow, force)
+        assert np.array_equal(cm["F"], out["F"])
+
+
+@pytest.mark.parametrize("gi_terms", [1, 0])
+def test_srt_equals_raw_mrt_with_equal_rates(oracle_lib, gi_terms):
+    """With every rate 1/tau (so zeta = nu) the raw-moment collision is the
+    velocity-space SRT collision: P^-1 is linear, f^eq = P^-1 m^eq and
+    S = P^-1 sigma.  The SRT side computes its corrections through its own
+    coefficients G_j, H_j and reduced stresses; a general 2-D metric
+    exercises every curvature term."""
+    o = oracle_lib
+    r = np.random.default_rng(12)
+    for _ in range(200):
+        metric, cs2, f, flow, force = _node(r)
+        tau = r.uniform(0.55, 2.0)
+        nu = cs2 * (tau - 0.5)
+        omega = np.full(9, 1.0 / tau)
+        raw = o.collide_node(o.bare_cfg(cs2=cs2, omega=omega, nu=nu, gi_terms=gi_terms,
+                                        collision="raw"), f, metric, flow, force)
+        srt = o.collide_node(o.bare_cfg(cs2=cs2, omega=omega, nu=nu, gi_terms=gi_terms,
+                                        collision="srt"), f, metric, flow, force)
+        assert np.max(np.abs(srt["ft"] - raw["ft"])) < 1e-13 * np.max(np.abs(f))
+        assert np.allclose(srt["F"], raw["F"], rtol=1e-12, atol=1e-20)
+
+
+def test_srt_corrections_are_general_ones_at_equal_viscosities(oracle_lib):
+    """The SRT coefficients G_j = (D3j + D4j)/2 and H_j = (D3j - D4j)/2 of the
+    general corrections at zeta = nu: with gradients present and a curved
+    metric, SRT and raw-moment MRT with equal rates differ only by rounding,
+    while an SRT run whose tau disagrees with the MRT's nu does not match
+    (the check is sensitive to the coefficients)."""
+    o = oracle_lib
+    r = np.random.default_rng(13)
+    metric, cs2, f, flow, force = _node(r)
+    flow = list(flow)
+    flow[3:7] = [2e-2, -1.5e-2, 1e-2, -2e-2]
+    tau = 0.9
+    omega = np.full(9, 1 / tau)
+    raw = o.collide_node(o.bare_cfg(cs2=cs2, omega=omega, nu=cs2 * (tau - 0.5),
+                                    collision="raw"), f, metric, flow, force)
+    srt = o.collide_node(o.bare_cfg(cs2=cs2, omega=omega, collision="srt"), f, metric, flow,
+                         force)
+    assert np.max(np.abs(srt["ft"] - raw["ft"])) < 1e-13 * np.max(np.abs(f))
+    off = o.collide_node(o.bare_cfg(cs2=cs2, omega=omega, nu=cs2 * (1.1 * tau - 0.5),
+                                    collision="raw"), f, metric, flow, force)
+    assert np.max(np.abs(off["ft"] - srt["ft"])) > 1e-7
+
+
+@pytest.mark.parametrize("collision", ["srt", "raw"])
+def test_unit_metric_equals_textbook_factorised_scheme(oracle_lib, collision):
+    """h1 = h2 = 1, cs2 = 1/3, no force, App. B(ii) coefficients (which
+    vanish there): the SRT model is the textbook BGK LBM and the raw-moment
+    model the textbook raw-moment MRT LBM, both with the factorised
+    equilibrium built from one-dimensional factors."""
+    o = oracle_lib
+    nx, ny = 10, 8
+    case = W.Case("p", nx, ny, "periodic", "periodic", flow="free", tau=0.7,
+                  body_force=(0.0, 0.0), gi_terms=0, collision=collision, storage="f64")
+    m = o.Model(case)
+    m.lat.cs2 = 1.0 / 3.0
+    if collision == "srt":
+        m.lat.omega = np.full(9, 1 / 0.7)
+    else:
+        m.lat.omega = np.array([1.0, 1.0, 1.0, 1.3, 1 / 0.7, 1 / 0.7, 1.1, 0.9, 1.2])
+    m.lat.nu = (1 / 3) * (0.7 - 0.5)
+    m.lat.zeta = (1 / 3) * (1 / m.lat.omega[3] - 0.5)
+    m.cfg = m._make_cfg()
+    rho, U1, U2 = W.smooth_fields(nx, ny, seed=7, amp=0.03)
+    m.init(rho, U1, U2)
+    f_ref = R.product_equilibrium(rho, U1, U2, 1 / 3)
+    assert np.allclose(m.f, f_ref, atol=1e-15)
+    for _ in range(6):
+        if collision == "srt":
+            f_ref = R.textbook_product_bgk_step(f_ref, 0.7, 1 / 3)
+        else:
+            f_ref = R.textbook_raw_mrt_step(f_ref, m.lat.omega, 1 / 3)
+        m.step(1)
+        assert np.max(np.abs(m.f - f_ref)) < 1e-14
+
+
+@pytest.mark.parametrize("collision", ["raw", "srt"])
+def test_variant_mass_and_momentum_bookkeeping(oracle_lib, collision):
+    """Mass is conserved on a walled, clustered cavity; on a periodic h = 1
+    grid every step after the first adds N F to the total momentum."""
+    o = oracle_lib
+    case = W.Case("c", 24, 20, "wall", "wall", ("tanh", 1.5), ("tanh", 1.2), flow="cavity",
+                  Re=50.0, u_lid=0.05, collision=collision, storage="f64")
+    m = o.Model(case).init()
+    M0 = m.mass()
+    m.step(300)
+    assert abs(m.mass() - M0) / M0 < 1e-13
+    assert np.all(np.isfinite(m.f))
+    F = (2e-5, -1e-5)
+    case = W.Case("p", 12, 10, "periodic", "periodic", flow="free", tau=0.7, body_force=F,
+                  collision=collision, storage="f64")
+    rho, U1, U2 = W.smooth_fields(12, 10, seed=3, amp=0.02)
+    m = o.Model(case).init(rho, U1, U2)
+    m.step(1)
+    mom = []
+    for _ in range(5):
+        mom.append([(m.f * R.EX[:, None, None]).sum(), (m.f * R.EY[:, None, None]).sum()])
+        m.step(1)
+    d = np.diff(np.array(mom), axis=0)
+    assert np.allclose(d[:, 0], 120 * F[0], rtol=1e-9)
+    assert np.allclose(d[:, 1], 120 * F[1], rtol=1e-9)
+
+
+def _ycoords(n, stretch):
+    from oracle import params
+    kind, p = stretch
+    xi = np.arange(n) + 0.5
+    return params.tanh_two_wall_y(n, p, xi) if kind == "tanh" else xi
+
+
+def _steady(m, chunk=2000, tol=1e-13, maxit=500):
+    prev = None
+    for _ in range(maxit):
+        m.step(chunk)
+        u = m.fields()["U1"][:, 1]
+        if prev is not None and np.max(np.abs(u - prev)) <= tol * max(np.max(np.abs(u)), 1e-30):
+            return u
+        prev = u
+    raise AssertionError("no steady state")
+
+
+@pytest.mark.parametrize("collision", ["raw", "srt"])
+def test_variant_poiseuille_steady_second_order(oracle_lib, collision):
+    """Steady body-force Poiseuille flow (Sec. 8.1) on tanh-clustered 3xN
+    strips converges to u = 4U (y/H)(1 - y/H) at second order with either
+    variant, as with the central-moment model."""
+    o = oracle_lib
+    errs = []
+    for N in (16, 32):
+        case = W.Case("p", 3, N, "periodic", "wall", ("uniform", 0.0), ("tanh", 1.5),
+                      flow="channel", Re=10.0, tau=1.0, collision=collision, storage="f64")
+        m = o.Model(case).init()
+        u = _steady(m)
+        y = _ycoords(N, case.stretch_y)
+        U = m.lat.extra["U"]
+        ua = 4 * U * (y / N) * (1 - y / N)
+        errs.append(np.linalg.norm(u - ua) / np.linalg.norm(ua))
+    assert errs[1] < 5e-3
+    assert math.log2(errs[0] / errs[1]) > 1.8
