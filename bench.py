@@ -19,6 +19,9 @@ Prints ONE JSON line:
                              with their field errors against the FP32 run
   batched                    the seeded 256-run batch in one launch per step
                              against the same runs one after another
+  collisions                 the main workload with the raw-moment MRT and the
+                             SRT collision bodies instead of the central-moment
+                             one (same data path, same launch)
 """
 from __future__ import annotations
 
@@ -190,6 +193,27 @@ def batched_form(steps: int):
     return out
 
 
+def collision_variants(case, steps: int, central_mlups: float):
+    """The main workload with the raw-moment MRT and the SRT collisions:
+    throughput, achieved bandwidth and the ratio to the central-moment run."""
+    from paper_2607_15362_amd import binding as B
+    n = max(500, steps // 5)
+    out = {}
+    for coll in ("raw", "srt"):
+        c = case.replace(name=f"{case.name}_{coll}", collision=coll)
+        r = B.Run(c)
+        tuned = r.tune(10)
+        w, e = time_run(r, n, 100)
+        d = r.derived()
+        nodes = c.nx * c.ny
+        out[coll] = {"steps": n, "MLUPS": round(nodes * n / w / 1e6, 1),
+                     "GB_s": round(d["bytes_per_node"] * nodes / (e / n) / 1e9, 1),
+                     "launch_us": round(e / n * 1e6, 2), "waves_per_cu": tuned["waves_per_cu"],
+                     "vs_central": round(nodes * n / w / 1e6 / central_mlups, 3)}
+        r.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,6 +224,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-collisions", action="store_true")
     ap.add_argument("--waves", type=float, default=0.0, metavar="W",
                     help="fixed launch plan of W waves per CU instead of the autotuner "
                          "(for profiler runs)")
@@ -266,6 +291,8 @@ def main():
     }
     run.close()
 
+    if not args.no_collisions:
+        out["collisions"] = collision_variants(case, args.steps, mlups)
     if not args.no_forms:
         out["forms"] = storage_forms(args.steps)
     if not args.no_batch:

@@ -7,7 +7,11 @@
  * conditions of App. C), optionally coupled to the D2Q5 vector-distribution
  * scheme for the magnetic induction equation (App. G), on the uniform
  * computational lattice of a straight clustered grid (metric factors
- * h1(xi1), h2(xi2); theta12 = theta21 = 0, the case of App. B(i)).
+ * h1(xi1), h2(xi2); theta12 = theta21 = 0, the case of App. B(i)).  Two
+ * simpler collision models run on the same data path: the raw-moment MRT
+ * model (the appendix summarising the raw-moment algorithm) and the
+ * single-relaxation-time model in velocity space (the appendix on
+ * velocity-space collisions); goc_params.collision selects one.
  *
  * Conventions shared by every entry point:
  *   - nodes (i, j), 0 <= i < nx, 0 <= j < ny, sit at xi = (i + 1/2, j + 1/2);
@@ -50,6 +54,16 @@ typedef enum {
                          arithmetic FP32                                         */
     GOC_BF16DEV = 3   /* as GOC_F16DEV with bfloat16                              */
 } goc_storage;
+
+typedef enum {
+    GOC_COLL_CENTRAL = 0,  /* central-moment MRT (App. E)                          */
+    GOC_COLL_RAW = 1,      /* raw-moment MRT: the nine combined raw moments relax
+                              to the Sec. 3 equilibria with the Sec. 5 corrections */
+    GOC_COLL_SRT = 2       /* single relaxation time tau = 1/omega[4] in velocity
+                              space, f^eq = P^-1 m^eq and S = P^-1 sigma; every
+                              rate is 1/tau, so zeta = nu.  Computed as the
+                              raw-moment body with equal rates (P is linear). */
+} goc_collision;
 
 typedef enum {
     GOC_STRETCH_ARRAY = 0,    /* metric factors given as arrays                   */
@@ -113,6 +127,11 @@ typedef struct {
     double tau_m;             /* magnetic relaxation time (> 1/2)            */
     double mu_m;              /* magnetic permeability                       */
     double B0;                /* applied field: wall and initial B2          */
+    int32_t collision;        /* goc_collision.  GOC_COLL_SRT reads omega[4]
+                                 only (the other entries are ignored) and
+                                 needs rho_terms = 0: its coefficients G_j,
+                                 H_j reduce from the Chapman-Enskog reading.
+                                 The runs of a batch share one model.        */
 } goc_params;
 
 /* Physical description used by goc_lbm_derive. */

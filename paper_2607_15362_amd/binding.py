@@ -20,6 +20,7 @@ STORAGE = {"f64": 0, "f32": 1, "f16dev": 2, "bf16dev": 3}
 STRETCH = {"array": 0, "uniform": 1, "tanh": 2, "roberts": 3}
 FLOW = {"channel": 0, "cavity": 1, "hartmann": 2, "free": 3}
 BC = {"periodic": 0, "wall": 1}
+COLLISION = {"central": 0, "raw": 1, "srt": 2}
 
 
 class GocError(RuntimeError):
@@ -44,7 +45,7 @@ class Params(C.Structure):
     _fields_ = [("omega", C.c_double * 9), ("rho0", C.c_double), ("F_ext", C.c_double * 2),
                 ("gi_terms", C.c_int32), ("q3_sign", C.c_int32), ("rho_terms", C.c_int32),
                 ("lid_corners", C.c_int32), ("mhd", C.c_int32), ("tau_m", C.c_double),
-                ("mu_m", C.c_double), ("B0", C.c_double)]
+                ("mu_m", C.c_double), ("B0", C.c_double), ("collision", C.c_int32)]
 
 
 class Physics(C.Structure):
@@ -144,6 +145,7 @@ def derive(case):
     _check(lib().goc_lbm_derive(C.byref(g), C.byref(m), C.byref(ph), C.byref(p)))
     p.gi_terms, p.q3_sign, p.rho_terms, p.lid_corners = (case.gi_terms, case.q3_sign,
                                                          case.rho_terms, case.lid_corners)
+    p.collision = COLLISION[getattr(case, "collision", "central")]
     if not case.mhd:
         p.mhd = 0
     return g, m, p

@@ -4,7 +4,11 @@
 // One fused pull-scheme kernel advances a whole time step of the
 // central-moment MRT GOC-LBM (App. E of Yahia & Premnath, with the local
 // shear stress of App. A and the boundary conditions of App. C) and, when
-// enabled, the D2Q5 vector-distribution scheme of App. G.  The metric is
+// enabled, the D2Q5 vector-distribution scheme of App. G.  A compile-time
+// selector swaps the collision body for the raw-moment MRT model of the
+// appendix that summarises it; the velocity-space SRT model of the
+// appendix on velocity-space collisions is that model with every rate equal
+// to 1/tau (f^eq = P^-1 m^eq and S = P^-1 sigma there, and P is linear).  The metric is
 // straight (h1(xi1), h2(xi2), theta12 = theta21 = 0; App. B(i)), which
 // removes every theta12 / theta21 term and makes the effective force equal
 // to its reduced form F~ (tau12 is not needed).
@@ -51,6 +55,9 @@ constexpr int kM = 5;
 constexpr int kWave = 64;
 constexpr int kOwn = kWave;   // columns owned per strip
 constexpr int kTab = 8;   // doubles per column / row table entry
+// Collision bodies selectable at compile time.
+constexpr int kCollCentral = 0;
+constexpr int kCollRaw = 1;
 
 __host__ __device__ constexpr int ex_(int a) { return (a == 1 || a == 5 || a == 8) ? 1 : (a == 3 || a == 6 || a == 7) ? -1 : 0; }
 __host__ __device__ constexpr int ey_(int a) { return (a == 2 || a == 5 || a == 6) ? 1 : (a == 4 || a == 7 || a == 8) ? -1 : 0; }
@@ -445,6 +452,25 @@ __device__ inline RawDev<T> raw_dev(const T* d)
     return m;
 }
 
+// Population increments P^-1 n of raw-moment increments n (n00 = 0).
+template <class T>
+__device__ inline void pop_increments(T n10, T n01, T n20, T n02, T n11, T n21, T n12, T n22, T* inc)
+{
+    const T hx = T(0.5) * (n20 - n22), hy = T(0.5) * (n02 - n22);
+    const T gx = T(0.5) * (n10 - n12), gy = T(0.5) * (n01 - n21);
+    const T qa = T(0.25) * (n22 + n11), qb = T(0.25) * (n22 - n11);
+    const T qc = T(0.25) * (n21 + n12), qd = T(0.25) * (n21 - n12);
+    inc[0] = n22 - n20 - n02;
+    inc[1] = hx + gx;
+    inc[3] = hx - gx;
+    inc[2] = hy + gy;
+    inc[4] = hy - gy;
+    inc[5] = qa + qc;
+    inc[6] = qb + qd;
+    inc[7] = qa - qc;
+    inc[8] = qb - qd;
+}
+
 // Central-moment collision of App. E (steps 2-5) at one node, written as an
 // increment: f~ = f + P^-1 F(U) dk, where dk = k~ - k are the changes of the
 // central moments (relaxation plus sources; dk00 = 0) and F(U) maps central
@@ -529,19 +555,48 @@ __device__ inline void cm_collide(const NodeParams<T>& p, const NodeMetric<T>& g
     const T n12 = b12 + U1 * b02;
     const T n22 = b22 + U1 * (b12 + n12);
     // step 5: population increments P^-1 dn
-    const T hx = T(0.5) * (n20 - n22), hy = T(0.5) * (n02 - n22);
-    const T gx = T(0.5) * (n10 - n12), gy = T(0.5) * (n01 - n21);
-    const T qa = T(0.25) * (n22 + n11), qb = T(0.25) * (n22 - n11);
-    const T qc = T(0.25) * (n21 + n12), qd = T(0.25) * (n21 - n12);
-    inc[0] = n22 - n20 - n02;
-    inc[1] = hx + gx;
-    inc[3] = hx - gx;
-    inc[2] = hy + gy;
-    inc[4] = hy - gy;
-    inc[5] = qa + qc;
-    inc[6] = qb + qd;
-    inc[7] = qa - qc;
-    inc[8] = qb - qd;
+    pop_increments(n10, n01, n20, n02, n11, n21, n12, n22, inc);
+}
+
+// Raw-moment MRT collision (the appendix summarising the raw-moment model),
+// as an increment f~ = f + P^-1 dm with dm = m~ - m: the nine combined raw
+// moments relax to the Sec. 3 equilibria (with the Sec. 5 corrections on
+// k20 + k02 and k20 - k02) and gain the Sec. 3 sources.  Equilibria enter as
+// deviations from the rest-state raw moments (h1 h2 rho0, 0, 0, (h2/h1) P0,
+// (h1/h2) P0, 0, 0, 0, rho0 c_s^4), so no large value is formed; dk'00 = 0
+// and the first-order increments use the lagged-force identity as in the
+// central-moment body.  With every rate 1/tau this is the velocity-space
+// SRT collision.
+template <class T>
+__device__ inline void raw_collide(const NodeParams<T>& p, const NodeMetric<T>& g, const RawDev<T>& m,
+                                   T rho, T drho, T U1, T U2, T Fp1, T Fp2, T F1, T F2, T n3, T n4, T* inc)
+{
+    const T r21 = g.h2 * g.ih1, r12 = g.h1 * g.ih2;
+    const T U11 = U1 * U1, U22 = U2 * U2;
+    const T rc = rho * p.cs2, drc = drho * p.cs2;
+    // equilibrium deviations
+    const T e20 = r21 * (rho * U11 + drc), e02 = r12 * (rho * U22 + drc);
+    const T e2s = e20 + e02 + n3, e2d = e20 - e02 + n4;
+    const T e11 = rho * U1 * U2;
+    const T e21 = (rc + rho * U11) * U2 * g.ih1;
+    const T e12 = (rc + rho * U22) * U1 * g.ih2;
+    const T e22 = drc * p.cs2 + rho * (p.cs2 * (U11 + U22) + U11 * U22);
+    // sources
+    const T sa = T(2) * F1 * U1 * g.ih1, sb = T(2) * F2 * U2 * g.ih2;
+    const T s11 = F1 * U2 * g.ih2 + F2 * U1 * g.ih1;
+    // relaxation increments
+    const T* w = p.w;
+    const T k2s = m.m20 + m.m02, k2d = m.m20 - m.m02;
+    const T d10 = T(0.5) * w[1] * Fp1 + (T(1) - T(0.5) * w[1]) * F1;
+    const T d01 = T(0.5) * w[2] * Fp2 + (T(1) - T(0.5) * w[2]) * F2;
+    const T d2s = w[3] * (e2s - k2s) + (T(1) - T(0.5) * w[3]) * (sa + sb);
+    const T d2d = w[4] * (e2d - k2d) + (T(1) - T(0.5) * w[4]) * (sa - sb);
+    const T d11 = w[5] * (e11 - m.m11) + (T(1) - T(0.5) * w[5]) * s11;
+    const T d21 = w[6] * (e21 - m.m21);
+    const T d12 = w[7] * (e12 - m.m12);
+    const T d22 = w[8] * (e22 - m.m22);
+    const T d20 = T(0.5) * (d2s + d2d), d02 = T(0.5) * (d2s - d2d);
+    pop_increments(d10, d01, d20, d02, d11, d21, d12, d22, inc);
 }
 
 // D2Q5 induction scheme of App. G on a straight grid (Y = 0: no source), in

@@ -152,6 +152,7 @@ struct goc_lbm {
     int device = 0;
     int nruns = 0;
     bool any_mhd = false;
+    int coll = goc::kCollCentral;   // collision body of the step kernel
     std::vector<RunDesc> runs;
     std::vector<goc_params> params;
     std::vector<goc_grid> grids;
@@ -223,12 +224,20 @@ int launch_step(goc_lbm* h, int k)
     return dispatch(h->storage, [&](auto tag) -> int {
         using S = decltype(tag);
         const auto pl = pools<S>(h, h->cur);
-        if (h->any_mhd)
-            hipLaunchKernelGGL((goc::step_kernel<S, true>), dim3(h->total_blocks), dim3(goc::kWave), 0,
-                               h->stream, h->runs_d, h->block_run_d, pl, h->step_ctr, k);
+        const dim3 grid(h->total_blocks), block(goc::kWave);
+        const bool raw = h->coll == goc::kCollRaw;
+        if (h->any_mhd && raw)
+            hipLaunchKernelGGL((goc::step_kernel<S, true, goc::kCollRaw>), grid, block, 0, h->stream,
+                               h->runs_d, h->block_run_d, pl, h->step_ctr, k);
+        else if (h->any_mhd)
+            hipLaunchKernelGGL((goc::step_kernel<S, true, goc::kCollCentral>), grid, block, 0, h->stream,
+                               h->runs_d, h->block_run_d, pl, h->step_ctr, k);
+        else if (raw)
+            hipLaunchKernelGGL((goc::step_kernel<S, false, goc::kCollRaw>), grid, block, 0, h->stream,
+                               h->runs_d, h->block_run_d, pl, h->step_ctr, k);
         else
-            hipLaunchKernelGGL((goc::step_kernel<S, false>), dim3(h->total_blocks), dim3(goc::kWave), 0,
-                               h->stream, h->runs_d, h->block_run_d, pl, h->step_ctr, k);
+            hipLaunchKernelGGL((goc::step_kernel<S, false, goc::kCollCentral>), grid, block, 0, h->stream,
+                               h->runs_d, h->block_run_d, pl, h->step_ctr, k);
         HIPOK(hipGetLastError());
         return GOC_OK;
     });
@@ -276,9 +285,15 @@ int free_all(goc_lbm* h)
 int check_params(const goc_params* p, const goc_grid* g, int run)
 {
     if (!p) return fail(GOC_EINVAL, "params is NULL");
-    for (int k = 0; k < 9; ++k)
+    if (p->collision < GOC_COLL_CENTRAL || p->collision > GOC_COLL_SRT)
+        return fail(GOC_EINVAL, "run %d: unknown collision model %d", run, p->collision);
+    for (int k = 0; k < 9; ++k) {
+        if (p->collision == GOC_COLL_SRT && k != 4) continue;   // SRT: one rate
         if (!(p->omega[k] > 0.0 && p->omega[k] < 2.0))
             return fail(GOC_EINVAL, "run %d: omega[%d] = %g outside (0, 2)", run, k, p->omega[k]);
+    }
+    if (p->collision == GOC_COLL_SRT && p->rho_terms)
+        return fail(GOC_EINVAL, "run %d: the SRT model takes rho_terms = 0", run);
     if (!(p->rho0 > 0.0)) return fail(GOC_EINVAL, "run %d: rho0 must be positive", run);
     if (p->mhd && !(p->tau_m > 0.5)) return fail(GOC_EINVAL, "run %d: tau_m must exceed 1/2", run);
     if (p->mhd && !(p->mu_m > 0.0)) return fail(GOC_EINVAL, "run %d: mu_m must be positive", run);
@@ -367,7 +382,10 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
         if ((rc = check_grid(&grid[r])) != GOC_OK) return bail(rc);
         if ((rc = check_params(&params[r], &grid[r], r)) != GOC_OK) return bail(rc);
         if ((rc = build_metric(grid[r], metric[r], tx, ty)) != GOC_OK) return bail(rc);
+        if (params[r].collision != params[0].collision)
+            return bail(fail(GOC_EINVAL, "run %d: the runs of a batch share one collision model", r));
     }
+    h->coll = params[0].collision == GOC_COLL_CENTRAL ? goc::kCollCentral : goc::kCollRaw;
     if (hipGetDevice(&h->device) != hipSuccess) return bail(fail(GOC_EDEVICE, "no HIP device"));
     int ncu = 256;
     {
@@ -427,7 +445,8 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
         d.rho_terms = p.rho_terms;
         d.lid_corners = p.lid_corners;
         d.mhd = p.mhd;
-        for (int k = 0; k < 9; ++k) d.omega[k] = p.omega[k];
+        // SRT: every moment relaxes at omega[4] = 1/tau (so zeta = nu)
+        for (int k = 0; k < 9; ++k) d.omega[k] = p.collision == GOC_COLL_SRT ? p.omega[4] : p.omega[k];
         d.Fx1 = p.F_ext[0];
         d.Fx2 = p.F_ext[1];
         d.rho0 = p.rho0;

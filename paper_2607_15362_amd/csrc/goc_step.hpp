@@ -347,8 +347,9 @@ __device__ inline void tile_of(const RunDesc& d, int local, int& strip, int& seg
 // segment of rows, and marches up the rows with four row slots (rows j-1,
 // j, j+1, j+2); the loads of rows j+2 and j+3 are in flight while row j is
 // collided.  Lanes 0 and 63 also pull the node beside the strip, one row
-// ahead, for the differences along xi1.
-template <class S, bool MHD>
+// ahead, for the differences along xi1.  COLL selects the collision body
+// (kCollCentral or kCollRaw) for every run of the launch.
+template <class S, bool MHD, int COLL>
 __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__ runs,
                                                      const int32_t* __restrict__ block_run,
                                                      Pools<S, typename ForceOf<S>::type> pl,
@@ -703,7 +704,10 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
         // 5. effective force, corrections, central-moment collision
         T F1, F2, n3, n4, inc[kQ];
         force_and_corrections<T>(p, g, rho, drho, U1, U2, d1U1, d2U2, d1r, d2r, Fx1, Fx2, F1, F2, n3, n4);
-        cm_collide<T>(p, g, raw_dev<T>(Cs.f), rho, drho, U1, U2, Cs.Fp1, Cs.Fp2, F1, F2, n3, n4, inc);
+        if constexpr (COLL == kCollRaw)
+            raw_collide<T>(p, g, raw_dev<T>(Cs.f), rho, drho, U1, U2, Cs.Fp1, Cs.Fp2, F1, F2, n3, n4, inc);
+        else
+            cm_collide<T>(p, g, raw_dev<T>(Cs.f), rho, drho, U1, U2, Cs.Fp1, Cs.Fp2, F1, F2, n3, n4, inc);
 
         // 6. D2Q9 writes: inc holds the collision increments; the writer adds the
         //    rest-state offsets of the interior axis slots (the reader is the

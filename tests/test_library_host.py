@@ -93,3 +93,24 @@ def test_create_rejects_bad_input_before_touching_the_device(lib):
     assert lib.goc_lbm_create(None, g, m, p, 1, None) == B.GOC_EINVAL
     g, m, p = B.derive(case)
     assert lib.goc_lbm_create(B.C.byref(h), g, m, p, 7, None) == B.GOC_EINVAL
+
+
+def test_create_rejects_bad_collision_choice_before_touching_the_device(lib):
+    """Collision selector: an unknown model, the SRT model with the printed
+    density coefficients, and a batch that mixes models are refused."""
+    case = W.channel_64()
+    h = B.VP()
+    g, m, p = B.derive(case)
+    p.collision = 3
+    assert lib.goc_lbm_create(B.C.byref(h), g, m, p, 1, None) == B.GOC_EINVAL
+    assert "collision" in lib.goc_lbm_last_error().decode()
+    g, m, p = B.derive(case.replace(collision="srt", rho_terms=1))
+    assert lib.goc_lbm_create(B.C.byref(h), g, m, p, 1, None) == B.GOC_EINVAL
+    assert "SRT" in lib.goc_lbm_last_error().decode()
+    structs = [B.derive(case.replace(collision=c)) for c in ("raw", "central")]
+    G = (B.Grid * 2)(*[s[0] for s in structs])
+    M = (B.Metric * 2)(*[s[1] for s in structs])
+    P = (B.Params * 2)(*[s[2] for s in structs])
+    assert lib.goc_lbm_create_batch(B.C.byref(h), 2, G, M, P, 1, None) == B.GOC_EINVAL
+    assert "share one collision" in lib.goc_lbm_last_error().decode()
+    assert not h.value
