@@ -81,6 +81,7 @@ class OracleCfg(C.Structure):
         ("h1_face_lo", C.POINTER(C.c_double)), ("h1_face_hi", C.POINTER(C.c_double)),
         ("h2_face_xlo", C.POINTER(C.c_double)), ("h2_face_xhi", C.POINTER(C.c_double)),
         ("collision", C.c_int32),
+        ("v_wall_lo", C.c_double), ("v_wall_hi", C.c_double),
     ]
 
 
@@ -181,32 +182,60 @@ def derive(case, h1, h2) -> Lattice:
 
 
 class Model:
-    """One oracle run: metric, lattice parameters and the FP64 state."""
+    """One oracle run: metric, lattice parameters and the FP64 state.
 
-    def __init__(self, case, lattice: Lattice | None = None):
+    The metric is the straight one of case.stretch_x / stretch_y, or a
+    general 2-D one: case.grid2d = ("annulus", a, Ro, n_theta) (the conformal
+    annular sector), or node arrays metric2d = (h1, h2) ([ny, nx]) whose
+    curvature elements come from second-order differences (reading: face
+    values are those of the adjacent nodes)."""
+
+    def __init__(self, case, lattice: Lattice | None = None, metric2d=None):
         self.case = case
         nx, ny = case.nx, case.ny
         self.nx, self.ny = nx, ny
-        h1, dh1, th1, h1lo, h1hi = metric_1d(nx, case.stretch_x)
-        h2, dh2, th2, h2lo, h2hi = metric_1d(ny, case.stretch_y)
-        self.h1_1d, self.h2_1d = h1, h2
-        self.dh1_1d, self.dh2_1d = dh1, dh2
+        g2 = getattr(case, "grid2d", None)
+        if g2 is None and metric2d is None:
+            h1, dh1, th1, h1lo, h1hi = metric_1d(nx, case.stretch_x)
+            h2, dh2, th2, h2lo, h2hi = metric_1d(ny, case.stretch_y)
+            self.h1_1d, self.h2_1d = h1, h2
+            self.dh1_1d, self.dh2_1d = dh1, dh2
+            # 2-D metric arrays (straight grid: theta12 = theta21 = 0)
+            self.h1 = np.ascontiguousarray(np.broadcast_to(h1[None, :], (ny, nx)))
+            self.h2 = np.ascontiguousarray(np.broadcast_to(h2[:, None], (ny, nx)))
+            self.th11 = np.ascontiguousarray(np.broadcast_to(th1[None, :], (ny, nx)))
+            self.th22 = np.ascontiguousarray(np.broadcast_to(th2[:, None], (ny, nx)))
+            self.th12 = np.zeros((ny, nx))
+            self.th21 = np.zeros((ny, nx))
+            self.h2_face_lo = np.full(nx, h2lo)
+            self.h2_face_hi = np.full(nx, h2hi)
+            self.h1_face_ylo = h1.copy()
+            self.h1_face_yhi = h1.copy()
+            self.h1_face_lo = np.full(ny, h1lo)
+            self.h1_face_hi = np.full(ny, h1hi)
+            self.h2_face_xlo = h2.copy()
+            self.h2_face_xhi = h2.copy()
+        else:
+            if metric2d is not None:
+                h1a, h2a = (np.ascontiguousarray(x, dtype=np.float64) for x in metric2d)
+                m = dict(h1=h1a, h2=h2a, **params.metric_from_arrays(h1a, h2a))
+                m.update(h1_face_lo=h1a[:, 0].copy(), h1_face_hi=h1a[:, -1].copy(),
+                         h2_face_xlo=h2a[:, 0].copy(), h2_face_xhi=h2a[:, -1].copy())
+            elif g2[0] == "annulus":
+                m = params.annulus(nx, ny, float(g2[1]), float(g2[2]), int(g2[3]))
+                self.radius = m["r"]
+            else:
+                raise ValueError(g2)
+            for k in ("h1", "h2", "th11", "th12", "th21", "th22"):
+                setattr(self, k, np.ascontiguousarray(m[k], dtype=np.float64))
+            self.h2_face_lo = self.h2[0].copy()
+            self.h2_face_hi = self.h2[-1].copy()
+            self.h1_face_ylo = self.h1[0].copy()
+            self.h1_face_yhi = self.h1[-1].copy()
+            for k in ("h1_face_lo", "h1_face_hi", "h2_face_xlo", "h2_face_xhi"):
+                setattr(self, k, np.ascontiguousarray(m[k], dtype=np.float64))
+            h1, h2 = self.h1, self.h2
         self.lat = lattice if lattice is not None else derive(case, h1, h2)
-        # 2-D metric arrays (straight grid: theta12 = theta21 = 0)
-        self.h1 = np.ascontiguousarray(np.broadcast_to(h1[None, :], (ny, nx)))
-        self.h2 = np.ascontiguousarray(np.broadcast_to(h2[:, None], (ny, nx)))
-        self.th11 = np.ascontiguousarray(np.broadcast_to(th1[None, :], (ny, nx)))
-        self.th22 = np.ascontiguousarray(np.broadcast_to(th2[:, None], (ny, nx)))
-        self.th12 = np.zeros((ny, nx))
-        self.th21 = np.zeros((ny, nx))
-        self.h2_face_lo = np.full(nx, h2lo)
-        self.h2_face_hi = np.full(nx, h2hi)
-        self.h1_face_ylo = h1.copy()
-        self.h1_face_yhi = h1.copy()
-        self.h1_face_lo = np.full(ny, h1lo)
-        self.h1_face_hi = np.full(ny, h1hi)
-        self.h2_face_xlo = h2.copy()
-        self.h2_face_xhi = h2.copy()
         self.cfg = self._make_cfg()
         self.N = nx * ny
         self.f = np.zeros((9, ny, nx))
@@ -224,6 +253,7 @@ class Model:
         c.collision = COLLISIONS[getattr(case, "collision", "central")]
         c.mhd = 1 if lat.mhd else 0
         c.u_wall_lo, c.u_wall_hi = lat.u_wall_lo, lat.u_wall_hi
+        c.v_wall_lo, c.v_wall_hi = (float(v) for v in getattr(case, "v_wall", (0.0, 0.0)))
         c.cs2 = lat.cs2
         for k in range(9):
             c.omega[k] = float(lat.omega[k])

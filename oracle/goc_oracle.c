@@ -95,6 +95,7 @@ typedef struct {
     const double *h1_face_lo, *h1_face_hi, *h2_face_xlo, *h2_face_xhi;  /* [ny] */
     int32_t collision;           /* 0 central-moment MRT, 1 raw-moment MRT,
                                     2 SRT with tau = 1/omega_4              */
+    double v_wall_lo, v_wall_hi; /* tangential (xi2) velocity of the xi1 = 0 / nx walls */
 } OracleCfg;
 
 /* ------------------------------------------------------------------ */
@@ -839,9 +840,14 @@ static void collide_at(const OracleCfg *c, const double *f, const double *g, Wor
    Wall (half-way bounce-back): f_a(x) = ft_opp(a)(x) plus, for a moving
    y-wall, the App. C momentum correction e_a1 rho_w cs2 U_w / (2 h2_wall),
    which gives f7 = ft5 - rho_w cs2 U_w/(2 h2_wall) and f8 = ft6 + ... at the
-   top wall.  reading: rho_w is the density of the wall-adjacent node at the
-   collision time level; with lid_corners a moving y-wall also owns the
-   corner ghost nodes.
+   top wall; for a moving x-wall (tangential velocity V_w along xi2) the same
+   construction, f^eq of App. C at (rho_w, 0, V_w), gives
+   e_a2 rho_w cs2 V_w / (2 h1_wall).  reading: rho_w is the density of the
+   wall-adjacent node at the collision time level; with lid_corners the
+   moving walls also own the corner ghost nodes, where the terms of both
+   walls add (the wall equilibria at (rho_w, U_w, V_w) to first order in the
+   speeds), which keeps each wall's pair of terms and so the mass; without
+   it the corner ghosts take none.
    D2Q5 walls use the App. G anti-bounce-back g_a,i(x) = -gt_opp(a),i(x)
    + 2 W h_wall B_i,wall with B_wall = (0, B0). */
 static void stream_at(const OracleCfg *c, const Work *w, double *fo, double *go, int i, int j)
@@ -853,7 +859,7 @@ static void stream_at(const OracleCfg *c, const Work *w, double *fo, double *go,
         int outx = 0, outy = 0;
         if (si < 0 || si >= c->nx) {
             if (c->bc_x == 0) si = (si + c->nx) % c->nx;
-            else outx = 1;
+            else outx = (si < 0) ? -1 : 1;
         }
         if (sj < 0 || sj >= c->ny) {
             if (c->bc_y == 0) sj = (sj + c->ny) % c->ny;
@@ -868,6 +874,11 @@ static void stream_at(const OracleCfg *c, const Work *w, double *fo, double *go,
             const double uw = (outy < 0) ? c->u_wall_lo : c->u_wall_hi;
             const double hw = (outy < 0) ? c->h2_face_lo[i] : c->h2_face_hi[i];
             v += EX[a] * w->rho[n] * c->cs2 * uw / (2.0 * hw);
+        }
+        if (outx && (!outy || c->lid_corners)) {
+            const double vw = (outx < 0) ? c->v_wall_lo : c->v_wall_hi;
+            const double hw = (outx < 0) ? c->h1_face_lo[j] : c->h1_face_hi[j];
+            v += EY[a] * w->rho[n] * c->cs2 * vw / (2.0 * hw);
         }
         fo[a * N + n] = v;
     }

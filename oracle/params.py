@@ -86,6 +86,49 @@ def roberts_y(n: int, gamma: float, xi, alpha: float = 0.5):
     return L * ((gamma + 2 * alpha) * l - gamma + 2 * alpha) / ((2 * alpha + 1) * (1 + l))
 
 
+def annulus(n1: int, n2: int, a: float, Ro: float, n_theta: int):
+    """Conformal map of an annular sector (the Taylor-Couette section):
+    Z = a exp(pi W / N_theta), shifted and scaled so that xi1 in [0, n1]
+    spans the radii a..Ro and xi2 in [0, n2] the polar angles
+    -pi/N_theta..pi/N_theta (node-centred reading: L_xi = n).  With
+    k = ln(Ro/a)/n1: r(xi1) = a exp(k xi1), h1 = a k exp(k xi1),
+    h2 = (2 pi a/(N_theta n2)) exp(k xi1), theta11 = theta21 = k/h1 =
+    exp(-k xi1)/a, theta12 = theta22 = 0.  Returns a dict of [n2, n1]
+    node arrays h1, h2, th11, th12, th21, th22, the radius r, and the
+    face values h1 on the xi1 = 0 / n1 walls per row and h2 beside them."""
+    k = math.log(Ro / a) / n1
+    xi1 = np.arange(n1, dtype=np.float64) + 0.5
+    e = np.exp(k * xi1)
+    h1 = a * k * e
+    h2 = 2.0 * math.pi * a / (n_theta * n2) * e
+    th = np.exp(-k * xi1) / a
+    rep = lambda v: np.ascontiguousarray(np.broadcast_to(v[None, :], (n2, n1)))
+    zero = np.zeros((n2, n1))
+    h2w = 2.0 * math.pi * a / (n_theta * n2)
+    return dict(h1=rep(h1), h2=rep(h2), th11=rep(th), th12=zero.copy(), th21=rep(th), th22=zero.copy(),
+                r=a * e, h1_face_lo=np.full(n2, a * k), h1_face_hi=np.full(n2, Ro * k),
+                h2_face_xlo=np.full(n2, h2w), h2_face_xhi=np.full(n2, h2w * Ro / a))
+
+
+def taylor_couette(r, R1: float, R2: float, Omega1: float, Omega2: float):
+    """Azimuthal speed u_theta(r) of steady circular Couette flow between
+    cylinders of radii R1 < R2 rotating at Omega1, Omega2."""
+    q = (R1 / R2) ** 2
+    r = np.asarray(r, dtype=np.float64)
+    return ((Omega2 - Omega1 * q) * r + R1 * R1 / r * (Omega1 - Omega2)) / (1.0 - q)
+
+
+def metric_from_arrays(h1, h2):
+    """Curvature elements of a 2-D orthogonal metric given at the nodes
+    ([ny, nx] arrays, unit node spacing), Sec. 2.1: theta11 = d1h1/h1^2,
+    theta12 = d2h1/(h1 h2), theta21 = d1h2/(h1 h2), theta22 = d2h2/h2^2,
+    with second-order differences (central inside, one-sided second order
+    at both ends of each axis)."""
+    d1h1, d2h1 = np.gradient(h1, axis=1, edge_order=2), np.gradient(h1, axis=0, edge_order=2)
+    d1h2, d2h2 = np.gradient(h2, axis=1, edge_order=2), np.gradient(h2, axis=0, edge_order=2)
+    return dict(th11=d1h1 / h1**2, th12=d2h1 / (h1 * h2), th21=d1h2 / (h1 * h2), th22=d2h2 / h2**2)
+
+
 # ------------------------------------------------------------ parameters ----
 
 def sound_speed_sq(h1, h2):

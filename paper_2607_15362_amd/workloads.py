@@ -48,6 +48,9 @@ class Case:
     lid_corners: int = 1
     rho_terms: int = 0
     collision: str = "central"        # "central" | "raw" (moment MRT) | "srt"
+    grid2d: tuple | None = None       # general 2-D metric: ("annulus", a, Ro, n_theta) or
+                                      # ("wavy", eps) (node arrays from wavy_metric)
+    v_wall: tuple = (0.0, 0.0)        # xi2 velocity of the walls at xi1 = 0 and xi1 = nx
     body_force: tuple = (0.0, 0.0)    # "free" flows: explicit force density
     init_seed: int | None = None      # smooth random initial fields when set
     init_amp: float = 0.0
@@ -108,6 +111,32 @@ def batch_256(seed: int = 15362, n: int = 256):
                          Re=float(Re[k]), Ha=float(Ha[k]), Pm=1.0, Ma=0.1, tau_max=1.0,
                          mhd=True, storage="f32", steps=1000))
     return runs
+
+
+def taylor_couette(n1: int = 256, n2: int = 6, R1: float = 32.0, n_theta: int = 60,
+                   U_in: float = 0.01, U_out: float = 0.015, tau: float = 1.0,
+                   storage: str = "f64", collision: str = "central") -> Case:
+    """Circular Couette flow in one annular sector on the conformal grid of
+    the curvilinear section: n1 radial nodes between the inner radius R1
+    and R2 = R1 + n1 (walls moving at the linear speeds U_in, U_out),
+    n2 periodic azimuthal nodes over 2 pi / n_theta, shear relaxation time
+    tau (the paper's sector: 256 x 6, R1 = 32, n_theta = 60, U0 = 0.01)."""
+    return Case(f"tc_{n1}x{n2}", n1, n2, "wall", "periodic", flow="free", tau=tau,
+                body_force=(0.0, 0.0), grid2d=("annulus", R1, R1 + n1, n_theta),
+                v_wall=(U_in, U_out), storage=storage, collision=collision, steps=0)
+
+
+def wavy_metric(nx: int, ny: int, eps: float):
+    """Node metric of the conformal map Z = W + eps (2L/pi) sin(pi W / (2L)),
+    L = max(nx, ny), W = xi1 + i xi2 at the nodes xi = (i + 1/2, j + 1/2):
+    h1 = h2 = |1 + eps cos(pi W / (2L))|, a non-separable orthogonal grid
+    (|h - 1| <= 2.6 eps over the domain).  Returns [ny, nx] arrays (h1, h2)."""
+    L = float(max(nx, ny))
+    x = np.arange(nx) + 0.5
+    y = np.arange(ny) + 0.5
+    W = x[None, :] + 1j * y[:, None]
+    h = np.abs(1.0 + eps * np.cos(0.5 * np.pi * W / L))
+    return np.ascontiguousarray(h), np.ascontiguousarray(h.copy())
 
 
 # ---- seeded smooth random fields ---------------------------------------------
