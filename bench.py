@@ -22,6 +22,9 @@ Prints ONE JSON line:
   collisions                 the main workload with the raw-moment MRT and the
                              SRT collision bodies instead of the central-moment
                              one (same data path, same launch)
+  curvilinear                the curvilinear step (general 2-D metric, two
+                             launches per step) on a 2048x512 conformal annular
+                             sector, FP32, with its algorithmic bytes
 """
 from __future__ import annotations
 
@@ -214,6 +217,33 @@ def collision_variants(case, steps: int, central_mlups: float):
     return out
 
 
+def curvilinear_form(steps: int):
+    """The curvilinear step on a large conformal annular sector (Taylor-Couette
+    geometry: 2048 radial x 512 azimuthal nodes, R1 = 256, R2 = R1 + 2048, the
+    sector angle chosen for cells of aspect ratio about one), FP32: MLUPS and
+    the achieved bandwidth in algorithmic bytes (populations and force read
+    and written, the 12 metric planes read), with the launch time of the two
+    kernels together from HIP events."""
+    import math
+    from paper_2607_15362_amd import binding as B
+    from paper_2607_15362_amd import workloads as W
+    n1, n2, R1 = 2048, 512, 256.0
+    n_theta = 2.0 * math.pi * n1 / (n2 * math.log((R1 + n1) / R1))
+    c = W.taylor_couette(n1=n1, n2=n2, R1=R1, n_theta=n_theta, U_in=0.01, U_out=0.015, storage="f32")
+    r = B.Run(c)
+    n = max(200, steps // 10)
+    w, e = time_run(r, n, 50)
+    d = r.derived()
+    nodes = n1 * n2
+    out = {"workload": f"annular sector {n1}x{n2}, R1 = {R1:g}, FP32", "steps": n,
+           "MLUPS": round(nodes * n / w / 1e6, 1), "step_us": round(e / n * 1e6, 2),
+           "bytes_per_node": d["bytes_per_node"],
+           "GB_s_algorithmic": round(d["bytes_per_node"] * nodes / (e / n) / 1e9, 1)}
+    out["frac_of_8TBs"] = round(out["GB_s_algorithmic"] / PEAK_HBM_GBS, 4)
+    r.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,6 +255,7 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-collisions", action="store_true")
+    ap.add_argument("--no-curvilinear", action="store_true")
     ap.add_argument("--waves", type=float, default=0.0, metavar="W",
                     help="fixed launch plan of W waves per CU instead of the autotuner "
                          "(for profiler runs)")
@@ -293,6 +324,8 @@ def main():
 
     if not args.no_collisions:
         out["collisions"] = collision_variants(case, args.steps, mlups)
+    if not args.no_curvilinear:
+        out["curvilinear"] = curvilinear_form(args.steps)
     if not args.no_forms:
         out["forms"] = storage_forms(args.steps)
     if not args.no_batch:

@@ -69,8 +69,16 @@ typedef enum {
     GOC_STRETCH_ARRAY = 0,    /* metric factors given as arrays                   */
     GOC_STRETCH_UNIFORM = 1,  /* h = 1                                            */
     GOC_STRETCH_TANH = 2,     /* Sec. 6.1 two-wall hyperbolic tangent, parameter beta */
-    GOC_STRETCH_ROBERTS = 3   /* Sec. 6.2 Roberts transformation, parameter gamma,
+    GOC_STRETCH_ROBERTS = 3,  /* Sec. 6.2 Roberts transformation, parameter gamma,
                                  clustered at both walls (alpha = 1/2)           */
+    /* General 2-D metrics (kind_x only; kind_y is then ignored): */
+    GOC_STRETCH_ANNULUS = 4,  /* the conformal annular sector of the curvilinear
+                                 section, Z = a exp(pi W / N_theta) shifted and
+                                 scaled: xi1 in [0, nx] spans the radii a = param_x
+                                 .. Ro = param_y, xi2 in [0, ny] the angle
+                                 2 pi / n_theta; h1, h2 and theta11 = theta21 in
+                                 closed form, theta12 = theta22 = 0              */
+    GOC_STRETCH_ARRAY2D = 5   /* node arrays h1_2d, h2_2d [ny*nx]               */
 } goc_stretch;
 
 typedef enum {
@@ -86,11 +94,16 @@ typedef enum {
 
 /* Lattice and boundaries.  u_wall_lo / u_wall_hi are the tangential (xi1)
    velocities of the walls at xi2 = 0 and xi2 = ny (momentum-augmented
-   bounce-back of App. C); they are used only when bc_y is GOC_BC_WALL. */
+   bounce-back of App. C); they are used only when bc_y is GOC_BC_WALL.
+   v_wall_lo / v_wall_hi are the tangential (xi2) velocities of the walls at
+   xi1 = 0 and xi1 = nx (the same construction: e_a2 rho_w c_s^2 V_w /
+   (2 h1_wall)), used only when bc_x is GOC_BC_WALL.  With lid_corners the
+   corner ghosts take the terms of both walls. */
 typedef struct {
     int32_t nx, ny;           /* >= 3 each                                   */
     int32_t bc_x, bc_y;       /* goc_bc                                      */
     double u_wall_lo, u_wall_hi;
+    double v_wall_lo, v_wall_hi;
 } goc_grid;
 
 /* Metric factors of a straight orthogonal grid.  For GOC_STRETCH_ARRAY the
@@ -99,13 +112,25 @@ typedef struct {
    (NULL: second-order finite differences, one-sided at the ends), and the
    values on the wall faces h1_face[2] (xi1 = 0, nx) and h2_face[2]
    (xi2 = 0, ny); a face value <= 0 means "the adjacent node's value".
-   For the analytic kinds only the kind and its parameter are read. */
+   For the analytic kinds only the kind and its parameter are read.
+   General 2-D metrics (kind_x GOC_STRETCH_ANNULUS or GOC_STRETCH_ARRAY2D):
+   for the annulus param_x, param_y and n_theta (> 0, param_y > param_x > 0);
+   for arrays h1_2d, h2_2d [ny*nx] (host, FP64, > 0) and either all four
+   derivative arrays d1h1, d2h1, d1h2, d2h2 [ny*nx] or none (second-order
+   differences: central, wrapped along a periodic axis, one-sided at the
+   ends of a walled one); their face values are the adjacent nodes'.  A run
+   on a 2-D metric takes the curvilinear step (two launches per step, the
+   metric read per node); it cannot be MHD, and the runs of a batch share
+   the metric kind (2-D or straight). */
 typedef struct {
     int32_t kind_x, kind_y;   /* goc_stretch                                 */
-    double param_x, param_y;  /* beta (tanh) or gamma (Roberts)              */
+    double param_x, param_y;  /* beta (tanh) or gamma (Roberts); annulus radii */
     const double *h1, *h2;
     const double *dh1, *dh2;
     double h1_face[2], h2_face[2];
+    double n_theta;           /* annulus: sectors in a full circle           */
+    const double *h1_2d, *h2_2d;
+    const double *d1h1, *d2h1, *d1h2, *d2h2;
 } goc_metric;
 
 /* Lattice parameters of a run (all in lattice units).  c_s^2 = q^2/3 with
@@ -265,8 +290,15 @@ int goc_lbm_derived(const goc_lbm_t *h, double out[16]);
 int goc_lbm_derived_run(const goc_lbm_t *h, int32_t run, double out[16]);
 
 /* Metric arrays as used by the kernels (FP64 host): h1, theta11 [nx],
-   h2, theta22 [ny]; any pointer may be NULL. */
+   h2, theta22 [ny]; any pointer may be NULL.  GOC_EINVAL for a run on a
+   2-D metric (use goc_lbm_metric_2d). */
 int goc_lbm_metric(const goc_lbm_t *h, double *h1, double *th11, double *h2, double *th22);
+/* Node metric of run `run` (FP64 host arrays [ny*nx], any may be NULL):
+   h1, h2 and the curvature elements theta11 = d1h1/h1^2, theta12 =
+   d2h1/(h1 h2), theta21 = d1h2/(h1 h2), theta22 = d2h2/h2^2 (Sec. 2.1), for
+   straight and 2-D metrics alike. */
+int goc_lbm_metric_2d(const goc_lbm_t *h, int32_t run, double *h1, double *h2, double *th11, double *th12,
+                      double *th21, double *th22);
 
 void goc_lbm_destroy(goc_lbm_t *h);
 const char *goc_lbm_last_error(void);

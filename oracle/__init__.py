@@ -218,11 +218,12 @@ class Model:
         else:
             if metric2d is not None:
                 h1a, h2a = (np.ascontiguousarray(x, dtype=np.float64) for x in metric2d)
-                m = dict(h1=h1a, h2=h2a, **params.metric_from_arrays(h1a, h2a))
+                m = dict(h1=h1a, h2=h2a, **params.metric_from_arrays(h1a, h2a, case.bc_x == "periodic",
+                                                                      case.bc_y == "periodic"))
                 m.update(h1_face_lo=h1a[:, 0].copy(), h1_face_hi=h1a[:, -1].copy(),
                          h2_face_xlo=h2a[:, 0].copy(), h2_face_xhi=h2a[:, -1].copy())
             elif g2[0] == "annulus":
-                m = params.annulus(nx, ny, float(g2[1]), float(g2[2]), int(g2[3]))
+                m = params.annulus(nx, ny, float(g2[1]), float(g2[2]), float(g2[3]))
                 self.radius = m["r"]
             else:
                 raise ValueError(g2)

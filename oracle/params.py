@@ -86,7 +86,7 @@ def roberts_y(n: int, gamma: float, xi, alpha: float = 0.5):
     return L * ((gamma + 2 * alpha) * l - gamma + 2 * alpha) / ((2 * alpha + 1) * (1 + l))
 
 
-def annulus(n1: int, n2: int, a: float, Ro: float, n_theta: int):
+def annulus(n1: int, n2: int, a: float, Ro: float, n_theta: float):
     """Conformal map of an annular sector (the Taylor-Couette section):
     Z = a exp(pi W / N_theta), shifted and scaled so that xi1 in [0, n1]
     spans the radii a..Ro and xi2 in [0, n2] the polar angles
@@ -118,14 +118,18 @@ def taylor_couette(r, R1: float, R2: float, Omega1: float, Omega2: float):
     return ((Omega2 - Omega1 * q) * r + R1 * R1 / r * (Omega1 - Omega2)) / (1.0 - q)
 
 
-def metric_from_arrays(h1, h2):
+def metric_from_arrays(h1, h2, periodic_x: bool = False, periodic_y: bool = False):
     """Curvature elements of a 2-D orthogonal metric given at the nodes
     ([ny, nx] arrays, unit node spacing), Sec. 2.1: theta11 = d1h1/h1^2,
     theta12 = d2h1/(h1 h2), theta21 = d1h2/(h1 h2), theta22 = d2h2/h2^2,
-    with second-order differences (central inside, one-sided second order
-    at both ends of each axis)."""
-    d1h1, d2h1 = np.gradient(h1, axis=1, edge_order=2), np.gradient(h1, axis=0, edge_order=2)
-    d1h2, d2h2 = np.gradient(h2, axis=1, edge_order=2), np.gradient(h2, axis=0, edge_order=2)
+    with second-order differences: central inside, wrapped along a periodic
+    axis, one-sided second order at the ends of a walled one."""
+    def d(f, axis, periodic):
+        if periodic:
+            return 0.5 * (np.roll(f, -1, axis=axis) - np.roll(f, 1, axis=axis))
+        return np.gradient(f, axis=axis, edge_order=2)
+    d1h1, d2h1 = d(h1, 1, periodic_x), d(h1, 0, periodic_y)
+    d1h2, d2h2 = d(h2, 1, periodic_x), d(h2, 0, periodic_y)
     return dict(th11=d1h1 / h1**2, th12=d2h1 / (h1 * h2), th21=d1h2 / (h1 * h2), th22=d2h2 / h2**2)
 
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libgoclbm.so")
 
 GOC_OK, GOC_EINVAL, GOC_ENOMEM, GOC_EDEVICE, GOC_EUNSTABLE, GOC_ESTATE = 0, -1, -2, -3, -4, -5
 STORAGE = {"f64": 0, "f32": 1, "f16dev": 2, "bf16dev": 3}
-STRETCH = {"array": 0, "uniform": 1, "tanh": 2, "roberts": 3}
+STRETCH = {"array": 0, "uniform": 1, "tanh": 2, "roberts": 3, "annulus": 4, "array2d": 5}
 FLOW = {"channel": 0, "cavity": 1, "hartmann": 2, "free": 3}
 BC = {"periodic": 0, "wall": 1}
 COLLISION = {"central": 0, "raw": 1, "srt": 2}
@@ -31,14 +31,19 @@ class GocError(RuntimeError):
 
 class Grid(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("bc_x", C.c_int32), ("bc_y", C.c_int32),
-                ("u_wall_lo", C.c_double), ("u_wall_hi", C.c_double)]
+                ("u_wall_lo", C.c_double), ("u_wall_hi", C.c_double),
+                ("v_wall_lo", C.c_double), ("v_wall_hi", C.c_double)]
 
 
 class Metric(C.Structure):
     _fields_ = [("kind_x", C.c_int32), ("kind_y", C.c_int32), ("param_x", C.c_double),
                 ("param_y", C.c_double), ("h1", C.POINTER(C.c_double)), ("h2", C.POINTER(C.c_double)),
                 ("dh1", C.POINTER(C.c_double)), ("dh2", C.POINTER(C.c_double)),
-                ("h1_face", C.c_double * 2), ("h2_face", C.c_double * 2)]
+                ("h1_face", C.c_double * 2), ("h2_face", C.c_double * 2),
+                ("n_theta", C.c_double),
+                ("h1_2d", C.POINTER(C.c_double)), ("h2_2d", C.POINTER(C.c_double)),
+                ("d1h1", C.POINTER(C.c_double)), ("d2h1", C.POINTER(C.c_double)),
+                ("d1h2", C.POINTER(C.c_double)), ("d2h2", C.POINTER(C.c_double))]
 
 
 class Params(C.Structure):
@@ -82,6 +87,7 @@ SIGNATURES = {
     "goc_lbm_set_state": (C.c_int, [VP, VP, C.c_size_t]),
     "goc_lbm_derived": (C.c_int, [VP, P_D]),
     "goc_lbm_metric": (C.c_int, [VP, P_D, P_D, P_D, P_D]),
+    "goc_lbm_metric_2d": (C.c_int, [VP, C.c_int32, P_D, P_D, P_D, P_D, P_D, P_D]),
     "goc_lbm_destroy": (None, [VP]),
     "goc_lbm_last_error": (C.c_char_p, []),
     "goc_lbm_num_runs": (C.c_int32, [VP]),
@@ -126,10 +132,24 @@ def _vptr(a):
 
 def case_structs(case):
     """Grid, Metric and Physics structs of a workload description."""
-    g = Grid(case.nx, case.ny, BC[case.bc_x], BC[case.bc_y], 0.0, 0.0)
+    vw = getattr(case, "v_wall", (0.0, 0.0))
+    g = Grid(case.nx, case.ny, BC[case.bc_x], BC[case.bc_y], 0.0, 0.0, float(vw[0]), float(vw[1]))
     m = Metric()
     m.kind_x, m.param_x = STRETCH[case.stretch_x[0]], float(case.stretch_x[1])
     m.kind_y, m.param_y = STRETCH[case.stretch_y[0]], float(case.stretch_y[1])
+    g2 = getattr(case, "grid2d", None)
+    if g2 is not None:
+        if g2[0] == "annulus":
+            m.kind_x = STRETCH["annulus"]
+            m.param_x, m.param_y, m.n_theta = float(g2[1]), float(g2[2]), float(g2[3])
+        elif g2[0] == "wavy":
+            from . import workloads as W
+            h1, h2 = W.wavy_metric(case.nx, case.ny, float(g2[1]))
+            m.kind_x = STRETCH["array2d"]
+            m.h1_2d, m.h2_2d = _dptr(h1), _dptr(h2)
+            m._keep = (h1, h2)     # the arrays must outlive the create call
+        else:
+            raise ValueError(f"unknown 2-D grid {g2[0]}")
     ph = Physics()
     ph.flow = FLOW[case.flow]
     ph.Re, ph.Ha, ph.Pm, ph.Ma = case.Re, case.Ha, case.Pm, case.Ma
@@ -236,6 +256,7 @@ class Run:
             params = (Params * n)()
             for k, c in enumerate(batch):
                 g, m, p = derive(c)
+                self._keep.append(m)
                 grids[k], metrics[k], params[k] = g, m, p
             st = STORAGE[storage or batch[0].storage]
             _check(lib().goc_lbm_create_batch(C.byref(h), n, grids, metrics, params, st, stream))
@@ -373,6 +394,13 @@ class Run:
         out = np.zeros(4)
         _check(lib().goc_lbm_tune(self.h, int(trial_steps), _dptr(out)))
         return dict(waves_per_cu=out[0], us_per_step=out[1], us_before=out[2], candidates=int(out[3]))
+
+    def metric_2d(self, run=0):
+        """Node metric (h1, h2, th11, th12, th21, th22), each [ny, nx] FP64."""
+        c = self.cases[run]
+        out = [np.zeros((c.ny, c.nx)) for _ in range(6)]
+        _check(lib().goc_lbm_metric_2d(self.h, int(run), *[_dptr(o) for o in out]))
+        return tuple(out)
 
     def metric_arrays(self):
         h1, t1 = np.zeros(self.nx), np.zeros(self.nx)

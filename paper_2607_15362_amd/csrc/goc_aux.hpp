@@ -103,16 +103,37 @@ __device__ inline void put_slot(S* base, const RunDesc& d, int i, int j, int a, 
 
 __device__ inline double sc_of(const RunDesc& d, int a, bool scaled) { return scaled ? d.sc[cls_(a)] : 1.0; }
 
-// Per-node metric of run d (FP64).
+// Per-node metric of run d (FP64): the column / row tables of a straight
+// grid, or the node planes of a general 2-D metric.
 struct NodeM {
-    double h1, h2;
+    double h1, h2, ih1, ih2, th11, th12, th21, th22;
 };
 template <class S, class FT>
 __device__ inline NodeM node_metric(const RunDesc& d, const Pools<S, FT>& pl, int i, int j)
 {
     NodeM m;
-    m.h1 = pl.col[(d.col_off + i) * kTab + T_H];
-    m.h2 = pl.row[(d.row_off + j) * kTab + T_H];
+    if (d.metric2d) {
+        const int64_t N = (int64_t)d.nx * d.ny;
+        const double* q = pl.met + d.met_off + (int64_t)j * d.nx + i;
+        m.h1 = q[M_H1 * N];
+        m.ih1 = q[M_IH1 * N];
+        m.h2 = q[M_H2 * N];
+        m.ih2 = q[M_IH2 * N];
+        m.th11 = q[M_TH11 * N];
+        m.th12 = q[M_TH12 * N];
+        m.th21 = q[M_TH21 * N];
+        m.th22 = q[M_TH22 * N];
+        return m;
+    }
+    const double* ct = pl.col + (d.col_off + i) * kTab;
+    const double* rt = pl.row + (d.row_off + j) * kTab;
+    m.h1 = ct[T_H];
+    m.ih1 = ct[T_IH];
+    m.th11 = ct[T_TH];
+    m.h2 = rt[T_H];
+    m.ih2 = rt[T_IH];
+    m.th22 = rt[T_TH];
+    m.th12 = m.th21 = 0.0;
     return m;
 }
 
@@ -135,15 +156,16 @@ __global__ void init_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, 
     const int j = blockIdx.y;
     if (i >= d.nx || j >= d.ny) return;
     const NodeParams<T> p = node_params<T>(d);
-    const double* ct = pl.col + (d.col_off + i) * kTab;
-    const double* rt = pl.row + (d.row_off + j) * kTab;
+    const NodeM nm = node_metric(d, pl, i, j);
     NodeMetric<T> g;
-    g.h1 = T(ct[T_H]);
-    g.ih1 = T(ct[T_IH]);
-    g.th11 = T(ct[T_TH]);
-    g.h2 = T(rt[T_H]);
-    g.ih2 = T(rt[T_IH]);
-    g.th22 = T(rt[T_TH]);
+    g.h1 = T(nm.h1);
+    g.ih1 = T(nm.ih1);
+    g.th11 = T(nm.th11);
+    g.h2 = T(nm.h2);
+    g.ih2 = T(nm.ih2);
+    g.th22 = T(nm.th22);
+    g.th12 = T(nm.th12);
+    g.th21 = T(nm.th21);
     auto at = [&](const double* a, int ii, int jj) -> T { return T(a[(int64_t)jj * d.nx + ii]); };
     T rho = p.rho0, U1 = T(0), U2 = T(0), d1U1 = T(0), d2U2 = T(0), d1r = T(0), d2r = T(0);
     T drho = T(0);
@@ -173,7 +195,11 @@ __global__ void init_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, 
         d2r = fdy(rho_in);
     }
     T F1, F2, n3, n4;
-    force_and_corrections<T>(p, g, rho, drho, U1, U2, d1U1, d2U2, d1r, d2r, p.Fx1, p.Fx2, F1, F2, n3, n4);
+    if (d.metric2d)   // (the corrections need tau^c only, not tau12)
+        force_and_corrections_gen<T>(p, g, rho, drho, U1, U2, d1U1, d2U2, d1r, d2r, p.Fx1, p.Fx2, rho * U1 * U2,
+                                     F1, F2, n3, n4);
+    else
+        force_and_corrections<T>(p, g, rho, drho, U1, U2, d1U1, d2U2, d1r, d2r, p.Fx1, p.Fx2, F1, F2, n3, n4);
     // raw-equilibrium deviations from the rest moments
     const T r21 = g.h2 * g.ih1, r12 = g.h1 * g.ih2, cs2 = p.cs2;
     const T dP = drho * cs2;
@@ -310,15 +336,14 @@ __global__ void fields_kernel(const RunDesc* __restrict__ runs, int run, Pools<S
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= d.nx || j >= d.ny) return;
-    const double* ct = pl.col + (d.col_off + i) * kTab;
-    const double* rt = pl.row + (d.row_off + j) * kTab;
+    const NodeM nm = node_metric(d, pl, i, j);
     T f[kQ], dg[2][kM];
     node_devs<S, T>(d, pl, i, j, f, d.mhd ? dg : nullptr);
     LaneCol L;
     L.col = i;
     L.valid = true;
     T dr, U1, U2, Fp1, Fp2;
-    row_moments<typename ForceOf<S>::type, T>(d, pl.Fin, L, j, f, T(d.rho0), T(ct[T_IH]), T(rt[T_IH]), dr,
+    row_moments<typename ForceOf<S>::type, T>(d, pl.Fin, L, j, f, T(d.rho0), T(nm.ih1), T(nm.ih2), dr,
                                               U1, U2, Fp1, Fp2);
     const int64_t N = (int64_t)d.nx * d.ny, o = (int64_t)j * d.nx + i;
     if (rho_o) rho_o[o] = d.rho0 + double(dr);
@@ -332,7 +357,7 @@ __global__ void fields_kernel(const RunDesc* __restrict__ runs, int run, Pools<S
             S1 += double(dg[0][a]);
             S2 += double(dg[1][a]);
         }
-        const double ihh = ct[T_IH] * rt[T_IH];
+        const double ihh = nm.ih1 * nm.ih2;
         B_o[o] = S1 * ihh;
         B_o[N + o] = d.B0 + S2 * ihh;
     }
@@ -354,18 +379,17 @@ __global__ void diag_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, 
     double v[kDiag] = {0, 0, 0, 0, 0, 0, 0};
     if (idx < N) {
         const int i = (int)(idx % d.nx), j = (int)(idx / d.nx);
-        const double* ct = pl.col + (d.col_off + i) * kTab;
-        const double* rt = pl.row + (d.row_off + j) * kTab;
+        const NodeM nm = node_metric(d, pl, i, j);
         T f[kQ], dg[2][kM];
         node_devs<S, T>(d, pl, i, j, f, d.mhd ? dg : nullptr);
         LaneCol L;
         L.col = i;
         L.valid = true;
         T dr, U1, U2, Fp1, Fp2;
-        row_moments<typename ForceOf<S>::type, T>(d, pl.Fin, L, j, f, T(d.rho0), T(ct[T_IH]), T(rt[T_IH]),
+        row_moments<typename ForceOf<S>::type, T>(d, pl.Fin, L, j, f, T(d.rho0), T(nm.ih1), T(nm.ih2),
                                                   dr, U1, U2, Fp1, Fp2);
         const double rho = d.rho0 + double(dr);
-        const double h1 = ct[T_H], h2 = rt[T_H];
+        const double h1 = nm.h1, h2 = nm.h2;
         double m = h1 * h2 * d.rho0;   // sum of the rest-state populations
         int bad = 0;
         for (int a = 0; a < kQ; ++a) {

@@ -80,7 +80,7 @@ enum { T_H = 0, T_IH, T_TH, T_AP, T_AM, T_BP, T_BM };
 enum {
     P_CS2 = 0, P_ICS2, P_NU, P_ZETA, P_RHO0, P_P0, P_W, P_FX1 = P_W + 9, P_FX2, P_CSM2, P_ICSM2, P_TAUM,
     P_ITAUM, P_ETA, P_IMU, P_B0, P_WM0, P_WM1, P_SC, P_ISC = P_SC + 4, P_SCG = P_ISC + 4, P_ISCG, P_CWLO,
-    P_CWHI, P_HWLO, P_HWHI, P_H1WLO, P_H1WHI, kNP
+    P_CWHI, P_HWLO, P_HWHI, P_H1WLO, P_H1WHI, P_CXLO, P_CXHI, kNP
 };
 
 struct RunDesc {
@@ -90,13 +90,16 @@ struct RunDesc {
     int32_t first_block;           // first work-group of this run
     int32_t gi_terms, q3_sign, rho_terms, lid_corners, mhd;
     int32_t pitchF;                // row stride of the force pool
+    int32_t metric2d;              // 1: general 2-D metric (per-node pool), else separable tables
     int64_t plane;                 // offset between planes within a row (the padded row length)
     int64_t f_off, F_off, g_off;   // element offsets of plane 0 in the f, force, g pools
     int64_t col_off, row_off;      // entry offsets into the column / row tables
+    int64_t met_off, face_off;     // 2-D metric: offsets into the node pool and the face pool
     double cs2, nu, zeta;
     double omega[9];
     double Fx1, Fx2, rho0;
-    double uw_lo, uw_hi;           // moving y-wall speeds
+    double uw_lo, uw_hi;           // moving y-wall speeds (along xi1)
+    double vw_lo, vw_hi;           // moving x-wall speeds (along xi2)
     double hw_lo, hw_hi;           // h2 on the y-wall faces
     double h1w_lo, h1w_hi;         // h1 on the x-wall faces
     double csm2, tau_m, eta, inv_mu, B0;
@@ -142,6 +145,8 @@ inline void set_step_params(RunDesc& d)
     v[P_HWHI] = d.hw_hi;
     v[P_H1WLO] = d.h1w_lo;
     v[P_H1WHI] = d.h1w_hi;
+    v[P_CXLO] = d.h1w_lo > 0 ? d.cs2 * d.vw_lo / (2.0 * d.h1w_lo) : 0.0;
+    v[P_CXHI] = d.h1w_hi > 0 ? d.cs2 * d.vw_hi / (2.0 * d.h1w_hi) : 0.0;
     for (int k = 0; k < kNP; ++k) {
         d.pd[k] = v[k];
         d.pf[k] = float(v[k]);
@@ -165,7 +170,21 @@ struct Pools {
     const double* row;   // row tables
     const float* colf;   // the same tables rounded to FP32
     const float* rowf;
+    // general 2-D metric: per-node planes (kMet of them, FP64 and FP32) and
+    // the wall-face values (per row: h1 on the xi1 = 0 / nx faces; per
+    // column: h2 on the xi2 = 0 / ny faces)
+    const double* met;
+    const float* metf;
+    const double* face;
 };
+
+// Planes of the 2-D metric pool, each nx * ny node values (row-major): the
+// metric factors, their reciprocals, the curvature elements and the
+// rest-state offsets of the four axis slots, f^rest_a(x) - f^rest_a(x + e_a)
+// = (P0/2) (h2/h1 (x) - h2/h1 (x + e_a)) along xi1 and the xi2 analogue with
+// h1/h2 (zero toward a wall, wrapped when periodic; computed in FP64, so the
+// two offsets of one link are exact negatives also after rounding).
+enum { M_H1 = 0, M_IH1, M_H2, M_IH2, M_TH11, M_TH12, M_TH21, M_TH22, M_AE, M_AW, M_AN, M_AS, kMet };
 
 // ---------------------------------------------------------------------------
 // Unbiased rounding of the stored values.  In a nearly steady flow a stored
@@ -360,6 +379,7 @@ __device__ inline void opaque_v(uint32_t& x) { asm volatile("" : "+v"(x)); }
 template <class T>
 struct NodeMetric {
     T h1, h2, ih1, ih2, th11, th22;
+    T th12, th21;   // general 2-D metric only
 };
 
 // Effective force on a straight grid (Sec. 2.2 with theta12 = theta21 = 0):
@@ -420,6 +440,86 @@ __device__ inline void force_and_corrections(const NodeParams<T>& p, const NodeM
         D42 = rho * (-nu * h1 * ics - (ze - nu) * ih1 + (T(2) * nu + ze) * s2);
         D33 = D34 = D43 = D44 = T(0);
         const T g1 = U1 * r21 * g.th11, g2 = U2 * r12 * g.th22;
+        C3 = T(2) * rho * ze * (g1 + g2);
+        C4 = T(2) * rho * nu * (g1 - g2);
+    }
+    n3 = D31 * d1U1 + D32 * d2U2 + D33 * d1r + D34 * d2r + C3;
+    n4 = D41 * d1U1 + D42 * d2U2 + D43 * d1r + D44 * d2r + C4;
+}
+
+// Effective force and equilibrium corrections on a general orthogonal grid
+// (theta12, theta21 != 0): the normal stresses with their curvature parts
+// tau^c (Sec. 2.2), the reduced force F~ (tau12 = 0), the local implicit
+// shear stress from the non-equilibrium raw moment k'11 relaxed at omega5
+// (App. A) and the full force F = F~ + 2 h theta tau12; the corrections
+// n3^eq(1), n4^eq(1) of Sec. 5 with their tau^c and theta12 / theta21 terms
+// (the App. B(ii) low-Mach set drops them, as on straight grids).  The
+// pressure is split into P0 and c_s^2 (rho - rho0) as in the straight form.
+template <class T>
+__device__ inline void force_and_corrections_gen(const NodeParams<T>& p, const NodeMetric<T>& g, T rho, T drho,
+                                                 T U1, T U2, T d1U1, T d2U2, T d1r, T d2r, T Fe1, T Fe2, T k11,
+                                                 T& F1, T& F2, T& n3, T& n4)
+{
+    const T nu = p.nu, ze = p.zeta, ics = p.inv_cs2;
+    const T h1 = g.h1, h2 = g.h2, ih1 = g.ih1, ih2 = g.ih2;
+    const T t11 = g.th11, t12 = g.th12, t21 = g.th21, t22 = g.th22;
+    const T dP = drho * p.cs2;
+    const T a1 = d1U1 * ih1, a2 = d2U2 * ih2;
+    const T tc11 = rho * ((ze + nu) * U2 * t12 + (ze - nu) * U1 * t21);
+    const T tc22 = rho * ((ze + nu) * U1 * t21 + (ze - nu) * U2 * t12);
+    const T tau11 = rho * ((ze + nu) * a1 + (ze - nu) * a2) + tc11;
+    const T tau22 = rho * ((ze + nu) * a2 + (ze - nu) * a1) + tc22;
+    const T uu = rho * U1 * U2;
+    const T Ft1 = h2 * (Fe1 + (t21 - t11) * dP + t11 * (tau11 - rho * U1 * U1) - T(2) * t12 * uu
+                        - t21 * (tau22 - rho * U2 * U2)) + h2 * (t21 - t11) * p.P0;
+    const T Ft2 = h1 * (Fe2 + (t12 - t22) * dP + t22 * (tau22 - rho * U2 * U2) - T(2) * t21 * uu
+                        - t12 * (tau11 - rho * U1 * U1)) + h1 * (t12 - t22) * p.P0;
+    const T a = T(1) - T(0.5) * p.w[5];
+    const T num = k11 + T(0.5) * (Ft1 * U2 * ih2 + Ft2 * U1 * ih1) - uu;
+    const T tau12 = -a * num / (T(1) + a * (t12 * U2 + t21 * U1));
+    F1 = Ft1 + T(2) * h2 * t12 * tau12;
+    F2 = Ft2 + T(2) * h1 * t21 * tau12;
+
+    const T r21 = h2 * ih1, r12 = h1 * ih2;
+    const T s1 = r21 * ih1, s2 = r12 * ih2;
+    const T u1s = U1 * U1 * ics, u2s = U2 * U2 * ics;
+    T D31, D32, D33, D34, C3, D41, D42, D43, D44, C4;
+    if (p.gi_terms) {
+        D31 = rho * (ze * h2 * ics - (ze - nu) * ih2 - (T(2) * ze + nu + T(3) * ze * u1s) * s1);
+        D32 = rho * (ze * h1 * ics - (ze - nu) * ih1 - (T(2) * ze + nu + T(3) * ze * u2s) * s2);
+        D41 = rho * (nu * h2 * ics + (ze - nu) * ih2 - (ze + T(2) * nu + T(3) * nu * u1s) * s1);
+        D42 = rho * (-nu * h1 * ics - (ze - nu) * ih1 + (ze + T(2) * nu + T(3) * nu * u2s) * s2);
+        T b1, b2, c1, c2;
+        if (p.rho_terms) {    // as printed
+            b1 = ((T(3) - u1s) * s1 - h2 * ics - u2s * ih2) * U1;
+            b2 = ((T(3) - u2s) * s2 - h1 * ics - u1s * ih1) * U2;
+            c1 = ((T(3) - u1s) * s1 - h2 * ics + u2s * ih2) * U1;
+            c2 = (-(T(3) - u2s) * s2 + h1 * ics - u1s * ih1) * U2;
+        } else {              // from the Chapman-Enskog deviation terms
+            b1 = ((T(3) + u1s) * s1 - h2 * ics) * U1;
+            b2 = ((T(3) + u2s) * s2 - h1 * ics) * U2;
+            c1 = b1;
+            c2 = -b2;
+        }
+        D33 = -ze * b1;
+        D34 = -ze * b2;
+        D43 = -nu * c1;
+        D44 = -nu * c2;
+        const T g1 = U1 * (u1s + T(1)) * r21 * t11;
+        const T g2 = U2 * (u2s + T(1)) * r12 * t22;
+        const T hh = h1 * h2 * ics;
+        const T q21 = U1 * (T(3) + u1s) * r21, q12 = U2 * (T(3) + u2s) * r12;
+        C3 = T(2) * rho * ze * (g1 + g2) - (r21 * tc11 + r12 * tc22)
+             - rho * ze * ((q21 + U1 * (T(2) * r12 - hh)) * t21 + (q12 + U2 * (T(2) * r21 - hh)) * t12);
+        C4 = T(2) * rho * nu * (g1 - g2) - (r21 * tc11 - r12 * tc22)
+             - rho * nu * ((q21 - U1 * (T(2) * r12 + hh)) * t21 + (-q12 + U2 * (T(2) * r21 + hh)) * t12);
+    } else {                  // App. B(ii)
+        D31 = rho * (ze * h2 * ics - (ze - nu) * ih2 - (T(2) * ze + nu) * s1);
+        D32 = rho * (ze * h1 * ics - (ze - nu) * ih1 - (T(2) * ze + nu) * s2);
+        D41 = rho * (nu * h2 * ics + (ze - nu) * ih2 - (T(2) * nu + ze) * s1);
+        D42 = rho * (-nu * h1 * ics - (ze - nu) * ih1 + (T(2) * nu + ze) * s2);
+        D33 = D34 = D43 = D44 = T(0);
+        const T g1 = U1 * r21 * t11, g2 = U2 * r12 * t22;
         C3 = T(2) * rho * ze * (g1 + g2);
         C4 = T(2) * rho * nu * (g1 - g2);
     }

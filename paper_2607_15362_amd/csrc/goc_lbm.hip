@@ -16,6 +16,7 @@
 
 #include "../../include/goc_lbm.h"
 #include "goc_aux.hpp"
+#include "goc_curv.hpp"
 
 using goc::RunDesc;
 
@@ -126,11 +127,143 @@ int metric_1d(int n, int kind, double param, const double* harr, const double* d
     return GOC_OK;
 }
 
+bool is_2d(const goc_metric& m) { return m.kind_x == GOC_STRETCH_ANNULUS || m.kind_x == GOC_STRETCH_ARRAY2D; }
+
+// A 2-D metric leaves the separable tables uniform (unused by its kernels).
 int build_metric(const goc_grid& g, const goc_metric& m, Metric1D& mx, Metric1D& my)
 {
+    if (is_2d(m)) {
+        int rc = metric_1d(g.nx, GOC_STRETCH_UNIFORM, 0.0, nullptr, nullptr, nullptr, false, mx);
+        return rc ? rc : metric_1d(g.ny, GOC_STRETCH_UNIFORM, 0.0, nullptr, nullptr, nullptr, false, my);
+    }
     int rc = metric_1d(g.nx, m.kind_x, m.param_x, m.h1, m.dh1, m.h1_face, g.bc_x == GOC_BC_PERIODIC, mx);
     if (rc) return rc;
     return metric_1d(g.ny, m.kind_y, m.param_y, m.h2, m.dh2, m.h2_face, g.bc_y == GOC_BC_PERIODIC, my);
+}
+
+// General 2-D metric at the nodes (FP64, row-major [ny][nx]): h1, h2 and
+// their derivatives, with the face values h1 on the xi1 = 0 / nx faces per
+// row and h2 on the xi2 = 0 / ny faces per column.
+struct Metric2D {
+    std::vector<double> h1, h2, d1h1, d2h1, d1h2, d2h2;
+    std::vector<double> h1_lo, h1_hi, h2_lo, h2_hi;
+    double qmin = 1.0;
+};
+
+int build_metric2d(const goc_grid& g, const goc_metric& m, Metric2D& out)
+{
+    const int nx = g.nx, ny = g.ny;
+    const size_t N = (size_t)nx * ny;
+    for (auto* v : {&out.h1, &out.h2, &out.d1h1, &out.d2h1, &out.d1h2, &out.d2h2}) v->assign(N, 0.0);
+    out.h1_lo.assign(ny, 0.0);
+    out.h1_hi.assign(ny, 0.0);
+    out.h2_lo.assign(nx, 0.0);
+    out.h2_hi.assign(nx, 0.0);
+    if (m.kind_x == GOC_STRETCH_ANNULUS) {
+        // Z = a exp(pi W / N_theta) on xi1 in [0, nx] (radii a .. Ro) and
+        // xi2 in [0, ny] (angle 2 pi / N_theta): r = a exp(k xi1), k =
+        // ln(Ro / a) / nx; h1 = dr/dxi1 = k r; h2 = r (2 pi / N_theta) / ny
+        const double a = m.param_x, Ro = m.param_y, nt = m.n_theta;
+        if (!(a > 0) || !(Ro > a) || !(nt > 0))
+            return fail(GOC_EINVAL, "annulus needs 0 < a < Ro and n_theta > 0 (got %g, %g, %g)", a, Ro, nt);
+        const double k = std::log(Ro / a) / nx, c2 = 2.0 * M_PI / (nt * ny);
+        for (int i = 0; i < nx; ++i) {
+            const double r = a * std::exp(k * (i + 0.5));
+            for (int j = 0; j < ny; ++j) {
+                const size_t n = (size_t)j * nx + i;
+                out.h1[n] = k * r;
+                out.h2[n] = c2 * r;
+                out.d1h1[n] = k * k * r;
+                out.d1h2[n] = k * c2 * r;
+            }
+            out.h2_lo[i] = out.h2_hi[i] = c2 * r;
+        }
+        for (int j = 0; j < ny; ++j) {
+            out.h1_lo[j] = k * a;
+            out.h1_hi[j] = k * Ro;
+        }
+    } else {
+        if (!m.h1_2d || !m.h2_2d) return fail(GOC_EINVAL, "2-D array metric needs h1_2d and h2_2d");
+        const int given = !!m.d1h1 + !!m.d2h1 + !!m.d1h2 + !!m.d2h2;
+        if (given != 0 && given != 4) return fail(GOC_EINVAL, "give all four metric derivative arrays or none");
+        for (size_t n = 0; n < N; ++n) {
+            if (!(m.h1_2d[n] > 0) || !(m.h2_2d[n] > 0) || !std::isfinite(m.h1_2d[n]) || !std::isfinite(m.h2_2d[n]))
+                return fail(GOC_EINVAL, "metric factors at node %zu must be positive", n);
+            out.h1[n] = m.h1_2d[n];
+            out.h2[n] = m.h2_2d[n];
+        }
+        if (given == 4) {
+            for (size_t n = 0; n < N; ++n) {
+                out.d1h1[n] = m.d1h1[n];
+                out.d2h1[n] = m.d2h1[n];
+                out.d1h2[n] = m.d1h2[n];
+                out.d2h2[n] = m.d2h2[n];
+            }
+        } else {
+            // second-order differences: central, wrapped along a periodic
+            // axis, one-sided at the ends of a walled one
+            auto dif = [&](const std::vector<double>& f, int i, int j, bool along_x) {
+                const int n = along_x ? nx : ny, k = along_x ? i : j;
+                auto v = [&](int t) { return along_x ? f[(size_t)j * nx + t] : f[(size_t)t * nx + i]; };
+                const bool per = along_x ? g.bc_x == GOC_BC_PERIODIC : g.bc_y == GOC_BC_PERIODIC;
+                if (per) return 0.5 * (v((k + 1) % n) - v((k + n - 1) % n));
+                if (k == 0) return 0.5 * (-3 * v(0) + 4 * v(1) - v(2));
+                if (k == n - 1) return 0.5 * (3 * v(n - 1) - 4 * v(n - 2) + v(n - 3));
+                return 0.5 * (v(k + 1) - v(k - 1));
+            };
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    const size_t n = (size_t)j * nx + i;
+                    out.d1h1[n] = dif(out.h1, i, j, true);
+                    out.d2h1[n] = dif(out.h1, i, j, false);
+                    out.d1h2[n] = dif(out.h2, i, j, true);
+                    out.d2h2[n] = dif(out.h2, i, j, false);
+                }
+        }
+        for (int j = 0; j < ny; ++j) {
+            out.h1_lo[j] = out.h1[(size_t)j * nx];
+            out.h1_hi[j] = out.h1[(size_t)j * nx + nx - 1];
+        }
+        for (int i = 0; i < nx; ++i) {
+            out.h2_lo[i] = out.h2[i];
+            out.h2_hi[i] = out.h2[(size_t)(ny - 1) * nx + i];
+        }
+    }
+    out.qmin = std::min(*std::min_element(out.h1.begin(), out.h1.end()),
+                        *std::min_element(out.h2.begin(), out.h2.end()));
+    return GOC_OK;
+}
+
+// Node planes of a 2-D run (goc::M_*), FP64, with P0 = rho0 c_s^2 for the
+// rest-state offsets of the axis slots.
+void metric2d_planes(const goc_grid& g, const Metric2D& m, double P0, double* out)
+{
+    const int nx = g.nx, ny = g.ny;
+    const size_t N = (size_t)nx * ny;
+    const bool px = g.bc_x == GOC_BC_PERIODIC, py = g.bc_y == GOC_BC_PERIODIC;
+    auto r21 = [&](int i, int j) { const size_t n = (size_t)j * nx + i; return m.h2[n] / m.h1[n]; };
+    auto r12 = [&](int i, int j) { const size_t n = (size_t)j * nx + i; return m.h1[n] / m.h2[n]; };
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const size_t n = (size_t)j * nx + i;
+            const double h1 = m.h1[n], h2 = m.h2[n];
+            out[goc::M_H1 * N + n] = h1;
+            out[goc::M_IH1 * N + n] = 1.0 / h1;
+            out[goc::M_H2 * N + n] = h2;
+            out[goc::M_IH2 * N + n] = 1.0 / h2;
+            out[goc::M_TH11 * N + n] = m.d1h1[n] / (h1 * h1);
+            out[goc::M_TH12 * N + n] = m.d2h1[n] / (h1 * h2);
+            out[goc::M_TH21 * N + n] = m.d1h2[n] / (h1 * h2);
+            out[goc::M_TH22 * N + n] = m.d2h2[n] / (h2 * h2);
+            const int ie = i + 1 < nx ? i + 1 : (px ? 0 : -1);
+            const int iw = i > 0 ? i - 1 : (px ? nx - 1 : -1);
+            const int jn = j + 1 < ny ? j + 1 : (py ? 0 : -1);
+            const int js = j > 0 ? j - 1 : (py ? ny - 1 : -1);
+            out[goc::M_AE * N + n] = ie < 0 ? 0.0 : 0.5 * P0 * (r21(i, j) - r21(ie, j));
+            out[goc::M_AW * N + n] = iw < 0 ? 0.0 : 0.5 * P0 * (r21(i, j) - r21(iw, j));
+            out[goc::M_AN * N + n] = jn < 0 ? 0.0 : 0.5 * P0 * (r12(i, j) - r12(i, jn));
+            out[goc::M_AS * N + n] = js < 0 ? 0.0 : 0.5 * P0 * (r12(i, j) - r12(i, js));
+        }
 }
 
 int check_grid(const goc_grid* g)
@@ -153,6 +286,12 @@ struct goc_lbm {
     int nruns = 0;
     bool any_mhd = false;
     int coll = goc::kCollCentral;   // collision body of the step kernel
+    bool m2d = false;               // runs on general 2-D metrics (curvilinear step)
+    std::vector<Metric2D> m2;
+    double* met_d = nullptr;        // 2-D metric planes, FP64 and FP32
+    float* metf_d = nullptr;
+    double* face_d = nullptr;       // 2-D metric face values
+    void* mac_d = nullptr;          // node moments between the two curvilinear launches
     std::vector<RunDesc> runs;
     std::vector<goc_params> params;
     std::vector<goc_grid> grids;
@@ -202,6 +341,9 @@ PoolsOf<S> pools(const goc_lbm* h, int in)
     p.row = h->row_d;
     p.colf = h->colf_d;
     p.rowf = h->rowf_d;
+    p.met = h->met_d;
+    p.metf = h->metf_d;
+    p.face = h->face_d;
     return p;
 }
 
@@ -224,6 +366,24 @@ int launch_step(goc_lbm* h, int k)
     return dispatch(h->storage, [&](auto tag) -> int {
         using S = decltype(tag);
         const auto pl = pools<S>(h, h->cur);
+        if (h->m2d) {   // curvilinear step: two launches per run
+            using T = typename goc::ComputeOf<S>::type;
+            T* mac = static_cast<T*>(h->mac_d);
+            for (int r = 0; r < h->nruns; ++r) {
+                const RunDesc& d = h->runs[r];
+                const dim3 cg((d.nx + goc::kCurvX - 1) / goc::kCurvX, (d.ny + goc::kCurvY - 1) / goc::kCurvY);
+                const dim3 cb(goc::kCurvX, goc::kCurvY);
+                hipLaunchKernelGGL((goc::curv_moments_kernel<S>), cg, cb, 0, h->stream, h->runs_d, r, pl, mac);
+                if (h->coll == goc::kCollRaw)
+                    hipLaunchKernelGGL((goc::curv_step_kernel<S, goc::kCollRaw>), cg, cb, 0, h->stream, h->runs_d,
+                                       r, pl, mac, h->step_ctr, k);
+                else
+                    hipLaunchKernelGGL((goc::curv_step_kernel<S, goc::kCollCentral>), cg, cb, 0, h->stream,
+                                       h->runs_d, r, pl, mac, h->step_ctr, k);
+            }
+            HIPOK(hipGetLastError());
+            return GOC_OK;
+        }
         const dim3 grid(h->total_blocks), block(goc::kWave);
         const bool raw = h->coll == goc::kCollRaw;
         if (h->any_mhd && raw)
@@ -279,6 +439,10 @@ int free_all(goc_lbm* h)
     (void)hipFree(h->diag_part);
     (void)hipFree(h->diag_out);
     (void)hipFree(h->step_ctr);
+    (void)hipFree(h->met_d);
+    (void)hipFree(h->metf_d);
+    (void)hipFree(h->face_d);
+    (void)hipFree(h->mac_d);
     return GOC_OK;
 }
 
@@ -384,6 +548,16 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
         if ((rc = build_metric(grid[r], metric[r], tx, ty)) != GOC_OK) return bail(rc);
         if (params[r].collision != params[0].collision)
             return bail(fail(GOC_EINVAL, "run %d: the runs of a batch share one collision model", r));
+        if (is_2d(metric[r]) != is_2d(metric[0]))
+            return bail(fail(GOC_EINVAL, "run %d: the runs of a batch share the metric kind (2-D or straight)", r));
+        if (is_2d(metric[r]) && params[r].mhd)
+            return bail(fail(GOC_EINVAL, "run %d: MHD runs need a straight metric", r));
+    }
+    h->m2d = is_2d(metric[0]);
+    if (h->m2d) {
+        h->m2.resize(nruns);
+        for (int r = 0; r < nruns; ++r)
+            if ((rc = build_metric2d(grid[r], metric[r], h->m2[r])) != GOC_OK) return bail(rc);
     }
     h->coll = params[0].collision == GOC_COLL_CENTRAL ? goc::kCollCentral : goc::kCollRaw;
     if (hipGetDevice(&h->device) != hipSuccess) return bail(fail(GOC_EDEVICE, "no HIP device"));
@@ -400,6 +574,7 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
     h->my.resize(nruns);
     h->q.resize(nruns);
     int64_t sum_nx = 0, sum_ny = 0, f_elems = 0, F_elems = 0, g_elems = 0;
+    int64_t met_elems = 0, face_elems = 0, max_nodes = 0;
     // one wave per work-group; aim for ~16 waves per CU over the whole batch
     std::vector<int32_t> block_run;
     for (int r = 0; r < nruns; ++r) {
@@ -438,6 +613,14 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
         }
         d.col_off = sum_nx;
         d.row_off = sum_ny;
+        d.metric2d = h->m2d ? 1 : 0;
+        d.met_off = met_elems;
+        d.face_off = face_elems;
+        if (h->m2d) {
+            met_elems += (int64_t)goc::kMet * g.nx * g.ny;
+            face_elems += 2 * (int64_t)(g.nx + g.ny);
+            max_nodes = std::max(max_nodes, (int64_t)g.nx * g.ny);
+        }
         sum_nx += g.nx;
         sum_ny += g.ny;
         d.gi_terms = p.gi_terms;
@@ -452,6 +635,10 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
         d.rho0 = p.rho0;
         d.uw_lo = g.bc_y ? g.u_wall_lo : 0.0;
         d.uw_hi = g.bc_y ? g.u_wall_hi : 0.0;
+        d.vw_lo = g.bc_x ? g.v_wall_lo : 0.0;
+        d.vw_hi = g.bc_x ? g.v_wall_hi : 0.0;
+        if (!std::isfinite(d.uw_lo) || !std::isfinite(d.uw_hi) || !std::isfinite(d.vw_lo) || !std::isfinite(d.vw_hi))
+            return bail(fail(GOC_EINVAL, "run %d: non-finite wall speed", r));
         d.hw_lo = h->my[r].face_lo;
         d.hw_hi = h->my[r].face_hi;
         d.h1w_lo = h->mx[r].face_lo;
@@ -517,7 +704,8 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
             cleanup_tmp();
             return bail(fail(GOC_EDEVICE, "metric precompute failed"));
         }
-        const double q = *std::min_element(bm.begin(), bm.end());
+        // (a 2-D metric: the minimum over its node arrays)
+        const double q = h->m2d ? h->m2[r].qmin : *std::min_element(bm.begin(), bm.end());
         h->q[r] = q;
         d.cs2 = q * q / 3.0;            // Sec. 3.2.1
         d.csm2 = d.cs2;                 // App. G: the same CFL-limited sound speed
@@ -547,6 +735,33 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
         }
     }
     cleanup_tmp();
+    if (h->m2d) {
+        // 2-D metric planes (FP64 on the host, with their FP32 copy), face
+        // values, and the node-moment buffer of the curvilinear step
+        std::vector<double> met(met_elems), face(face_elems);
+        for (int r = 0; r < nruns; ++r) {
+            const RunDesc& d = h->runs[r];
+            metric2d_planes(grid[r], h->m2[r], d.rho0 * d.cs2, met.data() + d.met_off);
+            double* fr = face.data() + d.face_off;
+            for (int j = 0; j < d.ny; ++j) {
+                fr[2 * j] = h->m2[r].h1_lo[j];
+                fr[2 * j + 1] = h->m2[r].h1_hi[j];
+            }
+            for (int i = 0; i < d.nx; ++i) {
+                fr[2 * d.ny + 2 * i] = h->m2[r].h2_lo[i];
+                fr[2 * d.ny + 2 * i + 1] = h->m2[r].h2_hi[i];
+            }
+        }
+        std::vector<float> metf(met.begin(), met.end());
+        const size_t tb = storage == GOC_F64 ? 8 : 4;
+        if ((rc = dev_alloc((void**)&h->met_d, met_elems * 8)) || (rc = dev_alloc((void**)&h->metf_d, met_elems * 4)) ||
+            (rc = dev_alloc((void**)&h->face_d, face_elems * 8)) || (rc = dev_alloc(&h->mac_d, 3 * max_nodes * tb)))
+            return bail(rc);
+        if (hipMemcpy(h->met_d, met.data(), met_elems * 8, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(h->metf_d, metf.data(), met_elems * 4, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(h->face_d, face.data(), face_elems * 8, hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(GOC_EDEVICE, "2-D metric upload failed"));
+    }
     {
         std::vector<double> th1(sum_nx), th2(sum_ny);
         if (hipMemcpy(th1.data(), h->th11_d, sum_nx * 8, hipMemcpyDeviceToHost) != hipSuccess ||
@@ -757,8 +972,12 @@ int goc_lbm_derive(goc_grid* grid, const goc_metric* metric, const goc_physics* 
     if (!metric || !phys || !out) return fail(GOC_EINVAL, "NULL metric, physics or output");
     Metric1D mx, my;
     if ((rc = build_metric(*grid, *metric, mx, my)) != GOC_OK) return rc;
-    const double q = std::min(*std::min_element(mx.h.begin(), mx.h.end()),
-                              *std::min_element(my.h.begin(), my.h.end()));
+    double q = std::min(*std::min_element(mx.h.begin(), mx.h.end()), *std::min_element(my.h.begin(), my.h.end()));
+    if (is_2d(*metric)) {
+        Metric2D m2;
+        if ((rc = build_metric2d(*grid, *metric, m2)) != GOC_OK) return rc;
+        q = m2.qmin;
+    }
     const double cs2 = q * q / 3.0;
     const double rho0 = phys->rho0 > 0 ? phys->rho0 : 1.0;
     goc_params p;
@@ -1001,6 +1220,21 @@ int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
     } ev;
     HIPOK(hipEventCreate(&ev.e[0]));
     HIPOK(hipEventCreate(&ev.e[1]));
+    if (h->m2d) {   // the curvilinear step has a fixed launch shape: time it only
+        int rc;
+        if ((rc = launch_step(h, 0))) return rc;
+        HIPOK(hipEventRecord(ev.e[0], h->stream));
+        for (int s = 0; s < trial_steps; ++s)
+            if ((rc = launch_step(h, s))) return rc;
+        HIPOK(hipEventRecord(ev.e[1], h->stream));
+        HIPOK(hipEventSynchronize(ev.e[1]));
+        float ms = 0.0f;
+        HIPOK(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
+        out[0] = h->waves_per_cu;
+        out[1] = out[2] = 1e3 * ms / trial_steps;
+        out[3] = 1;
+        return GOC_OK;
+    }
     const double prev = h->waves_per_cu;
     double best_us = 1e300, best_w = prev, prev_us = -1.0;
     // every trial launch reads the current buffers and writes the others,
@@ -1205,7 +1439,9 @@ int goc_lbm_derived_run(const goc_lbm_t* h, int32_t run, double out[16])
     out[10] = d.hw_lo;
     out[11] = d.hw_hi;
     out[12] = (double)h->step;
-    out[13] = 2.0 * (9.0 * sb + 2.0 * fb + (d.mhd ? 10.0 * sb : 0.0));
+    // algorithmic bytes per node update: populations and lagged force read
+    // and written, the D2Q5 slots for MHD, the metric planes of a 2-D run
+    out[13] = 2.0 * (9.0 * sb + 2.0 * fb + (d.mhd ? 10.0 * sb : 0.0)) + (d.metric2d ? goc::kMet * fb : 0.0);
     out[14] = d.nx;
     out[15] = d.ny;
     return GOC_OK;
@@ -1216,11 +1452,45 @@ int goc_lbm_derived(const goc_lbm_t* h, double out[16]) { return goc_lbm_derived
 int goc_lbm_metric(const goc_lbm_t* h, double* h1, double* th11, double* h2, double* th22)
 {
     if (!h) return fail(GOC_EINVAL, "handle is NULL");
+    if (h->m2d) return fail(GOC_EINVAL, "the run has a 2-D metric: use goc_lbm_metric_2d");
     const RunDesc& d = h->runs[0];
     if (h1) HIPOK(hipMemcpy(h1, h->h1_d + d.col_off, d.nx * 8, hipMemcpyDeviceToHost));
     if (th11) HIPOK(hipMemcpy(th11, h->th11_d + d.col_off, d.nx * 8, hipMemcpyDeviceToHost));
     if (h2) HIPOK(hipMemcpy(h2, h->h2_d + d.row_off, d.ny * 8, hipMemcpyDeviceToHost));
     if (th22) HIPOK(hipMemcpy(th22, h->th22_d + d.row_off, d.ny * 8, hipMemcpyDeviceToHost));
+    return GOC_OK;
+}
+
+int goc_lbm_metric_2d(const goc_lbm_t* h, int32_t run, double* h1, double* h2, double* th11, double* th12,
+                      double* th21, double* th22)
+{
+    if (!h) return fail(GOC_EINVAL, "handle is NULL");
+    if (run < 0 || run >= h->nruns) return fail(GOC_EINVAL, "run %d outside [0, %d)", run, h->nruns);
+    const RunDesc& d = h->runs[run];
+    const int64_t N = (int64_t)d.nx * d.ny;
+    double* outs[6] = {h1, h2, th11, th12, th21, th22};
+    if (h->m2d) {
+        const int planes[6] = {goc::M_H1, goc::M_H2, goc::M_TH11, goc::M_TH12, goc::M_TH21, goc::M_TH22};
+        for (int k = 0; k < 6; ++k)
+            if (outs[k])
+                HIPOK(hipMemcpy(outs[k], h->met_d + d.met_off + planes[k] * N, N * 8, hipMemcpyDeviceToHost));
+        return GOC_OK;
+    }
+    std::vector<double> c1(d.nx), t1(d.nx), c2(d.ny), t2(d.ny);
+    HIPOK(hipMemcpy(c1.data(), h->h1_d + d.col_off, d.nx * 8, hipMemcpyDeviceToHost));
+    HIPOK(hipMemcpy(t1.data(), h->th11_d + d.col_off, d.nx * 8, hipMemcpyDeviceToHost));
+    HIPOK(hipMemcpy(c2.data(), h->h2_d + d.row_off, d.ny * 8, hipMemcpyDeviceToHost));
+    HIPOK(hipMemcpy(t2.data(), h->th22_d + d.row_off, d.ny * 8, hipMemcpyDeviceToHost));
+    for (int j = 0; j < d.ny; ++j)
+        for (int i = 0; i < d.nx; ++i) {
+            const int64_t n = (int64_t)j * d.nx + i;
+            if (h1) h1[n] = c1[i];
+            if (h2) h2[n] = c2[j];
+            if (th11) th11[n] = t1[i];
+            if (th12) th12[n] = 0.0;
+            if (th21) th21[n] = 0.0;
+            if (th22) th22[n] = t2[j];
+        }
     return GOC_OK;
 }
 

@@ -733,6 +733,20 @@ __global__ void __launch_bounds__(kWave) step_kernel(const RunDesc* __restrict__
                 if (d.lid_corners || !xwall_lo) inc[7] += cw;
                 if (d.lid_corners || !xwall_hi) inc[8] -= cw;
             }
+            // the same for walls on the xi1 faces moving along xi2 (at a
+            // corner, with lid_corners, the terms of both walls add)
+            if (xwall_hi && d.vw_hi != 0.0) {
+                const T cx = rho * sp[P_CXHI];
+                // slot 5 is read back as f7, slot 8 as f6: f7 = ft5 - cx, f6 = ft8 + cx
+                if (d.lid_corners || !Gj.wp) inc[5] -= cx;
+                if (d.lid_corners || !Gj.wm) inc[8] += cx;
+            }
+            if (xwall_lo && d.vw_lo != 0.0) {
+                const T cx = rho * sp[P_CXLO];
+                // slot 7 is read back as f5, slot 6 as f8: f5 = ft7 + cx, f8 = ft6 - cx
+                if (d.lid_corners || !Gj.wm) inc[7] += cx;
+                if (d.lid_corners || !Gj.wp) inc[6] -= cx;
+            }
             const __amdgpu_buffer_rsrc_t rf = out_row(rb.fo, rb.pitch_s, rb.f_all, j + 1, act);
             S e[kQ];
 #pragma unroll
