@@ -552,6 +552,13 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
             return bail(fail(GOC_EINVAL, "run %d: the runs of a batch share the metric kind (2-D or straight)", r));
         if (is_2d(metric[r]) && params[r].mhd)
             return bail(fail(GOC_EINVAL, "run %d: MHD runs need a straight metric", r));
+        // the step kernel addresses a run's slot region (Q planes of padded
+        // rows, two ghost rows) with 32-bit byte offsets
+        const int64_t row = (grid[r].nx + 63) / 64 * 64;
+        const int64_t region = (params[r].mhd ? 10 : 9) * row * (grid[r].ny + 2) + 256;
+        if (region * (int64_t)storage_bytes(storage) > (int64_t)UINT32_MAX)
+            return bail(fail(GOC_EINVAL, "run %d: grid %d x %d too large for this storage "
+                             "(slot region of one run above 4 GiB)", r, grid[r].nx, grid[r].ny));
     }
     h->m2d = is_2d(metric[0]);
     if (h->m2d) {

@@ -114,3 +114,30 @@ def test_create_rejects_bad_collision_choice_before_touching_the_device(lib):
     assert lib.goc_lbm_create_batch(B.C.byref(h), 2, G, M, P, 1, None) == B.GOC_EINVAL
     assert "share one collision" in lib.goc_lbm_last_error().decode()
     assert not h.value
+
+
+@pytest.mark.parametrize("nx,ny,storage,mhd,ok", [
+    (8192, 8192, 1, 1, True),      # FP32 with the D2Q5 slots: 2.7 GB per slot region
+    (8192, 8192, 0, 1, False),     # FP64: 5.4 GB, above the 4 GiB of 32-bit offsets
+    (12288, 12288, 2, 0, True),    # 16-bit: 2.7 GB
+    (16384, 16384, 1, 0, False),   # FP32: 9.7 GB
+    (65536, 65536, 2, 0, False),   # beyond 2^31 nodes
+])
+def test_create_checks_size_limits_before_touching_the_device(lib, nx, ny, storage, mhd, ok):
+    """Sizes beyond the per-run limits are refused with GOC_EINVAL and a
+    message, before any device call; sizes within them pass validation (on a
+    host without a GPU they then fail at the device, with GOC_EDEVICE)."""
+    case = W.Case("big", nx, ny, "periodic", "wall", flow="free", tau=0.8, storage="f32", mhd=bool(mhd))
+    g, m, p = B.derive(case.replace(nx=64, ny=64))   # derive checks the grid too
+    g.nx, g.ny = nx, ny
+    p.mhd = mhd
+    p.tau_m = 1.0
+    h = B.VP()
+    rc = lib.goc_lbm_create(B.C.byref(h), g, m, p, storage, None)
+    if ok:
+        assert rc != B.GOC_EINVAL
+    else:
+        assert rc == B.GOC_EINVAL
+        assert "too large" in lib.goc_lbm_last_error().decode()
+    if h.value:
+        lib.goc_lbm_destroy(h)
