@@ -120,8 +120,10 @@ typedef struct {
    differences: central, wrapped along a periodic axis, one-sided at the
    ends of a walled one); their face values are the adjacent nodes'.  A run
    on a 2-D metric takes the curvilinear step (two launches per step, the
-   metric read per node); it cannot be MHD, and the runs of a batch share
-   the metric kind (2-D or straight). */
+   metric read per node); it cannot be MHD (the paper's GOC induction
+   equation diffuses each component of B as a scalar, which is the vector
+   Laplacian only on straight grids), and the runs of a batch share the
+   metric kind (2-D or straight). */
 typedef struct {
     int32_t kind_x, kind_y;   /* goc_stretch                                 */
     double param_x, param_y;  /* beta (tanh) or gamma (Roberts); annulus radii */
