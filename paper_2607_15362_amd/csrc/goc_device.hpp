@@ -8,10 +8,12 @@
 // selector swaps the collision body for the raw-moment MRT model of the
 // appendix that summarises it; the velocity-space SRT model of the
 // appendix on velocity-space collisions is that model with every rate equal
-// to 1/tau (f^eq = P^-1 m^eq and S = P^-1 sigma there, and P is linear).  The metric is
-// straight (h1(xi1), h2(xi2), theta12 = theta21 = 0; App. B(i)), which
-// removes every theta12 / theta21 term and makes the effective force equal
-// to its reduced form F~ (tau12 is not needed).
+// to 1/tau (f^eq = P^-1 m^eq and S = P^-1 sigma there, and P is linear).  The
+// march takes a straight metric (h1(xi1), h2(xi2), theta12 = theta21 = 0;
+// App. B(i)), which removes every theta12 / theta21 term and makes the
+// effective force equal to its reduced form F~ (tau12 is not needed); general
+// 2-D metrics take the curvilinear step of goc_curv.hpp, which keeps those
+// terms (force_and_corrections_gen below).
 //
 // State layout in HBM (one plane per direction, rows interleaved): the
 // element of plane a at node (i, j) is at a * plane + j * pitch + i, with

@@ -475,7 +475,7 @@ int choose_rows(int ny, int strips, int target_waves)
     return rows;
 }
 
-// Launch plan: each run gets work-groups (62-column strips x row segments)
+// Launch plan: each run gets work-groups (64-column strips x row segments)
 // in proportion to its nodes, about waves_per_cu per CU over the launch;
 // fills segs / first_block of the runs and the work-group -> run list.
 void plan_rows(goc_lbm* h, std::vector<int32_t>& block_run)

@@ -73,36 +73,6 @@ __device__ inline int row_wrap(const RunDesc& d, int r)
     return d.bc_y != 0 ? r : w;
 }
 
-// Element offset (within a run's pool region) of the slot pulled by
-// direction a into node (L.col, G.r): slot(a, x - e_a) in the interior,
-// slot(opp(a), x) through a wall.
-__device__ inline int64_t pull_index(const RunDesc& d, const LaneCol& L, const RowGeo& G, int a)
-{
-    const int ex = ex_(a), ey = ey_(a);
-    const bool wx = (ex > 0 && L.wm) || (ex < 0 && L.wp);
-    const bool wy = (ey > 0 && G.wm) || (ey < 0 && G.wp);
-    int sx = ex > 0 ? L.cm : (ex < 0 ? L.cp : L.col);
-    int sy = ey > 0 ? G.rm : (ey < 0 ? G.rp : G.r);
-    int pa = a;
-    if (wx || wy) {
-        sx = L.col;
-        sy = G.r;
-        pa = opp_(a);
-    }
-    return (int64_t)pa * d.plane + (int64_t)sy * d.pitch + sx;
-}
-
-// Pull the nine deviations of node (col, r).
-template <class S, class T>
-__device__ inline void pull9(const RunDesc& d, const S* __restrict__ fin, const LaneCol& L, const RowGeo& G,
-                             const T* sinv, T* f)
-{
-    const S* base = fin + d.f_off;
-#pragma unroll
-    for (int a = 0; a < kQ; ++a)
-        f[a] = L.valid ? T(Store<S>::ld(base, pull_index(d, L, G, a), sinv[cls_(a)])) : T(0);
-}
-
 // Moments of a pulled row: the density deviation dr = rho - rho0 =
 // dm00/(h1 h2) (kept as a deviation, so FP32 does not round it against
 // rho0), U1 = (dm10 + F1/2)/(rho h2), U2 = (dm01 + F2/2)/(rho h1) with the
