@@ -218,3 +218,39 @@ def test_taylor_couette_paper_sector_against_closed_form(u_in, u_out):
     assert err < 3e-3
     assert np.max(np.abs(fl["U1"])) < 1e-3 * U0
     assert np.max(np.abs(fl["U2"] - fl["U2"][:1])) < 1e-12 * U0   # azimuthally uniform
+
+
+def test_curvilinear_batch_fp64(oracle_lib):
+    """A batch of curvilinear runs (two annular sectors of different sizes and
+    a conformal grid, walls and periodic axes mixed) in one handle: each run
+    equals its own oracle run within 1e-12 after 150 steps."""
+    runs = [W.taylor_couette(n1=70, n2=6, R1=8.0, n_theta=20.0),
+            W.taylor_couette(n1=33, n2=5, R1=4.0, n_theta=9.0, U_in=0.004, U_out=-0.002),
+            _wavy(40, 21)]
+    g = B.Run(batch=runs)
+    g.step(150)
+    for r, case in enumerate(runs):
+        mt = W.wavy_metric(case.nx, case.ny, 0.3) if case.grid2d[0] == "wavy" else None
+        o = oracle_lib.Model(case, metric2d=mt).init()
+        o.step(150)
+        gf, of = g.fields(run=r), o.fields()
+        e = _tc_errors(gf, of) if case.grid2d[0] == "annulus" else G.field_errors(gf, of, o, "f64")
+        print(f"[curv batch] run {r} {case.nx}x{case.ny}", {k: f"{v:.1e}" for k, v in e.items()}, flush=True)
+        for k, v in e.items():
+            assert v < 1e-12, (r, k, e)
+
+
+def test_curvilinear_checkpoint_resume_is_bitwise():
+    case = _wavy(70, 45, storage="f32")
+    a = B.Run(case)
+    a.init(*W.smooth_fields(70, 45, seed=5, amp=0.01))
+    a.step(23)
+    blob = a.get_state()
+    a.step(120)
+    fa, Fa, _ = a.populations()
+    b = B.Run(case)
+    b.set_state(blob)
+    b.step(120)
+    fb, Fb, _ = b.populations()
+    assert np.array_equal(fa, fb) and np.array_equal(Fa, Fb)
+    assert b.derived()["step"] == 143
