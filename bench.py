@@ -22,8 +22,8 @@ Prints ONE JSON line:
   collisions                 the main workload with the raw-moment MRT and the
                              SRT collision bodies instead of the central-moment
                              one (same data path, same launch)
-  curvilinear                the curvilinear step (general 2-D metric, two
-                             launches per step) on a 2048x512 conformal annular
+  curvilinear                the curvilinear step (general 2-D metric, one
+                             launch per step) on a 2048x512 conformal annular
                              sector, FP32, with its algorithmic bytes
 """
 from __future__ import annotations
@@ -222,8 +222,8 @@ def curvilinear_form(steps: int):
     geometry: 2048 radial x 512 azimuthal nodes, R1 = 256, R2 = R1 + 2048, the
     sector angle chosen for cells of aspect ratio about one), FP32: MLUPS and
     the achieved bandwidth in algorithmic bytes (populations and force read
-    and written, the 12 metric planes read), with the launch time of the two
-    kernels together from HIP events."""
+    and written, the 12 metric planes read), with the launch time of the
+    kernel from HIP events."""
     import math
     from paper_2607_15362_amd import binding as B
     from paper_2607_15362_amd import workloads as W

@@ -119,8 +119,8 @@ typedef struct {
    derivative arrays d1h1, d2h1, d1h2, d2h2 [ny*nx] or none (second-order
    differences: central, wrapped along a periodic axis, one-sided at the
    ends of a walled one); their face values are the adjacent nodes'.  A run
-   on a 2-D metric takes the curvilinear step (two launches per step, the
-   metric read per node); it cannot be MHD (the paper's GOC induction
+   on a 2-D metric takes the curvilinear step (one launch per run and step,
+   the metric read per node); it cannot be MHD (the paper's GOC induction
    equation diffuses each component of B as a scalar, which is the vector
    Laplacian only on straight grids), and the runs of a batch share the
    metric kind (2-D or straight). */

@@ -5,26 +5,23 @@
 // the conformal annular sector) keeps the slot layout, the deviation
 // storage and the writer-side boundary conditions of the straight path, with
 // the metric read per node from a pool of planes (goc_device.hpp: M_*).  A
-// step is two launches of one thread per node:
-//   1. curv_moments_kernel: pull, decode and the moments rho - rho0, U1, U2
-//      of every node (App. E step 7, lagged force) into a node buffer;
-//   2. curv_step_kernel: pull and decode again, the second-order differences
-//      of U and rho from the buffer (one-sided next to walls, wrapped when
-//      periodic), the general stresses and effective force with the local
-//      shear stress (Sec. 2.2, App. A), the corrections of Sec. 5 with their
-//      curvature terms, the collision, and the writes of the nine slots,
-//      their ghost-row copies and the force.
-// The node buffer costs 12 (FP32) or 24 (FP64) bytes per node written and
-// read once more than a fused march would; in exchange the step needs no
-// halo bookkeeping for the differences.  The D2Q5 induction scheme is not
-// part of this path (the library refuses MHD runs on 2-D metrics).
+// step is one launch of one thread per node over 64 x 8 tiles: pull, decode
+// and the moments rho - rho0, U1, U2 (App. E step 7, lagged force) of the
+// tile and of the ring of nodes around it into LDS; the second-order
+// differences of U and rho from LDS (one-sided next to walls, wrapped when
+// periodic); the general stresses and effective force with the local shear
+// stress (Sec. 2.2, App. A), the corrections of Sec. 5 with their curvature
+// terms, the collision, and the writes of the nine slots, their ghost-row
+// copies and the force.  The ring is pulled twice (by this tile and by its
+// owner), which costs L2 reads, not HBM traffic.  The D2Q5 induction scheme
+// is not part of this path (the library refuses MHD runs on 2-D metrics).
 #pragma once
 
 #include "goc_step.hpp"
 
 namespace goc {
 
-constexpr int kCurvX = 64, kCurvY = 4;   // work-group tile: 64 columns x 4 rows
+constexpr int kCurvX = 64, kCurvY = 8;   // work-group tile: 64 columns x 8 rows
 
 // Metric of node n of a 2-D run in the compute type.
 template <class T, class S, class FT>
@@ -94,72 +91,94 @@ __device__ inline void curv_moments(const T* f, T Fp1, T Fp2, T rho0, T ih1, T i
     U2 = (m01 + T(0.5) * Fp2) * ih1 * irho;
 }
 
-// Launch: grid (ceil(nx/64), ceil(ny/4)), block (64, 4), one run.
-// mac: 3 planes of nx * ny values (rho - rho0, U1, U2).
-template <class S>
-__global__ void __launch_bounds__(kCurvX * kCurvY)
-curv_moments_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename ForceOf<S>::type> pl,
-                    typename ComputeOf<S>::type* __restrict__ mac)
-{
-    using T = typename ComputeOf<S>::type;
-    using FT = typename ForceOf<S>::type;
-    const RunDesc& d = runs[run];
-    const int i = blockIdx.x * kCurvX + threadIdx.x;
-    const int j = blockIdx.y * kCurvY + threadIdx.y;
-    if (i >= d.nx || j >= d.ny) return;
-    const int64_t N = (int64_t)d.nx * d.ny, n = (int64_t)j * d.nx + i;
-    T aE, aW, aN, aS;
-    const NodeMetric<T> g = curv_metric<T>(d, pl, n, N, aE, aW, aN, aS);
-    T f[kQ], Fp1, Fp2, dr, U1, U2;
-    curv_pull9<S, T, FT>(d, pl, i, j, f, Fp1, Fp2);
-    curv_moments<T>(f, Fp1, Fp2, T(step_params<T>(d)[P_RHO0]), g.ih1, g.ih2, dr, U1, U2);
-    mac[n] = dr;
-    mac[N + n] = U1;
-    mac[2 * N + n] = U2;
-}
-
-// Second-order difference along one axis of a node field: central inside,
-// wrapped when periodic, one-sided (-3 p0 + 4 p1 - p2)/2 next to a wall.
-// v(k) reads the field at index k of the axis; n >= 3.
+// Second-order difference along one axis of a node field held in a tile:
+// central inside and across a periodic edge (the halo holds the wrapped
+// neighbours), one-sided (-3 p0 + 4 p1 - p2)/2 next to a wall.  v(l) reads
+// the tile at local index l; k is the node's index on the axis, n its length.
 template <class T, class V>
-__device__ inline T curv_fd(V v, int k, int n, bool periodic)
+__device__ inline T tile_fd(V v, int l, int k, int n, bool periodic)
 {
-    if (periodic) return T(0.5) * (v(k == n - 1 ? 0 : k + 1) - v(k == 0 ? n - 1 : k - 1));
-    if (k == 0) return T(0.5) * (T(-3) * v(0) + T(4) * v(1) - v(2));
-    if (k == n - 1) return T(0.5) * (T(3) * v(n - 1) - T(4) * v(n - 2) + v(n - 3));
-    return T(0.5) * (v(k + 1) - v(k - 1));
+    if (!periodic && k == 0) return T(0.5) * (T(-3) * v(l) + T(4) * v(l + 1) - v(l + 2));
+    if (!periodic && k == n - 1) return T(0.5) * (T(3) * v(l) - T(4) * v(l - 1) + v(l - 2));
+    return T(0.5) * (v(l + 1) - v(l - 1));
 }
 
-// The step of every node of one run (after curv_moments_kernel).
+// The step of every node of one run.  Launch: grid (ceil(nx/64),
+// ceil(ny/8)), block (64, 8).  A work-group owns the 64 x 8 nodes at
+// (64 bx, 8 by); its tile is shifted back at the far edges of the grid so
+// that the three nodes of a one-sided difference lie in it (nodes of the
+// shifted part belong to the neighbouring work-group and are not written
+// here).  The moments of the tile and of the ring around it go to LDS.
 template <class S, int COLL>
 __global__ void __launch_bounds__(kCurvX * kCurvY)
 curv_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename ForceOf<S>::type> pl,
-                 const typename ComputeOf<S>::type* __restrict__ mac, const uint32_t* __restrict__ step_ctr,
-                 int k)
+                 const uint32_t* __restrict__ step_ctr, int k)
 {
     using T = typename ComputeOf<S>::type;
     using FT = typename ForceOf<S>::type;
+    __shared__ T sm[3][kCurvY + 2][kCurvX + 2];   // rho - rho0, U1, U2 of the tile and its ring
     const RunDesc& d = runs[run];
-    const int i = blockIdx.x * kCurvX + threadIdx.x;
-    const int j = blockIdx.y * kCurvY + threadIdx.y;
-    if (i >= d.nx || j >= d.ny) return;
     const int nx = d.nx, ny = d.ny;
+    const int tx = nx < kCurvX ? nx : kCurvX, ty = ny < kCurvY ? ny : kCurvY;   // tile extent
+    const int ox = blockIdx.x * kCurvX, oy = blockIdx.y * kCurvY;              // first owned node
+    const int x0 = ox < nx - tx ? ox : nx - tx, y0 = oy < ny - ty ? oy : ny - ty;   // tile origin
+    const int lx = threadIdx.x, ly = threadIdx.y;
+    const int i = x0 + lx, j = y0 + ly;
+    const bool in = lx < tx && ly < ty;
+    const bool px = d.bc_x == 0, py = d.bc_y == 0;
     const int64_t N = (int64_t)nx * ny, n = (int64_t)j * nx + i;
     const NodeParams<T> p = node_params<T>(d);
     const T* sp = step_params<T>(d);
-    T aE, aW, aN, aS;
-    const NodeMetric<T> g = curv_metric<T>(d, pl, n, N, aE, aW, aN, aS);
-    T f[kQ], Fp1, Fp2;
-    curv_pull9<S, T, FT>(d, pl, i, j, f, Fp1, Fp2);
-    const T dr = mac[n], U1 = mac[N + n], U2 = mac[2 * N + n];
+    NodeMetric<T> g{};
+    T aE = 0, aW = 0, aN = 0, aS = 0, f[kQ] = {}, Fp1 = 0, Fp2 = 0, dr = 0, U1 = 0, U2 = 0;
+    if (in) {
+        g = curv_metric<T>(d, pl, n, N, aE, aW, aN, aS);
+        curv_pull9<S, T, FT>(d, pl, i, j, f, Fp1, Fp2);
+        curv_moments<T>(f, Fp1, Fp2, p.rho0, g.ih1, g.ih2, dr, U1, U2);
+        sm[0][ly + 1][lx + 1] = dr;
+        sm[1][ly + 1][lx + 1] = U1;
+        sm[2][ly + 1][lx + 1] = U2;
+    }
+    // the ring: rows -1 and ty over the tile's columns, columns -1 and tx over
+    // its rows (the differences never reach the corners); wrapped across a
+    // periodic edge, absent beyond a wall
+    const T* mt = table_of<T>(pl.met, pl.metf) + d.met_off;
+    const int nh = 2 * tx + 2 * ty;
+    for (int h = ly * kCurvX + lx; h < nh; h += kCurvX * kCurvY) {
+        int hx, hy;
+        if (h < 2 * tx) {
+            hx = h < tx ? h : h - tx;
+            hy = h < tx ? -1 : ty;
+        } else {
+            hx = h < 2 * tx + ty ? -1 : tx;
+            hy = h < 2 * tx + ty ? h - 2 * tx : h - 2 * tx - ty;
+        }
+        int hi = x0 + hx, hj = y0 + hy;
+        if (hi < 0 || hi >= nx) {
+            if (!px) continue;
+            hi = hi < 0 ? hi + nx : hi - nx;
+        }
+        if (hj < 0 || hj >= ny) {
+            if (!py) continue;
+            hj = hj < 0 ? hj + ny : hj - ny;
+        }
+        const int64_t hn = (int64_t)hj * nx + hi;
+        T hf[kQ], hF1, hF2, hdr, hU1, hU2;
+        curv_pull9<S, T, FT>(d, pl, hi, hj, hf, hF1, hF2);
+        curv_moments<T>(hf, hF1, hF2, p.rho0, mt[M_IH1 * N + hn], mt[M_IH2 * N + hn], hdr, hU1, hU2);
+        sm[0][hy + 1][hx + 1] = hdr;
+        sm[1][hy + 1][hx + 1] = hU1;
+        sm[2][hy + 1][hx + 1] = hU2;
+    }
+    __syncthreads();
+    if (!in || i < ox || j < oy) return;
+
     const T rho = p.rho0 + dr;
-    const bool px = d.bc_x == 0, py = d.bc_y == 0;
-    const T* rowp = mac + (int64_t)j * nx;   // this row of each plane
-    const T* colp = mac + i;                 // this column of each plane
-    const T d1U1 = curv_fd<T>([&](int c) { return rowp[N + c]; }, i, nx, px);
-    const T d1r = curv_fd<T>([&](int c) { return rowp[c]; }, i, nx, px);
-    const T d2U2 = curv_fd<T>([&](int r) { return colp[2 * N + (int64_t)r * nx]; }, j, ny, py);
-    const T d2r = curv_fd<T>([&](int r) { return colp[(int64_t)r * nx]; }, j, ny, py);
+    const int cx = lx + 1, cy = ly + 1;
+    const T d1U1 = tile_fd<T>([&](int c) { return sm[1][cy][c]; }, cx, i, nx, px);
+    const T d1r = tile_fd<T>([&](int c) { return sm[0][cy][c]; }, cx, i, nx, px);
+    const T d2U2 = tile_fd<T>([&](int r) { return sm[2][r][cx]; }, cy, j, ny, py);
+    const T d2r = tile_fd<T>([&](int r) { return sm[0][r][cx]; }, cy, j, ny, py);
 
     const RawDev<T> m = raw_dev<T>(f);
     T F1, F2, n3, n4, inc[kQ];

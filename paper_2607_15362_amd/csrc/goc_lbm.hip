@@ -291,7 +291,6 @@ struct goc_lbm {
     double* met_d = nullptr;        // 2-D metric planes, FP64 and FP32
     float* metf_d = nullptr;
     double* face_d = nullptr;       // 2-D metric face values
-    void* mac_d = nullptr;          // node moments between the two curvilinear launches
     std::vector<RunDesc> runs;
     std::vector<goc_params> params;
     std::vector<goc_grid> grids;
@@ -366,20 +365,17 @@ int launch_step(goc_lbm* h, int k)
     return dispatch(h->storage, [&](auto tag) -> int {
         using S = decltype(tag);
         const auto pl = pools<S>(h, h->cur);
-        if (h->m2d) {   // curvilinear step: two launches per run
-            using T = typename goc::ComputeOf<S>::type;
-            T* mac = static_cast<T*>(h->mac_d);
+        if (h->m2d) {   // curvilinear step: one launch per run
             for (int r = 0; r < h->nruns; ++r) {
                 const RunDesc& d = h->runs[r];
                 const dim3 cg((d.nx + goc::kCurvX - 1) / goc::kCurvX, (d.ny + goc::kCurvY - 1) / goc::kCurvY);
                 const dim3 cb(goc::kCurvX, goc::kCurvY);
-                hipLaunchKernelGGL((goc::curv_moments_kernel<S>), cg, cb, 0, h->stream, h->runs_d, r, pl, mac);
                 if (h->coll == goc::kCollRaw)
                     hipLaunchKernelGGL((goc::curv_step_kernel<S, goc::kCollRaw>), cg, cb, 0, h->stream, h->runs_d,
-                                       r, pl, mac, h->step_ctr, k);
+                                       r, pl, h->step_ctr, k);
                 else
                     hipLaunchKernelGGL((goc::curv_step_kernel<S, goc::kCollCentral>), cg, cb, 0, h->stream,
-                                       h->runs_d, r, pl, mac, h->step_ctr, k);
+                                       h->runs_d, r, pl, h->step_ctr, k);
             }
             HIPOK(hipGetLastError());
             return GOC_OK;
@@ -442,7 +438,6 @@ int free_all(goc_lbm* h)
     (void)hipFree(h->met_d);
     (void)hipFree(h->metf_d);
     (void)hipFree(h->face_d);
-    (void)hipFree(h->mac_d);
     return GOC_OK;
 }
 
@@ -581,7 +576,7 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
     h->my.resize(nruns);
     h->q.resize(nruns);
     int64_t sum_nx = 0, sum_ny = 0, f_elems = 0, F_elems = 0, g_elems = 0;
-    int64_t met_elems = 0, face_elems = 0, max_nodes = 0;
+    int64_t met_elems = 0, face_elems = 0;
     // one wave per work-group; aim for ~16 waves per CU over the whole batch
     std::vector<int32_t> block_run;
     for (int r = 0; r < nruns; ++r) {
@@ -626,7 +621,6 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
         if (h->m2d) {
             met_elems += (int64_t)goc::kMet * g.nx * g.ny;
             face_elems += 2 * (int64_t)(g.nx + g.ny);
-            max_nodes = std::max(max_nodes, (int64_t)g.nx * g.ny);
         }
         sum_nx += g.nx;
         sum_ny += g.ny;
@@ -760,9 +754,8 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
             }
         }
         std::vector<float> metf(met.begin(), met.end());
-        const size_t tb = storage == GOC_F64 ? 8 : 4;
         if ((rc = dev_alloc((void**)&h->met_d, met_elems * 8)) || (rc = dev_alloc((void**)&h->metf_d, met_elems * 4)) ||
-            (rc = dev_alloc((void**)&h->face_d, face_elems * 8)) || (rc = dev_alloc(&h->mac_d, 3 * max_nodes * tb)))
+            (rc = dev_alloc((void**)&h->face_d, face_elems * 8)))
             return bail(rc);
         if (hipMemcpy(h->met_d, met.data(), met_elems * 8, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(h->metf_d, metf.data(), met_elems * 4, hipMemcpyHostToDevice) != hipSuccess ||
