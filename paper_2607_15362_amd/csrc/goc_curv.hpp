@@ -23,58 +23,77 @@ namespace goc {
 
 constexpr int kCurvX = 64, kCurvY = 8;   // work-group tile: 64 columns x 8 rows
 
-// Metric of node n of a 2-D run in the compute type.
+// A value at a lane's 32-bit byte offset from a work-group-uniform base:
+// the hardware forms such an address from a scalar base and a vector
+// offset, with no 64-bit arithmetic per lane.  Every offset of a run lies
+// below 4 GiB (the library refuses larger runs at creation).
+template <class V>
+__device__ inline V ld_at(const void* base, uint32_t off)
+{
+    return *reinterpret_cast<const V*>(static_cast<const char*>(base) + off);
+}
+template <class V>
+__device__ inline void st_at(void* base, uint32_t off, V v)
+{
+    *reinterpret_cast<V*>(static_cast<char*>(base) + off) = v;
+}
+
+// Metric of a node of a 2-D run in the compute type: nb = its node index
+// times sizeof(T), NB = one plane of the run in bytes.
 template <class T, class S, class FT>
-__device__ inline NodeMetric<T> curv_metric(const RunDesc& d, const Pools<S, FT>& pl, int64_t n, int64_t N,
+__device__ inline NodeMetric<T> curv_metric(const RunDesc& d, const Pools<S, FT>& pl, uint32_t nb, int64_t NB,
                                             T& aE, T& aW, T& aN, T& aS)
 {
-    const T* m = table_of<T>(pl.met, pl.metf) + d.met_off + n;
+    const char* m = reinterpret_cast<const char*>(table_of<T>(pl.met, pl.metf) + d.met_off);
     NodeMetric<T> g;
-    g.h1 = m[M_H1 * N];
-    g.ih1 = m[M_IH1 * N];
-    g.h2 = m[M_H2 * N];
-    g.ih2 = m[M_IH2 * N];
-    g.th11 = m[M_TH11 * N];
-    g.th12 = m[M_TH12 * N];
-    g.th21 = m[M_TH21 * N];
-    g.th22 = m[M_TH22 * N];
-    aE = m[M_AE * N];
-    aW = m[M_AW * N];
-    aN = m[M_AN * N];
-    aS = m[M_AS * N];
+    g.h1 = ld_at<T>(m + M_H1 * NB, nb);
+    g.ih1 = ld_at<T>(m + M_IH1 * NB, nb);
+    g.h2 = ld_at<T>(m + M_H2 * NB, nb);
+    g.ih2 = ld_at<T>(m + M_IH2 * NB, nb);
+    g.th11 = ld_at<T>(m + M_TH11 * NB, nb);
+    g.th12 = ld_at<T>(m + M_TH12 * NB, nb);
+    g.th21 = ld_at<T>(m + M_TH21 * NB, nb);
+    g.th22 = ld_at<T>(m + M_TH22 * NB, nb);
+    aE = ld_at<T>(m + M_AE * NB, nb);
+    aW = ld_at<T>(m + M_AW * NB, nb);
+    aN = ld_at<T>(m + M_AN * NB, nb);
+    aS = ld_at<T>(m + M_AS * NB, nb);
     return g;
 }
 
-// Element offset, from row 0 of a slot region, of the slot node (i, j)
-// pulls for direction a: through an xi1-wall its own slot of the opposite
-// direction; otherwise slot a of the source node x - e_a, wrapped across a
-// periodic xi1, in rows -1 .. ny (the ghost rows hold what lies beyond the
-// domain in xi2).  The same gather as the straight march.
-__device__ inline int64_t curv_pull(const RunDesc& d, int i, int j, int a)
-{
-    const int ex = ex_(a), ey = ey_(a);
-    int si = i - ex;
-    if (si < 0 || si >= d.nx) {
-        if (d.bc_x != 0) return (int64_t)opp_(a) * d.plane + (int64_t)j * d.pitch + i;
-        si = si < 0 ? si + d.nx : si - d.nx;
-    }
-    return (int64_t)a * d.plane + (int64_t)(j - ey) * d.pitch + si;
-}
-
-// Pull and decode the nine deviations of node (i, j) and its lagged force.
+// Pull and decode the nine deviations of node (i, j) and its lagged force
+// (planeF: one force plane in bytes).  Slot a is pulled, as in the straight
+// march, from the source node x - e_a, wrapped across a periodic xi1, in
+// rows -1 .. ny (the ghost rows hold what lies beyond the domain in xi2);
+// through an xi1-wall it is the node's own slot of the opposite direction.
+// Byte offsets from the base of the slot region (ghost row -1): the node's
+// own offset plus a work-group-uniform constant per direction, selected
+// per lane at the xi1 edges.
 template <class S, class T, class FT>
-__device__ inline void curv_pull9(const RunDesc& d, const Pools<S, FT>& pl, int i, int j, T* f, T& Fp1, T& Fp2)
+__device__ inline void curv_pull9(const RunDesc& d, const RunBytes& b, uint32_t planeF, int i, int j, T* f,
+                                  T& Fp1, T& Fp2)
 {
     const T* sp = step_params<T>(d);
-    const S* base = pl.fin + d.f_off;
+    const uint32_t cs = uint32_t(sizeof(S));
+    const uint32_t o = uint32_t(j + 1) * b.pitch_s + uint32_t(i) * cs;   // own node, plane 0
+    const bool wall = d.bc_x != 0;
+    const uint32_t span = uint32_t(d.nx) * cs;
 #pragma unroll
     for (int a = 0; a < kQ; ++a) {
+        const int ex = ex_(a), ey = ey_(a);
+        uint32_t off = o + uint32_t(a) * b.plane_s - uint32_t(ey) * b.pitch_s - uint32_t(ex) * cs;
+        if (ex != 0) {
+            const bool out = ex > 0 ? i == 0 : i == d.nx - 1;
+            const uint32_t wrapped = ex > 0 ? off + span : off - span;
+            const uint32_t bounced = o + uint32_t(opp_(a)) * b.plane_s;
+            off = out ? (wall ? bounced : wrapped) : off;
+        }
         const T sinv = Store<S>::scaled ? sp[P_ISC + cls_(a)] : T(1);
-        f[a] = T(Store<S>::ld(base, curv_pull(d, i, j, a), sinv));
+        f[a] = T(Store<S>::dec(ld_at<S>(b.f, off), sinv));
     }
-    const int64_t nf = d.F_off + (int64_t)j * d.pitchF + i;
-    Fp1 = T(pl.Fin[nf]);
-    Fp2 = T(pl.Fin[nf + d.plane]);
+    const uint32_t nf = uint32_t(j) * b.pitch_F + uint32_t(i) * uint32_t(sizeof(FT));
+    Fp1 = T(ld_at<FT>(b.F, nf));
+    Fp2 = T(ld_at<FT>(b.F, nf + planeF));
 }
 
 // Moments of a pulled node, as the straight march forms them: dr = rho -
@@ -103,12 +122,16 @@ __device__ inline T tile_fd(V v, int l, int k, int n, bool periodic)
     return T(0.5) * (v(l + 1) - v(l - 1));
 }
 
-// The step of every node of one run.  Launch: grid (ceil(nx/64),
-// ceil(ny/8)), block (64, 8).  A work-group owns the 64 x 8 nodes at
-// (64 bx, 8 by); its tile is shifted back at the far edges of the grid so
-// that the three nodes of a one-sided difference lie in it (nodes of the
-// shifted part belong to the neighbouring work-group and are not written
-// here).  The moments of the tile and of the ring around it go to LDS.
+// The step of every node of one run.  Launch: grid ceil(nx/64) *
+// ceil(ny/8) work-groups (1-D), block (64, 8).  A work-group owns the 64 x 8
+// nodes of tile (bx, by) at (64 bx, 8 by); its tile is shifted back at the
+// far edges of the grid so that the three nodes of a one-sided difference
+// lie in it (nodes of the shifted part belong to the neighbouring
+// work-group and are not written here).  The moments of the tile and of the
+// ring around it go to LDS.  The hardware deals consecutive work-groups to
+// the eight XCDs in turn; the tiles are renumbered so that each XCD gets a
+// contiguous band of them (row-major), whose rings and cross-tile pulls its
+// L2 then serves.
 template <class S, int COLL>
 __global__ void __launch_bounds__(kCurvX * kCurvY)
 curv_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename ForceOf<S>::type> pl,
@@ -120,20 +143,25 @@ curv_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
     const RunDesc& d = runs[run];
     const int nx = d.nx, ny = d.ny;
     const int tx = nx < kCurvX ? nx : kCurvX, ty = ny < kCurvY ? ny : kCurvY;   // tile extent
-    const int ox = blockIdx.x * kCurvX, oy = blockIdx.y * kCurvY;              // first owned node
+    const int gx = (nx + kCurvX - 1) / kCurvX, nt = gx * ((ny + kCurvY - 1) / kCurvY);
+    const int xcd = blockIdx.x & 7, q = nt >> 3, rem = nt & 7;
+    const int t = xcd * q + min(xcd, rem) + (int)(blockIdx.x >> 3);   // tile of this work-group
+    const int ox = (t % gx) * kCurvX, oy = (t / gx) * kCurvY;          // first owned node
     const int x0 = ox < nx - tx ? ox : nx - tx, y0 = oy < ny - ty ? oy : ny - ty;   // tile origin
     const int lx = threadIdx.x, ly = threadIdx.y;
     const int i = x0 + lx, j = y0 + ly;
     const bool in = lx < tx && ly < ty;
     const bool px = d.bc_x == 0, py = d.bc_y == 0;
-    const int64_t N = (int64_t)nx * ny, n = (int64_t)j * nx + i;
+    const int64_t NB = (int64_t)nx * ny * sizeof(T);   // one metric plane in bytes
+    const RunBytes b = run_bytes(d, pl);
+    const uint32_t planeF = uint32_t(d.plane * sizeof(FT));
     const NodeParams<T> p = node_params<T>(d);
     const T* sp = step_params<T>(d);
     NodeMetric<T> g{};
     T aE = 0, aW = 0, aN = 0, aS = 0, f[kQ] = {}, Fp1 = 0, Fp2 = 0, dr = 0, U1 = 0, U2 = 0;
     if (in) {
-        g = curv_metric<T>(d, pl, n, N, aE, aW, aN, aS);
-        curv_pull9<S, T, FT>(d, pl, i, j, f, Fp1, Fp2);
+        g = curv_metric<T>(d, pl, uint32_t(j * nx + i) * uint32_t(sizeof(T)), NB, aE, aW, aN, aS);
+        curv_pull9<S, T, FT>(d, b, planeF, i, j, f, Fp1, Fp2);
         curv_moments<T>(f, Fp1, Fp2, p.rho0, g.ih1, g.ih2, dr, U1, U2);
         sm[0][ly + 1][lx + 1] = dr;
         sm[1][ly + 1][lx + 1] = U1;
@@ -142,7 +170,7 @@ curv_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
     // the ring: rows -1 and ty over the tile's columns, columns -1 and tx over
     // its rows (the differences never reach the corners); wrapped across a
     // periodic edge, absent beyond a wall
-    const T* mt = table_of<T>(pl.met, pl.metf) + d.met_off;
+    const char* mt = reinterpret_cast<const char*>(table_of<T>(pl.met, pl.metf) + d.met_off);
     const int nh = 2 * tx + 2 * ty;
     for (int h = ly * kCurvX + lx; h < nh; h += kCurvX * kCurvY) {
         int hx, hy;
@@ -162,10 +190,11 @@ curv_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
             if (!py) continue;
             hj = hj < 0 ? hj + ny : hj - ny;
         }
-        const int64_t hn = (int64_t)hj * nx + hi;
+        const uint32_t hnb = uint32_t(hj * nx + hi) * uint32_t(sizeof(T));
         T hf[kQ], hF1, hF2, hdr, hU1, hU2;
-        curv_pull9<S, T, FT>(d, pl, hi, hj, hf, hF1, hF2);
-        curv_moments<T>(hf, hF1, hF2, p.rho0, mt[M_IH1 * N + hn], mt[M_IH2 * N + hn], hdr, hU1, hU2);
+        curv_pull9<S, T, FT>(d, b, planeF, hi, hj, hf, hF1, hF2);
+        curv_moments<T>(hf, hF1, hF2, p.rho0, ld_at<T>(mt + M_IH1 * NB, hnb), ld_at<T>(mt + M_IH2 * NB, hnb), hdr,
+                        hU1, hU2);
         sm[0][hy + 1][hx + 1] = hdr;
         sm[1][hy + 1][hx + 1] = hU1;
         sm[2][hy + 1][hx + 1] = hU2;
@@ -222,15 +251,15 @@ curv_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
     // stores: base + increment, rounded without bias (the same draws as the
     // straight march: node, population, step)
     const uint32_t seed = mix32(step_ctr[0] + uint32_t(k));
-    const int64_t nn = (int64_t)j * d.pitch + i;
-    const uint32_t hn = mix32(uint32_t(d.f_off + nn) ^ seed);
-    S* out = pl.fout + d.f_off;
+    const uint32_t hn = mix32((uint32_t(d.f_off) + uint32_t(j) * uint32_t(d.pitch) + uint32_t(i)) ^ seed);
+    const uint32_t cs = uint32_t(sizeof(S));
+    const uint32_t own = uint32_t(j + 1) * b.pitch_s + uint32_t(i) * cs;   // (slot regions start at row -1)
     S e[kQ];
 #pragma unroll
     for (int a = 0; a < kQ; ++a) {
         const T sfw = Store<S>::scaled ? sp[P_SC + cls_(a)] : T(1);
         e[a] = Store<S>::enc(f[a], inc[a], sfw, pop_draw(hn, a));
-        out[(int64_t)a * d.plane + nn] = e[a];
+        st_at<S>(b.fo, uint32_t(a) * b.plane_s + own, e[a]);
     }
     // ghost rows (rows 0 and ny - 1): walls take the bounced values at the
     // reader's source column, into the row beyond the wall; periodic xi2 takes
@@ -240,25 +269,24 @@ curv_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
     const bool bot = j == 0, top = j == ny - 1;
     if (bot || top) {
         const bool wall = !py;
-        const int grow = (wall ? bot : top) ? -1 : ny;
-        const int p0 = (wall == bot) ? 2 : 4;
-        const int p1 = wall ? (bot ? 5 : 8) : (bot ? 7 : 6);
-        const int p2 = wall ? (bot ? 6 : 7) : (bot ? 8 : 5);
+        const uint32_t grow = (wall ? bot : top) ? 0u : uint32_t(ny + 1) * b.pitch_s;   // row -1 or ny
+        const uint32_t p0 = (wall == bot) ? 2 : 4;
+        const uint32_t p1 = wall ? (bot ? 5 : 8) : (bot ? 7 : 6);
+        const uint32_t p2 = wall ? (bot ? 6 : 7) : (bot ? 8 : 5);
         const int cm = px ? (i == 0 ? nx - 1 : i - 1) : i - 1;
         const int cp = px ? (i == nx - 1 ? 0 : i + 1) : i + 1;
-        S* gr = out + (int64_t)grow * d.pitch;
-        gr[(int64_t)p0 * d.plane + i] = bot ? e[4] : e[2];
+        st_at<S>(b.fo, grow + p0 * b.plane_s + uint32_t(i) * cs, bot ? e[4] : e[2]);
         if (!wall) {
-            gr[(int64_t)p1 * d.plane + i] = bot ? e[7] : e[6];
-            gr[(int64_t)p2 * d.plane + i] = bot ? e[8] : e[5];
+            st_at<S>(b.fo, grow + p1 * b.plane_s + uint32_t(i) * cs, bot ? e[7] : e[6]);
+            st_at<S>(b.fo, grow + p2 * b.plane_s + uint32_t(i) * cs, bot ? e[8] : e[5]);
         } else {
-            if (!wxlo) gr[(int64_t)p1 * d.plane + cm] = bot ? e[7] : e[6];
-            if (!wxhi) gr[(int64_t)p2 * d.plane + cp] = bot ? e[8] : e[5];
+            if (!wxlo) st_at<S>(b.fo, grow + p1 * b.plane_s + uint32_t(cm) * cs, bot ? e[7] : e[6]);
+            if (!wxhi) st_at<S>(b.fo, grow + p2 * b.plane_s + uint32_t(cp) * cs, bot ? e[8] : e[5]);
         }
     }
-    const int64_t nf = d.F_off + (int64_t)j * d.pitchF + i;
-    pl.Fout[nf] = FT(F1);
-    pl.Fout[nf + d.plane] = FT(F2);
+    const uint32_t nf = uint32_t(j) * b.pitch_F + uint32_t(i) * uint32_t(sizeof(FT));
+    st_at<FT>(b.Fo, nf, FT(F1));
+    st_at<FT>(b.Fo, nf + planeF, FT(F2));
 }
 
 }  // namespace goc

@@ -368,7 +368,7 @@ int launch_step(goc_lbm* h, int k)
         if (h->m2d) {   // curvilinear step: one launch per run
             for (int r = 0; r < h->nruns; ++r) {
                 const RunDesc& d = h->runs[r];
-                const dim3 cg((d.nx + goc::kCurvX - 1) / goc::kCurvX, (d.ny + goc::kCurvY - 1) / goc::kCurvY);
+                const dim3 cg(((d.nx + goc::kCurvX - 1) / goc::kCurvX) * ((d.ny + goc::kCurvY - 1) / goc::kCurvY));
                 const dim3 cb(goc::kCurvX, goc::kCurvY);
                 if (h->coll == goc::kCollRaw)
                     hipLaunchKernelGGL((goc::curv_step_kernel<S, goc::kCollRaw>), cg, cb, 0, h->stream, h->runs_d,
