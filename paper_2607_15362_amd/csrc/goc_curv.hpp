@@ -157,44 +157,54 @@ curv_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
     const uint32_t planeF = uint32_t(d.plane * sizeof(FT));
     const NodeParams<T> p = node_params<T>(d);
     const T* sp = step_params<T>(d);
-    NodeMetric<T> g{};
-    T aE = 0, aW = 0, aN = 0, aS = 0, f[kQ] = {}, Fp1 = 0, Fp2 = 0, dr = 0, U1 = 0, U2 = 0;
+    const char* mt = reinterpret_cast<const char*>(table_of<T>(pl.met, pl.metf) + d.met_off);
+    // the own node, clamped into the grid for the threads of a ragged tile
+    // that have none (they load, but store nothing)
+    const int ic = in ? i : x0, jc = in ? j : y0;
+    // this thread's node of the ring around the tile: rows -1 and ty over the
+    // tile's columns, columns -1 and tx over its rows (the differences never
+    // reach the corners); wrapped across a periodic edge, absent beyond a
+    // wall.  Ring node h goes to lane h / 8 of wave h % 8, so that every wave
+    // pulls an eighth of the ring together with its own nodes.
+    static_assert(2 * kCurvX + 2 * kCurvY <= kCurvX * kCurvY, "one ring node per thread");
+    const int h = lx * kCurvY + ly, nh = 2 * tx + 2 * ty;
+    int hx, hy;
+    if (h < 2 * tx) {
+        hx = h < tx ? h : h - tx;
+        hy = h < tx ? -1 : ty;
+    } else {
+        hx = h < 2 * tx + ty ? -1 : tx;
+        hy = h < 2 * tx + ty ? h - 2 * tx : h - 2 * tx - ty;
+    }
+    int hi = x0 + hx, hj = y0 + hy;
+    bool hv = h < nh;
+    if (hi < 0 || hi >= nx) {
+        hv = hv && px;
+        hi = hi < 0 ? hi + nx : hi - nx;
+    }
+    if (hj < 0 || hj >= ny) {
+        hv = hv && py;
+        hj = hj < 0 ? hj + ny : hj - ny;
+    }
+    hi = hv ? hi : ic;
+    hj = hv ? hj : jc;
+    // all loads of both nodes, then the moments of both into LDS
+    const uint32_t hnb = uint32_t(hj * nx + hi) * uint32_t(sizeof(T));
+    T aE, aW, aN, aS;
+    const NodeMetric<T> g = curv_metric<T>(d, pl, uint32_t(jc * nx + ic) * uint32_t(sizeof(T)), NB, aE, aW, aN, aS);
+    T f[kQ], Fp1, Fp2, hf[kQ], hF1, hF2;
+    curv_pull9<S, T, FT>(d, b, planeF, ic, jc, f, Fp1, Fp2);
+    curv_pull9<S, T, FT>(d, b, planeF, hi, hj, hf, hF1, hF2);
+    const T hih1 = ld_at<T>(mt + M_IH1 * NB, hnb), hih2 = ld_at<T>(mt + M_IH2 * NB, hnb);
+    T dr, U1, U2, hdr, hU1, hU2;
+    curv_moments<T>(f, Fp1, Fp2, p.rho0, g.ih1, g.ih2, dr, U1, U2);
+    curv_moments<T>(hf, hF1, hF2, p.rho0, hih1, hih2, hdr, hU1, hU2);
     if (in) {
-        g = curv_metric<T>(d, pl, uint32_t(j * nx + i) * uint32_t(sizeof(T)), NB, aE, aW, aN, aS);
-        curv_pull9<S, T, FT>(d, b, planeF, i, j, f, Fp1, Fp2);
-        curv_moments<T>(f, Fp1, Fp2, p.rho0, g.ih1, g.ih2, dr, U1, U2);
         sm[0][ly + 1][lx + 1] = dr;
         sm[1][ly + 1][lx + 1] = U1;
         sm[2][ly + 1][lx + 1] = U2;
     }
-    // the ring: rows -1 and ty over the tile's columns, columns -1 and tx over
-    // its rows (the differences never reach the corners); wrapped across a
-    // periodic edge, absent beyond a wall
-    const char* mt = reinterpret_cast<const char*>(table_of<T>(pl.met, pl.metf) + d.met_off);
-    const int nh = 2 * tx + 2 * ty;
-    for (int h = ly * kCurvX + lx; h < nh; h += kCurvX * kCurvY) {
-        int hx, hy;
-        if (h < 2 * tx) {
-            hx = h < tx ? h : h - tx;
-            hy = h < tx ? -1 : ty;
-        } else {
-            hx = h < 2 * tx + ty ? -1 : tx;
-            hy = h < 2 * tx + ty ? h - 2 * tx : h - 2 * tx - ty;
-        }
-        int hi = x0 + hx, hj = y0 + hy;
-        if (hi < 0 || hi >= nx) {
-            if (!px) continue;
-            hi = hi < 0 ? hi + nx : hi - nx;
-        }
-        if (hj < 0 || hj >= ny) {
-            if (!py) continue;
-            hj = hj < 0 ? hj + ny : hj - ny;
-        }
-        const uint32_t hnb = uint32_t(hj * nx + hi) * uint32_t(sizeof(T));
-        T hf[kQ], hF1, hF2, hdr, hU1, hU2;
-        curv_pull9<S, T, FT>(d, b, planeF, hi, hj, hf, hF1, hF2);
-        curv_moments<T>(hf, hF1, hF2, p.rho0, ld_at<T>(mt + M_IH1 * NB, hnb), ld_at<T>(mt + M_IH2 * NB, hnb), hdr,
-                        hU1, hU2);
+    if (hv) {
         sm[0][hy + 1][hx + 1] = hdr;
         sm[1][hy + 1][hx + 1] = hU1;
         sm[2][hy + 1][hx + 1] = hU2;
