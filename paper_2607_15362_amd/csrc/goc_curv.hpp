@@ -5,9 +5,10 @@
 // the conformal annular sector) keeps the slot layout, the deviation
 // storage and the writer-side boundary conditions of the straight path, with
 // the metric read per node from a pool of planes (goc_device.hpp: M_*).  A
-// step is one launch of one thread per node over 64 x 8 tiles: pull, decode
-// and the moments rho - rho0, U1, U2 (App. E step 7, lagged force) of the
-// tile and of the ring of nodes around it into LDS; the second-order
+// step is one launch of one thread per node over 64 x 8 tiles (64 x 4 in
+// FP64): pull, decode and the moments rho - rho0, U1, U2 (App. E step 7,
+// lagged force) of the tile and of the ring of nodes around it into LDS;
+// the second-order
 // differences of U and rho from LDS (one-sided next to walls, wrapped when
 // periodic); the general stresses and effective force with the local shear
 // stress (Sec. 2.2, App. A), the corrections of Sec. 5 with their curvature
@@ -21,7 +22,10 @@
 
 namespace goc {
 
-constexpr int kCurvX = 64, kCurvY = 8;   // work-group tile: 64 columns x 8 rows
+constexpr int kCurvX = 64;   // work-group tile: 64 columns x curv_rows<S>() rows
+// 8 rows; 4 for FP64 storage, whose register count leaves room for fewer
+// waves per CU
+template <class S> constexpr int curv_rows() { return sizeof(S) == 8 ? 4 : 8; }
 
 // A value at a lane's 32-bit byte offset from a work-group-uniform base:
 // the hardware forms such an address from a scalar base and a vector
@@ -122,9 +126,9 @@ __device__ inline T tile_fd(V v, int l, int k, int n, bool periodic)
     return T(0.5) * (v(l + 1) - v(l - 1));
 }
 
-// The step of every node of one run.  Launch: grid ceil(nx/64) *
-// ceil(ny/8) work-groups (1-D), block (64, 8).  A work-group owns the 64 x 8
-// nodes of tile (bx, by) at (64 bx, 8 by); its tile is shifted back at the
+// The step of every node of one run.  Launch: grid ceil(nx/64) * ceil(ny/Y)
+// work-groups (1-D), block (64, Y), Y = curv_rows<S>().  A work-group owns
+// the 64 x Y nodes of tile (bx, by) at (64 bx, Y by); its tile is shifted back at the
 // far edges of the grid so that the three nodes of a one-sided difference
 // lie in it (nodes of the shifted part belong to the neighbouring
 // work-group and are not written here).  The moments of the tile and of the
@@ -133,12 +137,13 @@ __device__ inline T tile_fd(V v, int l, int k, int n, bool periodic)
 // contiguous band of them (row-major), whose rings and cross-tile pulls its
 // L2 then serves.
 template <class S, int COLL>
-__global__ void __launch_bounds__(kCurvX * kCurvY)
+__global__ void __launch_bounds__(kCurvX * curv_rows<S>())
 curv_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename ForceOf<S>::type> pl,
                  const uint32_t* __restrict__ step_ctr, int k)
 {
     using T = typename ComputeOf<S>::type;
     using FT = typename ForceOf<S>::type;
+    constexpr int kCurvY = curv_rows<S>();
     __shared__ T sm[3][kCurvY + 2][kCurvX + 2];   // rho - rho0, U1, U2 of the tile and its ring
     const RunDesc& d = runs[run];
     const int nx = d.nx, ny = d.ny;
@@ -164,10 +169,10 @@ curv_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
     // this thread's node of the ring around the tile: rows -1 and ty over the
     // tile's columns, columns -1 and tx over its rows (the differences never
     // reach the corners); wrapped across a periodic edge, absent beyond a
-    // wall.  Ring node h goes to lane h / 8 of wave h % 8, so that every wave
-    // pulls an eighth of the ring together with its own nodes.
+    // wall.  Ring node h goes to thread h in order (whole rows of the ring
+    // per wave: contiguous loads), and the waves beyond the ring skip it.
     static_assert(2 * kCurvX + 2 * kCurvY <= kCurvX * kCurvY, "one ring node per thread");
-    const int h = lx * kCurvY + ly, nh = 2 * tx + 2 * ty;
+    const int h = ly * kCurvX + lx, nh = 2 * tx + 2 * ty;
     int hx, hy;
     if (h < 2 * tx) {
         hx = h < tx ? h : h - tx;
@@ -188,26 +193,31 @@ curv_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
     }
     hi = hv ? hi : ic;
     hj = hv ? hj : jc;
-    // all loads of both nodes, then the moments of both into LDS
+    // the loads of the own node, then (in a wave holding ring nodes) those of
+    // the ring node, before either node's moments: one wait for both
     const uint32_t hnb = uint32_t(hj * nx + hi) * uint32_t(sizeof(T));
     T aE, aW, aN, aS;
     const NodeMetric<T> g = curv_metric<T>(d, pl, uint32_t(jc * nx + ic) * uint32_t(sizeof(T)), NB, aE, aW, aN, aS);
-    T f[kQ], Fp1, Fp2, hf[kQ], hF1, hF2;
+    T f[kQ], Fp1, Fp2;
     curv_pull9<S, T, FT>(d, b, planeF, ic, jc, f, Fp1, Fp2);
-    curv_pull9<S, T, FT>(d, b, planeF, hi, hj, hf, hF1, hF2);
-    const T hih1 = ld_at<T>(mt + M_IH1 * NB, hnb), hih2 = ld_at<T>(mt + M_IH2 * NB, hnb);
-    T dr, U1, U2, hdr, hU1, hU2;
+    if (ly * kCurvX < nh) {   // (uniform over the wave: one wave per row of the block)
+        T hf[kQ], hF1, hF2;
+        curv_pull9<S, T, FT>(d, b, planeF, hi, hj, hf, hF1, hF2);
+        const T hih1 = ld_at<T>(mt + M_IH1 * NB, hnb), hih2 = ld_at<T>(mt + M_IH2 * NB, hnb);
+        T hdr, hU1, hU2;
+        curv_moments<T>(hf, hF1, hF2, p.rho0, hih1, hih2, hdr, hU1, hU2);
+        if (hv) {
+            sm[0][hy + 1][hx + 1] = hdr;
+            sm[1][hy + 1][hx + 1] = hU1;
+            sm[2][hy + 1][hx + 1] = hU2;
+        }
+    }
+    T dr, U1, U2;
     curv_moments<T>(f, Fp1, Fp2, p.rho0, g.ih1, g.ih2, dr, U1, U2);
-    curv_moments<T>(hf, hF1, hF2, p.rho0, hih1, hih2, hdr, hU1, hU2);
     if (in) {
         sm[0][ly + 1][lx + 1] = dr;
         sm[1][ly + 1][lx + 1] = U1;
         sm[2][ly + 1][lx + 1] = U2;
-    }
-    if (hv) {
-        sm[0][hy + 1][hx + 1] = hdr;
-        sm[1][hy + 1][hx + 1] = hU1;
-        sm[2][hy + 1][hx + 1] = hU2;
     }
     __syncthreads();
     if (!in || i < ox || j < oy) return;

@@ -368,8 +368,9 @@ int launch_step(goc_lbm* h, int k)
         if (h->m2d) {   // curvilinear step: one launch per run
             for (int r = 0; r < h->nruns; ++r) {
                 const RunDesc& d = h->runs[r];
-                const dim3 cg(((d.nx + goc::kCurvX - 1) / goc::kCurvX) * ((d.ny + goc::kCurvY - 1) / goc::kCurvY));
-                const dim3 cb(goc::kCurvX, goc::kCurvY);
+                constexpr int cy = goc::curv_rows<S>();
+                const dim3 cg(((d.nx + goc::kCurvX - 1) / goc::kCurvX) * ((d.ny + cy - 1) / cy));
+                const dim3 cb(goc::kCurvX, cy);
                 if (h->coll == goc::kCollRaw)
                     hipLaunchKernelGGL((goc::curv_step_kernel<S, goc::kCollRaw>), cg, cb, 0, h->stream, h->runs_d,
                                        r, pl, h->step_ctr, k);
