@@ -44,16 +44,23 @@ METRIC = "MLUPS + % HBM peak; FP16-store & batched vs plain FP32 on same GPU"
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("goc_device.hpp", "goc_step.hpp"):
+    for f in ("goc_device.hpp", "goc_step.hpp", "goc_tile.hpp"):
         with open(os.path.join(ROOT, "paper_2607_15362_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, bytes_alg_per_launch: float):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"step_kernel_{workload}_pmc.json")
+def kernel_name(launch) -> str:
+    """The step kernel a launch plan runs: the tiled step (waves_per_cu 0) or
+    the march."""
+    return "goc::tile_step_kernel" if launch["waves_per_cu"] == 0 else "goc::step_kernel"
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of a kernel on a workload from a committed
+    rocprofv3 counter summary, if it was taken on the current kernel source;
+    else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel.split('::')[-1]}_{workload}_pmc.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -256,9 +263,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-collisions", action="store_true")
     ap.add_argument("--no-curvilinear", action="store_true")
-    ap.add_argument("--waves", type=float, default=0.0, metavar="W",
-                    help="fixed launch plan of W waves per CU instead of the autotuner "
-                         "(for profiler runs)")
+    ap.add_argument("--waves", type=float, default=-1.0, metavar="W",
+                    help="fixed step form instead of the autotuner (for profiler runs): W = 0 the "
+                         "tiled step, W > 0 the march with W waves per CU")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB mebibytes (counter calibration)")
     args = ap.parse_args()
@@ -276,7 +283,7 @@ def main():
 
     case = W.cavity_1024() if args.workload == "cavity_1024" else W.hartmann_4096()
     run = B.Run(case)
-    if args.waves > 0:
+    if args.waves >= 0:
         run.set_launch(args.waves)
         tuned = {"us_before": float("nan")}
     else:
@@ -289,7 +296,7 @@ def main():
     launch_s = ev / args.steps
     bytes_per_launch = d["bytes_per_node"] * nodes
     achieved = bytes_per_launch / launch_s / 1e9
-    traffic = measured_traffic(case.name, bytes_per_launch)
+    traffic = measured_traffic(kernel_name(launch), case.name)
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -314,8 +321,9 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic,
                      "bytes_per_node": d["bytes_per_node"], "launch_us": round(launch_s * 1e6, 2),
-                     "kernel": "goc::step_kernel",
-                     "launch_plan": {"waves_per_cu": launch["waves_per_cu"], "work_groups": launch["blocks"],
+                     "kernel": kernel_name(launch),
+                     "launch_plan": {"form": "tiled" if launch["waves_per_cu"] == 0 else "march",
+                                     "waves_per_cu": launch["waves_per_cu"], "work_groups": launch["blocks"],
                                      "rows_per_segment": round(launch["rows_per_segment"], 2),
                                      "untuned_us": (round(tuned["us_before"], 2)
                                                     if tuned["us_before"] == tuned["us_before"] else None)}},

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgoclbm.so")
 SOURCES = [os.path.join(CSRC, "goc_lbm.hip")]
-DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("goc_device.hpp", "goc_step.hpp", "goc_curv.hpp", "goc_aux.hpp")] + [
+DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("goc_device.hpp", "goc_step.hpp", "goc_tile.hpp", "goc_aux.hpp")] + [
     os.path.join(os.path.dirname(HERE), "include", "goc_lbm.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -16,7 +16,7 @@
 
 #include "../../include/goc_lbm.h"
 #include "goc_aux.hpp"
-#include "goc_curv.hpp"
+#include "goc_tile.hpp"
 
 using goc::RunDesc;
 
@@ -317,6 +317,7 @@ struct goc_lbm {
     uint32_t* step_ctr = nullptr;   // device: index of the next step's rounding draws
     int ncu = 256;                  // compute units of the device
     double waves_per_cu = 16.0;     // launch plan: work-groups per CU over the whole launch
+    bool tiled = false;             // straight single run stepped by the tiled kernel instead of the march
     int block_cap = 0;              // capacity of block_run_d (entries)
 };
 
@@ -365,18 +366,25 @@ int launch_step(goc_lbm* h, int k)
     return dispatch(h->storage, [&](auto tag) -> int {
         using S = decltype(tag);
         const auto pl = pools<S>(h, h->cur);
-        if (h->m2d) {   // curvilinear step: one launch per run
+        if (h->m2d || h->tiled) {   // tiled step: one launch per run
+            constexpr int cy = goc::curv_rows<S>();
+            const bool raw = h->coll == goc::kCollRaw;
             for (int r = 0; r < h->nruns; ++r) {
                 const RunDesc& d = h->runs[r];
-                constexpr int cy = goc::curv_rows<S>();
                 const dim3 cg(((d.nx + goc::kCurvX - 1) / goc::kCurvX) * ((d.ny + cy - 1) / cy));
                 const dim3 cb(goc::kCurvX, cy);
-                if (h->coll == goc::kCollRaw)
-                    hipLaunchKernelGGL((goc::curv_step_kernel<S, goc::kCollRaw>), cg, cb, 0, h->stream, h->runs_d,
-                                       r, pl, h->step_ctr, k);
-                else
-                    hipLaunchKernelGGL((goc::curv_step_kernel<S, goc::kCollCentral>), cg, cb, 0, h->stream,
+                if (h->m2d && raw)
+                    hipLaunchKernelGGL((goc::tile_step_kernel<S, goc::kCollRaw, true>), cg, cb, 0, h->stream,
                                        h->runs_d, r, pl, h->step_ctr, k);
+                else if (h->m2d)
+                    hipLaunchKernelGGL((goc::tile_step_kernel<S, goc::kCollCentral, true>), cg, cb, 0, h->stream,
+                                       h->runs_d, r, pl, h->step_ctr, k);
+                else if (raw)
+                    hipLaunchKernelGGL((goc::tile_step_kernel<S, goc::kCollRaw, false>), cg, cb, 0, h->stream,
+                                       h->runs_d, r, pl, h->step_ctr, k);
+                else
+                    hipLaunchKernelGGL((goc::tile_step_kernel<S, goc::kCollCentral, false>), cg, cb, 0,
+                                       h->stream, h->runs_d, r, pl, h->step_ctr, k);
             }
             HIPOK(hipGetLastError());
             return GOC_OK;
@@ -491,10 +499,36 @@ void plan_rows(goc_lbm* h, std::vector<int32_t>& block_run)
     h->total_blocks = (int)block_run.size();
 }
 
-// Apply a launch plan on the device: run table and work list (synchronous;
-// captured step graphs are dropped, as their grid changes).
+// The tiled kernel can step a handle of one straight run without MHD (the
+// march serves batches, whose runs share one launch, and the D2Q5 scheme).
+bool tile_eligible(const goc_lbm* h) { return !h->m2d && h->nruns == 1 && !h->any_mhd; }
+// Rows of a tile of the tiled kernel for the handle's storage.
+int tile_rows(const goc_lbm* h) { return h->storage == GOC_F64 ? 4 : 8; }
+
+void drop_graphs(goc_lbm* h)
+{
+    for (int k = 0; k < 2; ++k)
+        if (h->graph[k]) {
+            (void)hipGraphExecDestroy(h->graph[k]);
+            h->graph[k] = nullptr;
+        }
+}
+
+// Step an eligible handle with the tiled kernel (synchronous; captured step
+// graphs are dropped).
+int use_tiled(goc_lbm* h)
+{
+    HIPOK(hipStreamSynchronize(h->stream));
+    drop_graphs(h);
+    h->tiled = true;
+    return GOC_OK;
+}
+
+// Apply a launch plan of the march on the device: run table and work list
+// (synchronous; captured step graphs are dropped, as their grid changes).
 int apply_plan(goc_lbm* h, double waves_per_cu)
 {
+    h->tiled = false;
     h->waves_per_cu = waves_per_cu;
     std::vector<int32_t> block_run;
     plan_rows(h, block_run);
@@ -507,11 +541,7 @@ int apply_plan(goc_lbm* h, double waves_per_cu)
         h->block_cap = (int)block_run.size();
     }
     HIPOK(hipStreamSynchronize(h->stream));
-    for (int k = 0; k < 2; ++k)
-        if (h->graph[k]) {
-            (void)hipGraphExecDestroy(h->graph[k]);
-            h->graph[k] = nullptr;
-        }
+    drop_graphs(h);
     HIPOK(hipMemcpy(h->runs_d, h->runs.data(), h->nruns * sizeof(RunDesc), hipMemcpyHostToDevice));
     HIPOK(hipMemcpy(h->block_run_d, block_run.data(), block_run.size() * 4, hipMemcpyHostToDevice));
     return GOC_OK;
@@ -653,6 +683,7 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
     h->ncu = ncu;
     plan_rows(h, block_run);
     h->block_cap = (int)block_run.size();
+    h->tiled = tile_eligible(h);   // the faster form for a single straight run
     h->f_elems = f_elems;
     h->F_elems = F_elems;
     h->g_elems = g_elems;
@@ -1187,6 +1218,12 @@ int goc_lbm_step(goc_lbm_t* h, int64_t n)
 int goc_lbm_set_launch(goc_lbm_t* h, double waves_per_cu)
 {
     if (!check_handle(h)) return GOC_EINVAL;
+    if (waves_per_cu == 0.0) {
+        if (h->m2d) return GOC_OK;   // always tiled
+        if (!tile_eligible(h)) return fail(GOC_EINVAL, "the tiled step takes one straight run without MHD");
+        return use_tiled(h);
+    }
+    if (h->m2d) return fail(GOC_EINVAL, "a run on a 2-D metric has only the tiled step (waves_per_cu 0)");
     if (!(waves_per_cu >= 0.5 && waves_per_cu <= 1024.0))
         return fail(GOC_EINVAL, "waves_per_cu %g outside [0.5, 1024]", waves_per_cu);
     return apply_plan(h, waves_per_cu);
@@ -1200,6 +1237,20 @@ int goc_lbm_launch_info(const goc_lbm_t* h, double out[4])
         rows += (int64_t)d.ny * d.strips;
         segs += (int64_t)d.segs * d.strips;
         strips += d.strips;
+    }
+    if (h->m2d || h->tiled) {
+        const int ty = tile_rows(h);
+        int64_t tiles = 0, cols = 0;
+        for (const RunDesc& d : h->runs) {
+            const int64_t gx = (d.nx + goc::kCurvX - 1) / goc::kCurvX;
+            tiles += gx * ((d.ny + ty - 1) / ty);
+            cols += gx;
+        }
+        out[0] = 0.0;
+        out[1] = (double)tiles;
+        out[2] = ty;
+        out[3] = (double)cols;
+        return GOC_OK;
     }
     out[0] = h->waves_per_cu;
     out[1] = h->total_blocks;
@@ -1231,17 +1282,20 @@ int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
         HIPOK(hipEventSynchronize(ev.e[1]));
         float ms = 0.0f;
         HIPOK(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
-        out[0] = h->waves_per_cu;
+        out[0] = 0.0;
         out[1] = out[2] = 1e3 * ms / trial_steps;
         out[3] = 1;
         return GOC_OK;
     }
-    const double prev = h->waves_per_cu;
+    // candidate 0 is the tiled step (eligible handles only)
+    const bool elig = tile_eligible(h);
+    const double prev = h->tiled ? 0.0 : h->waves_per_cu;
     double best_us = 1e300, best_w = prev, prev_us = -1.0;
     // every trial launch reads the current buffers and writes the others,
     // which the next real step overwrites: the state does not change
-    for (int c = 0; c < ncand; ++c) {
-        int rc = apply_plan(h, cand[c]);
+    for (int c = elig ? -1 : 0; c < ncand; ++c) {
+        const double w = c < 0 ? 0.0 : cand[c];
+        int rc = w == 0.0 ? use_tiled(h) : apply_plan(h, w);
         if (rc) return rc;
         if ((rc = launch_step(h, 0))) return rc;
         HIPOK(hipEventRecord(ev.e[0], h->stream));
@@ -1252,17 +1306,17 @@ int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
         float ms = 0.0f;
         HIPOK(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
         const double us = 1e3 * ms / trial_steps;
-        if (cand[c] == prev) prev_us = us;
+        if (w == prev) prev_us = us;
         if (us < best_us) {
             best_us = us;
-            best_w = cand[c];
+            best_w = w;
         }
     }
-    if (int rc = apply_plan(h, best_w)) return rc;
+    if (int rc = best_w == 0.0 ? use_tiled(h) : apply_plan(h, best_w)) return rc;
     out[0] = best_w;
     out[1] = best_us;
     out[2] = prev_us;
-    out[3] = ncand;
+    out[3] = ncand + (elig ? 1 : 0);
     return GOC_OK;
 }
 

@@ -136,9 +136,9 @@ __device__ inline T tile_fd(V v, int l, int k, int n, bool periodic)
 // the eight XCDs in turn; the tiles are renumbered so that each XCD gets a
 // contiguous band of them (row-major), whose rings and cross-tile pulls its
 // L2 then serves.
-template <class S, int COLL>
+template <class S, int COLL, bool GEN>
 __global__ void __launch_bounds__(kCurvX * curv_rows<S>())
-curv_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename ForceOf<S>::type> pl,
+tile_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename ForceOf<S>::type> pl,
                  const uint32_t* __restrict__ step_ctr, int k)
 {
     using T = typename ComputeOf<S>::type;
@@ -196,14 +196,37 @@ curv_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
     // the loads of the own node, then (in a wave holding ring nodes) those of
     // the ring node, before either node's moments: one wait for both
     const uint32_t hnb = uint32_t(hj * nx + hi) * uint32_t(sizeof(T));
+    // GEN: the metric planes and the writer's rest-state offsets of the four
+    // axis slots; otherwise the column and row tables of the straight grid
+    // (the offsets a1+-, a2+- are scaled by h2 / h1 at the writes)
     T aE, aW, aN, aS;
-    const NodeMetric<T> g = curv_metric<T>(d, pl, uint32_t(jc * nx + ic) * uint32_t(sizeof(T)), NB, aE, aW, aN, aS);
+    NodeMetric<T> g;
+    const T* ctab = table_of<T>(pl.col, pl.colf) + (int64_t)d.col_off * kTab;
+    const T* rtab = table_of<T>(pl.row, pl.rowf) + (int64_t)d.row_off * kTab;
+    if constexpr (GEN) {
+        g = curv_metric<T>(d, pl, uint32_t(jc * nx + ic) * uint32_t(sizeof(T)), NB, aE, aW, aN, aS);
+    } else {
+        const T* ct = ctab + ic * kTab;
+        const T* rt = rtab + jc * kTab;
+        g.h1 = ct[T_H];
+        g.ih1 = ct[T_IH];
+        g.th11 = ct[T_TH];
+        g.h2 = rt[T_H];
+        g.ih2 = rt[T_IH];
+        g.th22 = rt[T_TH];
+        g.th12 = g.th21 = T(0);
+        aE = ct[T_AP];
+        aW = ct[T_AM];
+        aN = rt[T_AP];
+        aS = rt[T_AM];
+    }
     T f[kQ], Fp1, Fp2;
     curv_pull9<S, T, FT>(d, b, planeF, ic, jc, f, Fp1, Fp2);
     if (ly * kCurvX < nh) {   // (uniform over the wave: one wave per row of the block)
         T hf[kQ], hF1, hF2;
         curv_pull9<S, T, FT>(d, b, planeF, hi, hj, hf, hF1, hF2);
-        const T hih1 = ld_at<T>(mt + M_IH1 * NB, hnb), hih2 = ld_at<T>(mt + M_IH2 * NB, hnb);
+        const T hih1 = GEN ? ld_at<T>(mt + M_IH1 * NB, hnb) : ctab[hi * kTab + T_IH];
+        const T hih2 = GEN ? ld_at<T>(mt + M_IH2 * NB, hnb) : rtab[hj * kTab + T_IH];
         T hdr, hU1, hU2;
         curv_moments<T>(hf, hF1, hF2, p.rho0, hih1, hih2, hdr, hU1, hU2);
         if (hv) {
@@ -231,8 +254,11 @@ curv_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
 
     const RawDev<T> m = raw_dev<T>(f);
     T F1, F2, n3, n4, inc[kQ];
-    force_and_corrections_gen<T>(p, g, rho, dr, U1, U2, d1U1, d2U2, d1r, d2r, p.Fx1, p.Fx2, m.m11, F1, F2, n3,
-                                 n4);
+    if constexpr (GEN)
+        force_and_corrections_gen<T>(p, g, rho, dr, U1, U2, d1U1, d2U2, d1r, d2r, p.Fx1, p.Fx2, m.m11, F1, F2,
+                                     n3, n4);
+    else
+        force_and_corrections<T>(p, g, rho, dr, U1, U2, d1U1, d2U2, d1r, d2r, p.Fx1, p.Fx2, F1, F2, n3, n4);
     if constexpr (COLL == kCollRaw)
         raw_collide<T>(p, g, m, rho, dr, U1, U2, Fp1, Fp2, F1, F2, n3, n4, inc);
     else
@@ -240,32 +266,59 @@ curv_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
 
     // writer side: rest-state offsets of the axis slots (their readers are the
     // neighbours; zero toward walls) and the wall terms of App. C
-    inc[1] += aE;
-    inc[3] += aW;
-    inc[2] += aN;
-    inc[4] += aS;
     const bool wxlo = !px && i == 0, wxhi = !px && i == nx - 1;
     const bool wylo = !py && j == 0, wyhi = !py && j == ny - 1;
-    const double* face = pl.face + d.face_off;   // [2 ny] h1 on the xi1 faces, then [2 nx] h2 on the xi2 faces
-    if (wyhi && d.uw_hi != 0.0) {
-        const T cw = rho * T(0.5) * p.cs2 * T(d.uw_hi) / T(face[2 * ny + 2 * i + 1]);
-        if (d.lid_corners || !wxhi) inc[5] -= cw;
-        if (d.lid_corners || !wxlo) inc[6] += cw;
-    }
-    if (wylo && d.uw_lo != 0.0) {
-        const T cw = rho * T(0.5) * p.cs2 * T(d.uw_lo) / T(face[2 * ny + 2 * i]);
-        if (d.lid_corners || !wxlo) inc[7] += cw;
-        if (d.lid_corners || !wxhi) inc[8] -= cw;
-    }
-    if (wxhi && d.vw_hi != 0.0) {
-        const T cx = rho * T(0.5) * p.cs2 * T(d.vw_hi) / T(face[2 * j + 1]);
-        if (d.lid_corners || !wyhi) inc[5] -= cx;
-        if (d.lid_corners || !wylo) inc[8] += cx;
-    }
-    if (wxlo && d.vw_lo != 0.0) {
-        const T cx = rho * T(0.5) * p.cs2 * T(d.vw_lo) / T(face[2 * j]);
-        if (d.lid_corners || !wylo) inc[7] += cx;
-        if (d.lid_corners || !wyhi) inc[6] -= cx;
+    if constexpr (GEN) {
+        inc[1] += aE;
+        inc[3] += aW;
+        inc[2] += aN;
+        inc[4] += aS;
+        const double* face = pl.face + d.face_off;   // [2 ny] h1 on the xi1 faces, then [2 nx] h2 on the xi2 faces
+        if (wyhi && d.uw_hi != 0.0) {
+            const T cw = rho * T(0.5) * p.cs2 * T(d.uw_hi) / T(face[2 * ny + 2 * i + 1]);
+            if (d.lid_corners || !wxhi) inc[5] -= cw;
+            if (d.lid_corners || !wxlo) inc[6] += cw;
+        }
+        if (wylo && d.uw_lo != 0.0) {
+            const T cw = rho * T(0.5) * p.cs2 * T(d.uw_lo) / T(face[2 * ny + 2 * i]);
+            if (d.lid_corners || !wxlo) inc[7] += cw;
+            if (d.lid_corners || !wxhi) inc[8] -= cw;
+        }
+        if (wxhi && d.vw_hi != 0.0) {
+            const T cx = rho * T(0.5) * p.cs2 * T(d.vw_hi) / T(face[2 * j + 1]);
+            if (d.lid_corners || !wyhi) inc[5] -= cx;
+            if (d.lid_corners || !wylo) inc[8] += cx;
+        }
+        if (wxlo && d.vw_lo != 0.0) {
+            const T cx = rho * T(0.5) * p.cs2 * T(d.vw_lo) / T(face[2 * j]);
+            if (d.lid_corners || !wylo) inc[7] += cx;
+            if (d.lid_corners || !wyhi) inc[6] -= cx;
+        }
+    } else {   // the march's arithmetic: wall coefficients precomputed per run
+        inc[1] += g.h2 * aE;
+        inc[3] += g.h2 * aW;
+        inc[2] += g.h1 * aN;
+        inc[4] += g.h1 * aS;
+        if (wyhi && d.uw_hi != 0.0) {
+            const T cw = rho * sp[P_CWHI];
+            if (d.lid_corners || !wxhi) inc[5] -= cw;
+            if (d.lid_corners || !wxlo) inc[6] += cw;
+        }
+        if (wylo && d.uw_lo != 0.0) {
+            const T cw = rho * sp[P_CWLO];
+            if (d.lid_corners || !wxlo) inc[7] += cw;
+            if (d.lid_corners || !wxhi) inc[8] -= cw;
+        }
+        if (wxhi && d.vw_hi != 0.0) {
+            const T cx = rho * sp[P_CXHI];
+            if (d.lid_corners || !wyhi) inc[5] -= cx;
+            if (d.lid_corners || !wylo) inc[8] += cx;
+        }
+        if (wxlo && d.vw_lo != 0.0) {
+            const T cx = rho * sp[P_CXLO];
+            if (d.lid_corners || !wylo) inc[7] += cx;
+            if (d.lid_corners || !wyhi) inc[6] -= cx;
+        }
     }
 
     // stores: base + increment, rounded without bias (the same draws as the
