@@ -243,27 +243,39 @@ int goc_lbm_diagnostics(goc_lbm_t *h, double out[8]);
    makes goc_lbm_step return GOC_EUNSTABLE. */
 int goc_lbm_set_watchdog(goc_lbm_t *h, int64_t every);
 
-/* Launch plan of the step kernel.  One work-group (a wave of 64 lanes)
-   owns 64 columns of a run and a segment of rows (whole groups of 4 rows,
-   the last segment of a run taking the remainder); every run gets segments
-   in proportion to its nodes so that the launch holds about waves_per_cu
-   work-groups per compute unit (default 16; fewer where a run has too few
-   row groups).  Fewer, longer segments re-read fewer halo rows; more
-   segments fill the chip and balance uneven batches.  goc_lbm_set_launch
-   applies waves_per_cu in [0.5, 1024] (synchronous; GOC_EINVAL outside).
-   goc_lbm_launch_info writes out[0] = waves_per_cu, out[1] = work-groups
-   per step, out[2] = mean rows per segment, out[3] = strips (all runs). */
+/* Form and launch plan of the step.  Two kernels compute the same step
+   (App. E, every node once per step):
+   - the march: one work-group (a wave of 64 lanes) owns 64 columns of a
+     run and a segment of rows (whole groups of 4 rows, the last segment of
+     a run taking the remainder) and marches up it; every run gets segments
+     in proportion to its nodes so that the launch holds about waves_per_cu
+     work-groups per compute unit (default 16; fewer where a run has too
+     few row groups).  Fewer, longer segments re-read fewer halo rows; more
+     segments fill the chip and balance uneven batches.  It steps every
+     handle on straight metrics (batches and MHD runs always);
+   - the tiled step: one thread per node, 64 x 8 nodes per work-group (64 x
+     4 in FP64), the moments of the tile and its ring in LDS.  It steps a
+     single straight run without MHD (chosen by default there: it is the
+     faster form on most sizes) and every run on a 2-D metric (its only
+     form).  The two forms agree to rounding.
+   goc_lbm_set_launch: waves_per_cu = 0 selects the tiled step (GOC_EINVAL
+   where it does not apply); waves_per_cu in [0.5, 1024] the march with that
+   plan (GOC_EINVAL outside, and on a 2-D metric).  Synchronous.
+   goc_lbm_launch_info writes out[0] = waves_per_cu (0 for the tiled step),
+   out[1] = work-groups per step, out[2] = mean rows per segment (rows per
+   tile), out[3] = strips (column tiles), over all runs. */
 int goc_lbm_set_launch(goc_lbm_t *h, double waves_per_cu);
 int goc_lbm_launch_info(const goc_lbm_t *h, double out[4]);
 
-/* Autotuner of the launch plan: times trial_steps step launches (1..10000,
-   plus one warm-up) for each waves_per_cu in {2, 3, 4, 6, 8, 12, 16, 24, 32,
-   48, 64, 96, 128, 192, 256, 384, 512} on the handle's stream and keeps the
-   fastest.  The state does not
-   change: trial launches read the current buffers and write the spare ones.
-   out[0] = chosen waves_per_cu, out[1] = its microseconds per step,
-   out[2] = microseconds per step of the plan in use before (-1 if it was not
-   a candidate), out[3] = number of candidates.  Synchronous. */
+/* Autotuner of the step form and launch plan: times trial_steps step
+   launches (1..10000, plus one warm-up) for each waves_per_cu in {2, 3, 4,
+   6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512} and, where it
+   applies, the tiled step (waves_per_cu 0), on the handle's stream, and
+   keeps the fastest (a run on a 2-D metric: the tiled step, timed).  The
+   state does not change: trial launches read the current buffers and write
+   the spare ones.  out[0] = chosen waves_per_cu, out[1] = its microseconds
+   per step, out[2] = microseconds per step of the form in use before (-1 if
+   it was not a candidate), out[3] = number of candidates.  Synchronous. */
 int goc_lbm_tune(goc_lbm_t *h, int32_t trial_steps, double out[4]);
 
 /* Post-stream populations in FP64 (the quantities App. E step 1 reads):
