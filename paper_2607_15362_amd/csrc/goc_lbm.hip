@@ -373,18 +373,18 @@ int launch_step(goc_lbm* h, int k)
                 const RunDesc& d = h->runs[r];
                 const dim3 cg(((d.nx + goc::kCurvX - 1) / goc::kCurvX) * ((d.ny + cy - 1) / cy));
                 const dim3 cb(goc::kCurvX, cy);
-                if (h->m2d && raw)
-                    hipLaunchKernelGGL((goc::tile_step_kernel<S, goc::kCollRaw, true>), cg, cb, 0, h->stream,
-                                       h->runs_d, r, pl, h->step_ctr, k);
-                else if (h->m2d)
-                    hipLaunchKernelGGL((goc::tile_step_kernel<S, goc::kCollCentral, true>), cg, cb, 0, h->stream,
-                                       h->runs_d, r, pl, h->step_ctr, k);
-                else if (raw)
-                    hipLaunchKernelGGL((goc::tile_step_kernel<S, goc::kCollRaw, false>), cg, cb, 0, h->stream,
-                                       h->runs_d, r, pl, h->step_ctr, k);
+                auto go = [&](auto kernel) {
+                    hipLaunchKernelGGL(kernel, cg, cb, 0, h->stream, h->runs_d, r, pl, h->step_ctr, k);
+                };
+                if (h->m2d)
+                    raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, true, false>)
+                        : go(goc::tile_step_kernel<S, goc::kCollCentral, true, false>);
+                else if (h->any_mhd)
+                    raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, false, true>)
+                        : go(goc::tile_step_kernel<S, goc::kCollCentral, false, true>);
                 else
-                    hipLaunchKernelGGL((goc::tile_step_kernel<S, goc::kCollCentral, false>), cg, cb, 0,
-                                       h->stream, h->runs_d, r, pl, h->step_ctr, k);
+                    raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, false, false>)
+                        : go(goc::tile_step_kernel<S, goc::kCollCentral, false, false>);
             }
             HIPOK(hipGetLastError());
             return GOC_OK;
@@ -499,9 +499,9 @@ void plan_rows(goc_lbm* h, std::vector<int32_t>& block_run)
     h->total_blocks = (int)block_run.size();
 }
 
-// The tiled kernel can step a handle of one straight run without MHD (the
-// march serves batches, whose runs share one launch, and the D2Q5 scheme).
-bool tile_eligible(const goc_lbm* h) { return !h->m2d && h->nruns == 1 && !h->any_mhd; }
+// The tiled kernel can step a handle of one straight run (the march serves
+// batches, whose runs share one launch).
+bool tile_eligible(const goc_lbm* h) { return !h->m2d && h->nruns == 1; }
 // Rows of a tile of the tiled kernel for the handle's storage.
 int tile_rows(const goc_lbm* h) { return h->storage == GOC_F64 ? 4 : 8; }
 
@@ -1220,7 +1220,7 @@ int goc_lbm_set_launch(goc_lbm_t* h, double waves_per_cu)
     if (!check_handle(h)) return GOC_EINVAL;
     if (waves_per_cu == 0.0) {
         if (h->m2d) return GOC_OK;   // always tiled
-        if (!tile_eligible(h)) return fail(GOC_EINVAL, "the tiled step takes one straight run without MHD");
+        if (!tile_eligible(h)) return fail(GOC_EINVAL, "the tiled step takes a single run (not a batch)");
         return use_tiled(h);
     }
     if (h->m2d) return fail(GOC_EINVAL, "a run on a 2-D metric has only the tiled step (waves_per_cu 0)");

@@ -65,39 +65,59 @@ __device__ inline NodeMetric<T> curv_metric(const RunDesc& d, const Pools<S, FT>
     return g;
 }
 
+// Byte offset of the slot node (i, j) pulls for direction a, from the base
+// of a slot region (ghost row -1), as in the straight march: slot a of the
+// source node x - e_a, wrapped across a periodic xi1, in rows -1 .. ny (the
+// ghost rows hold what lies beyond the domain in xi2); through an xi1-wall
+// the node's own slot of the opposite direction.  The node's own offset plus
+// a work-group-uniform constant per direction, selected per lane at the xi1
+// edges.  The D2Q5 slots (a < 5) are pulled the same way, within their
+// component's five planes.
+template <class S>
+__device__ inline uint32_t pull_off(const RunDesc& d, const RunBytes& b, int i, int j, int a)
+{
+    const uint32_t cs = uint32_t(sizeof(S));
+    const uint32_t o = uint32_t(j + 1) * b.pitch_s + uint32_t(i) * cs;   // own node, plane 0
+    const int ex = ex_(a), ey = ey_(a);
+    uint32_t off = o + uint32_t(a) * b.plane_s - uint32_t(ey) * b.pitch_s - uint32_t(ex) * cs;
+    if (ex != 0) {
+        const bool out = ex > 0 ? i == 0 : i == d.nx - 1;
+        const uint32_t span = uint32_t(d.nx) * cs;
+        const uint32_t wrapped = ex > 0 ? off + span : off - span;
+        const uint32_t bounced = o + uint32_t(opp_(a)) * b.plane_s;
+        off = out ? (d.bc_x != 0 ? bounced : wrapped) : off;
+    }
+    return off;
+}
+
 // Pull and decode the nine deviations of node (i, j) and its lagged force
-// (planeF: one force plane in bytes).  Slot a is pulled, as in the straight
-// march, from the source node x - e_a, wrapped across a periodic xi1, in
-// rows -1 .. ny (the ghost rows hold what lies beyond the domain in xi2);
-// through an xi1-wall it is the node's own slot of the opposite direction.
-// Byte offsets from the base of the slot region (ghost row -1): the node's
-// own offset plus a work-group-uniform constant per direction, selected
-// per lane at the xi1 edges.
+// (planeF: one force plane in bytes).
 template <class S, class T, class FT>
 __device__ inline void curv_pull9(const RunDesc& d, const RunBytes& b, uint32_t planeF, int i, int j, T* f,
                                   T& Fp1, T& Fp2)
 {
     const T* sp = step_params<T>(d);
-    const uint32_t cs = uint32_t(sizeof(S));
-    const uint32_t o = uint32_t(j + 1) * b.pitch_s + uint32_t(i) * cs;   // own node, plane 0
-    const bool wall = d.bc_x != 0;
-    const uint32_t span = uint32_t(d.nx) * cs;
 #pragma unroll
     for (int a = 0; a < kQ; ++a) {
-        const int ex = ex_(a), ey = ey_(a);
-        uint32_t off = o + uint32_t(a) * b.plane_s - uint32_t(ey) * b.pitch_s - uint32_t(ex) * cs;
-        if (ex != 0) {
-            const bool out = ex > 0 ? i == 0 : i == d.nx - 1;
-            const uint32_t wrapped = ex > 0 ? off + span : off - span;
-            const uint32_t bounced = o + uint32_t(opp_(a)) * b.plane_s;
-            off = out ? (wall ? bounced : wrapped) : off;
-        }
         const T sinv = Store<S>::scaled ? sp[P_ISC + cls_(a)] : T(1);
-        f[a] = T(Store<S>::dec(ld_at<S>(b.f, off), sinv));
+        f[a] = T(Store<S>::dec(ld_at<S>(b.f, pull_off<S>(d, b, i, j, a)), sinv));
     }
     const uint32_t nf = uint32_t(j) * b.pitch_F + uint32_t(i) * uint32_t(sizeof(FT));
     Fp1 = T(ld_at<FT>(b.F, nf));
     Fp2 = T(ld_at<FT>(b.F, nf + planeF));
+}
+
+// Pull and decode the ten D2Q5 deviations of node (i, j) (sginv: the
+// inverse storage scale).
+template <class S, class T>
+__device__ inline void pull_g(const RunDesc& d, const RunBytes& b, int i, int j, T sginv, T (*dg)[kM])
+{
+#pragma unroll
+    for (int a = 0; a < kM; ++a) {
+        const uint32_t off = pull_off<S>(d, b, i, j, a);
+#pragma unroll
+        for (int ci = 0; ci < 2; ++ci) dg[ci][a] = T(Store<S>::dec(ld_at<S>(b.g, ci * b.g_comp + off), sginv));
+    }
 }
 
 // Moments of a pulled node, as the straight march forms them: dr = rho -
@@ -136,7 +156,7 @@ __device__ inline T tile_fd(V v, int l, int k, int n, bool periodic)
 // the eight XCDs in turn; the tiles are renumbered so that each XCD gets a
 // contiguous band of them (row-major), whose rings and cross-tile pulls its
 // L2 then serves.
-template <class S, int COLL, bool GEN>
+template <class S, int COLL, bool GEN, bool MHD>
 __global__ void __launch_bounds__(kCurvX * curv_rows<S>())
 tile_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename ForceOf<S>::type> pl,
                  const uint32_t* __restrict__ step_ctr, int k)
@@ -199,7 +219,7 @@ tile_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
     // GEN: the metric planes and the writer's rest-state offsets of the four
     // axis slots; otherwise the column and row tables of the straight grid
     // (the offsets a1+-, a2+- are scaled by h2 / h1 at the writes)
-    T aE, aW, aN, aS;
+    T aE, aW, aN, aS, b1p = 0, b1m = 0, b2p = 0, b2m = 0;
     NodeMetric<T> g;
     const T* ctab = table_of<T>(pl.col, pl.colf) + (int64_t)d.col_off * kTab;
     const T* rtab = table_of<T>(pl.row, pl.rowf) + (int64_t)d.row_off * kTab;
@@ -219,9 +239,19 @@ tile_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
         aW = ct[T_AM];
         aN = rt[T_AP];
         aS = rt[T_AM];
+        if constexpr (MHD) {
+            b1p = ct[T_BP];
+            b1m = ct[T_BM];
+            b2p = rt[T_BP];
+            b2m = rt[T_BM];
+        }
     }
+    static_assert(!(GEN && MHD), "the D2Q5 scheme runs on straight grids only");
     T f[kQ], Fp1, Fp2;
     curv_pull9<S, T, FT>(d, b, planeF, ic, jc, f, Fp1, Fp2);
+    T dg[2][kM];   // D2Q5 deviations (MHD)
+    const T sginv = Store<S>::scaled ? sp[P_ISCG] : T(1);
+    if constexpr (MHD) pull_g<S, T>(d, b, ic, jc, sginv, dg);
     if (ly * kCurvX < nh) {   // (uniform over the wave: one wave per row of the block)
         T hf[kQ], hF1, hF2;
         curv_pull9<S, T, FT>(d, b, planeF, hi, hj, hf, hF1, hF2);
@@ -252,13 +282,67 @@ tile_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
     const T d2U2 = tile_fd<T>([&](int r) { return sm[2][r][cx]; }, cy, j, ny, py);
     const T d2r = tile_fd<T>([&](int r) { return sm[0][r][cx]; }, cy, j, ny, py);
 
+    const bool wxlo = !px && i == 0, wxhi = !px && i == nx - 1;
+    const bool wylo = !py && j == 0, wyhi = !py && j == ny - 1;
+    const uint32_t seed = mix32(step_ctr[0] + uint32_t(k));
+    const uint32_t hn = mix32((uint32_t(d.f_off) + uint32_t(j) * uint32_t(d.pitch) + uint32_t(i)) ^ seed);
+    const uint32_t cs = uint32_t(sizeof(S));
+    const uint32_t own = uint32_t(j + 1) * b.pitch_s + uint32_t(i) * cs;   // (slot regions start at row -1)
+    const bool bot = j == 0, top = j == ny - 1;
+    // App. G, as the march: magnetic field, local derivatives, Lorentz
+    // force, the D2Q5 collision and writes (stored value = base + increment;
+    // anti-bounce-back slots negate the post-collision value; the writer adds
+    // the rest-state offsets of the interior axis slots of component 2)
+    T Fx1 = p.Fx1, Fx2 = p.Fx2;
+    if constexpr (MHD) {
+        T B1, B2, FL1, FL2, dgi[2][kM];
+        mie_node<T>(p, g, dg, U1, U2, B1, B2, FL1, FL2, dgi);
+        Fx1 += FL1;
+        Fx2 += FL2;
+        const T hh = g.h1 * g.h2;
+#pragma unroll
+        for (int a = 1; a < kM; ++a) {
+            const int ex = ex_(a), ey = ey_(a);
+            const bool wx = (ex > 0 && wxhi) || (ex < 0 && wxlo);
+            const bool wy = (ey > 0 && wyhi) || (ey < 0 && wylo);
+            if (wx || wy) {
+                // the reader (this node) sees -g~ + 2 W h_wall B_wall with B_wall = (0, B0)
+                const T hwall = wy ? g.h1 * sp[ey < 0 ? P_HWLO : P_HWHI] : sp[ex < 0 ? P_H1WLO : P_H1WHI] * g.h2;
+                dg[0][a] = -dg[0][a];
+                dgi[0][a] = -dgi[0][a];
+                dg[1][a] = -dg[1][a];
+                dgi[1][a] = -dgi[1][a] + T(2) * p.W1 * p.B0 * (hwall - hh);
+            } else {
+                dgi[1][a] += a == 1 ? g.h2 * b1p : a == 3 ? g.h2 * b1m : a == 2 ? g.h1 * b2p : g.h1 * b2m;
+            }
+        }
+        const T sgw = Store<S>::scaled ? sp[P_SCG] : T(1);
+        S eg[2][kM];
+#pragma unroll
+        for (int ci = 0; ci < 2; ++ci)
+#pragma unroll
+            for (int a = 0; a < kM; ++a) {
+                eg[ci][a] = Store<S>::enc(dg[ci][a], dgi[ci][a], sgw, pop_draw(hn, kQ + ci * kM + a));
+                st_at<S>(b.go, ci * b.g_comp + uint32_t(a) * b.plane_s + own, eg[ci][a]);
+            }
+        // ghost rows: plane 2 / 4 of each component, own column
+        if (bot || top) {
+            const bool wall = !py;
+            const uint32_t grow = (wall ? bot : top) ? 0u : uint32_t(ny + 1) * b.pitch_s;
+            const uint32_t pg = (wall == bot) ? 2u : 4u;
+#pragma unroll
+            for (int ci = 0; ci < 2; ++ci)
+                st_at<S>(b.go, grow + ci * b.g_comp + pg * b.plane_s + uint32_t(i) * cs, bot ? eg[ci][4] : eg[ci][2]);
+        }
+    }
+
     const RawDev<T> m = raw_dev<T>(f);
     T F1, F2, n3, n4, inc[kQ];
     if constexpr (GEN)
         force_and_corrections_gen<T>(p, g, rho, dr, U1, U2, d1U1, d2U2, d1r, d2r, p.Fx1, p.Fx2, m.m11, F1, F2,
                                      n3, n4);
     else
-        force_and_corrections<T>(p, g, rho, dr, U1, U2, d1U1, d2U2, d1r, d2r, p.Fx1, p.Fx2, F1, F2, n3, n4);
+        force_and_corrections<T>(p, g, rho, dr, U1, U2, d1U1, d2U2, d1r, d2r, Fx1, Fx2, F1, F2, n3, n4);
     if constexpr (COLL == kCollRaw)
         raw_collide<T>(p, g, m, rho, dr, U1, U2, Fp1, Fp2, F1, F2, n3, n4, inc);
     else
@@ -266,8 +350,6 @@ tile_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
 
     // writer side: rest-state offsets of the axis slots (their readers are the
     // neighbours; zero toward walls) and the wall terms of App. C
-    const bool wxlo = !px && i == 0, wxhi = !px && i == nx - 1;
-    const bool wylo = !py && j == 0, wyhi = !py && j == ny - 1;
     if constexpr (GEN) {
         inc[1] += aE;
         inc[3] += aW;
@@ -323,10 +405,6 @@ tile_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
 
     // stores: base + increment, rounded without bias (the same draws as the
     // straight march: node, population, step)
-    const uint32_t seed = mix32(step_ctr[0] + uint32_t(k));
-    const uint32_t hn = mix32((uint32_t(d.f_off) + uint32_t(j) * uint32_t(d.pitch) + uint32_t(i)) ^ seed);
-    const uint32_t cs = uint32_t(sizeof(S));
-    const uint32_t own = uint32_t(j + 1) * b.pitch_s + uint32_t(i) * cs;   // (slot regions start at row -1)
     S e[kQ];
 #pragma unroll
     for (int a = 0; a < kQ; ++a) {
@@ -339,7 +417,6 @@ tile_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
     // copies of the slots the opposite edge row pulls, into the ghost row
     // beyond that edge.  Planes: walls bottom {2, 5, 6}, top {4, 8, 7};
     // periodic bottom {4, 7, 8}, top {2, 6, 5}.
-    const bool bot = j == 0, top = j == ny - 1;
     if (bot || top) {
         const bool wall = !py;
         const uint32_t grow = (wall ? bot : top) ? 0u : uint32_t(ny + 1) * b.pitch_s;   // row -1 or ny

@@ -374,12 +374,16 @@ def test_batch_fp32_developed_1000_steps(oracle_lib):
 
 
 def test_autotuner_keeps_state_and_results():
-    """The launch-plan autotuner leaves the state untouched and any plan gives
-    bitwise the same steps (the rounding draws depend on node, population
-    and step only): a run tuned half-way equals an untuned one, for a
-    single run and for a batch of uneven runs."""
+    """The autotuner leaves the state untouched, and every launch plan of
+    the march gives bitwise the same steps (the rounding draws depend on
+    node, population and step only): a run re-planned half-way equals one
+    that kept its plan, for a single run and for a batch of uneven runs.
+    (The tiled step, which the tuner may also choose, agrees with the march
+    to rounding: tests/test_gpu_tiled.py.)"""
     case = W.hartmann_4096().replace(name="tune", nx=300, ny=130)
     a, b = B.Run(case), B.Run(case)
+    a.set_launch(16)
+    b.set_launch(16)
     a.step(50)
     before = a.populations()
     info = a.tune(5)
@@ -387,6 +391,7 @@ def test_autotuner_keeps_state_and_results():
     after = a.populations()
     for x, y in zip(before, after):
         assert np.array_equal(x, y)
+    a.set_launch(4)
     a.step(50)
     b.step(100)
     for x, y in zip(a.populations(), b.populations()):

@@ -1,18 +1,18 @@
-"""The tiled step on straight grids against the march.  A single straight run
-without MHD can be stepped by either kernel (one thread per node over LDS
-tiles, or one wave marching up a 64-column strip); both take the same
-arithmetic in the same order, up to where the compiler fuses a multiply and
-an add differently.  So one step from the same developed state stores the
-same values to rounding, measured at the largest stored value (a stored
-value may be a small difference of larger terms): a few eps in FP64 and
-FP32, two units in the 16-bit forms (where a stochastic rounding of nearly
-equal values can land on either neighbour); and in FP64 the fields still
-agree to 1e-12 after 201 steps.  (In FP32 and the 16-bit forms an ulp of difference changes the
-outcome of a stochastic rounding now and then, after which the two are
-independent random walks of the same size: the oracle parity of each is in
-the other GPU tests, through the tiled step, the default for such runs, and
-the march, which steps MHD runs and batches.)  Also the selection through
-goc_lbm_set_launch / goc_lbm_tune."""
+"""The tiled step on straight grids against the march.  A single straight
+run (with or without the D2Q5 scheme) can be stepped by either kernel (one
+thread per node over LDS tiles, or one wave marching up a 64-column strip);
+both take the same arithmetic in the same order, up to where the compiler
+fuses a multiply and an add differently.  So one step from the same
+developed state stores the same values to rounding, measured at the largest
+stored value (a stored value may be a small difference of larger terms): a
+few eps in FP64 and FP32, two units in the 16-bit forms (where a stochastic
+rounding of nearly equal values can land on either neighbour); and in FP64
+the fields still agree to 1e-12 after 201 steps.  (In FP32 and the 16-bit
+forms an ulp of difference changes the outcome of a stochastic rounding now
+and then, after which the two are independent random walks of the same
+size: the oracle parity of each is in the other GPU tests, through the tiled
+step, the default for single runs, and the march, which steps batches.)
+Also the selection through goc_lbm_set_launch / goc_lbm_tune."""
 import struct
 
 import numpy as np
@@ -32,6 +32,11 @@ def cav(nx, ny, storage, **kw):
 def periodic(nx, ny, storage, **kw):
     return W.Case("p", nx, ny, "periodic", "periodic", ("tanh", 0.8), ("tanh", 1.2), flow="free", tau=0.7,
                   body_force=(1e-6, -2e-6), storage=storage, **kw)
+
+
+def mhd(nx, ny, storage, **kw):
+    return W.Case("h", nx, ny, "periodic", "wall", ("uniform", 0.0), ("tanh", 3.0), flow="hartmann", Re=100.0,
+                  Ha=20.0, mhd=True, storage=storage, **kw)
 
 
 def edge(nx, ny, bcx, bcy, storage):
@@ -61,6 +66,15 @@ CASES = {
     "moving_xi1_walls": (W.Case("cxw", 127, 65, "wall", "wall", ("tanh", 1.5), ("tanh", 1.2), flow="free",
                                 tau=0.8, body_force=(0.0, 0.0), v_wall=(0.01, -0.005), storage="f64"),
                          None, 0.01),
+    "mhd_f64_ragged": (mhd(65, 33, "f64"), None, 0.0),
+    "mhd_f32_multi_tile": (mhd(200, 131, "f32"), None, 0.0),
+    "mhd_f16": (mhd(130, 70, "f16dev"), None, 0.0),
+    "mhd_bf16": (mhd(130, 70, "bf16dev"), None, 0.0),
+    "mhd_raw_f64": (mhd(65, 33, "f64", collision="raw"), None, 0.0),
+    "mhd_3x5": (W.Case("em", 3, 5, "periodic", "wall", ("uniform", 0.0), ("tanh", 0.5), flow="hartmann", Re=2.0,
+                       Ha=2.0, Ma=0.1, mhd=True, storage="f64"), None, 0.0),
+    "mhd_walls_all_round": (W.Case("mw", 40, 33, "wall", "wall", ("tanh", 1.0), ("tanh", 2.0), flow="hartmann",
+                                   Re=20.0, Ha=5.0, mhd=True, storage="f64"), None, 0.0),
 }
 
 
@@ -81,12 +95,14 @@ STORED = {"f64": (np.float64, np.float64), "f32": (np.float32, np.float32),
 
 
 def _stored(blob, storage):
-    """Raw populations (storage format) and lagged force of a checkpoint."""
-    _, _, _, _, _, step, fb, Fb, _ = HEADER.unpack_from(blob)
+    """Raw populations (storage format), lagged force and D2Q5 populations
+    (empty without MHD) of a checkpoint."""
+    _, _, _, _, _, step, fb, Fb, gb = HEADER.unpack_from(blob)
     tf, tF = STORED[storage]
     f = np.frombuffer(blob, dtype=tf, count=fb // np.dtype(tf).itemsize, offset=HEADER.size)
     F = np.frombuffer(blob, dtype=tF, count=Fb // np.dtype(tF).itemsize, offset=HEADER.size + fb)
-    return step, f, F
+    g = np.frombuffer(blob, dtype=tf, count=gb // np.dtype(tf).itemsize, offset=HEADER.size + fb + Fb)
+    return step, np.concatenate([f, g]), F
 
 
 # a few units of rounding: eps of FP64 / FP32, one unit of the 16-bit forms
@@ -160,10 +176,14 @@ def test_fp64_agrees_with_march_after_201_steps(name):
     print(name, {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
     for k, v in e.items():
         assert v < 1e-12, (k, e)
-    ft, Ft, _ = t.populations()
-    fm, Fm, _ = m.populations()
+    ft, Ft, gt = t.populations()
+    fm, Fm, gm = m.populations()
     assert np.max(np.abs(ft - fm)) < 1e-13 * np.max(np.abs(fm))
     assert np.max(np.abs(Ft - Fm)) < 1e-12 * max(np.max(np.abs(Fm)), 1e-300)
+    if case.mhd:
+        assert np.max(np.abs(gt - gm)) < 1e-13 * np.max(np.abs(gm))
+        for k in ("B1", "B2"):
+            assert np.linalg.norm(a[k] - b[k]) <= 1e-12 * np.linalg.norm(np.hypot(b["B1"], b["B2"])), k
     t.close()
     m.close()
 
@@ -182,19 +202,21 @@ def test_default_and_tuner_selection():
 
 
 def test_tiled_refused_where_it_does_not_apply():
-    """MHD runs and batches keep the march: waves_per_cu 0 is refused there;
-    a run on a 2-D metric has only the tiled step."""
-    h = B.Run(W.Case("h", 65, 33, "periodic", "wall", ("uniform", 0.0), ("tanh", 3.0), flow="hartmann",
-                     Re=100.0, Ha=20.0, mhd=True, storage="f64"))
-    assert h.launch_info()["waves_per_cu"] > 0
-    with pytest.raises(B.GocError) as ei:
-        h.set_launch(0)
-    assert ei.value.code == B.GOC_EINVAL
+    """Batches keep the march (their runs share one launch): waves_per_cu 0
+    is refused there; a single MHD run takes either form; a run on a 2-D
+    metric has only the tiled step."""
+    h = B.Run(mhd(65, 33, "f64"))
+    assert h.launch_info()["waves_per_cu"] == 0
+    h.set_launch(8)
+    assert h.launch_info()["waves_per_cu"] == 8
+    h.set_launch(0)
+    assert h.launch_info()["waves_per_cu"] == 0
     h.close()
     b = B.Run(batch=[cav(70, 45, "f64"), cav(40, 33, "f64")])
     assert b.launch_info()["waves_per_cu"] > 0
-    with pytest.raises(B.GocError):
+    with pytest.raises(B.GocError) as ei:
         b.set_launch(0)
+    assert ei.value.code == B.GOC_EINVAL
     b.close()
     c = B.Run(W.taylor_couette(n1=32, n2=6, R1=8.0, n_theta=20.0))
     assert c.launch_info()["waves_per_cu"] == 0
