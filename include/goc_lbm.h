@@ -251,13 +251,13 @@ int goc_lbm_set_watchdog(goc_lbm_t *h, int64_t every);
      in proportion to its nodes so that the launch holds about waves_per_cu
      work-groups per compute unit (default 16; fewer where a run has too
      few row groups).  Fewer, longer segments re-read fewer halo rows; more
-     segments fill the chip and balance uneven batches.  It steps every
-     handle on straight metrics (batches and MHD runs always);
+     segments fill the chip and balance uneven batches.  It can step every
+     handle on straight metrics (batches always);
    - the tiled step: one thread per node, 64 x 8 nodes per work-group (64 x
      4 in FP64), the moments of the tile and its ring in LDS.  It steps a
-     single straight run without MHD (chosen by default there: it is the
-     faster form on most sizes) and every run on a 2-D metric (its only
-     form).  The two forms agree to rounding.
+     single straight run, with or without MHD (chosen by default there: it
+     is the faster form on most sizes), and every run on a 2-D metric (its
+     only form).  The two forms agree to rounding.
    goc_lbm_set_launch: waves_per_cu = 0 selects the tiled step (GOC_EINVAL
    where it does not apply); waves_per_cu in [0.5, 1024] the march with that
    plan (GOC_EINVAL outside, and on a 2-D metric).  Synchronous.
