@@ -367,12 +367,12 @@ int launch_step(goc_lbm* h, int k)
         using S = decltype(tag);
         const auto pl = pools<S>(h, h->cur);
         if (h->m2d || h->tiled) {   // tiled step: one launch per run
-            constexpr int cy = goc::curv_rows<S>();
+            constexpr int cy = goc::tile_rows_of<S>();
             const bool raw = h->coll == goc::kCollRaw;
             for (int r = 0; r < h->nruns; ++r) {
                 const RunDesc& d = h->runs[r];
-                const dim3 cg(((d.nx + goc::kCurvX - 1) / goc::kCurvX) * ((d.ny + cy - 1) / cy));
-                const dim3 cb(goc::kCurvX, cy);
+                const dim3 cg(((d.nx + goc::kTileX - 1) / goc::kTileX) * ((d.ny + cy - 1) / cy));
+                const dim3 cb(goc::kTileX, cy);
                 auto go = [&](auto kernel) {
                     hipLaunchKernelGGL(kernel, cg, cb, 0, h->stream, h->runs_d, r, pl, h->step_ctr, k);
                 };
@@ -1242,7 +1242,7 @@ int goc_lbm_launch_info(const goc_lbm_t* h, double out[4])
         const int ty = tile_rows(h);
         int64_t tiles = 0, cols = 0;
         for (const RunDesc& d : h->runs) {
-            const int64_t gx = (d.nx + goc::kCurvX - 1) / goc::kCurvX;
+            const int64_t gx = (d.nx + goc::kTileX - 1) / goc::kTileX;
             tiles += gx * ((d.ny + ty - 1) / ty);
             cols += gx;
         }

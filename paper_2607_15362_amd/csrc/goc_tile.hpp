@@ -1,31 +1,35 @@
-// goc_curv.hpp -- the time step on a general orthogonal grid.
+// goc_tile.hpp -- the tiled time step: one thread per node over LDS tiles.
 //
-// A run whose metric factors vary with both coordinates (h1(xi1, xi2),
-// h2(xi1, xi2); theta12, theta21 != 0: curvilinear body-fitted grids such as
-// the conformal annular sector) keeps the slot layout, the deviation
-// storage and the writer-side boundary conditions of the straight path, with
-// the metric read per node from a pool of planes (goc_device.hpp: M_*).  A
-// step is one launch of one thread per node over 64 x 8 tiles (64 x 4 in
-// FP64): pull, decode and the moments rho - rho0, U1, U2 (App. E step 7,
-// lagged force) of the tile and of the ring of nodes around it into LDS;
-// the second-order
-// differences of U and rho from LDS (one-sided next to walls, wrapped when
-// periodic); the general stresses and effective force with the local shear
-// stress (Sec. 2.2, App. A), the corrections of Sec. 5 with their curvature
-// terms, the collision, and the writes of the nine slots, their ghost-row
-// copies and the force.  The ring is pulled twice (by this tile and by its
-// owner), which costs L2 reads, not HBM traffic.  The D2Q5 induction scheme
-// is not part of this path (the library refuses MHD runs on 2-D metrics).
+// The same step as the march of goc_step.hpp (App. E, every node once),
+// organised for parallelism instead of in-register reuse: a work-group owns
+// a tile of 64 x 8 nodes (64 x 4 in FP64) and steps it in one pass.  Pull,
+// decode and the moments rho - rho0, U1, U2 (App. E step 7, lagged force)
+// of the tile and of the ring of nodes around it go to LDS; after one
+// barrier the second-order differences of U and rho come from LDS
+// (one-sided next to walls, wrapped when periodic); then the stresses and
+// effective force (Sec. 2.2, App. A), the corrections of Sec. 5, the
+// collision and the writes of the nine slots, their ghost-row copies and
+// the force.  The ring is pulled twice (by this tile and by its owner),
+// which costs L2 reads, not HBM traffic.  Two metric sources:
+//  - GEN: a run whose metric factors vary with both coordinates (h1(xi1,
+//    xi2), h2(xi1, xi2); theta12, theta21 != 0: curvilinear body-fitted
+//    grids such as the conformal annular sector) reads its metric per node
+//    from a pool of planes (goc_device.hpp: M_*), with the general stresses,
+//    the local shear stress and the curvature terms of the corrections;
+//  - otherwise the column and row tables of a straight grid and the march's
+//    arithmetic, including (MHD) the D2Q5 scheme of App. G, whose node work
+//    is local.  The D2Q5 scheme does not run on 2-D metrics (the library
+//    refuses MHD runs there).
 #pragma once
 
 #include "goc_step.hpp"
 
 namespace goc {
 
-constexpr int kCurvX = 64;   // work-group tile: 64 columns x curv_rows<S>() rows
+constexpr int kTileX = 64;   // work-group tile: 64 columns x tile_rows_of<S>() rows
 // 8 rows; 4 for FP64 storage, whose register count leaves room for fewer
 // waves per CU
-template <class S> constexpr int curv_rows() { return sizeof(S) == 8 ? 4 : 8; }
+template <class S> constexpr int tile_rows_of() { return sizeof(S) == 8 ? 4 : 8; }
 
 // A value at a lane's 32-bit byte offset from a work-group-uniform base:
 // the hardware forms such an address from a scalar base and a vector
@@ -45,7 +49,7 @@ __device__ inline void st_at(void* base, uint32_t off, V v)
 // Metric of a node of a 2-D run in the compute type: nb = its node index
 // times sizeof(T), NB = one plane of the run in bytes.
 template <class T, class S, class FT>
-__device__ inline NodeMetric<T> curv_metric(const RunDesc& d, const Pools<S, FT>& pl, uint32_t nb, int64_t NB,
+__device__ inline NodeMetric<T> tile_metric2d(const RunDesc& d, const Pools<S, FT>& pl, uint32_t nb, int64_t NB,
                                             T& aE, T& aW, T& aN, T& aS)
 {
     const char* m = reinterpret_cast<const char*>(table_of<T>(pl.met, pl.metf) + d.met_off);
@@ -93,7 +97,7 @@ __device__ inline uint32_t pull_off(const RunDesc& d, const RunBytes& b, int i, 
 // Pull and decode the nine deviations of node (i, j) and its lagged force
 // (planeF: one force plane in bytes).
 template <class S, class T, class FT>
-__device__ inline void curv_pull9(const RunDesc& d, const RunBytes& b, uint32_t planeF, int i, int j, T* f,
+__device__ inline void tile_pull9(const RunDesc& d, const RunBytes& b, uint32_t planeF, int i, int j, T* f,
                                   T& Fp1, T& Fp2)
 {
     const T* sp = step_params<T>(d);
@@ -123,7 +127,7 @@ __device__ inline void pull_g(const RunDesc& d, const RunBytes& b, int i, int j,
 // Moments of a pulled node, as the straight march forms them: dr = rho -
 // rho0 = dm00/(h1 h2), U1 = (dm10 + F1/2)/(rho h2), U2 = (dm01 + F2/2)/(rho h1).
 template <class T>
-__device__ inline void curv_moments(const T* f, T Fp1, T Fp2, T rho0, T ih1, T ih2, T& dr, T& U1, T& U2)
+__device__ inline void tile_moments(const T* f, T Fp1, T Fp2, T rho0, T ih1, T ih2, T& dr, T& U1, T& U2)
 {
     const T m00 = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
     const T m10 = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
@@ -147,7 +151,7 @@ __device__ inline T tile_fd(V v, int l, int k, int n, bool periodic)
 }
 
 // The step of every node of one run.  Launch: grid ceil(nx/64) * ceil(ny/Y)
-// work-groups (1-D), block (64, Y), Y = curv_rows<S>().  A work-group owns
+// work-groups (1-D), block (64, Y), Y = tile_rows_of<S>().  A work-group owns
 // the 64 x Y nodes of tile (bx, by) at (64 bx, Y by); its tile is shifted back at the
 // far edges of the grid so that the three nodes of a one-sided difference
 // lie in it (nodes of the shifted part belong to the neighbouring
@@ -157,21 +161,21 @@ __device__ inline T tile_fd(V v, int l, int k, int n, bool periodic)
 // contiguous band of them (row-major), whose rings and cross-tile pulls its
 // L2 then serves.
 template <class S, int COLL, bool GEN, bool MHD>
-__global__ void __launch_bounds__(kCurvX * curv_rows<S>())
+__global__ void __launch_bounds__(kTileX * tile_rows_of<S>())
 tile_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename ForceOf<S>::type> pl,
                  const uint32_t* __restrict__ step_ctr, int k)
 {
     using T = typename ComputeOf<S>::type;
     using FT = typename ForceOf<S>::type;
-    constexpr int kCurvY = curv_rows<S>();
-    __shared__ T sm[3][kCurvY + 2][kCurvX + 2];   // rho - rho0, U1, U2 of the tile and its ring
+    constexpr int kTileY = tile_rows_of<S>();
+    __shared__ T sm[3][kTileY + 2][kTileX + 2];   // rho - rho0, U1, U2 of the tile and its ring
     const RunDesc& d = runs[run];
     const int nx = d.nx, ny = d.ny;
-    const int tx = nx < kCurvX ? nx : kCurvX, ty = ny < kCurvY ? ny : kCurvY;   // tile extent
-    const int gx = (nx + kCurvX - 1) / kCurvX, nt = gx * ((ny + kCurvY - 1) / kCurvY);
+    const int tx = nx < kTileX ? nx : kTileX, ty = ny < kTileY ? ny : kTileY;   // tile extent
+    const int gx = (nx + kTileX - 1) / kTileX, nt = gx * ((ny + kTileY - 1) / kTileY);
     const int xcd = blockIdx.x & 7, q = nt >> 3, rem = nt & 7;
     const int t = xcd * q + min(xcd, rem) + (int)(blockIdx.x >> 3);   // tile of this work-group
-    const int ox = (t % gx) * kCurvX, oy = (t / gx) * kCurvY;          // first owned node
+    const int ox = (t % gx) * kTileX, oy = (t / gx) * kTileY;          // first owned node
     const int x0 = ox < nx - tx ? ox : nx - tx, y0 = oy < ny - ty ? oy : ny - ty;   // tile origin
     const int lx = threadIdx.x, ly = threadIdx.y;
     const int i = x0 + lx, j = y0 + ly;
@@ -191,8 +195,8 @@ tile_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
     // reach the corners); wrapped across a periodic edge, absent beyond a
     // wall.  Ring node h goes to thread h in order (whole rows of the ring
     // per wave: contiguous loads), and the waves beyond the ring skip it.
-    static_assert(2 * kCurvX + 2 * kCurvY <= kCurvX * kCurvY, "one ring node per thread");
-    const int h = ly * kCurvX + lx, nh = 2 * tx + 2 * ty;
+    static_assert(2 * kTileX + 2 * kTileY <= kTileX * kTileY, "one ring node per thread");
+    const int h = ly * kTileX + lx, nh = 2 * tx + 2 * ty;
     int hx, hy;
     if (h < 2 * tx) {
         hx = h < tx ? h : h - tx;
@@ -224,7 +228,7 @@ tile_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
     const T* ctab = table_of<T>(pl.col, pl.colf) + (int64_t)d.col_off * kTab;
     const T* rtab = table_of<T>(pl.row, pl.rowf) + (int64_t)d.row_off * kTab;
     if constexpr (GEN) {
-        g = curv_metric<T>(d, pl, uint32_t(jc * nx + ic) * uint32_t(sizeof(T)), NB, aE, aW, aN, aS);
+        g = tile_metric2d<T>(d, pl, uint32_t(jc * nx + ic) * uint32_t(sizeof(T)), NB, aE, aW, aN, aS);
     } else {
         const T* ct = ctab + ic * kTab;
         const T* rt = rtab + jc * kTab;
@@ -248,17 +252,17 @@ tile_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
     }
     static_assert(!(GEN && MHD), "the D2Q5 scheme runs on straight grids only");
     T f[kQ], Fp1, Fp2;
-    curv_pull9<S, T, FT>(d, b, planeF, ic, jc, f, Fp1, Fp2);
+    tile_pull9<S, T, FT>(d, b, planeF, ic, jc, f, Fp1, Fp2);
     T dg[2][kM];   // D2Q5 deviations (MHD)
     const T sginv = Store<S>::scaled ? sp[P_ISCG] : T(1);
     if constexpr (MHD) pull_g<S, T>(d, b, ic, jc, sginv, dg);
-    if (ly * kCurvX < nh) {   // (uniform over the wave: one wave per row of the block)
+    if (ly * kTileX < nh) {   // (uniform over the wave: one wave per row of the block)
         T hf[kQ], hF1, hF2;
-        curv_pull9<S, T, FT>(d, b, planeF, hi, hj, hf, hF1, hF2);
+        tile_pull9<S, T, FT>(d, b, planeF, hi, hj, hf, hF1, hF2);
         const T hih1 = GEN ? ld_at<T>(mt + M_IH1 * NB, hnb) : ctab[hi * kTab + T_IH];
         const T hih2 = GEN ? ld_at<T>(mt + M_IH2 * NB, hnb) : rtab[hj * kTab + T_IH];
         T hdr, hU1, hU2;
-        curv_moments<T>(hf, hF1, hF2, p.rho0, hih1, hih2, hdr, hU1, hU2);
+        tile_moments<T>(hf, hF1, hF2, p.rho0, hih1, hih2, hdr, hU1, hU2);
         if (hv) {
             sm[0][hy + 1][hx + 1] = hdr;
             sm[1][hy + 1][hx + 1] = hU1;
@@ -266,7 +270,7 @@ tile_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
         }
     }
     T dr, U1, U2;
-    curv_moments<T>(f, Fp1, Fp2, p.rho0, g.ih1, g.ih2, dr, U1, U2);
+    tile_moments<T>(f, Fp1, Fp2, p.rho0, g.ih1, g.ih2, dr, U1, U2);
     if (in) {
         sm[0][ly + 1][lx + 1] = dr;
         sm[1][ly + 1][lx + 1] = U1;
