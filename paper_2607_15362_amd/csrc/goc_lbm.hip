@@ -317,7 +317,9 @@ struct goc_lbm {
     uint32_t* step_ctr = nullptr;   // device: index of the next step's rounding draws
     int ncu = 256;                  // compute units of the device
     double waves_per_cu = 16.0;     // launch plan: work-groups per CU over the whole launch
-    bool tiled = false;             // straight single run stepped by the tiled kernel instead of the march
+    bool tiled = false;             // straight runs stepped by the tiled kernel instead of the march
+    int32_t* tile_first_d = nullptr;   // device: first tile of each run of the tiled kernel, then the total
+    int32_t total_tiles = 0;
     int block_cap = 0;              // capacity of block_run_d (entries)
 };
 
@@ -366,26 +368,23 @@ int launch_step(goc_lbm* h, int k)
     return dispatch(h->storage, [&](auto tag) -> int {
         using S = decltype(tag);
         const auto pl = pools<S>(h, h->cur);
-        if (h->m2d || h->tiled) {   // tiled step: one launch per run
+        if (h->m2d || h->tiled) {   // tiled step: one launch for every run
             constexpr int cy = goc::tile_rows_of<S>();
             const bool raw = h->coll == goc::kCollRaw;
-            for (int r = 0; r < h->nruns; ++r) {
-                const RunDesc& d = h->runs[r];
-                const dim3 cg(((d.nx + goc::kTileX - 1) / goc::kTileX) * ((d.ny + cy - 1) / cy));
-                const dim3 cb(goc::kTileX, cy);
-                auto go = [&](auto kernel) {
-                    hipLaunchKernelGGL(kernel, cg, cb, 0, h->stream, h->runs_d, r, pl, h->step_ctr, k);
-                };
-                if (h->m2d)
-                    raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, true, false>)
-                        : go(goc::tile_step_kernel<S, goc::kCollCentral, true, false>);
-                else if (h->any_mhd)
-                    raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, false, true>)
-                        : go(goc::tile_step_kernel<S, goc::kCollCentral, false, true>);
-                else
-                    raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, false, false>)
-                        : go(goc::tile_step_kernel<S, goc::kCollCentral, false, false>);
-            }
+            const dim3 cg(h->total_tiles), cb(goc::kTileX, cy);
+            auto go = [&](auto kernel) {
+                hipLaunchKernelGGL(kernel, cg, cb, 0, h->stream, h->runs_d, h->tile_first_d, h->nruns, pl,
+                                   h->step_ctr, k);
+            };
+            if (h->m2d)
+                raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, true, false>)
+                    : go(goc::tile_step_kernel<S, goc::kCollCentral, true, false>);
+            else if (h->any_mhd)
+                raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, false, true>)
+                    : go(goc::tile_step_kernel<S, goc::kCollCentral, false, true>);
+            else
+                raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, false, false>)
+                    : go(goc::tile_step_kernel<S, goc::kCollCentral, false, false>);
             HIPOK(hipGetLastError());
             return GOC_OK;
         }
@@ -447,6 +446,7 @@ int free_all(goc_lbm* h)
     (void)hipFree(h->met_d);
     (void)hipFree(h->metf_d);
     (void)hipFree(h->face_d);
+    (void)hipFree(h->tile_first_d);
     return GOC_OK;
 }
 
@@ -499,9 +499,9 @@ void plan_rows(goc_lbm* h, std::vector<int32_t>& block_run)
     h->total_blocks = (int)block_run.size();
 }
 
-// The tiled kernel can step a handle of one straight run (the march serves
-// batches, whose runs share one launch).
-bool tile_eligible(const goc_lbm* h) { return !h->m2d && h->nruns == 1; }
+// The tiled kernel can step every handle on straight metrics (and is the
+// only form on 2-D metrics).
+bool tile_eligible(const goc_lbm* h) { return !h->m2d; }
 // Rows of a tile of the tiled kernel for the handle's storage.
 int tile_rows(const goc_lbm* h) { return h->storage == GOC_F64 ? 4 : 8; }
 
@@ -683,7 +683,7 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
     h->ncu = ncu;
     plan_rows(h, block_run);
     h->block_cap = (int)block_run.size();
-    h->tiled = tile_eligible(h);   // the faster form for a single straight run
+    h->tiled = tile_eligible(h) && nruns == 1;   // the faster form for a single straight run
     h->f_elems = f_elems;
     h->F_elems = F_elems;
     h->g_elems = g_elems;
@@ -800,12 +800,22 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
             hipMemcpy(th2.data(), h->th22_d, sum_ny * 8, hipMemcpyDeviceToHost) != hipSuccess)
             return bail(fail(GOC_EDEVICE, "metric download failed"));
     }
-    // run table and work list
+    // run table, work list of the march and first tiles of the tiled step
+    std::vector<int32_t> tile_first(nruns + 1, 0);
+    for (int r = 0; r < nruns; ++r) {
+        const int64_t gx = (grid[r].nx + goc::kTileX - 1) / goc::kTileX;
+        const int64_t nt = gx * ((grid[r].ny + tile_rows(h) - 1) / tile_rows(h));
+        if ((int64_t)tile_first[r] + nt > INT32_MAX) return bail(fail(GOC_EINVAL, "too many tiles in the launch"));
+        tile_first[r + 1] = tile_first[r] + (int32_t)nt;
+    }
+    h->total_tiles = tile_first[nruns];
     if ((rc = dev_alloc((void**)&h->runs_d, nruns * sizeof(RunDesc))) ||
-        (rc = dev_alloc((void**)&h->block_run_d, block_run.size() * 4)))
+        (rc = dev_alloc((void**)&h->block_run_d, block_run.size() * 4)) ||
+        (rc = dev_alloc((void**)&h->tile_first_d, (nruns + 1) * 4)))
         return bail(rc);
     if (hipMemcpy(h->runs_d, h->runs.data(), nruns * sizeof(RunDesc), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(h->block_run_d, block_run.data(), block_run.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(h->block_run_d, block_run.data(), block_run.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->tile_first_d, tile_first.data(), (nruns + 1) * 4, hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(GOC_EDEVICE, "run table upload failed"));
     if ((rc = dev_alloc((void**)&h->step_ctr, 4))) return bail(rc);
     // state pools
@@ -1220,7 +1230,6 @@ int goc_lbm_set_launch(goc_lbm_t* h, double waves_per_cu)
     if (!check_handle(h)) return GOC_EINVAL;
     if (waves_per_cu == 0.0) {
         if (h->m2d) return GOC_OK;   // always tiled
-        if (!tile_eligible(h)) return fail(GOC_EINVAL, "the tiled step takes a single run (not a batch)");
         return use_tiled(h);
     }
     if (h->m2d) return fail(GOC_EINVAL, "a run on a 2-D metric has only the tiled step (waves_per_cu 0)");

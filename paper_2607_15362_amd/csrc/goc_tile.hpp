@@ -150,32 +150,46 @@ __device__ inline T tile_fd(V v, int l, int k, int n, bool periodic)
     return T(0.5) * (v(l + 1) - v(l - 1));
 }
 
-// The step of every node of one run.  Launch: grid ceil(nx/64) * ceil(ny/Y)
-// work-groups (1-D), block (64, Y), Y = tile_rows_of<S>().  A work-group owns
-// the 64 x Y nodes of tile (bx, by) at (64 bx, Y by); its tile is shifted back at the
+// The step of every node of every run.  Launch: grid = the tiles of all
+// runs (1-D), block (64, Y), Y = tile_rows_of<S>(); tile_first[r] = the
+// first tile of run r (tile_first[nruns] = all tiles), a run's tiles being
+// ceil(nx/64) * ceil(ny/Y) in row-major order.  A work-group owns the 64 x Y
+// nodes of tile (bx, by) of its run at (64 bx, Y by); its tile is shifted back at the
 // far edges of the grid so that the three nodes of a one-sided difference
 // lie in it (nodes of the shifted part belong to the neighbouring
 // work-group and are not written here).  The moments of the tile and of the
 // ring around it go to LDS.  The hardware deals consecutive work-groups to
 // the eight XCDs in turn; the tiles are renumbered so that each XCD gets a
-// contiguous band of them (row-major), whose rings and cross-tile pulls its
-// L2 then serves.
+// contiguous band of them (run by run, row-major), whose rings and
+// cross-tile pulls its L2 then serves.
 template <class S, int COLL, bool GEN, bool MHD>
 __global__ void __launch_bounds__(kTileX * tile_rows_of<S>())
-tile_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename ForceOf<S>::type> pl,
-                 const uint32_t* __restrict__ step_ctr, int k)
+tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ tile_first, int nruns,
+                 Pools<S, typename ForceOf<S>::type> pl, const uint32_t* __restrict__ step_ctr, int k)
 {
     using T = typename ComputeOf<S>::type;
     using FT = typename ForceOf<S>::type;
     constexpr int kTileY = tile_rows_of<S>();
     __shared__ T sm[3][kTileY + 2][kTileX + 2];   // rho - rho0, U1, U2 of the tile and its ring
+    // tile of this work-group over all runs, in XCD bands, then its run (the
+    // last whose first tile is not beyond it) and its place in the run
+    const int nt = tile_first[nruns];
+    const int xcd = blockIdx.x & 7, q = nt >> 3, rem = nt & 7;
+    const int tg = xcd * q + min(xcd, rem) + (int)(blockIdx.x >> 3);
+    int rlo = 0, rhi = nruns - 1;
+    while (rlo < rhi) {
+        const int mid = (rlo + rhi + 1) >> 1;
+        if (tile_first[mid] <= tg) rlo = mid;
+        else rhi = mid - 1;
+    }
+    const int run = rlo;
+    const int t = tg - tile_first[run];
     const RunDesc& d = runs[run];
     const int nx = d.nx, ny = d.ny;
     const int tx = nx < kTileX ? nx : kTileX, ty = ny < kTileY ? ny : kTileY;   // tile extent
-    const int gx = (nx + kTileX - 1) / kTileX, nt = gx * ((ny + kTileY - 1) / kTileY);
-    const int xcd = blockIdx.x & 7, q = nt >> 3, rem = nt & 7;
-    const int t = xcd * q + min(xcd, rem) + (int)(blockIdx.x >> 3);   // tile of this work-group
+    const int gx = (nx + kTileX - 1) / kTileX;
     const int ox = (t % gx) * kTileX, oy = (t / gx) * kTileY;          // first owned node
+    const bool mhd_run = MHD && d.mhd;   // (a plain run of a mixed batch: no D2Q5 work)
     const int x0 = ox < nx - tx ? ox : nx - tx, y0 = oy < ny - ty ? oy : ny - ty;   // tile origin
     const int lx = threadIdx.x, ly = threadIdx.y;
     const int i = x0 + lx, j = y0 + ly;
@@ -255,7 +269,7 @@ tile_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
     tile_pull9<S, T, FT>(d, b, planeF, ic, jc, f, Fp1, Fp2);
     T dg[2][kM];   // D2Q5 deviations (MHD)
     const T sginv = Store<S>::scaled ? sp[P_ISCG] : T(1);
-    if constexpr (MHD) pull_g<S, T>(d, b, ic, jc, sginv, dg);
+    if (mhd_run) pull_g<S, T>(d, b, ic, jc, sginv, dg);
     if (ly * kTileX < nh) {   // (uniform over the wave: one wave per row of the block)
         T hf[kQ], hF1, hF2;
         tile_pull9<S, T, FT>(d, b, planeF, hi, hj, hf, hF1, hF2);
@@ -298,7 +312,7 @@ tile_step_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename Fo
     // anti-bounce-back slots negate the post-collision value; the writer adds
     // the rest-state offsets of the interior axis slots of component 2)
     T Fx1 = p.Fx1, Fx2 = p.Fx2;
-    if constexpr (MHD) {
+    if (mhd_run) {
         T B1, B2, FL1, FL2, dgi[2][kM];
         mie_node<T>(p, g, dg, U1, U2, B1, B2, FL1, FL2, dgi);
         Fx1 += FL1;

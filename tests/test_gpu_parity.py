@@ -404,8 +404,13 @@ def test_autotuner_keeps_state_and_results():
         assert np.array_equal(x, y)
     runs = W.batch_256(n=6)
     c, e = B.Run(batch=runs), B.Run(batch=runs)
+    c.set_launch(16)
+    e.set_launch(16)
     c.step(20)
+    before = c.get_state()
     c.tune(3)
+    assert c.get_state() == before
+    c.set_launch(64)
     c.step(20)
     e.step(40)
     for r in range(len(runs)):

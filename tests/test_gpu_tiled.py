@@ -11,8 +11,9 @@ the fields still agree to 1e-12 after 201 steps.  (In FP32 and the 16-bit
 forms an ulp of difference changes the outcome of a stochastic rounding now
 and then, after which the two are independent random walks of the same
 size: the oracle parity of each is in the other GPU tests, through the tiled
-step, the default for single runs, and the march, which steps batches.)
-Also the selection through goc_lbm_set_launch / goc_lbm_tune."""
+step, the default for single runs, and the march, the default for batches.)
+Batches of uneven runs (plain and MHD in one launch) likewise.  Also the
+selection through goc_lbm_set_launch / goc_lbm_tune."""
 import struct
 
 import numpy as np
@@ -201,9 +202,67 @@ def test_default_and_tuner_selection():
     r.close()
 
 
-def test_tiled_refused_where_it_does_not_apply():
-    """Batches keep the march (their runs share one launch): waves_per_cu 0
-    is refused there; a single MHD run takes either form; a run on a 2-D
+BATCHES = {
+    "batch_mixed_f64": [cav(70, 45, "f64"), mhd(65, 33, "f64"), cav(130, 70, "f64"), mhd(200, 67, "f64"),
+                        edge(3, 3, "wall", "wall", "f64")],
+    "batch_hartmann_f32": W.batch_256(n=6),
+    "batch_hartmann_f16": [c.replace(storage="f16dev") for c in W.batch_256(n=5)],
+}
+
+
+@pytest.mark.parametrize("name", list(BATCHES))
+def test_batch_one_step_within_rounding_of_march(name):
+    """A batch of uneven runs (plain and MHD in one launch) in one tiled
+    launch against the march, one step from the same developed state."""
+    runs = BATCHES[name]
+    storage = runs[0].storage
+    print("tiled vs march, batch:", name, len(runs), storage, flush=True)
+    m = B.Run(batch=runs)
+    assert m.launch_info()["waves_per_cu"] > 0   # batches start on the march
+    m.step(120)
+    t = B.Run(batch=runs)
+    t.set_launch(0)
+    t.set_state(m.get_state())
+    t.step(1)
+    m.step(1)
+    st, ft, Ft = _stored(t.get_state(), storage)
+    sm, fm, Fm = _stored(m.get_state(), storage)
+    assert st == sm == 121
+    d = np.abs(_ordered(ft) - _ordered(fm))
+    print(name, "max ulps", int(d.max()), "differing", f"{np.count_nonzero(d) / d.size:.3%}", flush=True)
+    assert np.count_nonzero(d) <= 0.25 * d.size
+    vt, vm = _values(ft, storage), _values(fm, storage)
+    assert np.max(np.abs(vt - vm)) <= LIMIT[storage] * np.max(np.abs(vm))
+    t.close()
+    m.close()
+
+
+def test_batch_fp64_agrees_with_march_after_201_steps():
+    runs = BATCHES["batch_mixed_f64"]
+    t, m = B.Run(batch=runs), B.Run(batch=runs)
+    t.set_launch(0)
+    for steps in (1, 40, 160):
+        t.step(steps)
+        m.step(steps)
+    for r, case in enumerate(runs):
+        a, b = t.fields(run=r), m.fields(run=r)
+        un = np.linalg.norm(np.hypot(b["U1"], b["U2"]))
+        e = {"rho": float(np.linalg.norm(a["rho"] - b["rho"]) / np.linalg.norm(b["rho"])),
+             "U1": float(np.linalg.norm(a["U1"] - b["U1"]) / un),
+             "U2": float(np.linalg.norm(a["U2"] - b["U2"]) / un)}
+        if case.mhd:
+            bn = np.linalg.norm(np.hypot(b["B1"], b["B2"]))
+            e["B"] = float(np.linalg.norm(np.hypot(a["B1"] - b["B1"], a["B2"] - b["B2"])) / bn)
+        print(r, case.name, {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+        for k, v in e.items():
+            assert v < 1e-12, (r, k, e)
+    t.close()
+    m.close()
+
+
+def test_selection_of_the_form():
+    """Single straight runs start on the tiled step, batches on the march;
+    either takes the other through goc_lbm_set_launch; a run on a 2-D
     metric has only the tiled step."""
     h = B.Run(mhd(65, 33, "f64"))
     assert h.launch_info()["waves_per_cu"] == 0
@@ -214,13 +273,14 @@ def test_tiled_refused_where_it_does_not_apply():
     h.close()
     b = B.Run(batch=[cav(70, 45, "f64"), cav(40, 33, "f64")])
     assert b.launch_info()["waves_per_cu"] > 0
-    with pytest.raises(B.GocError) as ei:
-        b.set_launch(0)
-    assert ei.value.code == B.GOC_EINVAL
+    b.set_launch(0)
+    li = b.launch_info()
+    assert li["waves_per_cu"] == 0 and li["blocks"] == 2 * 12 + 1 * 9   # tiles of 64 x 4 in FP64
     b.close()
     c = B.Run(W.taylor_couette(n1=32, n2=6, R1=8.0, n_theta=20.0))
     assert c.launch_info()["waves_per_cu"] == 0
     c.set_launch(0)
-    with pytest.raises(B.GocError):
+    with pytest.raises(B.GocError) as ei:
         c.set_launch(8)
+    assert ei.value.code == B.GOC_EINVAL
     c.close()
