@@ -252,15 +252,17 @@ int goc_lbm_set_watchdog(goc_lbm_t *h, int64_t every);
      work-groups per compute unit (default 16; fewer where a run has too
      few row groups).  Fewer, longer segments re-read fewer halo rows; more
      segments fill the chip and balance uneven batches.  It can step every
-     handle on straight metrics (batches always);
+     handle on straight metrics;
    - the tiled step: one thread per node, 64 x 8 nodes per work-group (64 x
-     4 in FP64), the moments of the tile and its ring in LDS.  It steps a
-     single straight run, with or without MHD (chosen by default there: it
-     is the faster form on most sizes), and every run on a 2-D metric (its
-     only form).  The two forms agree to rounding.
-   goc_lbm_set_launch: waves_per_cu = 0 selects the tiled step (GOC_EINVAL
-   where it does not apply); waves_per_cu in [0.5, 1024] the march with that
-   plan (GOC_EINVAL outside, and on a 2-D metric).  Synchronous.
+     4 in FP64), the moments of the tile and its ring in LDS, one launch
+     over the tiles of every run of the handle.  It steps straight runs,
+     with or without MHD, alone or batched (the default for a single run:
+     it is the faster form on most sizes; batches start on the march), and
+     every run on a 2-D metric (its only form).  The two forms agree to
+     rounding.
+   goc_lbm_set_launch: waves_per_cu = 0 selects the tiled step;
+   waves_per_cu in [0.5, 1024] the march with that plan (GOC_EINVAL
+   outside, and on a 2-D metric).  Synchronous.
    goc_lbm_launch_info writes out[0] = waves_per_cu (0 for the tiled step),
    out[1] = work-groups per step, out[2] = mean rows per segment (rows per
    tile), out[3] = strips (column tiles), over all runs. */
@@ -269,8 +271,8 @@ int goc_lbm_launch_info(const goc_lbm_t *h, double out[4]);
 
 /* Autotuner of the step form and launch plan: times trial_steps step
    launches (1..10000, plus one warm-up) for each waves_per_cu in {2, 3, 4,
-   6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512} and, where it
-   applies, the tiled step (waves_per_cu 0), on the handle's stream, and
+   6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512} and the tiled
+   step (waves_per_cu 0), on the handle's stream, and
    keeps the fastest (a run on a 2-D metric: the tiled step, timed).  The
    state does not change: trial launches read the current buffers and write
    the spare ones.  out[0] = chosen waves_per_cu, out[1] = its microseconds
