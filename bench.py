@@ -137,7 +137,7 @@ def storage_forms(steps: int):
         r = B.Run(c)
         dd = r.derived()
         r.init(*W.hartmann_start(c, dd["nu"], dd["F1"], dd["eta"], dd["B0"]))
-        tuned = r.tune(10)
+        tuned = r.tune(50)
         w, e = time_run(r, n, 100)
         fl = r.fields()
         forms[st] = {"workload": c.name, "steps": n + 100, "MLUPS": round(c.nx * c.ny * n / w / 1e6, 1),
@@ -177,7 +177,7 @@ def batched_form(steps: int):
     b = B.Run(batch=runs)
     for k, c in enumerate(runs):
         start(b, c, k)
-    tuned = b.tune(5)
+    tuned = b.tune(20)
     w, _ = time_run(b, n, 100)
     out = {"runs": len(runs), "nodes": nodes, "steps": n, "MLUPS": round(nodes * n / w / 1e6, 1),
            "waves_per_cu": tuned["waves_per_cu"]}
@@ -186,7 +186,7 @@ def batched_form(steps: int):
     for c in runs:
         r = B.Run(c)
         start(r, c)
-        r.tune(3)
+        r.tune(10)
         r.step(100)
         singles.append(r)
     for r in singles:
@@ -212,7 +212,7 @@ def collision_variants(case, steps: int, central_mlups: float):
     for coll in ("raw", "srt"):
         c = case.replace(name=f"{case.name}_{coll}", collision=coll)
         r = B.Run(c)
-        tuned = r.tune(10)
+        tuned = r.tune(50)
         w, e = time_run(r, n, 100)
         d = r.derived()
         nodes = c.nx * c.ny
@@ -287,7 +287,7 @@ def main():
         run.set_launch(args.waves)
         tuned = {"us_before": float("nan")}
     else:
-        tuned = run.tune(20)      # launch-plan autotuner (state unchanged)
+        tuned = run.tune(100)     # step form and launch-plan autotuner (state unchanged)
     launch = run.launch_info()
     wall, ev = time_run(run, args.steps, args.warmup)
     d = run.derived()
