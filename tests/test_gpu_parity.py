@@ -332,13 +332,16 @@ def test_determinism_and_graph_blocks(oracle_lib):
     assert np.array_equal(fa, fb)
 
 
-def test_batch_fp64_each_run_matches_oracle(oracle_lib):
+@pytest.mark.parametrize("waves", [16, 0], ids=["march", "tiled"])
+def test_batch_fp64_each_run_matches_oracle(oracle_lib, waves):
     """Batched form: the first 10 runs of the seeded 256-run batch (uneven
     grids, stretching, Re, Ha) in one launch per step, FP64, 300 steps from
-    rest; every run equals its own oracle run within 1e-12."""
+    rest, on the march and on the tiled step; every run equals its own oracle
+    run within 1e-12."""
     runs = [c.replace(storage="f64") for c in W.batch_256(n=10)]
     g = B.Run(batch=runs)
     assert g.num_runs() == len(runs)
+    g.set_launch(waves)
     g.step(300)
     for r, case in enumerate(runs):
         o = oracle_lib.Model(case).init()
@@ -352,25 +355,31 @@ def test_batch_fp64_each_run_matches_oracle(oracle_lib):
 
 def test_batch_fp32_developed_1000_steps(oracle_lib):
     """Batched form in FP32: 8 runs of the seeded batch, each started from its
-    closed-form developed Hartmann flow, 1000 steps in one launch per step;
-    every run within 1e-5 of its own oracle run."""
+    closed-form developed Hartmann flow, 1000 steps in one launch per step,
+    on the march and on the tiled step; every run within 1e-5 of its own
+    oracle run."""
     runs = W.batch_256(n=8)
     g = B.Run(batch=runs)
+    gt = B.Run(batch=runs)   # the same batch on the tiled step
+    gt.set_launch(0)
     inits = []
     for r, case in enumerate(runs):
         d = g.derived(run=r)
         init = W.hartmann_start(case, d["nu"], d["F1"], d["eta"], d["B0"])
         g.init_run(r, *init)
+        gt.init_run(r, *init)
         inits.append(init)
     g.step(1000)
+    gt.step(1000)
     for r, case in enumerate(runs):
         o = oracle_lib.Model(case).init(*inits[r])
         o.step(1000)
-        e = field_errors(g.fields(run=r), o.fields(), o, "f32")
-        print(f"[batch f32] run {r} {case.nx}x{case.ny} Ha {case.Ha:.0f}", {k: f"{v:.1e}" for k, v in e.items()},
-              flush=True)
-        for k, v in e.items():
-            assert v < 1e-5, (r, k, e)
+        for form, run in (("march", g), ("tiled", gt)):
+            e = field_errors(run.fields(run=r), o.fields(), o, "f32")
+            print(f"[batch f32 {form}] run {r} {case.nx}x{case.ny} Ha {case.Ha:.0f}",
+                  {k: f"{v:.1e}" for k, v in e.items()}, flush=True)
+            for k, v in e.items():
+                assert v < 1e-5, (form, r, k, e)
 
 
 def test_autotuner_keeps_state_and_results():
