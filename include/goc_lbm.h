@@ -272,12 +272,15 @@ int goc_lbm_launch_info(const goc_lbm_t *h, double out[4]);
 /* Autotuner of the step form and launch plan: times trial_steps step
    launches (1..10000, plus one warm-up) for each waves_per_cu in {2, 3, 4,
    6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512} and the tiled
-   step (waves_per_cu 0), on the handle's stream, and
-   keeps the fastest (a run on a 2-D metric: the tiled step, timed).  The
-   state does not change: trial launches read the current buffers and write
-   the spare ones.  out[0] = chosen waves_per_cu, out[1] = its microseconds
-   per step, out[2] = microseconds per step of the form in use before (-1 if
-   it was not a candidate), out[3] = number of candidates.  Synchronous. */
+   step (waves_per_cu 0), on the handle's stream; the candidates within 5 %
+   of the fastest are timed again with three times the steps (at most
+   10000), and the fastest of that second timing is kept (a run on a 2-D
+   metric: the tiled step, timed).  The state does not change: trial
+   launches read the current buffers and write the spare ones.  out[0] =
+   chosen waves_per_cu, out[1] = its microseconds per step (second timing),
+   out[2] = microseconds per step of the form in use before in the first
+   timing (-1 if it was not a candidate), out[3] = number of candidates.
+   Synchronous. */
 int goc_lbm_tune(goc_lbm_t *h, int32_t trial_steps, double out[4]);
 
 /* Post-stream populations in FP64 (the quantities App. E step 1 reads):
