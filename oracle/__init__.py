@@ -125,7 +125,7 @@ class Lattice:
 
 
 def derive(case, h1, h2) -> Lattice:
-    """Lattice parameters of a workload (Sec. 3.2.1, Sec. 5, App. G, Sec. 8).
+    """Lattice parameters of a workload (Sec. 3.2.1, Sec. 4, App. G, Sec. 7).
 
     reading: omega_0,1,2,6,7,8 = 1 and omega_3 = 1 (bulk viscosity
     zeta = c_s^2/2); omega_4 = omega_5 from the shear viscosity.  The SRT

@@ -71,7 +71,7 @@ enum { K00 = 0, K10, K01, K20, K02, K11, K21, K12, K22 };
 typedef struct {
     int32_t nx, ny;
     int32_t bc_x, bc_y;          /* 0 periodic, 1 wall                      */
-    int32_t gi_terms;            /* 1: full correction coefficients (Sec. 5)
+    int32_t gi_terms;            /* 1: full correction coefficients (Sec. 4)
                                     0: App. B(ii) low-Mach straight-grid forms */
     int32_t q3_sign;             /* 0: binomial transform (reading), 1: printed q21, q12 */
     int32_t lid_corners;         /* 1: a moving y-wall owns the corner ghosts */
@@ -232,7 +232,7 @@ static void force_terms(const OracleCfg *c, const Metric *g, const NodeFlow *n,
     effective_force(c, g, n, k11raw, c->omega[5], t);
 }
 
-/* Sec. 5: equilibrium corrections n3^eq(1) (combined k2s) and n4^eq(1)
+/* Sec. 4: equilibrium corrections n3^eq(1) (combined k2s) and n4^eq(1)
    (combined k2d), Delta t = 1.  gi_terms = 1 uses the full coefficient sets
    D3k, C3, D4k, C4; gi_terms = 0 uses App. B(ii) (straight grids, no cubic
    Galilean-invariance terms). */
@@ -425,7 +425,7 @@ static void raw_sources(const Metric *g, double U1, double U2, double F1, double
 }
 
 /* Raw-moment collision at one node: step 1 (m = P f), step 2 (stresses,
-   local tau12, effective force, sources, base equilibria plus the Sec. 5
+   local tau12, effective force, sources, base equilibria plus the Sec. 4
    corrections on the combined diagonal moments, relaxation of the nine
    combined moments, split back to k20, k02) and step 3 (f~ = P^-1 m~). */
 static void raw_collide(const OracleCfg *c, const Metric *g, const double f[NQ],
@@ -1014,7 +1014,7 @@ int oracle_fields(const OracleCfg *c, const double *f, const double *Fp, const d
 }
 
 /* Initial state (App. C): f = P^-1 m^eq,eff(rho_i, U_i) with the raw-moment
-   equilibria of Sec. 3 and the corrections of Sec. 5 (gradients of the
+   equilibria of Sec. 3 and the corrections of Sec. 4 (gradients of the
    initial fields by the same finite differences); g = g^eq(0)(B_i, U_i)
    (App. G) with B_i the given field, or (0, B0) when B1_i / B2_i are NULL;
    reading: the lagged force before the first step is zero, so the first

@@ -142,7 +142,7 @@ def sound_speed_sq(h1, h2):
 
 
 def viscosity_from_tau(cs2: float, tau: float) -> float:
-    """Shear viscosity nu = c_s^2 (1/omega - 1/2) with omega = 1/tau (Sec. 5)."""
+    """Shear viscosity nu = c_s^2 (1/omega - 1/2) with omega = 1/tau (Sec. 4)."""
     return cs2 * (tau - 0.5)
 
 
@@ -152,7 +152,7 @@ def omega_from_viscosity(cs2: float, nu: float) -> float:
 
 
 def poiseuille(H: float, nu: float, Re: float, rho0: float = 1.0):
-    """Sec. 8.1: Re = U (H/2)/nu and U = F (H/2)^2 / (2 nu); returns (U, F)."""
+    """Sec. 7.1: Re = U (H/2)/nu and U = F (H/2)^2 / (2 nu); returns (U, F)."""
     U = Re * nu / (H / 2.0)
     F = 2.0 * nu * U * rho0 / (H / 2.0) ** 2
     return U, F
@@ -160,7 +160,7 @@ def poiseuille(H: float, nu: float, Re: float, rho0: float = 1.0):
 
 def hartmann(H: float, Ha: float, Re: float, Pm: float, Uc: float, rho0: float = 1.0,
              mu_m: float = 1.0):
-    """Sec. 8.4 Hartmann flow between plates 2H apart.
+    """Sec. 7.4 Hartmann flow between plates 2H apart.
 
     reading: Re = U_c H / nu with U_c the analytic centre-line velocity;
     eta = nu / Pm; Ha = B0 H sqrt(sigma/(rho nu)) with sigma = 1/(eta mu_m);
@@ -182,7 +182,7 @@ def hartmann(H: float, Ha: float, Re: float, Pm: float, Uc: float, rho0: float =
 
 
 def hartmann_profile(ystar, Ha: float, Ur: float, Br: float):
-    """Closed-form u_x(y*) and B_x(y*) of Sec. 8.4, y* in [-1, 1] from the centre."""
+    """Closed-form u_x(y*) and B_x(y*) of Sec. 7.4, y* in [-1, 1] from the centre."""
     y = np.asarray(ystar, dtype=np.float64)
     u = Ur * (1.0 / (Ha * math.tanh(Ha))) * (1.0 - np.cosh(Ha * y) / math.cosh(Ha))
     b = Br * (-y / Ha + (1.0 / (Ha * math.tanh(Ha))) * np.sinh(Ha * y) / math.cosh(Ha))

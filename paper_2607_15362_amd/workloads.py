@@ -7,9 +7,9 @@ none of the method's arithmetic; the HIP library and the oracle each derive
 their lattice parameters and metric factors from these descriptions with
 their own code.
 
-The workloads follow the paper's benchmark families (Sec. 8): the
-body-force channel of Sec. 8.1, the lid-driven cavity of Sec. 8.3 and the
-Hartmann flow of Sec. 8.4, all on tanh-clustered grids (Sec. 6.1).
+The workloads follow the paper's benchmark families (Sec. 7): the
+body-force channel of Sec. 7.1, the lid-driven cavity of Sec. 7.3 and the
+Hartmann flow of Sec. 7.4, all on tanh-clustered grids (Sec. 6.1).
 """
 from __future__ import annotations
 
@@ -164,7 +164,7 @@ def smooth_fields(nx: int, ny: int, seed: int, amp: float, rho0: float = 1.0, mo
 
 def hartmann_start(case: Case, nu: float, F1: float, eta: float = 0.0, B0: float = 0.0):
     """Developed Hartmann flow as an initial state (rho, U1, U2, B1, B2) of
-    shape [ny, nx], from the closed forms between the plates (Sec. 8.4):
+    shape [ny, nx], from the closed forms between the plates (Sec. 7.4):
     rho = rho0, u(y*) = U_r (cosh Ha - cosh(Ha y*)) / (Ha sinh Ha),
     B1(y*) = B_r (sinh(Ha y*) / (Ha tanh(Ha) cosh(Ha)) - y* / Ha), B2 = B0,
     with U_r = H^2 F1 / (rho0 nu), B_r = H^2 F1 mu_m sqrt(sigma / (rho0 nu)),

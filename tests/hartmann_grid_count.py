@@ -12,7 +12,7 @@ FP64, Pm = 1, Re = U_c H / nu (default 100), U_c at Mach 0.1 lowered by the
 relaxation-time cap tau <= 1, started from the closed-form Hartmann profiles
 (u_x, B_x) at the node positions and run until u changes by less than 1e-12
 (relative) over 20000 steps or max_steps (default 2M).  It prints the
-relative L2 errors of u_x and B_x against the closed forms (Sec. 8.4).
+relative L2 errors of u_x and B_x against the closed forms (Sec. 7.4).
 """
 from __future__ import annotations
 

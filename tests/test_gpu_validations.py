@@ -1,5 +1,5 @@
 """The paper's channel validations on the GPU, through the C-ABI, against
-their closed forms (Sec. 8.1 and 8.2), at the strip sizes the paper uses:
+their closed forms (Sec. 7.1 and 7.2), at the strip sizes the paper uses:
 steady body-force Poiseuille flow on a tanh-clustered 3 x 40 strip (and its
 second-order convergence), plane Couette flow with the momentum-augmented
 bounce-back of App. C (exact on a uniform grid, second order on a clustered

@@ -9,7 +9,7 @@ O(eps) conservation laws), the combinations
 
   -1/2 (1 - w3/2) n3^(1) -/+ 1/2 (1 - w4/2) n4^(1) - w3/4 n3^eq(1) -/+ w4/4 n4^eq(1)
 
-must equal (h2/h1) tau11 and (h1/h2) tau22 (Sec. 5, momentum-flux matching).
+must equal (h2/h1) tau11 and (h1/h2) tau22 (Sec. 4, momentum-flux matching).
 The check uses a general curvilinear metric (all four theta_ij non-zero),
 smooth analytic fields, sympy derivatives and high-precision evaluation.
 """

@@ -195,7 +195,7 @@ def _steady(m, field, col=1, chunk=2000, tol=1e-13, maxit=500):
 
 
 def test_poiseuille_steady_second_order(oracle_lib):
-    """Steady body-force Poiseuille flow (Sec. 8.1) on tanh-clustered 3xN
+    """Steady body-force Poiseuille flow (Sec. 7.1) on tanh-clustered 3xN
     strips converges to u = 4U (y/H)(1 - y/H) at second order."""
     o = oracle_lib
     errs = []
@@ -215,7 +215,7 @@ def test_poiseuille_steady_second_order(oracle_lib):
 def test_couette_moving_wall(oracle_lib):
     """Momentum-augmented bounce-back of App. C: steady Couette flow is exact
     on a uniform grid and converges at second order on a clustered grid;
-    the transient matches the series of Sec. 8.2 (Roberts grid, 6x50,
+    the transient matches the series of Sec. 7.2 (Roberts grid, 6x50,
     tau = 1, U = 0.02)."""
     o = oracle_lib
 
@@ -246,7 +246,7 @@ def test_couette_moving_wall(oracle_lib):
 
 
 def test_hartmann_closed_form(oracle_lib):
-    """Coupled D2Q9 + D2Q5 Hartmann flow (Sec. 8.4) on a tanh-clustered 3x32
+    """Coupled D2Q9 + D2Q5 Hartmann flow (Sec. 7.4) on a tanh-clustered 3x32
     strip reaches the analytic u_x(y) and B_x(y) profiles, with B_y = B0."""
     o = oracle_lib
     from oracle import params

@@ -184,7 +184,7 @@ def _steady(m, chunk=2000, tol=1e-13, maxit=500):
 
 @pytest.mark.parametrize("collision", ["raw", "srt"])
 def test_variant_poiseuille_steady_second_order(oracle_lib, collision):
-    """Steady body-force Poiseuille flow (Sec. 8.1) on tanh-clustered 3xN
+    """Steady body-force Poiseuille flow (Sec. 7.1) on tanh-clustered 3xN
     strips converges to u = 4U (y/H)(1 - y/H) at second order with either
     variant, as with the central-moment model."""
     o = oracle_lib
