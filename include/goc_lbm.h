@@ -42,7 +42,7 @@ typedef enum {
     GOC_ENOMEM = -2,     /* device or host allocation failed              */
     GOC_EDEVICE = -3,    /* a HIP call failed                             */
     GOC_EUNSTABLE = -4,  /* the watchdog found a non-finite value         */
-    GOC_ESTATE = -5      /* state blob of the wrong size or version       */
+    GOC_ESTATE = -5      /* state blob of another version, size or grid   */
 } goc_status;
 
 typedef enum { GOC_BC_PERIODIC = 0, GOC_BC_WALL = 1 } goc_bc;
@@ -51,14 +51,27 @@ typedef enum {
     GOC_F64 = 0,      /* populations FP64, arithmetic FP64                       */
     GOC_F32 = 1,      /* populations FP32, arithmetic FP32                       */
     GOC_F16DEV = 2,   /* populations FP16 as scaled deviations from the rest state,
-                         arithmetic FP32                                         */
+                         less a per-row reference (below), arithmetic FP32       */
     GOC_BF16DEV = 3   /* as GOC_F16DEV with bfloat16                              */
 } goc_storage;
+/* The 16-bit forms (GOC_F16DEV, GOC_BF16DEV) store each slot as the deviation
+   of its population from the rest state (rho0, U = 0; App. C), minus a
+   reference: the mean over the reader's row of the deviations pulled along
+   the reader's direction (one table of 19 FP32 values per row and run: nine
+   D2Q9 and ten D2Q5 directions), times a fixed scale per direction class,
+   rounded stochastically.  Where the flow varies little along a row the
+   stored residual is far smaller than the deviation, which carries the
+   velocity, the lagged force and the magnetic field.  Every initialisation
+   (goc_lbm_init*, goc_lbm_set_populations) forms the table from the state it
+   writes; goc_lbm_step refreshes it from the current state after the first
+   step and then every 100 steps (the step then decodes with the old table
+   and encodes with the new one); checkpoints carry it.  The 16-bit forms
+   step with the tiled kernel only (goc_lbm_set_launch). */
 
 typedef enum {
     GOC_COLL_CENTRAL = 0,  /* central-moment MRT (App. E)                          */
     GOC_COLL_RAW = 1,      /* raw-moment MRT: the nine combined raw moments relax
-                              to the Sec. 3 equilibria with the Sec. 5 corrections */
+                              to the Sec. 3 equilibria with the Sec. 4 corrections */
     GOC_COLL_SRT = 2       /* single relaxation time tau = 1/omega[4] in velocity
                               space, f^eq = P^-1 m^eq and S = P^-1 sigma; every
                               rate is 1/tau, so zeta = nu.  Computed as the
@@ -82,11 +95,11 @@ typedef enum {
 } goc_stretch;
 
 typedef enum {
-    GOC_FLOW_CHANNEL = 0,   /* body-force channel, Sec. 8.1: Re = U (H/2)/nu, tau given */
-    GOC_FLOW_CAVITY = 1,    /* lid-driven cavity, Sec. 8.3: Re = U_lid L / nu,
+    GOC_FLOW_CHANNEL = 0,   /* body-force channel, Sec. 7.1: Re = U (H/2)/nu, tau given */
+    GOC_FLOW_CAVITY = 1,    /* lid-driven cavity, Sec. 7.3: Re = U_lid L / nu,
                                U_lid = u_lid, or Ma c_s when u_lid <= 0, then
                                lowered so that tau <= tau_max when tau_max > 1/2  */
-    GOC_FLOW_HARTMANN = 2,  /* MHD channel, Sec. 8.4: Re = U_c H / nu, H half-width,
+    GOC_FLOW_HARTMANN = 2,  /* MHD channel, Sec. 7.4: Re = U_c H / nu, H half-width,
                                U_c = Ma c_s lowered so that tau <= tau_max when
                                tau_max > 1/2; eta = nu / Pm                          */
     GOC_FLOW_FREE = 3       /* no derived forcing: tau and F_ext given                */
@@ -135,16 +148,23 @@ typedef struct {
     const double *d1h1, *d2h1, *d1h2, *d2h2;
 } goc_metric;
 
-/* Lattice parameters of a run (all in lattice units).  c_s^2 = q^2/3 with
+/* Lattice parameters of a run (all in lattice units).  The physical
+   parameters of the paper's flows (Reynolds number Re, Hartmann number Ha,
+   magnetic Prandtl number Pm, Mach number Ma) are not fields here: they
+   enter through goc_lbm_derive, which turns a goc_physics description into
+   these fields (omega[4] = omega[5] from the viscosity that Re fixes;
+   F_ext from Re, or from Re and Ha for the Hartmann flow; tau_m from
+   eta = nu / Pm; B0 from Ha), and the caller passes the result to
+   goc_lbm_create.  c_s^2 = q^2/3 with
    q the minimum metric factor (Sec. 3.2.1) is derived by the library from
    the metric, as is the MHD sound speed c_sm = c_s (App. G).  nu and zeta
    follow from omega[4] (= omega[5] for the default reading) and omega[3]:
-   nu = c_s^2 (1/omega5 - 1/2), zeta = c_s^2 (1/omega3 - 1/2) (Sec. 5). */
+   nu = c_s^2 (1/omega5 - 1/2), zeta = c_s^2 (1/omega3 - 1/2) (Sec. 4). */
 typedef struct {
     double omega[9];          /* relaxation rates, each in (0, 2)            */
     double rho0;              /* reference (initial) density                 */
     double F_ext[2];          /* external body-force density, GOC components */
-    int32_t gi_terms;         /* 1: full correction coefficients (Sec. 5);
+    int32_t gi_terms;         /* 1: full correction coefficients (Sec. 4);
                                  0: App. B(ii) low-Mach forms                */
     int32_t q3_sign;          /* 0: binomial-transform sign of q21, q12; 1: as printed */
     int32_t rho_terms;        /* 0: density-gradient coefficients from the
@@ -175,8 +195,10 @@ typedef struct {
 
 typedef struct goc_lbm goc_lbm_t;
 
-/* Derive lattice parameters from physical ones (Sec. 3.2.1, Sec. 5,
-   App. G, Sec. 8), for the given grid and metric: c_s^2 from the metric;
+/* Derive lattice parameters from physical ones (Sec. 3.2.1, Sec. 4,
+   App. G, Sec. 7), for the given grid and metric: the bridge from the
+   paper's dimensionless numbers (Re, Ha, Pm, Ma in *phys) to goc_params,
+   which goc_lbm_create takes.  c_s^2 from the metric;
    channel: nu = c_s^2 (tau - 1/2), U = Re nu/(H/2), F = 2 nu U rho0/(H/2)^2
    with H = ny; cavity: nu = U_lid nx / Re (U_lid reduced if tau would
    exceed tau_max and u_lid <= 0) and grid->u_wall_hi = U_lid;
@@ -222,8 +244,11 @@ int goc_lbm_init_run(goc_lbm_t *h, int32_t run, const double *rho, const double 
                      const double *b1, const double *b2, int32_t on_device);
 
 /* Advance n >= 0 time steps (App. E steps 1-7 and App. G steps 1-6 per
-   step, one fused kernel launch each).  Asynchronous on the stream unless
-   the watchdog interval is due (goc_lbm_set_watchdog). */
+   step, one fused kernel launch each; with a non-NULL stream, blocks of 100
+   steps replay a captured HIP graph).  16-bit storage: the reference table
+   is refreshed on the steps given above the storage enum, and graph blocks
+   start on them.  Asynchronous on the stream unless the watchdog interval
+   is due (goc_lbm_set_watchdog). */
 int goc_lbm_step(goc_lbm_t *h, int64_t n);
 
 /* Hydrodynamic and magnetic fields of the current state (App. E step 7,
@@ -258,11 +283,11 @@ int goc_lbm_set_watchdog(goc_lbm_t *h, int64_t every);
      over the tiles of every run of the handle.  It steps straight runs,
      with or without MHD, alone or batched (the default for a single run:
      it is the faster form on most sizes; batches start on the march), and
-     every run on a 2-D metric (its only form).  The two forms agree to
-     rounding.
+     every run on a 2-D metric or in 16-bit storage (its only form).  The two
+     forms agree to rounding.
    goc_lbm_set_launch: waves_per_cu = 0 selects the tiled step;
    waves_per_cu in [0.5, 1024] the march with that plan (GOC_EINVAL
-   outside, and on a 2-D metric).  Synchronous.
+   outside, on a 2-D metric and in 16-bit storage).  Synchronous.
    goc_lbm_launch_info writes out[0] = waves_per_cu (0 for the tiled step),
    out[1] = work-groups per step, out[2] = mean rows per segment (rows per
    tile), out[3] = strips (column tiles), over all runs. */
@@ -275,7 +300,7 @@ int goc_lbm_launch_info(const goc_lbm_t *h, double out[4]);
    step (waves_per_cu 0), on the handle's stream; the candidates within 5 %
    of the fastest are timed again with three times the steps (at most
    10000), and the fastest of that second timing is kept (a run on a 2-D
-   metric: the tiled step, timed).  The state does not change: trial
+   metric or in 16-bit storage: the tiled step, timed).  The state does not change: trial
    launches read the current buffers and write the spare ones.  out[0] =
    chosen waves_per_cu, out[1] = its microseconds per step (second timing),
    out[2] = microseconds per step of the form in use before in the first
@@ -294,9 +319,14 @@ int goc_lbm_set_populations(goc_lbm_t *h, const double *f, const double *F, cons
 
 /* Checkpoint in storage precision (host buffer).  get: with buf NULL writes
    the required size to *bytes; otherwise *bytes must be >= that size.
-   set: bytes must match exactly (GOC_ESTATE otherwise).  The blob holds the
-   step counter and the raw state; restoring it and stepping reproduces an
-   uninterrupted run bit for bit. */
+   The blob holds a header (format version 2, storage, run count, step
+   counter, the byte sizes of its regions, the step of the last
+   initialisation), each run's (nx, ny, mhd), then the raw device state: the
+   16-bit reference table, the slots, the lagged force and the D2Q5 slots.
+   set: checks the header, the region sizes and every run's shape against
+   the handle before copying anything and returns GOC_ESTATE on any
+   mismatch (the handle is then unchanged).  Restoring a blob and stepping
+   reproduces an uninterrupted run bit for bit. */
 int goc_lbm_get_state(goc_lbm_t *h, void *buf, size_t *bytes);
 int goc_lbm_set_state(goc_lbm_t *h, const void *buf, size_t bytes);
 

@@ -101,6 +101,16 @@ __device__ inline void put_slot(S* base, const RunDesc& d, int i, int j, int a, 
     if (ghost_index(d, i, j, a, gi)) Store<S>::st(base, gi, v, s);
 }
 
+// Reference entry k of row j of run d in the table in use (16-bit storage;
+// zero otherwise): what the stored value of a slot whose reader lies in
+// row j leaves out.
+template <class S, class FT>
+__device__ inline double ref_of(const Pools<S, FT>& pl, const RunDesc& d, int j, int k)
+{
+    if constexpr (Store<S>::scaled) return double(pl.ref_in[(d.row_off + j) * kRef + k]);
+    return 0.0;
+}
+
 __device__ inline double sc_of(const RunDesc& d, int a, bool scaled) { return scaled ? d.sc[cls_(a)] : 1.0; }
 
 // Per-node metric of run d (FP64): the column / row tables of a straight
@@ -137,24 +147,19 @@ __device__ inline NodeM node_metric(const RunDesc& d, const Pools<S, FT>& pl, in
     return m;
 }
 
-// Initial state of App. C from node fields (rho, U1, U2) and, for MHD runs,
-// (B1, B2), FP64 inputs [ny][nx] (nullptr: rest state rho0, U = 0, and the
-// applied field B = (0, B0)).  The deviation from the rest
-// state of the raw equilibria of Sec. 3 with the corrections of Sec. 5
-// (finite-difference gradients of the fields) is mapped through P^-1 and
-// scattered to the slots; D2Q5: g^eq(0) of App. G; lagged force zero.
+// Deviations from the rest state of the initial populations of node (i, j)
+// (App. C): the raw equilibria of Sec. 3 with the corrections of Sec. 4
+// (finite-difference gradients of the fields) mapped through P^-1; D2Q5 (dg
+// not null): g^eq(0) of App. G.  Fields: FP64 [ny][nx] (rho_in nullptr: the
+// rest state rho0, U = 0; b1_in nullptr: the applied field B = (0, B0)).
 template <class S>
-__global__ void init_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename ForceOf<S>::type> pl,
-                            const double* __restrict__ rho_in, const double* __restrict__ u1_in,
-                            const double* __restrict__ u2_in, const double* __restrict__ b1_in,
-                            const double* __restrict__ b2_in)
+__device__ inline void init_devs(const RunDesc& d, const Pools<S, typename ForceOf<S>::type>& pl, int i, int j,
+                                 const double* __restrict__ rho_in, const double* __restrict__ u1_in,
+                                 const double* __restrict__ u2_in, const double* __restrict__ b1_in,
+                                 const double* __restrict__ b2_in, typename ComputeOf<S>::type* f,
+                                 typename ComputeOf<S>::type (*dgo)[kM])
 {
     using T = typename ComputeOf<S>::type;
-    using FT = typename ForceOf<S>::type;
-    const RunDesc& d = runs[run];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= d.nx || j >= d.ny) return;
     const NodeParams<T> p = node_params<T>(d);
     const NodeM nm = node_metric(d, pl, i, j);
     NodeMetric<T> g;
@@ -211,7 +216,6 @@ __global__ void init_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, 
     const T m21 = rho * (cs2 + U1 * U1) * U2 * g.ih1;
     const T m12 = rho * (cs2 + U2 * U2) * U1 * g.ih2;
     const T m22 = drho * cs2 * cs2 + rho * cs2 * (U1 * U1 + U2 * U2) + rho * U1 * U1 * U2 * U2;
-    T f[kQ];
     f[0] = m00 - m20 - m02 + m22;
     f[1] = T(0.5) * (m10 + m20 - m12 - m22);
     f[2] = T(0.5) * (m01 + m02 - m21 - m22);
@@ -221,30 +225,103 @@ __global__ void init_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, 
     f[6] = T(0.25) * (-m11 + m21 - m12 + m22);
     f[7] = T(0.25) * (m11 - m21 - m12 + m22);
     f[8] = T(0.25) * (-m11 - m21 + m12 + m22);
-    for (int a = 0; a < kQ; ++a)
-        put_slot<S, T>(pl.fout + d.f_off, d, i, j, a, f[a], T(sc_of(d, a, Store<S>::scaled)));
-    const int64_t n = (int64_t)j * d.pitchF + i;   // force pool
-    pl.Fout[d.F_off + n] = FT(0);
-    pl.Fout[d.F_off + n + d.plane] = FT(0);
-    if (d.mhd) {
-        T dB[2] = {T(0), T(0)};   // deviation of B from the applied field (0, B0)
-        if (b1_in) {
-            dB[0] = T(b1_in[(int64_t)j * d.nx + i]);
-            dB[1] = T(b2_in[(int64_t)j * d.nx + i] - d.B0);
+    if (!dgo) return;
+    T dB[2] = {T(0), T(0)};   // deviation of B from the applied field (0, B0)
+    if (b1_in) {
+        dB[0] = T(b1_in[(int64_t)j * d.nx + i]);
+        dB[1] = T(b2_in[(int64_t)j * d.nx + i] - d.B0);
+    }
+    const T B[2] = {dB[0], p.B0 + dB[1]};
+    const T U[2] = {U1, U2};
+    for (int ci = 0; ci < 2; ++ci) {
+        const T A1 = U[0] * B[ci] - B[0] * U[ci];
+        const T A2 = U[1] * B[ci] - B[1] * U[ci];
+        for (int a = 0; a < kM; ++a) {
+            const T W = a == 0 ? p.W0 : p.W1;
+            // g^eq(0) minus the rest state W h1 h2 B_rest
+            dgo[ci][a] = W * (g.h1 * g.h2 * dB[ci] + (T(ex_(a)) * g.h2 * A1 + T(ey_(a)) * g.h1 * A2) * p.inv_csm2);
         }
-        const T B[2] = {dB[0], p.B0 + dB[1]};
-        const T U[2] = {U1, U2};
-        const T sg = Store<S>::scaled ? T(d.scg) : T(1);
-        for (int ci = 0; ci < 2; ++ci) {
-            const T A1 = U[0] * B[ci] - B[0] * U[ci];
-            const T A2 = U[1] * B[ci] - B[1] * U[ci];
-            for (int a = 0; a < kM; ++a) {
-                const T W = a == 0 ? p.W0 : p.W1;
-                // g^eq(0) minus the rest state W h1 h2 B_rest
-                const T dg = W * (g.h1 * g.h2 * dB[ci] + (T(ex_(a)) * g.h2 * A1 + T(ey_(a)) * g.h1 * A2) * p.inv_csm2);
-                put_slot<S, T>(pl.gout + d.g_off + ci * kM * d.plane, d, i, j, a, dg, sg);
-            }
+    }
+}
+
+// Store the node deviations of row j of run d, given by dev(i, f, dg), at the
+// slots their pulls read.  16-bit storage: the work-group first forms the row
+// means of the deviations (FP64, fixed order), writes them as the row's
+// entries of the reference table ref_tab (the table in use) and stores each
+// deviation minus its mean.  One work-group of 256 threads per row.
+template <class S, class Dev>
+__device__ inline void store_row(const RunDesc& d, const Pools<S, typename ForceOf<S>::type>& pl, int j,
+                                 float* __restrict__ ref_tab, Dev dev)
+{
+    using T = typename ComputeOf<S>::type;
+    constexpr int nk = kRefG + 2 * kM;
+    __shared__ float ref[kRef];
+    if constexpr (Store<S>::scaled) {
+        __shared__ double sh[nk][256];
+        double acc[nk];
+        for (int k = 0; k < nk; ++k) acc[k] = 0.0;
+        for (int i = threadIdx.x; i < d.nx; i += blockDim.x) {
+            T f[kQ], dg[2][kM] = {};
+            dev(i, f, d.mhd ? dg : nullptr);
+            for (int a = 0; a < kQ; ++a) acc[a] += double(f[a]);
+            for (int ci = 0; ci < 2; ++ci)
+                for (int a = 0; a < kM; ++a) acc[kRefG + ci * kM + a] += double(dg[ci][a]);
         }
+        for (int k = 0; k < nk; ++k) sh[k][threadIdx.x] = acc[k];
+        __syncthreads();
+        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s)
+                for (int k = 0; k < nk; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x < kRef) {
+            const float v = threadIdx.x < nk ? float(sh[threadIdx.x][0] / d.nx) : 0.0f;
+            ref[threadIdx.x] = v;
+            ref_tab[(d.row_off + j) * kRef + threadIdx.x] = v;
+        }
+        __syncthreads();
+    } else {
+        if (threadIdx.x < kRef) ref[threadIdx.x] = 0.0f;
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < d.nx; i += blockDim.x) {
+        T f[kQ], dg[2][kM];
+        dev(i, f, d.mhd ? dg : nullptr);
+        for (int a = 0; a < kQ; ++a)
+            put_slot<S, T>(pl.fout + d.f_off, d, i, j, a, f[a] - T(ref[a]), T(sc_of(d, a, Store<S>::scaled)));
+        if (d.mhd) {
+            const T sg = Store<S>::scaled ? T(d.scg) : T(1);
+            for (int ci = 0; ci < 2; ++ci)
+                for (int a = 0; a < kM; ++a)
+                    put_slot<S, T>(pl.gout + d.g_off + ci * kM * d.plane, d, i, j, a,
+                                   dg[ci][a] - T(ref[kRefG + ci * kM + a]), sg);
+        }
+    }
+}
+
+// Initial state of App. C from node fields (rho, U1, U2) and, for MHD runs,
+// (B1, B2) (see init_devs), stored with the reference table of the 16-bit
+// storage formed from it; lagged force zero.  Grid: one work-group of 256
+// threads per row of run `run`.
+template <class S>
+__global__ void __launch_bounds__(256) init_kernel(const RunDesc* __restrict__ runs, int run,
+                                                   Pools<S, typename ForceOf<S>::type> pl, float* __restrict__ ref_tab,
+                                                   const double* __restrict__ rho_in, const double* __restrict__ u1_in,
+                                                   const double* __restrict__ u2_in, const double* __restrict__ b1_in,
+                                                   const double* __restrict__ b2_in)
+{
+    using T = typename ComputeOf<S>::type;
+    using FT = typename ForceOf<S>::type;
+    const RunDesc& d = runs[run];
+    const int j = blockIdx.x;
+    if (j >= d.ny) return;
+    store_row<S>(d, pl, j, ref_tab, [&](int i, T* f, T (*dg)[kM]) {
+        init_devs<S>(d, pl, i, j, rho_in, u1_in, u2_in, b1_in, b2_in, f, dg);
+    });
+    for (int i = threadIdx.x; i < d.nx; i += blockDim.x) {
+        const int64_t n = (int64_t)j * d.pitchF + i;   // force pool
+        pl.Fout[d.F_off + n] = FT(0);
+        pl.Fout[d.F_off + n + d.plane] = FT(0);
     }
 }
 
@@ -262,7 +339,8 @@ __global__ void gather_kernel(const RunDesc* __restrict__ runs, int run, Pools<S
     const int64_t N = (int64_t)d.nx * d.ny, o = (int64_t)j * d.nx + i;
     const bool sc = Store<S>::scaled;
     for (int a = 0; a < kQ; ++a) {
-        const double dv = double(Store<S>::ld(pl.fin + d.f_off, slot_index(d, i, j, a), 1.0f)) / sc_of(d, a, sc);
+        const double dv = double(Store<S>::ld(pl.fin + d.f_off, slot_index(d, i, j, a), 1.0f)) / sc_of(d, a, sc) +
+                          ref_of(pl, d, j, a);
         f[a * N + o] = dv + rest_pop(a, m.h1, m.h2, d.rho0, d.cs2);
     }
     const int64_t n = (int64_t)j * d.pitchF + i;   // force pool
@@ -273,41 +351,44 @@ __global__ void gather_kernel(const RunDesc* __restrict__ runs, int run, Pools<S
         for (int ci = 0; ci < 2; ++ci)
             for (int a = 0; a < kM; ++a) {
                 const double dv = double(Store<S>::ld(pl.gin + d.g_off + ci * kM * d.plane,
-                                                      slot_index(d, i, j, a), 1.0f)) / scg;
+                                                      slot_index(d, i, j, a), 1.0f)) / scg +
+                                  ref_of(pl, d, j, kRefG + ci * kM + a);
                 const double W = a == 0 ? 1.0 - 2.0 * d.csm2 : 0.5 * d.csm2;
                 g[(ci * kM + a) * N + o] = dv + (ci == 1 ? W * m.h1 * m.h2 * d.B0 : 0.0);
             }
     }
 }
 
+// Populations given as FP64 node arrays (as gather_kernel writes them)
+// stored as deviations from the rest state (with the reference table of the
+// 16-bit storage formed from them).  One work-group of 256 threads per row.
 template <class S>
-__global__ void scatter_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename ForceOf<S>::type> pl,
-                               const double* __restrict__ f, const double* __restrict__ F,
-                               const double* __restrict__ g)
+__global__ void __launch_bounds__(256) scatter_kernel(const RunDesc* __restrict__ runs, int run,
+                                                      Pools<S, typename ForceOf<S>::type> pl, float* __restrict__ ref_tab,
+                                                      const double* __restrict__ f, const double* __restrict__ F,
+                                                      const double* __restrict__ g)
 {
     using T = typename ComputeOf<S>::type;
     using FT = typename ForceOf<S>::type;
     const RunDesc& d = runs[run];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= d.nx || j >= d.ny) return;
-    const NodeM m = node_metric(d, pl, i, j);
-    const int64_t N = (int64_t)d.nx * d.ny, o = (int64_t)j * d.nx + i;
-    const bool sc = Store<S>::scaled;
-    for (int a = 0; a < kQ; ++a) {
-        const double dv = f[a * N + o] - rest_pop(a, m.h1, m.h2, d.rho0, d.cs2);
-        put_slot<S, T>(pl.fout + d.f_off, d, i, j, a, T(dv), T(sc_of(d, a, sc)));
-    }
-    const int64_t n = (int64_t)j * d.pitchF + i;   // force pool
-    pl.Fout[d.F_off + n] = FT(F[o]);
-    pl.Fout[d.F_off + n + d.plane] = FT(F[N + o]);
-    if (d.mhd && g) {
-        for (int ci = 0; ci < 2; ++ci)
-            for (int a = 0; a < kM; ++a) {
-                const double W = a == 0 ? 1.0 - 2.0 * d.csm2 : 0.5 * d.csm2;
-                const double dv = g[(ci * kM + a) * N + o] - (ci == 1 ? W * m.h1 * m.h2 * d.B0 : 0.0);
-                put_slot<S, T>(pl.gout + d.g_off + ci * kM * d.plane, d, i, j, a, T(dv), T(sc ? d.scg : 1.0));
-            }
+    const int j = blockIdx.x;
+    if (j >= d.ny) return;
+    const int64_t N = (int64_t)d.nx * d.ny;
+    store_row<S>(d, pl, j, ref_tab, [&](int i, T* fo, T (*dg)[kM]) {
+        const NodeM m = node_metric(d, pl, i, j);
+        const int64_t o = (int64_t)j * d.nx + i;
+        for (int a = 0; a < kQ; ++a) fo[a] = T(f[a * N + o] - rest_pop(a, m.h1, m.h2, d.rho0, d.cs2));
+        if (dg)
+            for (int ci = 0; ci < 2; ++ci)
+                for (int a = 0; a < kM; ++a) {
+                    const double W = a == 0 ? 1.0 - 2.0 * d.csm2 : 0.5 * d.csm2;
+                    dg[ci][a] = T(g[(ci * kM + a) * N + o] - (ci == 1 ? W * m.h1 * m.h2 * d.B0 : 0.0));
+                }
+    });
+    for (int i = threadIdx.x; i < d.nx; i += blockDim.x) {
+        const int64_t o = (int64_t)j * d.nx + i, n = (int64_t)j * d.pitchF + i;   // force pool
+        pl.Fout[d.F_off + n] = FT(F[o]);
+        pl.Fout[d.F_off + n + d.plane] = FT(F[N + o]);
     }
 }
 
@@ -318,12 +399,14 @@ __device__ inline void node_devs(const RunDesc& d, const Pools<S, typename Force
 {
     const bool sc = Store<S>::scaled;
     for (int a = 0; a < kQ; ++a)
-        f[a] = Store<S>::ld(pl.fin + d.f_off, slot_index(d, i, j, a), T(1.0 / sc_of(d, a, sc)));
+        f[a] = Store<S>::ld(pl.fin + d.f_off, slot_index(d, i, j, a), T(1.0 / sc_of(d, a, sc))) +
+               T(ref_of(pl, d, j, a));
     if (dg)
         for (int ci = 0; ci < 2; ++ci)
             for (int a = 0; a < kM; ++a)
                 dg[ci][a] = Store<S>::ld(pl.gin + d.g_off + ci * kM * d.plane, slot_index(d, i, j, a),
-                                         T(sc ? 1.0 / d.scg : 1.0));
+                                         T(sc ? 1.0 / d.scg : 1.0)) +
+                            T(ref_of(pl, d, j, kRefG + ci * kM + a));
 }
 
 // Hydrodynamic and magnetic fields of the current state (FP64 outputs).
@@ -452,6 +535,55 @@ __global__ void diag_final_kernel(const double* __restrict__ part, int nparts, d
     }
     if (threadIdx.x == 0)
         for (int k = 0; k < kDiag; ++k) out[k] = sh[k][0];
+}
+
+// New reference table of the 16-bit storage (written to ref_new) from the
+// current state, decoded with the table in use: entry k of a row is the mean
+// over the row of the deviation its nodes pull along direction k (FP64
+// sums, rounded to FP32 once).  One work-group of 256 threads per row of
+// every run (grid = the rows of all runs; a run's rows start at row_off).
+template <class S>
+__global__ void __launch_bounds__(256) ref_kernel(const RunDesc* __restrict__ runs, int nruns,
+                                                  Pools<S, typename ForceOf<S>::type> pl, float* __restrict__ ref_new)
+{
+    using T = typename ComputeOf<S>::type;
+    constexpr int nk = kRefG + 2 * kM;
+    __shared__ double sh[nk][256];
+    const int gr = blockIdx.x;
+    int lo = 0, hi = nruns - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (runs[mid].row_off <= gr) lo = mid;
+        else hi = mid - 1;
+    }
+    const RunDesc& d = runs[lo];
+    const int j = gr - (int)d.row_off;
+    double acc[nk];
+    for (int k = 0; k < nk; ++k) acc[k] = 0.0;
+    for (int i = threadIdx.x; i < d.nx; i += blockDim.x) {
+        T f[kQ], dg[2][kM];
+        node_devs<S, T>(d, pl, i, j, f, d.mhd ? dg : nullptr);
+        for (int a = 0; a < kQ; ++a) acc[a] += double(f[a]);
+        if (d.mhd)
+            for (int ci = 0; ci < 2; ++ci)
+                for (int a = 0; a < kM; ++a) acc[kRefG + ci * kM + a] += double(dg[ci][a]);
+    }
+    for (int k = 0; k < nk; ++k) sh[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int k = 0; k < nk; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < kRef)
+        ref_new[(int64_t)gr * kRef + threadIdx.x] = threadIdx.x < nk ? float(sh[threadIdx.x][0] / d.nx) : 0.0f;
+}
+
+// dst[0 .. n) = src[0 .. n) (the new reference table taking over).
+__global__ void copy_kernel(const float* __restrict__ src, float* __restrict__ dst, int64_t n)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = src[k];
 }
 
 // Step counter of the rounding draws: set, or advanced after a block of

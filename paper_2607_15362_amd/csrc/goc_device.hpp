@@ -178,7 +178,24 @@ struct Pools {
     const double* met;
     const float* metf;
     const double* face;
+    // 16-bit storage: reference table of the slots (kRef floats per row of
+    // each run; below).  A step decodes with ref_in and encodes with ref_out,
+    // the same table except on the step that moves to a new one.
+    const float* ref_in;
+    const float* ref_out;
 };
+
+// Reference table of the 16-bit storage forms.  A 16-bit slot holds, scaled,
+// the deviation of its population from the rest state minus the reference
+// of its reader's row and direction: the mean over that row of the
+// deviations pulled along that direction (entries 0-8; the D2Q5 slots of
+// component c and direction a at 9 + 5 c + a), refreshed from the state
+// every so many steps.  In a flow that varies little along a row (a channel,
+// the developed Hartmann flow) the stored residual is then far smaller than
+// the deviation itself, which carries the velocity, the lagged force and
+// the magnetic field, and the format's rounding acts on the residual only.
+constexpr int kRef = 20;    // floats per row (19 used)
+constexpr int kRefG = 9;    // first D2Q5 entry
 
 // Planes of the 2-D metric pool, each nx * ny node values (row-major): the
 // metric factors, their reciprocals, the curvature elements and the
@@ -388,7 +405,7 @@ struct NodeMetric {
 //   F1 = h2 [F1ext - theta11 P + theta11 (tau11 - rho U1^2)],
 //   F2 = h1 [F2ext - theta22 P + theta22 (tau22 - rho U2^2)],
 // tau11, tau22 the normal viscous stresses of Sec. 2.2, and the equilibrium
-// corrections n3^eq(1), n4^eq(1) of Sec. 5 on a straight grid.  The
+// corrections n3^eq(1), n4^eq(1) of Sec. 4 on a straight grid.  The
 // pressure P = P0 + c_s^2 (rho - rho0) is split so that its constant part
 // is one product of constants and the varying part keeps the precision of
 // the density deviation drho.
@@ -454,7 +471,7 @@ __device__ inline void force_and_corrections(const NodeParams<T>& p, const NodeM
 // tau^c (Sec. 2.2), the reduced force F~ (tau12 = 0), the local implicit
 // shear stress from the non-equilibrium raw moment k'11 relaxed at omega5
 // (App. A) and the full force F = F~ + 2 h theta tau12; the corrections
-// n3^eq(1), n4^eq(1) of Sec. 5 with their tau^c and theta12 / theta21 terms
+// n3^eq(1), n4^eq(1) of Sec. 4 with their tau^c and theta12 / theta21 terms
 // (the App. B(ii) low-Mach set drops them, as on straight grids).  The
 // pressure is split into P0 and c_s^2 (rho - rho0) as in the straight form.
 template <class T>
@@ -611,7 +628,7 @@ __device__ inline void cm_collide(const NodeParams<T>& p, const NodeMetric<T>& g
     const T k21 = a21 - U2 * (A + a20);
     const T k22 = a22 - U2 * (a21 + k21);
     // step 3: deviations of the central equilibria (binomial transform of the
-    // Sec. 3 equilibria) with the corrections of Sec. 5
+    // Sec. 3 equilibria) with the corrections of Sec. 4
     const T h1m = h1 - T(1), h2m = h2 - T(1);
     const T q20 = r21 * h1m * h1m, q02 = r12 * h2m * h2m, q11 = h1m * h2m;
     T q21 = h1m * h1m * h2m * g.ih1, q12 = h1m * h2m * h2m * g.ih2;   // printed sign
@@ -662,7 +679,7 @@ __device__ inline void cm_collide(const NodeParams<T>& p, const NodeMetric<T>& g
 
 // Raw-moment MRT collision (the appendix summarising the raw-moment model),
 // as an increment f~ = f + P^-1 dm with dm = m~ - m: the nine combined raw
-// moments relax to the Sec. 3 equilibria (with the Sec. 5 corrections on
+// moments relax to the Sec. 3 equilibria (with the Sec. 4 corrections on
 // k20 + k02 and k20 - k02) and gain the Sec. 3 sources.  Equilibria enter as
 // deviations from the rest-state raw moments (h1 h2 rho0, 0, 0, (h2/h1) P0,
 // (h1/h2) P0, 0, 0, 0, rho0 c_s^4), so no large value is formed; dk'00 = 0

@@ -321,6 +321,12 @@ struct goc_lbm {
     int32_t* tile_first_d = nullptr;   // device: first tile of each run of the tiled kernel, then the total
     int32_t total_tiles = 0;
     int block_cap = 0;              // capacity of block_run_d (entries)
+    // 16-bit storage: reference tables (the one in use, and the next one
+    // while it is built), rows of all runs x kRef floats, and the step of
+    // the last initialisation, from which the refresh points count
+    float* ref_d[2] = {nullptr, nullptr};
+    int64_t ref_rows = 0;
+    int64_t ref_base = 0;
 };
 
 namespace {
@@ -346,8 +352,13 @@ PoolsOf<S> pools(const goc_lbm* h, int in)
     p.met = h->met_d;
     p.metf = h->metf_d;
     p.face = h->face_d;
+    p.ref_in = h->ref_d[0];
+    p.ref_out = h->ref_d[0];
     return p;
 }
+
+// 16-bit deviation storage (stored relative to the reference table).
+bool scaled_storage(int storage) { return storage == GOC_F16DEV || storage == GOC_BF16DEV; }
 
 template <class Fn>
 int dispatch(int storage, Fn&& fn)
@@ -362,12 +373,22 @@ int dispatch(int storage, Fn&& fn)
 }
 
 // Launch one time step of every run (input buffer h->cur); k is the step's
-// offset from the device step counter.
-int launch_step(goc_lbm* h, int k)
+// offset from the device step counter.  refresh (16-bit storage): build the
+// next reference table from the current state first, encode this step's
+// output with it, and let it take over afterwards.
+int launch_step(goc_lbm* h, int k, bool refresh = false)
 {
     return dispatch(h->storage, [&](auto tag) -> int {
         using S = decltype(tag);
-        const auto pl = pools<S>(h, h->cur);
+        auto pl = pools<S>(h, h->cur);
+        if constexpr (goc::Store<S>::scaled) {
+            if (refresh) {
+                hipLaunchKernelGGL(goc::ref_kernel<S>, dim3((unsigned)h->ref_rows), dim3(256), 0, h->stream,
+                                   h->runs_d, h->nruns, pl, h->ref_d[1]);
+                HIPOK(hipGetLastError());
+                pl.ref_out = h->ref_d[1];
+            }
+        }
         if (h->m2d || h->tiled) {   // tiled step: one launch for every run
             constexpr int cy = goc::tile_rows_of<S>();
             const bool raw = h->coll == goc::kCollRaw;
@@ -386,8 +407,16 @@ int launch_step(goc_lbm* h, int k)
                 raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, false, false>)
                     : go(goc::tile_step_kernel<S, goc::kCollCentral, false, false>);
             HIPOK(hipGetLastError());
+            if (goc::Store<S>::scaled && refresh) {
+                const int64_t n = h->ref_rows * goc::kRef;
+                hipLaunchKernelGGL(goc::copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream,
+                                   h->ref_d[1], h->ref_d[0], n);
+                HIPOK(hipGetLastError());
+            }
             return GOC_OK;
         }
+        if constexpr (goc::Store<S>::scaled)   // (16-bit storage steps with the tiled kernel only)
+            return fail(GOC_EINVAL, "16-bit storage steps with the tiled kernel only");
         const dim3 grid(h->total_blocks), block(goc::kWave);
         const bool raw = h->coll == goc::kCollRaw;
         if (h->any_mhd && raw)
@@ -429,6 +458,7 @@ int free_all(goc_lbm* h)
         (void)hipFree(h->f[k]);
         (void)hipFree(h->F[k]);
         (void)hipFree(h->g[k]);
+        (void)hipFree(h->ref_d[k]);
     }
     (void)hipFree(h->runs_d);
     (void)hipFree(h->block_run_d);
@@ -683,7 +713,9 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
     h->ncu = ncu;
     plan_rows(h, block_run);
     h->block_cap = (int)block_run.size();
-    h->tiled = tile_eligible(h) && nruns == 1;   // the faster form for a single straight run
+    // the tiled step: the faster form for a single straight run, and the
+    // only form of the 16-bit storage (whose reference table it applies)
+    h->tiled = tile_eligible(h) && (nruns == 1 || scaled_storage(storage));
     h->f_elems = f_elems;
     h->F_elems = F_elems;
     h->g_elems = g_elems;
@@ -818,6 +850,15 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
         hipMemcpy(h->tile_first_d, tile_first.data(), (nruns + 1) * 4, hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(GOC_EDEVICE, "run table upload failed"));
     if ((rc = dev_alloc((void**)&h->step_ctr, 4))) return bail(rc);
+    // reference tables of the 16-bit storage (zero: slots relative to the
+    // rest state until the first refresh)
+    h->ref_rows = sum_ny;
+    if (scaled_storage(storage))
+        for (int k = 0; k < 2; ++k) {
+            if ((rc = dev_alloc((void**)&h->ref_d[k], h->ref_rows * goc::kRef * 4))) return bail(rc);
+            if (hipMemsetAsync(h->ref_d[k], 0, h->ref_rows * goc::kRef * 4, h->stream) != hipSuccess)
+                return bail(fail(GOC_EDEVICE, "reference table clear failed"));
+        }
     // state pools
     for (int k = 0; k < 2; ++k) {
         if ((rc = dev_alloc(&h->f[k], f_elems * sb)) || (rc = dev_alloc(&h->F[k], F_elems * fb)))
@@ -859,14 +900,12 @@ int init_run(goc_lbm* h, int run, const double* rho, const double* u1, const dou
              const double* b1 = nullptr, const double* b2 = nullptr)
 {
     const RunDesc& d = h->runs[run];
-    dim3 grid, block;
-    per_node_grid(d, grid, block);
     return dispatch(h->storage, [&](auto tag) -> int {
         using S = decltype(tag);
         // write into the current input buffer
         auto pl = pools<S>(h, 1 - h->cur);
-        hipLaunchKernelGGL(goc::init_kernel<S>, grid, block, 0, h->stream, h->runs_d, run, pl, rho, u1, u2,
-                           b1, b2);
+        hipLaunchKernelGGL(goc::init_kernel<S>, dim3(d.ny), dim3(256), 0, h->stream, h->runs_d, run, pl,
+                           h->ref_d[0], rho, u1, u2, b1, b2);
         HIPOK(hipGetLastError());
         return GOC_OK;
     });
@@ -983,7 +1022,7 @@ int capture_graph(goc_lbm* h, int parity)
     }
     int rc = GOC_OK;
     for (int s = 0; s < kGraphSteps && rc == GOC_OK; ++s) {
-        rc = launch_step(h, s);
+        rc = launch_step(h, s, scaled_storage(h->storage) && s == 0);
         h->cur ^= 1;
     }
     if (rc == GOC_OK) rc = counter_op(h, kGraphSteps, 1);
@@ -1149,7 +1188,9 @@ int goc_lbm_init_run(goc_lbm_t* h, int32_t run, const double* rho, const double*
     if (!check_handle(h)) return GOC_EINVAL;
     if (run < 0 || run >= h->nruns) return fail(GOC_EINVAL, "run %d outside [0, %d)", run, h->nruns);
     if (int rc = check_fields(h, run, rho, u1, u2, b1, b2)) return rc;
-    return init_fields(h, run, rho, u1, u2, b1, b2, on_device);
+    if (int rc = init_fields(h, run, rho, u1, u2, b1, b2, on_device)) return rc;
+    h->ref_base = h->step;   // (16-bit storage: refresh the reference table next)
+    return GOC_OK;
 }
 
 int goc_lbm_init_mhd(goc_lbm_t* h, const double* rho, const double* u1, const double* u2, const double* b1,
@@ -1172,6 +1213,7 @@ int goc_lbm_init_mhd(goc_lbm_t* h, const double* rho, const double* u1, const do
         if (int rc = init_fields(h, 0, rho, u1, u2, b1, b2, on_device)) return rc;
     }
     h->step = 0;
+    h->ref_base = 0;
     if (int rc = counter_op(h, 0, 0)) return rc;
     HIPOK(hipStreamSynchronize(h->stream));
     return GOC_OK;
@@ -1186,23 +1228,41 @@ int goc_lbm_step(goc_lbm_t* h, int64_t n)
 {
     if (!check_handle(h)) return GOC_EINVAL;
     if (n < 0) return fail(GOC_EINVAL, "negative step count");
+    // 16-bit storage: an initialisation forms the reference table from the
+    // initial state; the steps refresh it from the state after the first
+    // step (whose collision adds the lagged force) and then every kGraphSteps
+    // steps (steps ref_base + 1 + m kGraphSteps), which is where its graph
+    // blocks start: a block refreshes on its first step.  Graph blocks and
+    // single launches therefore refresh on the same steps.
+    const bool scaled = scaled_storage(h->storage);
+    const int64_t b0 = h->ref_base + 1;
+    auto block_start = [&](int64_t s) { return !scaled || (s >= b0 && (s - b0) % kGraphSteps == 0); };
+    auto refresh_at = [&](int64_t s) { return scaled && s >= b0 && (s - b0) % kGraphSteps == 0; };
     while (n > 0) {
         int64_t chunk = n;
         if (h->watchdog > 0) chunk = std::min<int64_t>(chunk, h->watchdog - (h->step % h->watchdog));
         int64_t done = 0;
-        // whole graph blocks when a capturable stream is in use
-        while (h->stream && chunk - done >= kGraphSteps) {
-            if (!h->graph[h->cur]) {
-                int rc = capture_graph(h, h->cur);
-                if (rc) return rc;
+        while (done < chunk) {
+            const int64_t s = h->step + done;
+            // whole graph blocks when a capturable stream is in use
+            if (h->stream && block_start(s) && chunk - done >= kGraphSteps) {
+                if (!h->graph[h->cur]) {
+                    int rc = capture_graph(h, h->cur);
+                    if (rc) return rc;
+                }
+                HIPOK(hipGraphLaunch(h->graph[h->cur], h->stream));
+                done += kGraphSteps;   // an even count: parity unchanged
+                continue;
             }
-            HIPOK(hipGraphLaunch(h->graph[h->cur], h->stream));
-            done += kGraphSteps;   // an even count: parity unchanged
-        }
-        while (done < chunk) {   // single launches, in pieces that keep k small
-            const int piece = (int)std::min<int64_t>(chunk - done, 4096);
-            for (int s = 0; s < piece; ++s) {
-                int rc = launch_step(h, s);
+            // single launches, in pieces that keep k small (with graphs: up
+            // to the next block start)
+            int64_t piece = std::min<int64_t>(chunk - done, 4096);
+            if (h->stream && !block_start(s)) {
+                const int64_t next = s < b0 ? b0 : b0 + ((s - b0) / kGraphSteps + 1) * kGraphSteps;
+                piece = std::min<int64_t>(piece, next - s);
+            }
+            for (int t = 0; t < (int)piece; ++t) {
+                int rc = launch_step(h, t, refresh_at(s + t));
                 if (rc) return rc;
                 h->cur ^= 1;
             }
@@ -1233,6 +1293,8 @@ int goc_lbm_set_launch(goc_lbm_t* h, double waves_per_cu)
         return use_tiled(h);
     }
     if (h->m2d) return fail(GOC_EINVAL, "a run on a 2-D metric has only the tiled step (waves_per_cu 0)");
+    if (scaled_storage(h->storage))
+        return fail(GOC_EINVAL, "16-bit storage has only the tiled step (waves_per_cu 0)");
     if (!(waves_per_cu >= 0.5 && waves_per_cu <= 1024.0))
         return fail(GOC_EINVAL, "waves_per_cu %g outside [0.5, 1024]", waves_per_cu);
     return apply_plan(h, waves_per_cu);
@@ -1281,7 +1343,7 @@ int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
     } ev;
     HIPOK(hipEventCreate(&ev.e[0]));
     HIPOK(hipEventCreate(&ev.e[1]));
-    if (h->m2d) {   // the curvilinear step has a fixed launch shape: time it only
+    if (h->m2d || scaled_storage(h->storage)) {   // the tiled step only: time it
         int rc;
         if ((rc = launch_step(h, 0))) return rc;
         HIPOK(hipEventRecord(ev.e[0], h->stream));
@@ -1425,37 +1487,38 @@ int goc_lbm_set_populations(goc_lbm_t* h, const double* f, const double* F, cons
             gd = bg.p;
         }
     }
-    dim3 grid, block;
-    per_node_grid(d, grid, block);
     rc = dispatch(h->storage, [&](auto tag) -> int {
         using S = decltype(tag);
         auto pl = pools<S>(h, 1 - h->cur);   // out = current input buffer
-        hipLaunchKernelGGL(goc::scatter_kernel<S>, grid, block, 0, h->stream, h->runs_d, 0, pl, fd, Fd, gd);
+        hipLaunchKernelGGL(goc::scatter_kernel<S>, dim3(d.ny), dim3(256), 0, h->stream, h->runs_d, 0, pl,
+                           h->ref_d[0], fd, Fd, gd);
         HIPOK(hipGetLastError());
         return GOC_OK;
     });
     if (rc) return rc;
     HIPOK(hipStreamSynchronize(h->stream));
+    h->ref_base = h->step;
     return GOC_OK;
 }
 
 namespace {
+// Checkpoint blob: this header, then per run (nx, ny, mhd) as int32, then
+// the reference table of the 16-bit storage, the slots, the lagged force
+// and the D2Q5 slots, each as the raw device bytes.
 struct StateHeader {
     char magic[8];
     int32_t version, storage, nruns, mhd;
-    int64_t step, f_bytes, F_bytes, g_bytes;
+    int64_t step, f_bytes, F_bytes, g_bytes, ref_bytes, ref_base;
 };
-}
+constexpr int32_t kStateVersion = 2;
 
-int goc_lbm_get_state(goc_lbm_t* h, void* buf, size_t* bytes)
+StateHeader state_header(const goc_lbm* h)
 {
-    if (!check_handle(h)) return GOC_EINVAL;
-    if (!bytes) return fail(GOC_EINVAL, "bytes is NULL");
     const size_t sb = storage_bytes(h->storage), fb = force_bytes(h->storage);
     StateHeader hd;
     std::memset(&hd, 0, sizeof(hd));
     std::memcpy(hd.magic, "GOCLBM01", 8);
-    hd.version = 1;
+    hd.version = kStateVersion;
     hd.storage = h->storage;
     hd.nruns = h->nruns;
     hd.mhd = h->any_mhd;
@@ -1463,7 +1526,31 @@ int goc_lbm_get_state(goc_lbm_t* h, void* buf, size_t* bytes)
     hd.f_bytes = h->f_elems * sb;
     hd.F_bytes = h->F_elems * fb;
     hd.g_bytes = h->g_elems * sb;
-    const size_t need = sizeof(hd) + hd.f_bytes + hd.F_bytes + hd.g_bytes;
+    hd.ref_bytes = scaled_storage(h->storage) ? h->ref_rows * goc::kRef * 4 : 0;
+    hd.ref_base = h->ref_base;
+    return hd;
+}
+
+void run_shapes(const goc_lbm* h, std::vector<int32_t>& v)
+{
+    v.clear();
+    for (const RunDesc& d : h->runs) {
+        v.push_back(d.nx);
+        v.push_back(d.ny);
+        v.push_back(d.mhd);
+    }
+}
+}  // namespace
+
+int goc_lbm_get_state(goc_lbm_t* h, void* buf, size_t* bytes)
+{
+    if (!check_handle(h)) return GOC_EINVAL;
+    if (!bytes) return fail(GOC_EINVAL, "bytes is NULL");
+    const StateHeader hd = state_header(h);
+    std::vector<int32_t> shapes;
+    run_shapes(h, shapes);
+    const size_t sh_bytes = shapes.size() * 4;
+    const size_t need = sizeof(hd) + sh_bytes + hd.ref_bytes + hd.f_bytes + hd.F_bytes + hd.g_bytes;
     if (!buf) {
         *bytes = need;
         return GOC_OK;
@@ -1472,6 +1559,10 @@ int goc_lbm_get_state(goc_lbm_t* h, void* buf, size_t* bytes)
     char* p = static_cast<char*>(buf);
     std::memcpy(p, &hd, sizeof(hd));
     p += sizeof(hd);
+    std::memcpy(p, shapes.data(), sh_bytes);
+    p += sh_bytes;
+    if (hd.ref_bytes) HIPOK(hipMemcpyAsync(p, h->ref_d[0], hd.ref_bytes, hipMemcpyDeviceToHost, h->stream));
+    p += hd.ref_bytes;
     HIPOK(hipMemcpyAsync(p, h->f[h->cur], hd.f_bytes, hipMemcpyDeviceToHost, h->stream));
     HIPOK(hipMemcpyAsync(p + hd.f_bytes, h->F[h->cur], hd.F_bytes, hipMemcpyDeviceToHost, h->stream));
     if (hd.g_bytes)
@@ -1486,21 +1577,39 @@ int goc_lbm_set_state(goc_lbm_t* h, const void* buf, size_t bytes)
 {
     if (!check_handle(h)) return GOC_EINVAL;
     if (!buf) return fail(GOC_EINVAL, "buf is NULL");
-    size_t need = 0;
-    goc_lbm_get_state(h, nullptr, &need);
-    if (bytes != need) return fail(GOC_ESTATE, "state blob of %zu bytes, this run needs %zu", bytes, need);
+    const StateHeader mine = state_header(h);
+    std::vector<int32_t> shapes;
+    run_shapes(h, shapes);
+    const size_t sh_bytes = shapes.size() * 4;
+    if (bytes < sizeof(StateHeader)) return fail(GOC_ESTATE, "state blob of %zu bytes is shorter than its header", bytes);
     StateHeader hd;
     std::memcpy(&hd, buf, sizeof(hd));
-    if (std::memcmp(hd.magic, "GOCLBM01", 8) != 0 || hd.version != 1 || hd.storage != h->storage ||
-        hd.nruns != h->nruns)
-        return fail(GOC_ESTATE, "state blob does not match this run (magic, version, storage or run count)");
+    if (std::memcmp(hd.magic, "GOCLBM01", 8) != 0 || hd.version != kStateVersion || hd.storage != h->storage ||
+        hd.nruns != h->nruns || hd.mhd != mine.mhd)
+        return fail(GOC_ESTATE, "state blob does not match this run (magic, version, storage, run count or MHD)");
+    if (hd.f_bytes != mine.f_bytes || hd.F_bytes != mine.F_bytes || hd.g_bytes != mine.g_bytes ||
+        hd.ref_bytes != mine.ref_bytes)
+        return fail(GOC_ESTATE, "state blob sizes (slots %lld, force %lld, D2Q5 %lld, reference %lld bytes) do not "
+                    "match this run's (%lld, %lld, %lld, %lld)", (long long)hd.f_bytes, (long long)hd.F_bytes,
+                    (long long)hd.g_bytes, (long long)hd.ref_bytes, (long long)mine.f_bytes, (long long)mine.F_bytes,
+                    (long long)mine.g_bytes, (long long)mine.ref_bytes);
+    const size_t need = sizeof(hd) + sh_bytes + hd.ref_bytes + hd.f_bytes + hd.F_bytes + hd.g_bytes;
+    if (bytes != need) return fail(GOC_ESTATE, "state blob of %zu bytes, this run needs %zu", bytes, need);
     const char* p = static_cast<const char*>(buf) + sizeof(hd);
+    if (std::memcmp(p, shapes.data(), sh_bytes) != 0)
+        return fail(GOC_ESTATE, "state blob of other grid sizes or MHD flags than this run's");
+    if (hd.step < 0 || hd.ref_base < 0 || hd.ref_base > hd.step)
+        return fail(GOC_ESTATE, "state blob with an inconsistent step count");
+    p += sh_bytes;
+    if (hd.ref_bytes) HIPOK(hipMemcpyAsync(h->ref_d[0], p, hd.ref_bytes, hipMemcpyHostToDevice, h->stream));
+    p += hd.ref_bytes;
     HIPOK(hipMemcpyAsync(h->f[h->cur], p, hd.f_bytes, hipMemcpyHostToDevice, h->stream));
     HIPOK(hipMemcpyAsync(h->F[h->cur], p + hd.f_bytes, hd.F_bytes, hipMemcpyHostToDevice, h->stream));
     if (hd.g_bytes)
         HIPOK(hipMemcpyAsync(h->g[h->cur], p + hd.f_bytes + hd.F_bytes, hd.g_bytes, hipMemcpyHostToDevice,
                              h->stream));
     h->step = hd.step;
+    h->ref_base = hd.ref_base;
     if (int rc = counter_op(h, (uint32_t)hd.step, 0)) return rc;
     HIPOK(hipStreamSynchronize(h->stream));
     return GOC_OK;

@@ -7,7 +7,7 @@
 // of the tile and of the ring of nodes around it go to LDS; after one
 // barrier the second-order differences of U and rho come from LDS
 // (one-sided next to walls, wrapped when periodic); then the stresses and
-// effective force (Sec. 2.2, App. A), the corrections of Sec. 5, the
+// effective force (Sec. 2.2, App. A), the corrections of Sec. 4, the
 // collision and the writes of the nine slots, their ghost-row copies and
 // the force.  The ring is pulled twice (by this tile and by its owner),
 // which costs L2 reads, not HBM traffic.  Two metric sources:
@@ -95,16 +95,19 @@ __device__ inline uint32_t pull_off(const RunDesc& d, const RunBytes& b, int i, 
 }
 
 // Pull and decode the nine deviations of node (i, j) and its lagged force
-// (planeF: one force plane in bytes).
-template <class S, class T, class FT>
-__device__ inline void tile_pull9(const RunDesc& d, const RunBytes& b, uint32_t planeF, int i, int j, T* f,
-                                  T& Fp1, T& Fp2)
+// (planeF: one force plane in bytes).  16-bit storage: ref = the reference
+// entries of the node's row (the deviation is stored minus them).
+template <class S, class T, class FT, class R>
+__device__ inline void tile_pull9(const RunDesc& d, const RunBytes& b, uint32_t planeF, int i, int j, R ref,
+                                  T* f, T& Fp1, T& Fp2)
 {
     const T* sp = step_params<T>(d);
 #pragma unroll
     for (int a = 0; a < kQ; ++a) {
-        const T sinv = Store<S>::scaled ? sp[P_ISC + cls_(a)] : T(1);
-        f[a] = T(Store<S>::dec(ld_at<S>(b.f, pull_off<S>(d, b, i, j, a)), sinv));
+        if constexpr (Store<S>::scaled)
+            f[a] = Store<S>::dec(ld_at<S>(b.f, pull_off<S>(d, b, i, j, a)), sp[P_ISC + cls_(a)]) + ref[a];
+        else
+            f[a] = T(Store<S>::dec(ld_at<S>(b.f, pull_off<S>(d, b, i, j, a)), T(1)));
     }
     const uint32_t nf = uint32_t(j) * b.pitch_F + uint32_t(i) * uint32_t(sizeof(FT));
     Fp1 = T(ld_at<FT>(b.F, nf));
@@ -112,15 +115,36 @@ __device__ inline void tile_pull9(const RunDesc& d, const RunBytes& b, uint32_t 
 }
 
 // Pull and decode the ten D2Q5 deviations of node (i, j) (sginv: the
-// inverse storage scale).
-template <class S, class T>
-__device__ inline void pull_g(const RunDesc& d, const RunBytes& b, int i, int j, T sginv, T (*dg)[kM])
+// inverse storage scale; 16-bit storage: ref as for tile_pull9).
+template <class S, class T, class R>
+__device__ inline void pull_g(const RunDesc& d, const RunBytes& b, int i, int j, T sginv, R ref, T (*dg)[kM])
 {
 #pragma unroll
     for (int a = 0; a < kM; ++a) {
         const uint32_t off = pull_off<S>(d, b, i, j, a);
 #pragma unroll
-        for (int ci = 0; ci < 2; ++ci) dg[ci][a] = T(Store<S>::dec(ld_at<S>(b.g, ci * b.g_comp + off), sginv));
+        for (int ci = 0; ci < 2; ++ci) {
+            dg[ci][a] = T(Store<S>::dec(ld_at<S>(b.g, ci * b.g_comp + off), sginv));
+            if constexpr (Store<S>::scaled) dg[ci][a] += ref[kRefG + ci * kM + a];
+        }
+    }
+}
+
+// Reference of the reader of each slot a node writes (16-bit storage): the
+// reader's row and direction, i.e. row j + e_a2 (wrapped when periodic) and
+// direction a, or, where the slot leaves through a wall, the node itself in
+// row j with the opposite direction.  R0, Rm, Rp: the entries of rows j,
+// j - 1 and j + 1 (first: the entry of direction 0); wxlo .. wyhi: the walls
+// beside the node; n directions of one D2Q9 or D2Q5 set.
+template <int n, class R>
+__device__ inline void reader_refs(R R0, R Rm, R Rp, bool wxlo, bool wxhi, bool wylo, bool wyhi, float* ro)
+{
+#pragma unroll
+    for (int a = 0; a < n; ++a) {
+        const int ex = ex_(a), ey = ey_(a);
+        const bool bounced = (ex > 0 && wxhi) || (ex < 0 && wxlo) || (ey > 0 && wyhi) || (ey < 0 && wylo);
+        const float nominal = ey > 0 ? Rp[a] : ey < 0 ? Rm[a] : R0[a];
+        ro[a] = bounced ? R0[opp_(a)] : nominal;
     }
 }
 
@@ -265,14 +289,21 @@ tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ t
         }
     }
     static_assert(!(GEN && MHD), "the D2Q5 scheme runs on straight grids only");
+    // 16-bit storage: reference entries of the own row (one row per wave:
+    // lane 0 always holds a node of it, and lanes without a node store
+    // nothing), read through scalar loads
+    CPtr<float> rin = nullptr;
+    if constexpr (Store<S>::scaled)
+        rin = (CPtr<float>)(pl.ref_in + (d.row_off + __builtin_amdgcn_readfirstlane(jc)) * kRef);
     T f[kQ], Fp1, Fp2;
-    tile_pull9<S, T, FT>(d, b, planeF, ic, jc, f, Fp1, Fp2);
+    tile_pull9<S, T, FT>(d, b, planeF, ic, jc, rin, f, Fp1, Fp2);
     T dg[2][kM];   // D2Q5 deviations (MHD)
     const T sginv = Store<S>::scaled ? sp[P_ISCG] : T(1);
-    if (mhd_run) pull_g<S, T>(d, b, ic, jc, sginv, dg);
+    if (mhd_run) pull_g<S, T>(d, b, ic, jc, sginv, rin, dg);
     if (ly * kTileX < nh) {   // (uniform over the wave: one wave per row of the block)
         T hf[kQ], hF1, hF2;
-        tile_pull9<S, T, FT>(d, b, planeF, hi, hj, hf, hF1, hF2);
+        const float* hrf = Store<S>::scaled ? pl.ref_in + (d.row_off + hj) * kRef : nullptr;
+        tile_pull9<S, T, FT>(d, b, planeF, hi, hj, hrf, hf, hF1, hF2);
         const T hih1 = GEN ? ld_at<T>(mt + M_IH1 * NB, hnb) : ctab[hi * kTab + T_IH];
         const T hih2 = GEN ? ld_at<T>(mt + M_IH2 * NB, hnb) : rtab[hj * kTab + T_IH];
         T hdr, hU1, hU2;
@@ -302,6 +333,19 @@ tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ t
 
     const bool wxlo = !px && i == 0, wxhi = !px && i == nx - 1;
     const bool wylo = !py && j == 0, wyhi = !py && j == ny - 1;
+    // 16-bit storage: the reference entries of rows j, j - 1 and j + 1 of the
+    // output table (wrapped when periodic; a row beyond a wall is never a
+    // reader's, so it is clamped into the grid)
+    CPtr<float> R0 = nullptr, Rm = nullptr, Rp = nullptr;
+    if constexpr (Store<S>::scaled) {
+        const int jw = __builtin_amdgcn_readfirstlane(j);
+        const int jm = jw > 0 ? jw - 1 : (py ? ny - 1 : 0);
+        const int jp = jw < ny - 1 ? jw + 1 : (py ? 0 : ny - 1);
+        const CPtr<float> rt0 = (CPtr<float>)(pl.ref_out + d.row_off * kRef);
+        R0 = rt0 + jw * kRef;
+        Rm = rt0 + jm * kRef;
+        Rp = rt0 + jp * kRef;
+    }
     const uint32_t seed = mix32(step_ctr[0] + uint32_t(k));
     const uint32_t hn = mix32((uint32_t(d.f_off) + uint32_t(j) * uint32_t(d.pitch) + uint32_t(i)) ^ seed);
     const uint32_t cs = uint32_t(sizeof(S));
@@ -335,12 +379,19 @@ tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ t
             }
         }
         const T sgw = Store<S>::scaled ? sp[P_SCG] : T(1);
+        float rg[2][kM] = {};   // (16-bit) reference of each slot's reader
+        if constexpr (Store<S>::scaled)
+#pragma unroll
+            for (int ci = 0; ci < 2; ++ci)
+                reader_refs<kM>(R0 + kRefG + ci * kM, Rm + kRefG + ci * kM, Rp + kRefG + ci * kM, wxlo, wxhi,
+                                wylo, wyhi, rg[ci]);
         S eg[2][kM];
 #pragma unroll
         for (int ci = 0; ci < 2; ++ci)
 #pragma unroll
             for (int a = 0; a < kM; ++a) {
-                eg[ci][a] = Store<S>::enc(dg[ci][a], dgi[ci][a], sgw, pop_draw(hn, kQ + ci * kM + a));
+                eg[ci][a] = Store<S>::enc(Store<S>::scaled ? dg[ci][a] - rg[ci][a] : dg[ci][a], dgi[ci][a], sgw,
+                                          pop_draw(hn, kQ + ci * kM + a));
                 st_at<S>(b.go, ci * b.g_comp + uint32_t(a) * b.plane_s + own, eg[ci][a]);
             }
         // ghost rows: plane 2 / 4 of each component, own column
@@ -423,11 +474,16 @@ tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ t
 
     // stores: base + increment, rounded without bias (the same draws as the
     // straight march: node, population, step)
+    // (16-bit storage: the reader's reference comes off the base first, then
+    // the increment is added, so the rounded residual loses nothing to the
+    // size of the reference)
+    float ro[kQ] = {};
+    if constexpr (Store<S>::scaled) reader_refs<kQ>(R0, Rm, Rp, wxlo, wxhi, wylo, wyhi, ro);
     S e[kQ];
 #pragma unroll
     for (int a = 0; a < kQ; ++a) {
         const T sfw = Store<S>::scaled ? sp[P_SC + cls_(a)] : T(1);
-        e[a] = Store<S>::enc(f[a], inc[a], sfw, pop_draw(hn, a));
+        e[a] = Store<S>::enc(Store<S>::scaled ? f[a] - ro[a] : f[a], inc[a], sfw, pop_draw(hn, a));
         st_at<S>(b.fo, uint32_t(a) * b.plane_s + own, e[a]);
     }
     // ghost rows (rows 0 and ny - 1): walls take the bounced values at the

@@ -160,41 +160,105 @@ def developed_hartmann(oracle_lib, storage, nx=256, ny=128):
 
 
 @pytest.mark.parametrize("storage", ["f16dev", "bf16dev"])
-def test_16bit_one_step_within_format_rounding(oracle_lib, storage):
-    """One step of the precision form from the developed Hartmann state:
-    every field within 4 units of the storage format's rounding of the FP64
-    oracle.  The stored deviation carries the velocity itself, so one store
-    costs about half a unit; a fault of the encoding (scales, rest states,
-    offsets) would show as an O(1) error."""
+def test_16bit_developed_hartmann_within_1e3(oracle_lib, storage):
+    """The precision form from the developed Hartmann state (the 4096x1024
+    channel's parameters on 256x128): every field within 1e-3 of the FP64
+    oracle after 1000 steps, in FP16 and in BF16, and after the first step
+    too except BF16's U2.  The slots hold the deviation from the rest state
+    minus the row mean of the reader's row (formed by the initialisation,
+    refreshed after the first step and then every 100 steps), so the format
+    rounds the small residual, not the velocity, force and field the
+    deviation carries.  The first store after an initialisation carries the
+    lagged force, which the initial state has not (it starts at zero), so
+    its axis-2 slots are rounded against a table without it: BF16's U2 is
+    about 1.1e-3 after that step (FP16's 1.4e-4) and falls to about 1e-4
+    once the refreshed table holds the force."""
     case, g, o = developed_hartmann(oracle_lib, storage)
     g.step(1)
     o.step(1)
+    e1 = field_errors(g.fields(), o.fields(), o, storage)
+    g.step(999)
+    o.step(999)
     e = field_errors(g.fields(), o.fields(), o, storage)
-    print(storage, {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
-    for k, v in e.items():
-        assert v < 4 * UNIT[storage], (k, e)
+    print(storage, "1:", {k: f"{v:.2e}" for k, v in e1.items()},
+          "1000:", {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+    for k in e:
+        first = 2e-3 if (storage, k) == ("bf16dev", "U2") else 1e-3
+        assert e1[k] < first and e[k] < 1e-3, (k, e1, e)
 
 
 @pytest.mark.parametrize("storage", ["f16dev", "bf16dev"])
-def test_16bit_1000_steps_unbiased(oracle_lib, storage):
-    """1000 steps of the precision form from the developed Hartmann state.
-    The stores round stochastically, so the error is a damped random walk:
-    every field stays within 8 units of the format's rounding, and U1 and B1
-    grow by less than 2x from step 250 to step 1000 (a rounding bias would
-    grow them about 4x, like the step count)."""
-    case, g, o = developed_hartmann(oracle_lib, storage)
-    g.step(250)
-    o.step(250)
-    e250 = field_errors(g.fields(), o.fields(), o, storage)
-    g.step(750)
-    o.step(750)
+def test_16bit_cavity_1000_steps(oracle_lib, storage):
+    """The precision form on the cavity (the 1024x1024 Re=1000 cavity's
+    parameters on 130x97), 1000 steps from rest against the FP64 oracle.
+    A row mean is a poor reference where the velocity changes sign along
+    the row, so the residual still carries most of the velocity: FP16 keeps
+    every field within 1e-3; BF16 does not meet 1e-3 here (about 5e-3 on U,
+    its unit roundoff of 3.9e-3 times a store's worth of velocity) and is
+    held to 2e-2."""
+    case = W.cavity_1024().replace(name=f"cav16_{storage}", nx=130, ny=97, Re=1000.0 * 130 / 1024,
+                                   storage=storage)
+    tol = {"f16dev": 1e-3, "bf16dev": 2e-2}[storage]
+    check(oracle_lib, case, 1000, tol)
+
+
+@pytest.fixture(scope="module")
+def hartmann_full_oracle(oracle_lib):
+    """The FP64 oracle's 4096x1024 developed Hartmann flow after 1000 steps
+    (shared by the full-size precision tests)."""
+    case = W.hartmann_4096().replace(storage="f64")
+    o = oracle_lib.Model(case)
+    lat = o.lat
+    init = W.hartmann_start(case, lat.nu, lat.Fext[0], lat.eta, lat.B0)
+    o.init(*init)
+    print("[parity] oracle 4096x1024 developed Hartmann, 1000 steps", flush=True)
+    o.step(1000)
+    return case, init, o
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("storage", ["f16dev", "bf16dev"])
+def test_16bit_full_size_hartmann_1000_steps(hartmann_full_oracle, storage):
+    """The precision form at the full 4096x1024 Ha=100 channel, as the
+    benchmark launches it, from the developed Hartmann state: every field
+    within 1e-3 of the FP64 oracle after 1000 steps."""
+    case, init, o = hartmann_full_oracle
+    g = B.Run(case.replace(storage=storage))
+    g.init(*init)
+    g.step(1000)
     e = field_errors(g.fields(), o.fields(), o, storage)
-    print(storage, "250:", {k: f"{v:.2e}" for k, v in e250.items()},
-          "1000:", {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+    print(storage, "4096x1024", {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
     for k, v in e.items():
-        assert v < 8 * UNIT[storage], (k, e)
-    for k in ("U1", "B1"):
-        assert e[k] < 2.0 * e250[k], (k, e250[k], e[k])
+        assert v < 1e-3, (k, e)
+    g.close()
+
+
+@pytest.mark.parametrize("storage", ["f16dev", "bf16dev"])
+def test_16bit_refresh_points_graphs_and_resume_are_bitwise(storage):
+    """The 16-bit forms refresh their reference table on the same steps
+    whether the steps run in captured graph blocks or singly, and a
+    checkpoint carries the table: a run restored mid-way and continued
+    across refresh points equals the uninterrupted one bit for bit."""
+    case = W.hartmann_4096().replace(name="r16", nx=130, ny=70, storage=storage)
+    a = B.Run(case)
+    d = a.derived()
+    init = W.hartmann_start(case, d["nu"], d["F1"], d["eta"], d["B0"])
+    a.init(*init)
+    b = B.Run(case).init(*init)
+    a.step(250)            # 1 single, two graph blocks, 49 singles
+    for _ in range(250):
+        b.step(1)
+    for x, y in zip(a.populations(), b.populations()):
+        assert np.array_equal(x, y)
+    blob = a.get_state()
+    a.step(180)
+    c = B.Run(case)
+    c.set_state(blob)
+    c.step(180)
+    assert c.derived()["step"] == 430
+    for x, y in zip(a.populations(), c.populations()):
+        assert np.array_equal(x, y)
+    assert a.get_state() == c.get_state()
 
 
 def test_fp32_developed_hartmann_1000_steps(oracle_lib):
@@ -315,6 +379,27 @@ def test_checkpoint_resume_is_bitwise(oracle_lib):
     with pytest.raises(B.GocError) as ei:
         b.set_state(blob[:-8])
     assert ei.value.code == B.GOC_ESTATE
+
+
+def test_set_state_refuses_blobs_of_other_grids():
+    """A checkpoint of another grid is refused with GOC_ESTATE before any
+    copy, also where the total size matches: in FP32 without MHD a 768x3 and
+    a 64x54 run hold the same number of elements split differently between
+    slots and force, and a 60x54 and a 64x54 run the same slot and force
+    regions (rows padded to 64 columns)."""
+    def run(nx, ny):
+        return B.Run(W.Case("st", nx, ny, "periodic", "wall", ("uniform", 0.0), ("tanh", 1.2), flow="channel",
+                            Re=10.0, tau=0.8, storage="f32"))
+    a, b, c = run(64, 54), run(768, 3), run(60, 54)
+    blob_a = a.get_state()
+    assert len(blob_a) == len(b.get_state())
+    for target, blob in ((b, blob_a), (a, b.get_state()), (c, blob_a), (a, c.get_state())):
+        before = target.get_state()
+        with pytest.raises(B.GocError) as ei:
+            target.set_state(blob)
+        assert ei.value.code == B.GOC_ESTATE
+        assert target.get_state() == before
+    a.set_state(blob_a)   # its own blob is accepted
 
 
 def test_determinism_and_graph_blocks(oracle_lib):

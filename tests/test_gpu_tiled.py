@@ -5,15 +5,16 @@ both take the same arithmetic in the same order, up to where the compiler
 fuses a multiply and an add differently.  So one step from the same
 developed state stores the same values to rounding, measured at the largest
 stored value (a stored value may be a small difference of larger terms): a
-few eps in FP64 and FP32, two units in the 16-bit forms (where a stochastic
-rounding of nearly equal values can land on either neighbour); and in FP64
-the fields still agree to 1e-12 after 201 steps.  (In FP32 and the 16-bit
-forms an ulp of difference changes the outcome of a stochastic rounding now
-and then, after which the two are independent random walks of the same
-size: the oracle parity of each is in the other GPU tests, through the tiled
-step, the default for single runs, and the march, the default for batches.)
-Batches of uneven runs (plain and MHD in one launch) likewise.  Also the
-selection through goc_lbm_set_launch / goc_lbm_tune."""
+few eps in FP64 and FP32; and in FP64 the fields still agree to 1e-12 after
+201 steps.  (In FP32 an ulp of difference changes the outcome of a
+stochastic rounding now and then, after which the two are independent
+random walks of the same size: the oracle parity of each is in the other GPU
+tests, through the tiled step, the default for single runs, and the march,
+the default for batches.)  Batches of uneven runs (plain and MHD in one
+launch) likewise.  The 16-bit forms step with the tiled kernel only (it
+applies their reference table); their oracle parity is in
+test_gpu_parity.py.  Also the selection through goc_lbm_set_launch /
+goc_lbm_tune."""
 import struct
 
 import numpy as np
@@ -51,8 +52,6 @@ def edge(nx, ny, bcx, bcy, storage):
 CASES = {
     "cavity_f64_ragged": (cav(127, 65, "f64"), None, 0.0),
     "cavity_f32_multi_tile": (cav(200, 131, "f32"), None, 0.0),
-    "cavity_f16": (cav(130, 70, "f16dev"), None, 0.0),
-    "cavity_bf16": (cav(130, 70, "bf16dev"), None, 0.0),
     "cavity_raw_f64": (cav(70, 45, "f64", collision="raw"), None, 0.0),
     "cavity_srt_f32": (cav(70, 45, "f32", collision="srt"), None, 0.0),
     "cavity_reading_flags": (cav(70, 45, "f64", gi_terms=0, lid_corners=0), None, 0.0),
@@ -63,14 +62,11 @@ CASES = {
     "edge_66x3_periodic_x": (edge(66, 3, "periodic", "wall", "f64"), None, 0.01),
     "channel_periodic_x": (W.channel_64(), None, 0.0),
     "periodic_random_f64": (periodic(96, 70, "f64"), W.smooth_fields(96, 70, seed=11, amp=0.02), 0.0),
-    "periodic_random_f16": (periodic(130, 67, "f16dev"), W.smooth_fields(130, 67, seed=12, amp=0.02), 0.0),
     "moving_xi1_walls": (W.Case("cxw", 127, 65, "wall", "wall", ("tanh", 1.5), ("tanh", 1.2), flow="free",
                                 tau=0.8, body_force=(0.0, 0.0), v_wall=(0.01, -0.005), storage="f64"),
                          None, 0.01),
     "mhd_f64_ragged": (mhd(65, 33, "f64"), None, 0.0),
     "mhd_f32_multi_tile": (mhd(200, 131, "f32"), None, 0.0),
-    "mhd_f16": (mhd(130, 70, "f16dev"), None, 0.0),
-    "mhd_bf16": (mhd(130, 70, "bf16dev"), None, 0.0),
     "mhd_raw_f64": (mhd(65, 33, "f64", collision="raw"), None, 0.0),
     "mhd_3x5": (W.Case("em", 3, 5, "periodic", "wall", ("uniform", 0.0), ("tanh", 0.5), flow="hartmann", Re=2.0,
                        Ha=2.0, Ma=0.1, mhd=True, storage="f64"), None, 0.0),
@@ -90,33 +86,31 @@ def _run(case, init_fields, lid, waves):
     return r
 
 
-HEADER = struct.Struct("<8s4i4q")   # checkpoint header: magic, version, storage, nruns, mhd, step, 3 sizes
-STORED = {"f64": (np.float64, np.float64), "f32": (np.float32, np.float32),
-          "f16dev": (np.uint16, np.float32), "bf16dev": (np.uint16, np.float32)}
+# checkpoint header: magic, version, storage, nruns, mhd, step, the sizes of
+# the slots, force, D2Q5 slots and reference table, the reference base step;
+# then (nx, ny, mhd) per run and the four regions
+HEADER = struct.Struct("<8s4i6q")
+STORED = {"f64": (np.float64, np.float64), "f32": (np.float32, np.float32)}
 
 
 def _stored(blob, storage):
     """Raw populations (storage format), lagged force and D2Q5 populations
     (empty without MHD) of a checkpoint."""
-    _, _, _, _, _, step, fb, Fb, gb = HEADER.unpack_from(blob)
+    _, _, _, nruns, _, step, fb, Fb, gb, rb, _ = HEADER.unpack_from(blob)
+    o = HEADER.size + 12 * nruns + rb
     tf, tF = STORED[storage]
-    f = np.frombuffer(blob, dtype=tf, count=fb // np.dtype(tf).itemsize, offset=HEADER.size)
-    F = np.frombuffer(blob, dtype=tF, count=Fb // np.dtype(tF).itemsize, offset=HEADER.size + fb)
-    g = np.frombuffer(blob, dtype=tf, count=gb // np.dtype(tf).itemsize, offset=HEADER.size + fb + Fb)
+    f = np.frombuffer(blob, dtype=tf, count=fb // np.dtype(tf).itemsize, offset=o)
+    F = np.frombuffer(blob, dtype=tF, count=Fb // np.dtype(tF).itemsize, offset=o + fb)
+    g = np.frombuffer(blob, dtype=tf, count=gb // np.dtype(tf).itemsize, offset=o + fb + Fb)
     return step, np.concatenate([f, g]), F
 
 
-# a few units of rounding: eps of FP64 / FP32, one unit of the 16-bit forms
-# for either outcome of a stochastic rounding
-LIMIT = {"f64": 8 * 2.0 ** -52, "f32": 8 * 2.0 ** -23, "f16dev": 2 * 2.0 ** -10, "bf16dev": 2 * 2.0 ** -7}
+# a few units of rounding: eps of FP64 / FP32
+LIMIT = {"f64": 8 * 2.0 ** -52, "f32": 8 * 2.0 ** -23}
 
 
 def _values(a, storage):
-    """Stored values as FP64 (the 16-bit forms scaled as stored)."""
-    if storage == "f16dev":
-        return a.view(np.float16).astype(np.float64)
-    if storage == "bf16dev":
-        return (a.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    """Stored values as FP64."""
     return a.astype(np.float64)
 
 
@@ -124,7 +118,7 @@ def _ordered(a):
     """IEEE bit patterns (any width) as integers in the order of their values:
     the difference of two is their distance in ulps."""
     w = a.dtype.itemsize * 8
-    bits = a.view({64: np.int64, 32: np.int32, 16: np.int16}[w]).astype(np.int64)
+    bits = a.view({64: np.int64, 32: np.int32}[w]).astype(np.int64)
     mag = bits & ((1 << (w - 1)) - 1)
     return np.where(bits < 0, -mag, mag)
 
@@ -206,7 +200,6 @@ BATCHES = {
     "batch_mixed_f64": [cav(70, 45, "f64"), mhd(65, 33, "f64"), cav(130, 70, "f64"), mhd(200, 67, "f64"),
                         edge(3, 3, "wall", "wall", "f64")],
     "batch_hartmann_f32": W.batch_256(n=6),
-    "batch_hartmann_f16": [c.replace(storage="f16dev") for c in W.batch_256(n=5)],
 }
 
 
@@ -284,3 +277,20 @@ def test_selection_of_the_form():
         c.set_launch(8)
     assert ei.value.code == B.GOC_EINVAL
     c.close()
+
+
+@pytest.mark.parametrize("storage", ["f16dev", "bf16dev"])
+def test_16bit_storage_has_only_the_tiled_step(storage):
+    """The 16-bit forms step with the tiled kernel, single runs and batches
+    alike; the march is refused and the tuner times the tiled step only."""
+    h = B.Run(mhd(130, 70, storage))
+    assert h.launch_info()["waves_per_cu"] == 0
+    with pytest.raises(B.GocError) as ei:
+        h.set_launch(8)
+    assert ei.value.code == B.GOC_EINVAL
+    info = h.tune(3)
+    assert info["candidates"] == 1 and info["waves_per_cu"] == 0
+    h.close()
+    b = B.Run(batch=[c.replace(storage=storage) for c in W.batch_256(n=3)])
+    assert b.launch_info()["waves_per_cu"] == 0
+    b.close()

@@ -1,7 +1,7 @@
 """GPU parity of the two collision variants (raw-moment MRT and SRT) through
 the C-ABI against the FP64 oracle's own implementations of them, at the
 tolerances of the central-moment model: 1e-12 in FP64, 1e-5 after 1000 FP32
-steps, a few units of the format's rounding for the 16-bit storage.  The
+steps, 1e-3 after 1000 steps of the 16-bit storage.  The
 oracle computes SRT in velocity space (f^eq and S as P^-1 of their moments,
 with its own coefficients G_j, H_j); the library runs it as the raw-moment
 body with equal rates."""
@@ -88,14 +88,16 @@ def test_variant_fp32_developed_hartmann_1000_steps(oracle_lib, collision):
 
 
 @pytest.mark.parametrize("storage", ["f16dev", "bf16dev"])
-def test_raw_16bit_one_step_within_format_rounding(oracle_lib, storage):
+def test_raw_16bit_developed_hartmann_1000_steps(oracle_lib, storage):
+    """The raw-moment body in the precision form: every field within 1e-3 of
+    the FP64 oracle after 1000 steps from the developed Hartmann state."""
     g, o = _developed(oracle_lib, "raw", storage)
-    g.step(1)
-    o.step(1)
+    g.step(1000)
+    o.step(1000)
     e = G.field_errors(g.fields(), o.fields(), o, storage)
     print("raw", storage, {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
     for k, v in e.items():
-        assert v < 4 * G.UNIT[storage], (k, e)
+        assert v < 1e-3, (k, e)
 
 
 @pytest.mark.parametrize("collision", VARIANTS)
