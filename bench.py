@@ -2,35 +2,42 @@
 """Benchmark of the GOC-LBM hot path on one MI355X.
 
 One step = one pass of the whole hot path (one fused collide-and-stream
-kernel launch of the central-moment GOC-LBM, plus the D2Q5 induction sweep
-for MHD workloads) over the synthetic workload, inputs resident in HBM.
+kernel launch of the central-moment GOC-LBM with the coupled D2Q5 induction
+sweep) over the synthetic workload, inputs resident in HBM.  The headline
+workload is the 4096 x 1024 Ha = 100 Hartmann channel in plain FP32
+(D2Q9 + D2Q5, 168 algorithmic bytes per node, a 0.7 GB state that does not
+fit in the 256 MB Infinity Cache).
 
 Prints ONE JSON line:
   metric / value / unit      MLUPS of the workload (whole job, one GPU)
   roofline                   HBM roofline of the step kernel: algorithmic
                              bytes per launch / mean launch time (HIP events
-                             on the launch stream) against 8 TB/s, plus the
-                             measured HBM traffic when a counter profile of
-                             the current kernel source is committed
-  cpu_baseline               the FP64 oracle on the host cores, on a bounded
-                             sample of the same workload
-  forms                      the same GPU on the 4096x1024 MHD workload in
-                             FP32 and the FP16 / BF16 deviation-storage forms,
-                             with their field errors against the FP32 run
+                             on the launch stream) against 8 TB/s, and the
+                             measured HBM traffic per launch when a counter
+                             profile of the current kernel source is
+                             committed under profiles/
+  cpu_baseline               the FP64 oracle on the host cores (all of them,
+                             and one), on a bounded sample of the workload
+  forms                      the same GPU on the same workload in FP32 and the
+                             FP16 / BF16 deviation-storage forms, from the
+                             developed Hartmann flow, with their field
+                             differences from the FP32 run
   batched                    the seeded 256-run batch in one launch per step
                              against the same runs one after another
-  collisions                 the main workload with the raw-moment MRT and the
-                             SRT collision bodies instead of the central-moment
-                             one (same data path, same launch)
-  curvilinear                the curvilinear step (general 2-D metric, one
-                             launch per step) on a 2048x512 conformal annular
-                             sector, FP32, with its algorithmic bytes
+  collisions                 the workload with the raw-moment MRT and the SRT
+                             collision bodies instead of the central-moment one
+  curvilinear                the curvilinear step (general 2-D metric) on a
+                             2048x512 conformal annular sector, FP32
+  cache_resident             the 1024x1024 Re = 1000 cavity in FP32, whose
+                             92 MB state stays in the Infinity Cache: its
+                             bytes per second are not an HBM figure
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -56,11 +63,18 @@ def kernel_name(launch) -> str:
     return "goc::tile_step_kernel" if launch["waves_per_cu"] == 0 else "goc::step_kernel"
 
 
-def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of a kernel on a workload from a committed
-    rocprofv3 counter summary, if it was taken on the current kernel source;
+def form_tag(launch) -> str:
+    """Short name of a step form, as the profile summaries are named."""
+    if launch["waves_per_cu"] == 0:
+        return f"tiled{int(launch['rows_per_segment'])}{'nt' if launch['nontemporal'] else ''}"
+    return f"march{launch['waves_per_cu']:g}"
+
+
+def measured_traffic(kernel: str, workload: str, tag: str):
+    """HBM bytes per launch of a kernel in a step form on a workload, from a
+    committed rocprofv3 counter summary taken on the current kernel source;
     else None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel.split('::')[-1]}_{workload}_pmc.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel.split('::')[-1]}_{workload}_{tag}_pmc.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -71,6 +85,7 @@ def measured_traffic(kernel: str, workload: str):
 
 
 def time_run(run, steps: int, warmup: int):
+    """Wall time and HIP-event time (on the run's stream) of `steps` steps."""
     from paper_2607_15362_amd import binding as B
     run.step(warmup)
     run.synchronize()
@@ -85,21 +100,30 @@ def time_run(run, steps: int, warmup: int):
 
 
 def cpu_baseline(case, seconds: float):
-    """The FP64 oracle, untuned, on the host cores: full grid of the same
-    workload, as many steps as fit in about `seconds`."""
+    """The FP64 oracle, untuned, on the host cores (all of them, then one):
+    full grid of the same workload, as many steps as fit in about `seconds`
+    each, after one untimed step."""
     import oracle
-    m = oracle.Model(case).init()
-    t0 = time.perf_counter()
-    m.step(1)
-    t1 = time.perf_counter() - t0
-    n = max(1, int(seconds / max(t1, 1e-6)))
-    t0 = time.perf_counter()
-    m.step(n)
-    dt = time.perf_counter() - t0
-    return {"value": case.nx * case.ny * n / dt / 1e6, "unit": "MLUPS", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"{n} steps of the full {case.nx}x{case.ny} {case.name} grid in FP64 "
-                      f"({dt:.1f} s), after one untimed step"}
+    all_cores = oracle.threads()
+    out = {}
+    for label, n_threads in (("all", all_cores), ("one", 1)):
+        oracle.set_threads(n_threads)
+        m = oracle.Model(case).init()
+        t0 = time.perf_counter()
+        m.step(1)
+        t1 = time.perf_counter() - t0
+        n = max(1, int(seconds / max(t1, 1e-6)))
+        t0 = time.perf_counter()
+        m.step(n)
+        dt = time.perf_counter() - t0
+        out[label] = (case.nx * case.ny * n / dt / 1e6, n, dt)
+    oracle.set_threads(all_cores)
+    v, n, dt = out["all"]
+    v1, n1, dt1 = out["one"]
+    return {"value": v, "unit": "MLUPS", "cores": all_cores, "kind": "oracle",
+            "sample": f"{n} steps of the full {case.nx}x{case.ny} {case.name} grid in FP64 on {all_cores} "
+                      f"threads ({dt:.1f} s), and {n1} on one ({dt1:.1f} s), each after one untimed step",
+            "one_core_value": v1}
 
 
 def copy_calibration(mib: int, reps: int):
@@ -121,28 +145,35 @@ def copy_calibration(mib: int, reps: int):
                       "GB_s": round(8 * n / dt / 1e9, 1)}), flush=True)
 
 
-def storage_forms(steps: int):
-    """The 4096x1024 Ha=100 channel in plain FP32 and in the FP16 / BF16
-    deviation-storage forms on the same GPU, each started from the
-    closed-form developed Hartmann flow: throughput, bytes moved, and the
-    relative L2 difference of every field from the plain FP32 run after the
-    same number of steps."""
+def developed(run, case):
+    """Start a Hartmann run from its closed-form developed flow."""
+    from paper_2607_15362_amd import workloads as W
+    d = run.derived()
+    run.init(*W.hartmann_start(case, d["nu"], d["F1"], d["eta"], d["B0"]))
+
+
+def storage_forms(case, steps: int):
+    """The workload in plain FP32 and in the FP16 / BF16 deviation-storage
+    forms on the same GPU, each started from the closed-form developed
+    Hartmann flow: throughput, bytes moved, and the relative L2 difference of
+    every field from the plain FP32 run after the same number of steps."""
     import numpy as np
     from paper_2607_15362_amd import binding as B
-    from paper_2607_15362_amd import workloads as W
-    n = max(200, steps // 10)
+    n = max(600, steps // 4)
     forms, ref = {}, None
     for st in ("f32", "f16dev", "bf16dev"):
-        c = W.hartmann_4096_precision(st) if st != "f32" else W.hartmann_4096()
+        c = case.replace(name=case.name if st == "f32" else f"{case.name}_{st}", storage=st)
         r = B.Run(c)
-        dd = r.derived()
-        r.init(*W.hartmann_start(c, dd["nu"], dd["F1"], dd["eta"], dd["B0"]))
+        developed(r, c)
         tuned = r.tune(50)
+        li = r.launch_info()
         w, e = time_run(r, n, 100)
+        dd = r.derived()
         fl = r.fields()
         forms[st] = {"workload": c.name, "steps": n + 100, "MLUPS": round(c.nx * c.ny * n / w / 1e6, 1),
                      "GB_s": round(dd["bytes_per_node"] * c.nx * c.ny / (e / n) / 1e9, 1),
-                     "bytes_per_node": dd["bytes_per_node"], "waves_per_cu": tuned["waves_per_cu"]}
+                     "bytes_per_node": dd["bytes_per_node"], "form": form_tag(li),
+                     "waves_per_cu": tuned["waves_per_cu"]}
         if ref is None:
             ref = fl
         else:
@@ -151,6 +182,7 @@ def storage_forms(steps: int):
                      "B1": np.linalg.norm(ref["B1"]), "B2": np.linalg.norm(ref["B2"])}
             forms[st]["rel_l2_vs_f32"] = {k: float(f"{np.linalg.norm(fl[k] - ref[k]) / norms[k]:.3e}")
                                           for k in norms}
+            forms[st]["vs_f32_MLUPS"] = round(forms[st]["MLUPS"] / forms["f32"]["MLUPS"], 3)
         r.close()
     return forms
 
@@ -178,8 +210,11 @@ def batched_form(steps: int):
     for k, c in enumerate(runs):
         start(b, c, k)
     tuned = b.tune(20)
-    w, _ = time_run(b, n, 100)
+    li = b.launch_info()
+    w, e = time_run(b, n, 100)
+    d = b.derived()
     out = {"runs": len(runs), "nodes": nodes, "steps": n, "MLUPS": round(nodes * n / w / 1e6, 1),
+           "GB_s": round(d["bytes_per_node"] * nodes / (e / n) / 1e9, 1), "form": form_tag(li),
            "waves_per_cu": tuned["waves_per_cu"]}
     b.close()
     singles = []
@@ -204,7 +239,7 @@ def batched_form(steps: int):
 
 
 def collision_variants(case, steps: int, central_mlups: float):
-    """The main workload with the raw-moment MRT and the SRT collisions:
+    """The workload with the raw-moment MRT and the SRT collisions:
     throughput, achieved bandwidth and the ratio to the central-moment run."""
     from paper_2607_15362_amd import binding as B
     n = max(500, steps // 5)
@@ -213,12 +248,13 @@ def collision_variants(case, steps: int, central_mlups: float):
         c = case.replace(name=f"{case.name}_{coll}", collision=coll)
         r = B.Run(c)
         tuned = r.tune(50)
+        li = r.launch_info()
         w, e = time_run(r, n, 100)
         d = r.derived()
         nodes = c.nx * c.ny
         out[coll] = {"steps": n, "MLUPS": round(nodes * n / w / 1e6, 1),
                      "GB_s": round(d["bytes_per_node"] * nodes / (e / n) / 1e9, 1),
-                     "launch_us": round(e / n * 1e6, 2), "waves_per_cu": tuned["waves_per_cu"],
+                     "launch_us": round(e / n * 1e6, 2), "form": form_tag(li), "waves_per_cu": tuned["waves_per_cu"],
                      "vs_central": round(nodes * n / w / 1e6 / central_mlups, 3)}
         r.close()
     return out
@@ -229,43 +265,104 @@ def curvilinear_form(steps: int):
     geometry: 2048 radial x 512 azimuthal nodes, R1 = 256, R2 = R1 + 2048, the
     sector angle chosen for cells of aspect ratio about one), FP32: MLUPS and
     the achieved bandwidth in algorithmic bytes (populations and force read
-    and written, the 12 metric planes read), with the launch time of the
-    kernel from HIP events."""
-    import math
+    and written, the 12 metric planes read)."""
     from paper_2607_15362_amd import binding as B
     from paper_2607_15362_amd import workloads as W
     n1, n2, R1 = 2048, 512, 256.0
     n_theta = 2.0 * math.pi * n1 / (n2 * math.log((R1 + n1) / R1))
     c = W.taylor_couette(n1=n1, n2=n2, R1=R1, n_theta=n_theta, U_in=0.01, U_out=0.015, storage="f32")
     r = B.Run(c)
+    r.tune(50)
+    li = r.launch_info()
     n = max(200, steps // 10)
     w, e = time_run(r, n, 50)
     d = r.derived()
     nodes = n1 * n2
     out = {"workload": f"annular sector {n1}x{n2}, R1 = {R1:g}, FP32", "steps": n,
            "MLUPS": round(nodes * n / w / 1e6, 1), "step_us": round(e / n * 1e6, 2),
-           "bytes_per_node": d["bytes_per_node"],
+           "bytes_per_node": d["bytes_per_node"], "form": form_tag(li),
            "GB_s_algorithmic": round(d["bytes_per_node"] * nodes / (e / n) / 1e9, 1)}
     out["frac_of_8TBs"] = round(out["GB_s_algorithmic"] / PEAK_HBM_GBS, 4)
     r.close()
     return out
 
 
+def cache_resident(steps: int):
+    """The 1024x1024 Re = 1000 cavity in FP32 (92 MB of state, inside the
+    256 MB Infinity Cache): MLUPS and algorithmic bytes per second, which
+    here measure the cache, not HBM."""
+    from paper_2607_15362_amd import binding as B
+    from paper_2607_15362_amd import workloads as W
+    c = W.cavity_1024()
+    r = B.Run(c)
+    r.tune(100)
+    li = r.launch_info()
+    n = max(2000, steps)
+    w, e = time_run(r, n, 300)
+    d = r.derived()
+    nodes = c.nx * c.ny
+    ulid, cs = B.derive(c)[0].u_wall_hi, math.sqrt(d["cs2"])
+    out = {"workload": f"{c.name}: lid-driven cavity {c.nx}x{c.ny}, tanh beta=2 on both axes, Re=1000, "
+                       f"lid speed {ulid:.3e} (Mach {ulid / cs:.3f} of the GOC sound speed), FP32; "
+                       "cache-resident (92 MB of state)",
+           "steps": n, "MLUPS": round(nodes * n / w / 1e6, 1), "step_us": round(e / n * 1e6, 2),
+           "form": form_tag(li), "GB_s_algorithmic": round(d["bytes_per_node"] * nodes / (e / n) / 1e9, 1)}
+    out["frac_of_8TBs_not_hbm"] = round(out["GB_s_algorithmic"] / PEAK_HBM_GBS, 4)
+    r.close()
+    return out
+
+
+def workload_case(name: str, storage: str):
+    from paper_2607_15362_amd import workloads as W
+    if name == "cavity_1024":
+        c = W.cavity_1024()
+    else:
+        c = W.hartmann_4096()
+    if storage != "f32":
+        c = c.replace(name=f"{c.name}_{storage}", storage=storage)
+    return c
+
+
+def describe(case, run) -> str:
+    d = run.derived()
+    cs = math.sqrt(d["cs2"])
+    if case.flow == "cavity":
+        from paper_2607_15362_amd import binding as B
+        ulid = B.derive(case)[0].u_wall_hi
+        return (f"{case.name}: lid-driven cavity {case.nx}x{case.ny}, tanh beta=2 on both axes, Re=1000, "
+                f"lid speed {ulid:.3e} (Mach {ulid / cs:.3f}), {case.storage} storage; cache-resident")
+    H = case.ny / 2.0
+    Uc = case.Re * d["nu"] / H
+    return (f"{case.name}: Hartmann channel {case.nx}x{case.ny}, tanh beta=3, Ha=100, Re=100, Pm=1, "
+            f"centre-line speed {Uc:.3e} (Mach {Uc / cs:.4f}, tau = 1), D2Q9+D2Q5, {case.storage} storage, "
+            "FP32 arithmetic")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5000)
-    ap.add_argument("--warmup", type=int, default=300)
-    ap.add_argument("--workload", default="cavity_1024", choices=["cavity_1024", "hartmann_4096"])
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="hartmann_4096", choices=["hartmann_4096", "cavity_1024"])
+    ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16dev", "bf16dev"])
+    ap.add_argument("--developed", action="store_true",
+                    help="start the Hartmann workload from its developed flow (default: from rest)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-collisions", action="store_true")
     ap.add_argument("--no-curvilinear", action="store_true")
+    ap.add_argument("--no-cache-resident", action="store_true")
+    ap.add_argument("--only-main", action="store_true", help="the main line only (all of the --no-* options)")
     ap.add_argument("--waves", type=float, default=-1.0, metavar="W",
-                    help="fixed step form instead of the autotuner (for profiler runs): W = 0 the "
-                         "tiled step, W > 0 the march with W waves per CU")
+                    help="fixed step form instead of the autotuner (for profiler runs): W > 0 the march with "
+                         "W waves per CU; W = 0 the tiled step with --tile rows")
+    ap.add_argument("--tile", default="", metavar="ROWS[nt]",
+                    help="fixed tiled step (for profiler runs): 4, 8 or 16 rows, 'nt' for non-temporal "
+                         "stores, e.g. 4nt")
+    ap.add_argument("--batch", action="store_true",
+                    help="the main line is the seeded 256-run batch (FP32, developed flows)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB mebibytes (counter calibration)")
     args = ap.parse_args()
@@ -277,13 +374,31 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration, max(1, args.steps))
         return
+    if args.only_main:
+        args.no_cpu_baseline = args.no_forms = args.no_batch = args.no_collisions = True
+        args.no_curvilinear = args.no_cache_resident = True
 
     from paper_2607_15362_amd import binding as B
     from paper_2607_15362_amd import workloads as W
 
-    case = W.cavity_1024() if args.workload == "cavity_1024" else W.hartmann_4096()
-    run = B.Run(case)
-    if args.waves >= 0:
+    if args.batch:
+        runs = [c.replace(storage=args.storage) for c in W.batch_256()]
+        run = B.Run(batch=runs)
+        for k, c in enumerate(runs):
+            d = run.derived(run=k)
+            run.init_run(k, *W.hartmann_start(c, d["nu"], d["F1"], d["eta"], d["B0"]))
+        case = runs[0].replace(name=f"batch_256_{args.storage}")
+        nodes = sum(c.nx * c.ny for c in runs)
+    else:
+        case = workload_case(args.workload, args.storage)
+        run = B.Run(case)
+        if args.developed and case.flow == "hartmann":
+            developed(run, case)
+        nodes = case.nx * case.ny
+    if args.tile:
+        run.set_tile(int(args.tile.rstrip("nt")), args.tile.endswith("nt"))
+        tuned = {"us_before": float("nan")}
+    elif args.waves > 0:
         run.set_launch(args.waves)
         tuned = {"us_before": float("nan")}
     else:
@@ -291,12 +406,12 @@ def main():
     launch = run.launch_info()
     wall, ev = time_run(run, args.steps, args.warmup)
     d = run.derived()
-    nodes = case.nx * case.ny
     mlups = nodes * args.steps / wall / 1e6
     launch_s = ev / args.steps
     bytes_per_launch = d["bytes_per_node"] * nodes
     achieved = bytes_per_launch / launch_s / 1e9
-    traffic = measured_traffic(kernel_name(launch), case.name)
+    workload = "batch_256" if args.batch else case.name
+    traffic = measured_traffic(kernel_name(launch), workload, form_tag(launch))
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -308,40 +423,41 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f64": "f64", "f32": "f32"}.get(case.storage, "f32"),
+        "dtype": {"f64": "f64", "f32": "f32", "f16dev": "f16 storage, f32 arithmetic",
+                  "bf16dev": "bf16 storage, f32 arithmetic"}[case.storage],
         "data": "synthetic",
-        "config": {"workload": f"{case.name}: lid-driven cavity {case.nx}x{case.ny}, tanh beta=2 "
-                               f"on both axes, Re=1000, lid at Mach 0.1 of the finest cell, FP32 storage and arithmetic"
-                   if case.flow == "cavity" else
-                   f"{case.name}: Hartmann channel {case.nx}x{case.ny}, tanh beta=3, Ha=100, "
-                   f"Re=100, Pm=1, D2Q9+D2Q5, FP32",
-                   "nx": case.nx, "ny": case.ny, "storage": case.storage,
+        "config": {"workload": (f"batch_256: the seeded 256 Hartmann channels (128x64 .. 1024x512), "
+                                f"{args.storage} storage" if args.batch else describe(case, run)),
+                   "nx": case.nx, "ny": case.ny, "nodes": nodes, "storage": case.storage,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic,
                      "bytes_per_node": d["bytes_per_node"], "launch_us": round(launch_s * 1e6, 2),
                      "kernel": kernel_name(launch),
-                     "launch_plan": {"form": "tiled" if launch["waves_per_cu"] == 0 else "march",
+                     "launch_plan": {"form": form_tag(launch),
                                      "waves_per_cu": launch["waves_per_cu"], "work_groups": launch["blocks"],
                                      "rows_per_segment": round(launch["rows_per_segment"], 2),
+                                     "nontemporal_stores": bool(launch["nontemporal"]),
                                      "untuned_us": (round(tuned["us_before"], 2)
                                                     if tuned["us_before"] == tuned["us_before"] else None)}},
     }
     run.close()
 
-    if not args.no_collisions:
-        out["collisions"] = collision_variants(case, args.steps, mlups)
-    if not args.no_curvilinear:
-        out["curvilinear"] = curvilinear_form(args.steps)
-    if not args.no_forms:
-        out["forms"] = storage_forms(args.steps)
-    if not args.no_batch:
+    if not args.no_forms and not args.batch and case.flow == "hartmann" and case.storage == "f32":
+        out["forms"] = storage_forms(case, args.steps)
+    if not args.no_batch and not args.batch:
         out["batched"] = batched_form(args.steps)
         if "forms" in out:
             out["batched"]["vs_plain_fp32_4096x1024"] = round(out["batched"]["MLUPS"] / out["forms"]["f32"]["MLUPS"], 3)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
+    if not args.no_collisions and not args.batch:
+        out["collisions"] = collision_variants(case, args.steps, mlups)
+    if not args.no_curvilinear:
+        out["curvilinear"] = curvilinear_form(args.steps)
+    if not args.no_cache_resident and case.flow != "cavity":
+        out["cache_resident"] = cache_resident(args.steps)
+    if not args.no_cpu_baseline and not args.batch:
+        out["cpu_baseline"] = cpu_baseline(case.replace(storage="f64"), args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

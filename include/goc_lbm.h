@@ -278,8 +278,9 @@ int goc_lbm_set_watchdog(goc_lbm_t *h, int64_t every);
      few row groups).  Fewer, longer segments re-read fewer halo rows; more
      segments fill the chip and balance uneven batches.  It can step every
      handle on straight metrics;
-   - the tiled step: one thread per node, 64 x 8 nodes per work-group (64 x
-     4 in FP64), the moments of the tile and its ring in LDS, one launch
+   - the tiled step: one thread per node, 64 x 4, 8 or 16 nodes per
+     work-group (by default 8, 4 in FP64; goc_lbm_set_tile), the moments
+     of the tile and its ring in LDS, non-temporal or plain stores, one launch
      over the tiles of every run of the handle.  It steps straight runs,
      with or without MHD, alone or batched (the default for a single run:
      it is the faster form on most sizes; batches start on the march), and
@@ -290,22 +291,36 @@ int goc_lbm_set_watchdog(goc_lbm_t *h, int64_t every);
    outside, on a 2-D metric and in 16-bit storage).  Synchronous.
    goc_lbm_launch_info writes out[0] = waves_per_cu (0 for the tiled step),
    out[1] = work-groups per step, out[2] = mean rows per segment (rows per
-   tile), out[3] = strips (column tiles), over all runs. */
+   tile), out[3] = strips (column tiles), over all runs, out[4] = 1 when the
+   tiled step stores non-temporally, else 0. */
 int goc_lbm_set_launch(goc_lbm_t *h, double waves_per_cu);
-int goc_lbm_launch_info(const goc_lbm_t *h, double out[4]);
+int goc_lbm_launch_info(const goc_lbm_t *h, double out[5]);
+/* Select the tiled step with tiles of `rows` rows (4, 8 or 16, FP64 4 or
+   8; 64 columns each, one thread per node) and non-temporal stores
+   (nontemporal = 1) or plain ones (0); GOC_EINVAL otherwise.  Taller tiles
+   re-read fewer ring rows, shorter ones spread a grid over more
+   work-groups; non-temporal stores suit a state larger than the caches
+   (the default where one copy of the state exceeds 128 MiB), plain ones a
+   state the next step finds in the Infinity Cache.  Synchronous; captured
+   step graphs are dropped. */
+int goc_lbm_set_tile(goc_lbm_t *h, int32_t rows, int32_t nontemporal);
 
 /* Autotuner of the step form and launch plan: times trial_steps step
-   launches (1..10000, plus one warm-up) for each waves_per_cu in {2, 3, 4,
-   6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512} and the tiled
-   step (waves_per_cu 0), on the handle's stream; the candidates within 5 %
+   launches (1..10000, plus one warm-up) for the tiled step at each tile
+   height (4, 8, 16 rows; FP64 4, 8), with non-temporal and with plain
+   stores, and, for straight FP64 / FP32 handles, the march
+   at each waves_per_cu in {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128,
+   192, 256, 384, 512}, on the handle's stream; the candidates within 5 %
    of the fastest are timed again with three times the steps (at most
    10000), and the fastest of that second timing is kept (a run on a 2-D
-   metric or in 16-bit storage: the tiled step, timed).  The state does not change: trial
-   launches read the current buffers and write the spare ones.  out[0] =
-   chosen waves_per_cu, out[1] = its microseconds per step (second timing),
-   out[2] = microseconds per step of the form in use before in the first
-   timing (-1 if it was not a candidate), out[3] = number of candidates.
-   Synchronous. */
+   metric or in 16-bit storage has the tiled step only: its heights are
+   timed).  The state does not change: trial launches read the current
+   buffers and write the spare ones.  out[0] = chosen waves_per_cu (0: the
+   tiled step; its height and stores are launch_info's out[2], out[4]),
+   out[1] = its
+   microseconds per step (second timing), out[2] = microseconds per step of
+   the form in use before in the first timing (-1 if it was not a
+   candidate), out[3] = number of candidates.  Synchronous. */
 int goc_lbm_tune(goc_lbm_t *h, int32_t trial_steps, double out[4]);
 
 /* Post-stream populations in FP64 (the quantities App. E step 1 reads):

@@ -26,10 +26,11 @@ LIB = os.path.join(HERE, "libgoc_oracle.so")
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle shared library (gcc -O2, FP64, no fast-math)."""
+    """Compile the oracle shared library (gcc -O3, FP64, no fast-math: the
+    optimiser keeps the source's order of floating-point operations)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+        subprocess.check_call(["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp",
                                "-fno-fast-math", "-ffp-contract=off", "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
@@ -55,12 +56,19 @@ def lib():
         _lib.oracle_central_eq.argtypes = [cfgp] + [C.c_double] * 7 + [P, P]
         _lib.oracle_mie_node.argtypes = [cfgp, P, P, P, P]
         _lib.oracle_threads.restype = C.c_int
+        _lib.oracle_set_threads.argtypes = [C.c_int]
+        _lib.oracle_set_threads.restype = C.c_int
     return _lib
 
 
 def threads() -> int:
     """OpenMP threads the oracle's loops use."""
     return int(lib().oracle_threads())
+
+
+def set_threads(n: int) -> int:
+    """Use n OpenMP threads in the oracle's loops; returns the number in use."""
+    return int(lib().oracle_set_threads(int(n)))
 
 
 class OracleCfg(C.Structure):

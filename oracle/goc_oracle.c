@@ -1164,3 +1164,15 @@ int oracle_threads(void)
     return 1;
 #endif
 }
+
+/* Set the number of threads of the OpenMP loops (for timing the oracle on
+   one core and on all of them); returns the number now in use. */
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+    return oracle_threads();
+}

@@ -278,7 +278,9 @@ template <> struct Store<__half> {
     __device__ static void st(__half* p, int64_t i, float v, float s) { p[i] = __float2half_rn(v * s); }
     __device__ static __half enc(float b, float inc, float s, uint32_t r)
     {
-        goc_f16x2 h = {};
+        // (the conversion writes the low half; the high half keeps the draw's
+        // bits, which are dropped: no register needs clearing first)
+        goc_f16x2 h = __builtin_bit_cast(goc_f16x2, r);
         h = __builtin_amdgcn_cvt_sr_f16_f32(h, (b + inc) * s, r, false);
         return __builtin_bit_cast(__half, uint16_t(__builtin_bit_cast(uint32_t, h)));
     }
@@ -297,7 +299,7 @@ template <> struct Store<__hip_bfloat16> {
     __device__ static void st(__hip_bfloat16* p, int64_t i, float v, float s) { p[i] = __float2bfloat16(v * s); }
     __device__ static __hip_bfloat16 enc(float b, float inc, float s, uint32_t r)
     {
-        goc_bf16x2 h = {};
+        goc_bf16x2 h = __builtin_bit_cast(goc_bf16x2, r);   // (as for FP16)
         h = __builtin_amdgcn_cvt_sr_bf16_f32(h, (b + inc) * s, r, false);
         return __builtin_bit_cast(__hip_bfloat16, uint16_t(__builtin_bit_cast(uint32_t, h)));
     }

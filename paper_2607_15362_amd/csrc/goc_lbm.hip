@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/goc_lbm.h"
@@ -320,6 +321,8 @@ struct goc_lbm {
     bool tiled = false;             // straight runs stepped by the tiled kernel instead of the march
     int32_t* tile_first_d = nullptr;   // device: first tile of each run of the tiled kernel, then the total
     int32_t total_tiles = 0;
+    int tile_rows = 8;              // rows of a tile of the tiled step (goc::kTileRows)
+    bool tile_nt = false;           // the tiled step stores non-temporally
     int block_cap = 0;              // capacity of block_run_d (entries)
     // 16-bit storage: reference tables (the one in use, and the next one
     // while it is built), rows of all runs x kRef floats, and the step of
@@ -390,22 +393,38 @@ int launch_step(goc_lbm* h, int k, bool refresh = false)
             }
         }
         if (h->m2d || h->tiled) {   // tiled step: one launch for every run
-            constexpr int cy = goc::tile_rows_of<S>();
             const bool raw = h->coll == goc::kCollRaw;
-            const dim3 cg(h->total_tiles), cb(goc::kTileX, cy);
-            auto go = [&](auto kernel) {
-                hipLaunchKernelGGL(kernel, cg, cb, 0, h->stream, h->runs_d, h->tile_first_d, h->nruns, pl,
-                                   h->step_ctr, k);
+            auto tiled = [&](auto rows, auto nts) {
+                constexpr int TY = decltype(rows)::value;
+                constexpr bool NT = decltype(nts)::value;
+                const dim3 cg(h->total_tiles), cb(goc::kTileX, TY);
+                auto go = [&](auto kernel) {
+                    hipLaunchKernelGGL(kernel, cg, cb, 0, h->stream, h->runs_d, h->tile_first_d, h->nruns, pl,
+                                       h->step_ctr, k);
+                };
+                if constexpr (sizeof(S) == 8 && TY > 8) {   // (FP64: at most 8 rows, see tile_rows_built)
+                    return;
+                } else if (h->m2d) {
+                    raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, true, false, TY, NT>)
+                        : go(goc::tile_step_kernel<S, goc::kCollCentral, true, false, TY, NT>);
+                } else if (h->any_mhd) {
+                    raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, false, true, TY, NT>)
+                        : go(goc::tile_step_kernel<S, goc::kCollCentral, false, true, TY, NT>);
+                } else {
+                    raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, false, false, TY, NT>)
+                        : go(goc::tile_step_kernel<S, goc::kCollCentral, false, false, TY, NT>);
+                }
             };
-            if (h->m2d)
-                raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, true, false>)
-                    : go(goc::tile_step_kernel<S, goc::kCollCentral, true, false>);
-            else if (h->any_mhd)
-                raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, false, true>)
-                    : go(goc::tile_step_kernel<S, goc::kCollCentral, false, true>);
-            else
-                raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, false, false>)
-                    : go(goc::tile_step_kernel<S, goc::kCollCentral, false, false>);
+            auto tiled_nt = [&](auto rows) {
+                if (h->tile_nt) tiled(rows, std::true_type{});
+                else tiled(rows, std::false_type{});
+            };
+            switch (h->tile_rows) {
+            case 4: tiled_nt(std::integral_constant<int, 4>{}); break;
+            case 8: tiled_nt(std::integral_constant<int, 8>{}); break;
+            case 16: tiled_nt(std::integral_constant<int, 16>{}); break;
+            default: return fail(GOC_EINVAL, "tile height %d not built", h->tile_rows);
+            }
             HIPOK(hipGetLastError());
             if (goc::Store<S>::scaled && refresh) {
                 const int64_t n = h->ref_rows * goc::kRef;
@@ -532,8 +551,29 @@ void plan_rows(goc_lbm* h, std::vector<int32_t>& block_run)
 // The tiled kernel can step every handle on straight metrics (and is the
 // only form on 2-D metrics).
 bool tile_eligible(const goc_lbm* h) { return !h->m2d; }
-// Rows of a tile of the tiled kernel for the handle's storage.
-int tile_rows(const goc_lbm* h) { return h->storage == GOC_F64 ? 4 : 8; }
+// First tile of every run of the tiled step (and the total) for the
+// handle's tile height.
+void tile_table(const goc_lbm* h, std::vector<int32_t>& tile_first, bool& overflow)
+{
+    tile_first.assign(h->nruns + 1, 0);
+    overflow = false;
+    for (int r = 0; r < h->nruns; ++r) {
+        const int64_t gx = (h->runs[r].nx + goc::kTileX - 1) / goc::kTileX;
+        const int64_t nt = gx * ((h->runs[r].ny + h->tile_rows - 1) / h->tile_rows);
+        if ((int64_t)tile_first[r] + nt > INT32_MAX) overflow = true;
+        tile_first[r + 1] = overflow ? 0 : tile_first[r] + (int32_t)nt;
+    }
+}
+
+// Tile heights built for a storage: 4, 8 and 16 rows; FP64 up to 8 (at 16
+// rows, 1024 threads per work-group, its registers would spill).
+bool tile_rows_built(int rows, int storage)
+{
+    if (storage == GOC_F64 && rows > 8) return false;
+    for (int r : goc::kTileRows)
+        if (r == rows) return true;
+    return false;
+}
 
 void drop_graphs(goc_lbm* h)
 {
@@ -544,13 +584,28 @@ void drop_graphs(goc_lbm* h)
         }
 }
 
-// Step an eligible handle with the tiled kernel (synchronous; captured step
-// graphs are dropped).
-int use_tiled(goc_lbm* h)
+// Step an eligible handle with the tiled kernel, with tiles of `rows` rows
+// (0: the current height) and non-temporal stores or not (nt < 0: as now);
+// synchronous, captured step graphs are dropped.
+int use_tiled(goc_lbm* h, int rows = 0, int nt = -1)
 {
     HIPOK(hipStreamSynchronize(h->stream));
     drop_graphs(h);
     h->tiled = true;
+    if (nt >= 0) h->tile_nt = nt != 0;
+    if (rows && rows != h->tile_rows) {
+        const int old = h->tile_rows;
+        h->tile_rows = rows;
+        std::vector<int32_t> tf;
+        bool overflow;
+        tile_table(h, tf, overflow);
+        if (overflow) {
+            h->tile_rows = old;
+            return fail(GOC_EINVAL, "too many tiles in the launch");
+        }
+        HIPOK(hipMemcpy(h->tile_first_d, tf.data(), (h->nruns + 1) * 4, hipMemcpyHostToDevice));
+        h->total_tiles = tf[h->nruns];
+    }
     return GOC_OK;
 }
 
@@ -833,13 +888,17 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
             return bail(fail(GOC_EDEVICE, "metric download failed"));
     }
     // run table, work list of the march and first tiles of the tiled step
-    std::vector<int32_t> tile_first(nruns + 1, 0);
-    for (int r = 0; r < nruns; ++r) {
-        const int64_t gx = (grid[r].nx + goc::kTileX - 1) / goc::kTileX;
-        const int64_t nt = gx * ((grid[r].ny + tile_rows(h) - 1) / tile_rows(h));
-        if ((int64_t)tile_first[r] + nt > INT32_MAX) return bail(fail(GOC_EINVAL, "too many tiles in the launch"));
-        tile_first[r + 1] = tile_first[r] + (int32_t)nt;
-    }
+    // (tiles of the smallest height built, so that every height fits)
+    std::vector<int32_t> tile_first;
+    bool overflow = false;
+    h->tile_rows = goc::kTileRows[0];
+    tile_table(h, tile_first, overflow);
+    if (overflow) return bail(fail(GOC_EINVAL, "too many tiles in the launch"));
+    h->tile_rows = goc::default_tile_rows((int)storage_bytes(storage));
+    tile_table(h, tile_first, overflow);
+    // non-temporal stores where one copy of the state exceeds half the
+    // 256 MiB Infinity Cache (the autotuner times both)
+    h->tile_nt = f_elems * sb + F_elems * fb + g_elems * sb > (size_t(128) << 20);
     h->total_tiles = tile_first[nruns];
     if ((rc = dev_alloc((void**)&h->runs_d, nruns * sizeof(RunDesc))) ||
         (rc = dev_alloc((void**)&h->block_run_d, block_run.size() * 4)) ||
@@ -1300,7 +1359,7 @@ int goc_lbm_set_launch(goc_lbm_t* h, double waves_per_cu)
     return apply_plan(h, waves_per_cu);
 }
 
-int goc_lbm_launch_info(const goc_lbm_t* h, double out[4])
+int goc_lbm_launch_info(const goc_lbm_t* h, double out[5])
 {
     if (!h || !out) return fail(GOC_EINVAL, "NULL handle or output");
     int64_t rows = 0, segs = 0, strips = 0;
@@ -1310,7 +1369,7 @@ int goc_lbm_launch_info(const goc_lbm_t* h, double out[4])
         strips += d.strips;
     }
     if (h->m2d || h->tiled) {
-        const int ty = tile_rows(h);
+        const int ty = h->tile_rows;
         int64_t tiles = 0, cols = 0;
         for (const RunDesc& d : h->runs) {
             const int64_t gx = (d.nx + goc::kTileX - 1) / goc::kTileX;
@@ -1321,13 +1380,24 @@ int goc_lbm_launch_info(const goc_lbm_t* h, double out[4])
         out[1] = (double)tiles;
         out[2] = ty;
         out[3] = (double)cols;
+        out[4] = h->tile_nt ? 1.0 : 0.0;
         return GOC_OK;
     }
     out[0] = h->waves_per_cu;
     out[1] = h->total_blocks;
     out[2] = segs ? double(rows) / double(segs) : 0.0;
     out[3] = (double)strips;
+    out[4] = 0.0;
     return GOC_OK;
+}
+
+int goc_lbm_set_tile(goc_lbm_t* h, int32_t rows, int32_t nontemporal)
+{
+    if (!check_handle(h)) return GOC_EINVAL;
+    if (!tile_rows_built(rows, h->storage))
+        return fail(GOC_EINVAL, "tile height %d: 4, 8 or 16 rows (FP64: 4 or 8)", rows);
+    if (nontemporal != 0 && nontemporal != 1) return fail(GOC_EINVAL, "nontemporal must be 0 or 1");
+    return use_tiled(h, rows, nontemporal);
 }
 
 int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
@@ -1336,32 +1406,24 @@ int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
     if (!out) return fail(GOC_EINVAL, "out is NULL");
     if (trial_steps < 1 || trial_steps > 10000) return fail(GOC_EINVAL, "trial_steps %d outside [1, 10000]", trial_steps);
     static const double cand[] = {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512};
-    const int ncand = (int)(sizeof(cand) / sizeof(cand[0]));
     struct Ev {
         hipEvent_t e[2] = {nullptr, nullptr};
         ~Ev() { for (auto x : e) if (x) (void)hipEventDestroy(x); }
     } ev;
     HIPOK(hipEventCreate(&ev.e[0]));
     HIPOK(hipEventCreate(&ev.e[1]));
-    if (h->m2d || scaled_storage(h->storage)) {   // the tiled step only: time it
-        int rc;
-        if ((rc = launch_step(h, 0))) return rc;
-        HIPOK(hipEventRecord(ev.e[0], h->stream));
-        for (int s = 0; s < trial_steps; ++s)
-            if ((rc = launch_step(h, s))) return rc;
-        HIPOK(hipEventRecord(ev.e[1], h->stream));
-        HIPOK(hipEventSynchronize(ev.e[1]));
-        float ms = 0.0f;
-        HIPOK(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
-        out[0] = 0.0;
-        out[1] = out[2] = 1e3 * ms / trial_steps;
-        out[3] = 1;
-        return GOC_OK;
-    }
     // every trial launch reads the current buffers and writes the others,
-    // which the next real step overwrites: the state does not change
-    auto time_form = [&](double w, int steps, double& us) -> int {
-        int rc = w == 0.0 ? use_tiled(h) : apply_plan(h, w);
+    // which the next real step overwrites: the state does not change.  A
+    // candidate is (waves_per_cu, tile rows): waves_per_cu 0 is the tiled
+    // step with that tile height, a positive one the march with that plan.
+    struct Cand {
+        double w;    // 0: the tiled step, > 0: the march with this plan
+        int rows;    // tile height
+        int nt;      // non-temporal stores (tiled step)
+    };
+    auto select = [&](const Cand& c) -> int { return c.w == 0.0 ? use_tiled(h, c.rows, c.nt) : apply_plan(h, c.w); };
+    auto time_form = [&](const Cand& c, int steps, double& us) -> int {
+        int rc = select(c);
         if (rc) return rc;
         if ((rc = launch_step(h, 0))) return rc;
         HIPOK(hipEventRecord(ev.e[0], h->stream));
@@ -1374,21 +1436,27 @@ int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
         us = 1e3 * ms / steps;
         return GOC_OK;
     };
-    // candidate 0 is the tiled step (eligible handles only)
-    const bool elig = tile_eligible(h);
-    const double prev = h->tiled ? 0.0 : h->waves_per_cu;
-    double best_us = 1e300, best_w = prev, prev_us = -1.0;
-    std::vector<double> ws, times;
-    for (int c = elig ? -1 : 0; c < ncand; ++c) {
-        const double w = c < 0 ? 0.0 : cand[c];
+    // the tiled step at every tile height, with and without non-temporal
+    // stores, then (straight FP64 / FP32 runs) the march at every plan
+    const bool march = tile_eligible(h) && !scaled_storage(h->storage);
+    const Cand prev = {(h->m2d || h->tiled) ? 0.0 : h->waves_per_cu, h->tile_rows, h->tile_nt ? 1 : 0};
+    std::vector<Cand> cands;
+    for (int rows : goc::kTileRows)
+        if (tile_rows_built(rows, h->storage))
+            for (int nt = 0; nt < 2; ++nt) cands.push_back({0.0, rows, nt});
+    if (march)
+        for (double w : cand) cands.push_back({w, prev.rows, prev.nt});
+    double best_us = 1e300, prev_us = -1.0;
+    Cand best = prev;
+    std::vector<double> times;
+    for (const auto& c : cands) {
         double us = 0.0;
-        if (int rc = time_form(w, trial_steps, us)) return rc;
-        ws.push_back(w);
+        if (int rc = time_form(c, trial_steps, us)) return rc;
         times.push_back(us);
-        if (w == prev) prev_us = us;
+        if (c.w == prev.w && (prev.w != 0.0 || (c.rows == prev.rows && c.nt == prev.nt))) prev_us = us;
         if (us < best_us) {
             best_us = us;
-            best_w = w;
+            best = c;
         }
     }
     // the close finishers (within 5 % of the fastest) once more with three
@@ -1396,21 +1464,20 @@ int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
     // percent of each other
     const int steps2 = std::min(10000, 3 * trial_steps);
     double best2 = 1e300;
-    for (size_t c = 0; c < ws.size(); ++c) {
+    for (size_t c = 0; c < cands.size(); ++c) {
         if (times[c] > 1.05 * best_us) continue;
         double us = 0.0;
-        if (int rc = time_form(ws[c], steps2, us)) return rc;
+        if (int rc = time_form(cands[c], steps2, us)) return rc;
         if (us < best2) {
             best2 = us;
-            best_w = ws[c];
+            best = cands[c];
         }
     }
-    best_us = best2;
-    if (int rc = best_w == 0.0 ? use_tiled(h) : apply_plan(h, best_w)) return rc;
-    out[0] = best_w;
-    out[1] = best_us;
+    if (int rc = select(best)) return rc;
+    out[0] = best.w;
+    out[1] = best2;
     out[2] = prev_us;
-    out[3] = ncand + (elig ? 1 : 0);
+    out[3] = (double)cands.size();
     return GOC_OK;
 }
 

@@ -26,10 +26,12 @@
 
 namespace goc {
 
-constexpr int kTileX = 64;   // work-group tile: 64 columns x tile_rows_of<S>() rows
-// 8 rows; 4 for FP64 storage, whose register count leaves room for fewer
-// waves per CU
-template <class S> constexpr int tile_rows_of() { return sizeof(S) == 8 ? 4 : 8; }
+constexpr int kTileX = 64;   // work-group tile: 64 columns x TY rows (one wave per row)
+// Tile heights the library instantiates (the autotuner picks one per handle)
+// and the default: 8 rows, 4 for FP64 storage, whose register count leaves
+// room for fewer waves per CU.
+constexpr int kTileRows[3] = {4, 8, 16};
+constexpr int default_tile_rows(int storage_bytes) { return storage_bytes == 8 ? 4 : 8; }
 
 // A value at a lane's 32-bit byte offset from a work-group-uniform base:
 // the hardware forms such an address from a scalar base and a vector
@@ -44,6 +46,26 @@ template <class V>
 __device__ inline void st_at(void* base, uint32_t off, V v)
 {
     *reinterpret_cast<V*>(static_cast<char*>(base) + off) = v;
+}
+// The same as a non-temporal store when NT: where the state is larger than
+// the caches, the step's outputs are read once, by the next step, after the
+// whole state has streamed through them, so keeping them cached only
+// displaces the data in flight (measured on the step's access pattern
+// without arithmetic, 4096 x 1024 with the D2Q5 slots: 142.6 us per launch
+// with plain stores, 134.5 us non-temporal); where it fits in the Infinity
+// Cache, the next step reads it from there, and plain stores keep it.
+template <bool NT, class V>
+__device__ inline void st_nt(void* base, uint32_t off, V v)
+{
+    char* p = static_cast<char*>(base) + off;
+    if constexpr (!NT)
+        *reinterpret_cast<V*>(p) = v;
+    else if constexpr (sizeof(V) == 2)
+        __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, v), reinterpret_cast<uint16_t*>(p));
+    else if constexpr (sizeof(V) == 4)
+        __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, v), reinterpret_cast<uint32_t*>(p));
+    else
+        __builtin_nontemporal_store(__builtin_bit_cast(uint64_t, v), reinterpret_cast<uint64_t*>(p));
 }
 
 // Metric of a node of a 2-D run in the compute type: nb = its node index
@@ -132,19 +154,36 @@ __device__ inline void pull_g(const RunDesc& d, const RunBytes& b, int i, int j,
 
 // Reference of the reader of each slot a node writes (16-bit storage): the
 // reader's row and direction, i.e. row j + e_a2 (wrapped when periodic) and
-// direction a, or, where the slot leaves through a wall, the node itself in
+// direction a, or, where the slot leaves through a y-wall, the node itself in
 // row j with the opposite direction.  R0, Rm, Rp: the entries of rows j,
-// j - 1 and j + 1 (first: the entry of direction 0); wxlo .. wyhi: the walls
-// beside the node; n directions of one D2Q9 or D2Q5 set.
+// j - 1 and j + 1 (first: the entry of direction 0), wylo / wyhi: the node's
+// row lies next to a y-wall; all uniform over a wave (one row per wave), so
+// the references are scalar values.  n directions of one D2Q9 or D2Q5 set.
 template <int n, class R>
-__device__ inline void reader_refs(R R0, R Rm, R Rp, bool wxlo, bool wxhi, bool wylo, bool wyhi, float* ro)
+__device__ inline void reader_refs(R R0, R Rm, R Rp, bool wylo, bool wyhi, float* ro)
 {
 #pragma unroll
     for (int a = 0; a < n; ++a) {
-        const int ex = ex_(a), ey = ey_(a);
-        const bool bounced = (ex > 0 && wxhi) || (ex < 0 && wxlo) || (ey > 0 && wyhi) || (ey < 0 && wylo);
-        const float nominal = ey > 0 ? Rp[a] : ey < 0 ? Rm[a] : R0[a];
-        ro[a] = bounced ? R0[opp_(a)] : nominal;
+        const int ey = ey_(a);
+        const bool bounced = (ey > 0 && wyhi) || (ey < 0 && wylo);
+        // (the choice is made on the uniform address, so one scalar load reads it)
+        const R src = bounced ? R0 + opp_(a) : ey > 0 ? Rp + a : ey < 0 ? Rm + a : R0 + a;
+        ro[a] = *src;
+    }
+}
+
+// The slots that leave through an xi1-wall are read by the node itself with
+// the opposite direction: the change of reference, added to the increments
+// of those slots of the nodes beside the wall (n directions as above).
+template <int n, class R, class T>
+__device__ inline void xwall_refs(R R0, const float* ro, bool wxlo, bool wxhi, T* inc)
+{
+#pragma unroll
+    for (int a = 0; a < n; ++a) {
+        const int ex = ex_(a);
+        if (ex == 0) continue;
+        const bool bounced = (ex > 0 && wxhi) || (ex < 0 && wxlo);
+        if (bounced) inc[a] -= T(R0[opp_(a)] - ro[a]);
     }
 }
 
@@ -175,9 +214,9 @@ __device__ inline T tile_fd(V v, int l, int k, int n, bool periodic)
 }
 
 // The step of every node of every run.  Launch: grid = the tiles of all
-// runs (1-D), block (64, Y), Y = tile_rows_of<S>(); tile_first[r] = the
+// runs (1-D), block (64, TY); NT: non-temporal stores; tile_first[r] = the
 // first tile of run r (tile_first[nruns] = all tiles), a run's tiles being
-// ceil(nx/64) * ceil(ny/Y) in row-major order.  A work-group owns the 64 x Y
+// ceil(nx/64) * ceil(ny/TY) in row-major order.  A work-group owns the 64 x TY
 // nodes of tile (bx, by) of its run at (64 bx, Y by); its tile is shifted back at the
 // far edges of the grid so that the three nodes of a one-sided difference
 // lie in it (nodes of the shifted part belong to the neighbouring
@@ -186,14 +225,14 @@ __device__ inline T tile_fd(V v, int l, int k, int n, bool periodic)
 // the eight XCDs in turn; the tiles are renumbered so that each XCD gets a
 // contiguous band of them (run by run, row-major), whose rings and
 // cross-tile pulls its L2 then serves.
-template <class S, int COLL, bool GEN, bool MHD>
-__global__ void __launch_bounds__(kTileX * tile_rows_of<S>())
+template <class S, int COLL, bool GEN, bool MHD, int TY, bool NT>
+__global__ void __launch_bounds__(kTileX * TY)
 tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ tile_first, int nruns,
                  Pools<S, typename ForceOf<S>::type> pl, const uint32_t* __restrict__ step_ctr, int k)
 {
     using T = typename ComputeOf<S>::type;
     using FT = typename ForceOf<S>::type;
-    constexpr int kTileY = tile_rows_of<S>();
+    constexpr int kTileY = TY;
     __shared__ T sm[3][kTileY + 2][kTileX + 2];   // rho - rho0, U1, U2 of the tile and its ring
     // tile of this work-group over all runs, in XCD bands, then its run (the
     // last whose first tile is not beyond it) and its place in the run
@@ -226,8 +265,11 @@ tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ t
     const T* sp = step_params<T>(d);
     const char* mt = reinterpret_cast<const char*>(table_of<T>(pl.met, pl.metf) + d.met_off);
     // the own node, clamped into the grid for the threads of a ragged tile
-    // that have none (they load, but store nothing)
+    // that have none (they load, but store nothing); its row, uniform over
+    // the wave (one row of the tile per wave: lane 0 always holds a node of
+    // it, and lanes without a node compute nothing that is kept)
     const int ic = in ? i : x0, jc = in ? j : y0;
+    const int jw = __builtin_amdgcn_readfirstlane(jc);
     // this thread's node of the ring around the tile: rows -1 and ty over the
     // tile's columns, columns -1 and tx over its rows (the differences never
     // reach the corners); wrapped across a periodic edge, absent beyond a
@@ -269,7 +311,7 @@ tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ t
         g = tile_metric2d<T>(d, pl, uint32_t(jc * nx + ic) * uint32_t(sizeof(T)), NB, aE, aW, aN, aS);
     } else {
         const T* ct = ctab + ic * kTab;
-        const T* rt = rtab + jc * kTab;
+        const CPtr<T> rt = (CPtr<T>)(rtab + jw * kTab);   // (scalar loads)
         g.h1 = ct[T_H];
         g.ih1 = ct[T_IH];
         g.th11 = ct[T_TH];
@@ -293,8 +335,7 @@ tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ t
     // lane 0 always holds a node of it, and lanes without a node store
     // nothing), read through scalar loads
     CPtr<float> rin = nullptr;
-    if constexpr (Store<S>::scaled)
-        rin = (CPtr<float>)(pl.ref_in + (d.row_off + __builtin_amdgcn_readfirstlane(jc)) * kRef);
+    if constexpr (Store<S>::scaled) rin = (CPtr<float>)(pl.ref_in + (d.row_off + jw) * kRef);
     T f[kQ], Fp1, Fp2;
     tile_pull9<S, T, FT>(d, b, planeF, ic, jc, rin, f, Fp1, Fp2);
     T dg[2][kM];   // D2Q5 deviations (MHD)
@@ -331,16 +372,19 @@ tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ t
     const T d2U2 = tile_fd<T>([&](int r) { return sm[2][r][cx]; }, cy, j, ny, py);
     const T d2r = tile_fd<T>([&](int r) { return sm[0][r][cx]; }, cy, j, ny, py);
 
+    // (from here on every lane of the wave holds a node of row jw = j)
     const bool wxlo = !px && i == 0, wxhi = !px && i == nx - 1;
-    const bool wylo = !py && j == 0, wyhi = !py && j == ny - 1;
+    // (forced to scalar registers: the compiler otherwise keeps these
+    // row-uniform flags and the rows below in vector lanes)
+    const bool wylo = __builtin_amdgcn_readfirstlane(int(!py && jw == 0)) != 0;
+    const bool wyhi = __builtin_amdgcn_readfirstlane(int(!py && jw == ny - 1)) != 0;
     // 16-bit storage: the reference entries of rows j, j - 1 and j + 1 of the
     // output table (wrapped when periodic; a row beyond a wall is never a
     // reader's, so it is clamped into the grid)
     CPtr<float> R0 = nullptr, Rm = nullptr, Rp = nullptr;
     if constexpr (Store<S>::scaled) {
-        const int jw = __builtin_amdgcn_readfirstlane(j);
-        const int jm = jw > 0 ? jw - 1 : (py ? ny - 1 : 0);
-        const int jp = jw < ny - 1 ? jw + 1 : (py ? 0 : ny - 1);
+        const int jm = __builtin_amdgcn_readfirstlane(jw > 0 ? jw - 1 : (py ? ny - 1 : 0));
+        const int jp = __builtin_amdgcn_readfirstlane(jw < ny - 1 ? jw + 1 : (py ? 0 : ny - 1));
         const CPtr<float> rt0 = (CPtr<float>)(pl.ref_out + d.row_off * kRef);
         R0 = rt0 + jw * kRef;
         Rm = rt0 + jm * kRef;
@@ -350,7 +394,7 @@ tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ t
     const uint32_t hn = mix32((uint32_t(d.f_off) + uint32_t(j) * uint32_t(d.pitch) + uint32_t(i)) ^ seed);
     const uint32_t cs = uint32_t(sizeof(S));
     const uint32_t own = uint32_t(j + 1) * b.pitch_s + uint32_t(i) * cs;   // (slot regions start at row -1)
-    const bool bot = j == 0, top = j == ny - 1;
+    const bool bot = jw == 0, top = jw == ny - 1;
     // App. G, as the march: magnetic field, local derivatives, Lorentz
     // force, the D2Q5 collision and writes (stored value = base + increment;
     // anti-bounce-back slots negate the post-collision value; the writer adds
@@ -380,11 +424,15 @@ tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ t
         }
         const T sgw = Store<S>::scaled ? sp[P_SCG] : T(1);
         float rg[2][kM] = {};   // (16-bit) reference of each slot's reader
-        if constexpr (Store<S>::scaled)
+        if constexpr (Store<S>::scaled) {
 #pragma unroll
             for (int ci = 0; ci < 2; ++ci)
-                reader_refs<kM>(R0 + kRefG + ci * kM, Rm + kRefG + ci * kM, Rp + kRefG + ci * kM, wxlo, wxhi,
-                                wylo, wyhi, rg[ci]);
+                reader_refs<kM>(R0 + kRefG + ci * kM, Rm + kRefG + ci * kM, Rp + kRefG + ci * kM, wylo, wyhi,
+                                rg[ci]);
+            if (!px)   // (uniform: walls on the xi1 faces)
+#pragma unroll
+                for (int ci = 0; ci < 2; ++ci) xwall_refs<kM>(R0 + kRefG + ci * kM, rg[ci], wxlo, wxhi, dgi[ci]);
+        }
         S eg[2][kM];
 #pragma unroll
         for (int ci = 0; ci < 2; ++ci)
@@ -392,7 +440,7 @@ tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ t
             for (int a = 0; a < kM; ++a) {
                 eg[ci][a] = Store<S>::enc(Store<S>::scaled ? dg[ci][a] - rg[ci][a] : dg[ci][a], dgi[ci][a], sgw,
                                           pop_draw(hn, kQ + ci * kM + a));
-                st_at<S>(b.go, ci * b.g_comp + uint32_t(a) * b.plane_s + own, eg[ci][a]);
+                st_nt<NT, S>(b.go, ci * b.g_comp + uint32_t(a) * b.plane_s + own, eg[ci][a]);
             }
         // ghost rows: plane 2 / 4 of each component, own column
         if (bot || top) {
@@ -401,7 +449,7 @@ tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ t
             const uint32_t pg = (wall == bot) ? 2u : 4u;
 #pragma unroll
             for (int ci = 0; ci < 2; ++ci)
-                st_at<S>(b.go, grow + ci * b.g_comp + pg * b.plane_s + uint32_t(i) * cs, bot ? eg[ci][4] : eg[ci][2]);
+                st_nt<NT, S>(b.go, grow + ci * b.g_comp + pg * b.plane_s + uint32_t(i) * cs, bot ? eg[ci][4] : eg[ci][2]);
         }
     }
 
@@ -478,13 +526,16 @@ tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ t
     // the increment is added, so the rounded residual loses nothing to the
     // size of the reference)
     float ro[kQ] = {};
-    if constexpr (Store<S>::scaled) reader_refs<kQ>(R0, Rm, Rp, wxlo, wxhi, wylo, wyhi, ro);
+    if constexpr (Store<S>::scaled) {
+        reader_refs<kQ>(R0, Rm, Rp, wylo, wyhi, ro);
+        if (!px) xwall_refs<kQ>(R0, ro, wxlo, wxhi, inc);   // (uniform: walls on the xi1 faces)
+    }
     S e[kQ];
 #pragma unroll
     for (int a = 0; a < kQ; ++a) {
         const T sfw = Store<S>::scaled ? sp[P_SC + cls_(a)] : T(1);
         e[a] = Store<S>::enc(Store<S>::scaled ? f[a] - ro[a] : f[a], inc[a], sfw, pop_draw(hn, a));
-        st_at<S>(b.fo, uint32_t(a) * b.plane_s + own, e[a]);
+        st_nt<NT, S>(b.fo, uint32_t(a) * b.plane_s + own, e[a]);
     }
     // ghost rows (rows 0 and ny - 1): walls take the bounced values at the
     // reader's source column, into the row beyond the wall; periodic xi2 takes
@@ -499,18 +550,18 @@ tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ t
         const uint32_t p2 = wall ? (bot ? 6 : 7) : (bot ? 8 : 5);
         const int cm = px ? (i == 0 ? nx - 1 : i - 1) : i - 1;
         const int cp = px ? (i == nx - 1 ? 0 : i + 1) : i + 1;
-        st_at<S>(b.fo, grow + p0 * b.plane_s + uint32_t(i) * cs, bot ? e[4] : e[2]);
+        st_nt<NT, S>(b.fo, grow + p0 * b.plane_s + uint32_t(i) * cs, bot ? e[4] : e[2]);
         if (!wall) {
-            st_at<S>(b.fo, grow + p1 * b.plane_s + uint32_t(i) * cs, bot ? e[7] : e[6]);
-            st_at<S>(b.fo, grow + p2 * b.plane_s + uint32_t(i) * cs, bot ? e[8] : e[5]);
+            st_nt<NT, S>(b.fo, grow + p1 * b.plane_s + uint32_t(i) * cs, bot ? e[7] : e[6]);
+            st_nt<NT, S>(b.fo, grow + p2 * b.plane_s + uint32_t(i) * cs, bot ? e[8] : e[5]);
         } else {
-            if (!wxlo) st_at<S>(b.fo, grow + p1 * b.plane_s + uint32_t(cm) * cs, bot ? e[7] : e[6]);
-            if (!wxhi) st_at<S>(b.fo, grow + p2 * b.plane_s + uint32_t(cp) * cs, bot ? e[8] : e[5]);
+            if (!wxlo) st_nt<NT, S>(b.fo, grow + p1 * b.plane_s + uint32_t(cm) * cs, bot ? e[7] : e[6]);
+            if (!wxhi) st_nt<NT, S>(b.fo, grow + p2 * b.plane_s + uint32_t(cp) * cs, bot ? e[8] : e[5]);
         }
     }
     const uint32_t nf = uint32_t(j) * b.pitch_F + uint32_t(i) * uint32_t(sizeof(FT));
-    st_at<FT>(b.Fo, nf, FT(F1));
-    st_at<FT>(b.Fo, nf + planeF, FT(F2));
+    st_nt<NT, FT>(b.Fo, nf, FT(F1));
+    st_nt<NT, FT>(b.Fo, nf + planeF, FT(F2));
 }
 
 }  // namespace goc

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 @pytest.mark.gpu
 def test_bench_json_line():
     cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "200", "--warmup", "20", "--no-forms",
-           "--no-batch", "--no-collisions", "--no-curvilinear", "--cpu-seconds", "1"]
+           "--no-batch", "--no-collisions", "--no-curvilinear", "--no-cache-resident", "--cpu-seconds", "1"]
     out = subprocess.run(cmd, capture_output=True, text=True, timeout=240, cwd=ROOT)
     assert out.returncode == 0, out.stderr[-2000:]
     lines = [ln for ln in out.stdout.splitlines() if ln.startswith("{")]
@@ -26,7 +26,7 @@ def test_bench_json_line():
         assert k in d, k
     assert d["n_gpus"] == 1 and d["steps"] == 200 and d["warmup"] == 20
     assert d["value"] > 0 and d["ms_per_step"] > 0 and d["higher_is_better"] is True
-    assert d["config"]["workload"].startswith("cavity_1024")
+    assert d["config"]["workload"].startswith("hartmann_4096x1024") and d["config"]["storage"] == "f32"
     r = d["roofline"]
     for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert k in r, k
@@ -35,7 +35,7 @@ def test_bench_json_line():
     c = d["cpu_baseline"]
     for k in ("value", "unit", "cores", "kind", "sample"):
         assert k in c, k
-    assert c["kind"] == "oracle" and c["value"] > 0 and c["cores"] >= 1
+    assert c["kind"] == "oracle" and c["value"] > 0 and c["cores"] >= 1 and c["one_core_value"] > 0
 
 
 def test_bench_refuses_more_than_one_gpu():

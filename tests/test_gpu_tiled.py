@@ -184,12 +184,13 @@ def test_fp64_agrees_with_march_after_201_steps(name):
 
 
 def test_default_and_tuner_selection():
-    """A single straight run starts on the tiled step; the tuner times it as
-    one more candidate (waves_per_cu 0) and keeps whichever is faster."""
+    """A single straight run starts on the tiled step; the tuner times it at
+    its three tile heights, each with non-temporal and with plain stores,
+    beside the 17 plans of the march and keeps whichever is fastest."""
     r = B.Run(cav(256, 256, "f32"))
     assert r.launch_info()["waves_per_cu"] == 0
     info = r.tune(5)
-    assert info["candidates"] == 18
+    assert info["candidates"] == 23   # three heights x two store policies, 17 march plans
     assert info["us_before"] > 0.0   # the tiled step was in use and was timed
     li = r.launch_info()
     assert li["waves_per_cu"] == info["waves_per_cu"]
@@ -289,8 +290,68 @@ def test_16bit_storage_has_only_the_tiled_step(storage):
         h.set_launch(8)
     assert ei.value.code == B.GOC_EINVAL
     info = h.tune(3)
-    assert info["candidates"] == 1 and info["waves_per_cu"] == 0
+    assert info["candidates"] == 6 and info["waves_per_cu"] == 0
+    assert h.launch_info()["rows_per_segment"] in (4, 8, 16)
     h.close()
     b = B.Run(batch=[c.replace(storage=storage) for c in W.batch_256(n=3)])
     assert b.launch_info()["waves_per_cu"] == 0
     b.close()
+
+
+@pytest.mark.parametrize("name", ["cavity_f64_ragged", "mhd_f64_ragged", "moving_xi1_walls"])
+def test_tile_heights_agree_fp64(name):
+    """The tiled step at 4 and 8 rows per tile (FP64's heights) computes the
+    same step: fields within 1e-13 after 201 steps."""
+    case, init_fields, lid = CASES[name]
+    runs = {}
+    for rows in (4, 8):
+        r = _run(case, init_fields, lid, 0)
+        r.set_tile(rows)
+        assert r.launch_info()["rows_per_segment"] == rows
+        for steps in (1, 40, 160):
+            r.step(steps)
+        runs[rows] = r
+    a, b = runs[8].fields(), runs[4].fields()
+    un = np.linalg.norm(np.hypot(b["U1"], b["U2"]))
+    for k in a:
+        ref = un if k.startswith("U") else np.linalg.norm(b[k])
+        assert np.linalg.norm(a[k] - b[k]) <= 1e-13 * ref, (name, k)
+    for r in runs.values():
+        r.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16dev", "bf16dev"])
+def test_tile_heights_agree(storage):
+    """The tiled step at 4, 8 and 16 rows per tile from the same developed
+    state (a batch of plain and MHD runs): FP32 stores the same values within
+    a few eps of the largest; the 16-bit forms' fields agree far inside their
+    rounding (an ulp of FP32 difference can flip a stochastic rounding)."""
+    runs = [c.replace(storage=storage) for c in W.batch_256(n=3)] + [cav(130, 70, storage)]
+    base = B.Run(batch=runs)
+    base.set_launch(0)
+    base.step(120)
+    blob = base.get_state()
+    out = {}
+    for rows in (4, 8, 16):
+        r = B.Run(batch=runs)
+        r.set_tile(rows, rows == 8)   # (both store policies)
+        r.set_state(blob)
+        r.step(1)
+        out[rows] = r
+    for rows in (8, 16):
+        for k, case in enumerate(runs):
+            if storage == "f32":
+                fa, Fa, ga = out[rows].populations(run=k)
+                fb, Fb, gb = out[4].populations(run=k)
+                assert np.max(np.abs(fa - fb)) <= LIMIT["f32"] * np.max(np.abs(fb)), (rows, k)
+                if case.mhd:
+                    assert np.max(np.abs(ga - gb)) <= LIMIT["f32"] * np.max(np.abs(gb)), (rows, k)
+            else:
+                a, b = out[rows].fields(run=k), out[4].fields(run=k)
+                un = np.linalg.norm(np.hypot(b["U1"], b["U2"]))
+                for q in a:
+                    ref = un if q.startswith("U") else np.linalg.norm(b[q])
+                    assert np.linalg.norm(a[q] - b[q]) <= 1e-5 * ref, (rows, k, q)
+    for r in out.values():
+        r.close()
+    base.close()
