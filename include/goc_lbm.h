@@ -258,11 +258,17 @@ int goc_lbm_step(goc_lbm_t *h, int64_t n);
    the stream when on_device is 0. */
 int goc_lbm_moments(goc_lbm_t *h, double *rho, double *u, double *B, int32_t on_device);
 
-/* Global sums in FP64 (host out[8]): [0] mass sum f, [1] sum h2 rho U1,
-   [2] sum h1 rho U2, [3] mean over columns of the flow rate sum_j h2 rho U1,
-   [4] sum h1 h2 B1, [5] sum h1 h2 B2, [6] max |U|, [7] number of
-   non-finite populations.  Synchronises the stream. */
+/* Global sums in FP64 over the nodes of run 0 (host out[8]): [0] mass
+   sum f (App. E step 7: the populations sum to h1 h2 rho), [1] sum h2 rho U1,
+   [2] sum h1 rho U2 (the momentum of App. E step 7 without the lagged
+   force's half), [3] mean over columns of the flow rate sum_j h2 rho U1
+   (the physical integral of rho u across the channel), [4] sum h1 h2 B1,
+   [5] sum h1 h2 B2 (the fluxes of the field of App. G; 0 without MHD),
+   [6] max |U|, [7] number of non-finite populations.  Work-group partials
+   summed in a fixed order: deterministic.  Synchronises the stream. */
 int goc_lbm_diagnostics(goc_lbm_t *h, double out[8]);
+/* The same for run `run` of a batch (GOC_EINVAL outside [0, num_runs)). */
+int goc_lbm_diagnostics_run(goc_lbm_t *h, int32_t run, double out[8]);
 
 /* Check every `every` steps (0 = never) for non-finite populations; a hit
    makes goc_lbm_step return GOC_EUNSTABLE. */

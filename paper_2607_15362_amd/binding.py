@@ -79,6 +79,7 @@ SIGNATURES = {
     "goc_lbm_moments": (C.c_int, [VP, VP, VP, VP, C.c_int32]),
     "goc_lbm_moments_run": (C.c_int, [VP, C.c_int32, VP, VP, VP, C.c_int32]),
     "goc_lbm_diagnostics": (C.c_int, [VP, P_D]),
+    "goc_lbm_diagnostics_run": (C.c_int, [VP, C.c_int32, P_D]),
     "goc_lbm_set_watchdog": (C.c_int, [VP, C.c_int64]),
     "goc_lbm_get_populations": (C.c_int, [VP, VP, VP, VP, C.c_int32]),
     "goc_lbm_get_populations_run": (C.c_int, [VP, C.c_int32, VP, VP, VP, C.c_int32]),
@@ -352,9 +353,13 @@ class Run:
             gp = g.ctypes.data
         _check(lib().goc_lbm_set_populations(self.h, f.ctypes.data, F.ctypes.data, gp, 0))
 
-    def diagnostics(self):
+    def diagnostics(self, run=None):
+        """The eight global sums (run 0, or run `run` of a batch)."""
         out = np.zeros(8)
-        _check(lib().goc_lbm_diagnostics(self.h, _dptr(out)))
+        if run is None:
+            _check(lib().goc_lbm_diagnostics(self.h, _dptr(out)))
+        else:
+            _check(lib().goc_lbm_diagnostics_run(self.h, int(run), _dptr(out)))
         return out
 
     def set_watchdog(self, every):

@@ -446,21 +446,25 @@ __global__ void fields_kernel(const RunDesc* __restrict__ runs, int run, Pools<S
     }
 }
 
-// Global sums (FP64 accumulation), one partial per work-group of 256 nodes:
-// [0] sum f, [1] sum h2 rho U1, [2] sum h1 rho U2, [3] sum h1 h2 B1,
-// [4] sum h1 h2 B2, [5] max |U|, [6] non-finite count.
+// Global sums (FP64 accumulation): each work-group of 256 threads strides
+// over the nodes of run `run` (node idx, idx + 256 gridDim.x, ...) and
+// writes one partial: [0] sum f, [1] sum h2 rho U1, [2] sum h1 rho U2,
+// [3] sum h1 h2 B1, [4] sum h1 h2 B2, [5] max |U|, [6] non-finite count.
+// The grid is at most kDiagBlocks work-groups, so the partials never exceed
+// kDiagBlocks * kDiag doubles.
 constexpr int kDiag = 7;
+constexpr int kDiagBlocks = 4096;
 template <class S>
-__global__ void diag_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, typename ForceOf<S>::type> pl,
-                            double* __restrict__ part)
+__global__ void __launch_bounds__(256) diag_kernel(const RunDesc* __restrict__ runs, int run,
+                                                   Pools<S, typename ForceOf<S>::type> pl, double* __restrict__ part)
 {
     using T = typename ComputeOf<S>::type;
     __shared__ double sh[kDiag][256];
     const RunDesc& d = runs[run];
     const int64_t N = (int64_t)d.nx * d.ny;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double v[kDiag] = {0, 0, 0, 0, 0, 0, 0};
-    if (idx < N) {
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < N;
+         idx += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(idx % d.nx), j = (int)(idx / d.nx);
         const NodeM nm = node_metric(d, pl, i, j);
         T f[kQ], dg[2][kM];
@@ -479,9 +483,9 @@ __global__ void diag_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, 
             m += double(f[a]);
             bad += isfinite(double(f[a])) ? 0 : 1;
         }
-        v[0] = m;
-        v[1] = h2 * rho * double(U1);
-        v[2] = h1 * rho * double(U2);
+        v[0] += m;
+        v[1] += h2 * rho * double(U1);
+        v[2] += h1 * rho * double(U2);
         if (d.mhd) {
             double S1 = 0, S2 = 0;
             for (int a = 0; a < kM; ++a) {
@@ -489,15 +493,13 @@ __global__ void diag_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, 
                 S2 += double(dg[1][a]);
                 bad += (isfinite(double(dg[0][a])) ? 0 : 1) + (isfinite(double(dg[1][a])) ? 0 : 1);
             }
-            v[3] = S1;
-            v[4] = h1 * h2 * d.B0 + S2;
+            v[3] += S1;
+            v[4] += h1 * h2 * d.B0 + S2;
         }
-        v[5] = sqrt(double(U1) * double(U1) + double(U2) * double(U2));
-        if (!isfinite(v[5])) {
-            v[5] = 0;
-            bad += 1;
-        }
-        v[6] = bad;
+        const double um = sqrt(double(U1) * double(U1) + double(U2) * double(U2));
+        if (isfinite(um)) v[5] = fmax(v[5], um);
+        else bad += 1;
+        v[6] += bad;
     }
     for (int k = 0; k < kDiag; ++k) sh[k][threadIdx.x] = v[k];
     __syncthreads();
@@ -513,8 +515,11 @@ __global__ void diag_kernel(const RunDesc* __restrict__ runs, int run, Pools<S, 
         for (int k = 0; k < kDiag; ++k) part[(int64_t)blockIdx.x * kDiag + k] = sh[k][0];
 }
 
-// Second pass over the partials (one work-group), fixed order: deterministic.
-__global__ void diag_final_kernel(const double* __restrict__ part, int nparts, double* __restrict__ out)
+// Second pass over the partials (one work-group), fixed order:
+// deterministic.  Writes the eight outputs of goc_lbm_diagnostics: the sums
+// of [0] - [2], the mean flow rate [3] = [1] / nx, the fluxes, max |U| and
+// the non-finite count.
+__global__ void diag_final_kernel(const double* __restrict__ part, int nparts, int nx, double* __restrict__ out)
 {
     __shared__ double sh[kDiag][256];
     double v[kDiag] = {0, 0, 0, 0, 0, 0, 0};
@@ -533,8 +538,16 @@ __global__ void diag_final_kernel(const double* __restrict__ part, int nparts, d
             }
         __syncthreads();
     }
-    if (threadIdx.x == 0)
-        for (int k = 0; k < kDiag; ++k) out[k] = sh[k][0];
+    if (threadIdx.x == 0) {
+        out[0] = sh[0][0];
+        out[1] = sh[1][0];
+        out[2] = sh[2][0];
+        out[3] = sh[1][0] / nx;
+        out[4] = sh[3][0];
+        out[5] = sh[4][0];
+        out[6] = sh[5][0];
+        out[7] = sh[6][0];
+    }
 }
 
 // New reference table of the 16-bit storage (written to ref_new) from the

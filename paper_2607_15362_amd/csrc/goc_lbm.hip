@@ -1040,11 +1040,38 @@ int fields_run(goc_lbm* h, int run, double* rho, double* u, double* B, int on_de
     return GOC_OK;
 }
 
-int diag_run(goc_lbm* h, int run, double out[goc::kDiag])
+// Work-groups of the diagnostics' first pass over a run (each strides over
+// the nodes; at most goc::kDiagBlocks).
+int diag_blocks(const RunDesc& d)
 {
-    const RunDesc& d = h->runs[run];
     const int64_t N = (int64_t)d.nx * d.ny;
-    const int nb = (int)((N + 255) / 256);
+    return (int)std::min<int64_t>((N + 255) / 256, goc::kDiagBlocks);
+}
+
+// The two passes of the diagnostics of run `run` into out_dev (8 doubles,
+// device), with `part` (diag_blocks doubles x goc::kDiag) as the partials.
+int launch_diag(goc_lbm* h, int run, double* part, double* out_dev)
+{
+    const int nb = diag_blocks(h->runs[run]);
+    int rc = dispatch(h->storage, [&](auto tag) -> int {
+        using S = decltype(tag);
+        auto pl = pools<S>(h, h->cur);
+        hipLaunchKernelGGL(goc::diag_kernel<S>, dim3(nb), dim3(256), 0, h->stream, h->runs_d, run, pl, part);
+        HIPOK(hipGetLastError());
+        return GOC_OK;
+    });
+    if (rc) return rc;
+    hipLaunchKernelGGL(goc::diag_final_kernel, dim3(1), dim3(256), 0, h->stream, part, nb, h->runs[run].nx,
+                       out_dev);
+    HIPOK(hipGetLastError());
+    return GOC_OK;
+}
+
+// Diagnostics of run `run` into the host array out[8] (the partials in a
+// buffer of the handle, allocated on first use).
+int diag_run(goc_lbm* h, int run, double out[8])
+{
+    const int nb = diag_blocks(h->runs[run]);
     if (nb > h->diag_cap) {
         (void)hipFree(h->diag_part);
         h->diag_part = nullptr;
@@ -1052,20 +1079,10 @@ int diag_run(goc_lbm* h, int run, double out[goc::kDiag])
             return fail(GOC_ENOMEM, "diagnostics scratch allocation failed");
         h->diag_cap = nb;
     }
-    if (!h->diag_out && hipMalloc(&h->diag_out, goc::kDiag * 8) != hipSuccess)
+    if (!h->diag_out && hipMalloc(&h->diag_out, 8 * 8) != hipSuccess)
         return fail(GOC_ENOMEM, "diagnostics allocation failed");
-    int rc = dispatch(h->storage, [&](auto tag) -> int {
-        using S = decltype(tag);
-        auto pl = pools<S>(h, h->cur);
-        hipLaunchKernelGGL(goc::diag_kernel<S>, dim3(nb), dim3(256), 0, h->stream, h->runs_d, run, pl,
-                           h->diag_part);
-        HIPOK(hipGetLastError());
-        return GOC_OK;
-    });
-    if (rc) return rc;
-    hipLaunchKernelGGL(goc::diag_final_kernel, dim3(1), dim3(256), 0, h->stream, h->diag_part, nb, h->diag_out);
-    HIPOK(hipGetLastError());
-    HIPOK(hipMemcpyAsync(out, h->diag_out, goc::kDiag * 8, hipMemcpyDeviceToHost, h->stream));
+    if (int rc = launch_diag(h, run, h->diag_part, h->diag_out)) return rc;
+    HIPOK(hipMemcpyAsync(out, h->diag_out, 8 * 8, hipMemcpyDeviceToHost, h->stream));
     HIPOK(hipStreamSynchronize(h->stream));
     return GOC_OK;
 }
@@ -1333,10 +1350,10 @@ int goc_lbm_step(goc_lbm_t* h, int64_t n)
         n -= chunk;
         if (h->watchdog > 0 && h->step % h->watchdog == 0) {
             for (int r = 0; r < h->nruns; ++r) {
-                double o[goc::kDiag];
+                double o[8];
                 int rc = diag_run(h, r, o);
                 if (rc) return rc;
-                if (o[6] > 0) return fail(GOC_EUNSTABLE, "run %d: %g non-finite values at step %lld", r, o[6],
+                if (o[7] > 0) return fail(GOC_EUNSTABLE, "run %d: %g non-finite values at step %lld", r, o[7],
                                           (long long)h->step);
             }
         }
@@ -1501,23 +1518,15 @@ int goc_lbm_moments(goc_lbm_t* h, double* rho, double* u, double* B, int32_t on_
     return goc_lbm_moments_run(h, 0, rho, u, B, on_device);
 }
 
-int goc_lbm_diagnostics(goc_lbm_t* h, double out[8])
+int goc_lbm_diagnostics_run(goc_lbm_t* h, int32_t run, double out[8])
 {
     if (!check_handle(h)) return GOC_EINVAL;
     if (!out) return fail(GOC_EINVAL, "out is NULL");
-    double o[goc::kDiag];
-    int rc = diag_run(h, 0, o);
-    if (rc) return rc;
-    out[0] = o[0];
-    out[1] = o[1];
-    out[2] = o[2];
-    out[3] = o[1] / h->runs[0].nx;
-    out[4] = o[3];
-    out[5] = o[4];
-    out[6] = o[5];
-    out[7] = o[6];
-    return GOC_OK;
+    if (run < 0 || run >= h->nruns) return fail(GOC_EINVAL, "run %d outside [0, %d)", run, h->nruns);
+    return diag_run(h, run, out);
 }
+
+int goc_lbm_diagnostics(goc_lbm_t* h, double out[8]) { return goc_lbm_diagnostics_run(h, 0, out); }
 
 int goc_lbm_get_populations_run(goc_lbm_t* h, int32_t run, double* f, double* F, double* g, int32_t on_device)
 {

@@ -532,3 +532,106 @@ def test_create_rejects_bad_grid():
     with pytest.raises(B.GocError) as ei:
         B.Run(case, structs=(g, m, p))
     assert ei.value.code == B.GOC_EINVAL
+
+
+def _diag_expected(o, nx):
+    """The eight global sums formed from the oracle's populations and fields
+    (FP64), and a scale for each to measure differences against."""
+    f = o.fields()
+    h1, h2 = o.h1, o.h2
+    rho, U1, U2 = f["rho"], f["U1"], f["U2"]
+    e, sc = np.zeros(8), np.ones(8)
+    e[0], sc[0] = o.f.sum(), np.abs(o.f).sum()
+    m1, m2 = h2 * rho * U1, h1 * rho * U2
+    e[1], e[2] = m1.sum(), m2.sum()
+    sc[1] = sc[2] = np.abs(m1).sum() + np.abs(m2).sum()
+    e[3], sc[3] = e[1] / nx, sc[1] / nx
+    if "B1" in f:
+        b1, b2 = h1 * h2 * f["B1"], h1 * h2 * f["B2"]
+        e[4], e[5] = b1.sum(), b2.sum()
+        sc[4] = sc[5] = np.abs(b1).sum() + np.abs(b2).sum()
+    e[6] = sc[6] = np.max(np.hypot(U1, U2))
+    e[7] = 0.0
+    return e, sc
+
+
+def _check_diag(d, e, sc, what):
+    print(what, "diagnostics", np.array2string(d, precision=6), flush=True)
+    for k in range(7):
+        assert abs(d[k] - e[k]) <= 1e-12 * sc[k], (what, k, d[k], e[k])
+    assert d[7] == 0.0, what
+
+
+@pytest.mark.parametrize("which", ["mhd_channel", "cavity"])
+def test_diagnostics_every_output_matches_oracle(oracle_lib, which):
+    """All eight outputs of goc_lbm_diagnostics (mass, the two momentum sums,
+    the mean flow rate, the two magnetic fluxes, max |U| and the non-finite
+    count) against the same sums formed from the FP64 oracle's populations
+    and fields, within 1e-12 of each sum's scale, on an MHD channel and on a
+    cavity with a moving lid, FP64, from smooth random fields."""
+    if which == "mhd_channel":
+        case = W.Case("dg", 70, 40, "periodic", "wall", ("uniform", 0.0), ("tanh", 3.0), flow="hartmann",
+                      Re=100.0, Ha=30.0, mhd=True, storage="f64")
+    else:
+        case = cavity(70, 45, "f64")
+    fields = W.smooth_fields(case.nx, case.ny, seed=21, amp=0.01)
+    g, o = run_pair(oracle_lib, case, 100, fields)
+    e, sc = _diag_expected(o, case.nx)
+    _check_diag(g.diagnostics(), e, sc, which)
+    _check_diag(g.diagnostics(run=0), e, sc, which)
+
+
+def test_diagnostics_of_every_batch_run(oracle_lib):
+    """goc_lbm_diagnostics_run on each run of a batch (uneven grids, plain
+    and MHD runs, FP64, 60 steps from smooth random fields) against that
+    run's own oracle sums."""
+    runs = [c.replace(storage="f64") for c in W.batch_256(n=3)]
+    runs.append(W.Case("bc", 70, 33, "periodic", "wall", ("uniform", 0.0), ("tanh", 1.5), flow="channel",
+                       Re=10.0, tau=0.8, storage="f64"))
+    g = B.Run(batch=runs)
+    inits = [W.smooth_fields(c.nx, c.ny, seed=30 + r, amp=0.01) for r, c in enumerate(runs)]
+    for r, init in enumerate(inits):
+        g.init_run(r, *init)
+    g.step(60)
+    for r, case in enumerate(runs):
+        o = oracle_lib.Model(case).init(*inits[r]).step(60)
+        e, sc = _diag_expected(o, case.nx)
+        _check_diag(g.diagnostics(run=r), e, sc, f"batch run {r}")
+    with pytest.raises(B.GocError) as ei:
+        g.diagnostics(run=len(runs))
+    assert ei.value.code == B.GOC_EINVAL
+
+
+def test_moments_and_init_on_device_tensors(oracle_lib):
+    """goc_lbm_moments with on_device = 1 writes into torch device tensors
+    exactly what the host path returns, and goc_lbm_init_mhd from device
+    tensors gives the same state as from host arrays."""
+    torch = pytest.importorskip("torch")
+    case = W.Case("dv", 70, 40, "periodic", "wall", ("uniform", 0.0), ("tanh", 3.0), flow="hartmann",
+                  Re=100.0, Ha=30.0, mhd=True, storage="f32")
+    rho, u1, u2 = W.smooth_fields(case.nx, case.ny, seed=8, amp=0.01)
+    b1 = 1e-4 * u1
+    b2 = np.full_like(u1, 0.0)
+    a = B.Run(case)
+    b2 += a.derived()["B0"]
+    a.init(rho, u1, u2, b1, b2)
+    c = B.Run(case)
+    dev = [torch.from_numpy(np.ascontiguousarray(x)).to("cuda") for x in (rho, u1, u2, b1, b2)]
+    torch.cuda.synchronize()
+    B._check(B.lib().goc_lbm_init_mhd(c.h, *[t.data_ptr() for t in dev], 1))
+    assert a.get_state() == c.get_state()
+    a.step(50)
+    N = case.nx * case.ny
+    t_rho = torch.empty(N, dtype=torch.float64, device="cuda")
+    t_u = torch.empty(2 * N, dtype=torch.float64, device="cuda")
+    t_B = torch.empty(2 * N, dtype=torch.float64, device="cuda")
+    a.fields_device(t_rho, t_u, t_B)
+    a.synchronize()
+    torch.cuda.synchronize()
+    host = a.fields()
+    sh = (case.ny, case.nx)
+    assert np.array_equal(t_rho.cpu().numpy().reshape(sh), host["rho"])
+    assert np.array_equal(t_u.cpu().numpy()[:N].reshape(sh), host["U1"])
+    assert np.array_equal(t_u.cpu().numpy()[N:].reshape(sh), host["U2"])
+    assert np.array_equal(t_B.cpu().numpy()[:N].reshape(sh), host["B1"])
+    assert np.array_equal(t_B.cpu().numpy()[N:].reshape(sh), host["B2"])
