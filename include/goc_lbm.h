@@ -269,6 +269,18 @@ int goc_lbm_moments(goc_lbm_t *h, double *rho, double *u, double *B, int32_t on_
 int goc_lbm_diagnostics(goc_lbm_t *h, double out[8]);
 /* The same for run `run` of a batch (GOC_EINVAL outside [0, num_runs)). */
 int goc_lbm_diagnostics_run(goc_lbm_t *h, int32_t run, double out[8]);
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, hosts that forbid hipMalloc): the eight
+   outputs of goc_lbm_diagnostics_run, computed by the same kernels, written
+   to the device buffer out_dev (8 doubles, on the handle's device), queued
+   on the handle's stream with no synchronisation and no allocation.  The
+   partial sums live in a static device array of the library (4096 x 7
+   doubles, 229 KB on every device it runs on, held until the process ends;
+   every grid fits it, since the first pass strides over the nodes).  Calls
+   that overlap on one GPU (other streams, other threads) race on that array.
+   GOC_EINVAL for a run outside [0, num_runs), a NULL out_dev, or a current
+   device other than the handle's. */
+int goc_lbm_diagnostics_noalloc(goc_lbm_t *h, int32_t run, double *out_dev);
 
 /* Check every `every` steps (0 = never) for non-finite populations; a hit
    makes goc_lbm_step return GOC_EUNSTABLE. */

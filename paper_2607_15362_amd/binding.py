@@ -80,6 +80,7 @@ SIGNATURES = {
     "goc_lbm_moments_run": (C.c_int, [VP, C.c_int32, VP, VP, VP, C.c_int32]),
     "goc_lbm_diagnostics": (C.c_int, [VP, P_D]),
     "goc_lbm_diagnostics_run": (C.c_int, [VP, C.c_int32, P_D]),
+    "goc_lbm_diagnostics_noalloc": (C.c_int, [VP, C.c_int32, VP]),
     "goc_lbm_set_watchdog": (C.c_int, [VP, C.c_int64]),
     "goc_lbm_get_populations": (C.c_int, [VP, VP, VP, VP, C.c_int32]),
     "goc_lbm_get_populations_run": (C.c_int, [VP, C.c_int32, VP, VP, VP, C.c_int32]),

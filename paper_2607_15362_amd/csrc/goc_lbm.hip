@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -1087,6 +1088,36 @@ int diag_run(goc_lbm* h, int run, double out[8])
     return GOC_OK;
 }
 
+// Scratch of goc_lbm_diagnostics_noalloc: room for the partials of the
+// diagnostics' first pass at its largest grid (goc::kDiagBlocks x
+// goc::kDiag doubles, 229 KB), in every device's memory from the library's
+// loading until the process ends.  Host code never uses the name itself
+// (a host-side stand-in): each device's copy is reached through the address
+// scratch_on returns.
+__device__ __align__(256) double scratch[goc::kDiagBlocks * goc::kDiag];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};   // device address of `scratch` on each device
+
+// The address of `scratch` on the current device `device`, looked up with
+// that device current on its first use and kept.
+int scratch_on(int device, double** out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= kMaxDevices) return fail(GOC_EDEVICE, "device %d beyond %d", device, kMaxDevices);
+    if (!g_scratch_dev[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(GOC_EDEVICE, "hipGetSymbolAddress of the diagnostics scratch failed: %s",
+                        hipGetErrorString(e));
+        g_scratch_dev[device] = static_cast<double*>(p);
+    }
+    *out = g_scratch_dev[device];
+    return GOC_OK;
+}
+
 int capture_graph(goc_lbm* h, int parity)
 {
     hipGraph_t g = nullptr;
@@ -1527,6 +1558,23 @@ int goc_lbm_diagnostics_run(goc_lbm_t* h, int32_t run, double out[8])
 }
 
 int goc_lbm_diagnostics(goc_lbm_t* h, double out[8]) { return goc_lbm_diagnostics_run(h, 0, out); }
+
+int goc_lbm_diagnostics_noalloc(goc_lbm_t* h, int32_t run, double* out_dev)
+{
+    if (!check_handle(h)) return GOC_EINVAL;
+    if (!out_dev) return fail(GOC_EINVAL, "out_dev is NULL");
+    if (run < 0 || run >= h->nruns) return fail(GOC_EINVAL, "run %d outside [0, %d)", run, h->nruns);
+    int device = -1;
+    HIPOK(hipGetDevice(&device));
+    if (device != h->device)
+        return fail(GOC_EINVAL, "current device %d is not the handle's device %d", device, h->device);
+    if (diag_blocks(h->runs[run]) > goc::kDiagBlocks)   // (the first pass strides: never true)
+        return fail(GOC_EINVAL, "diagnostics of run %d need more than the %d partials of the scratch", run,
+                    goc::kDiagBlocks);
+    double* part = nullptr;
+    if (int rc = scratch_on(device, &part)) return rc;
+    return launch_diag(h, run, part, out_dev);
+}
 
 int goc_lbm_get_populations_run(goc_lbm_t* h, int32_t run, double* f, double* F, double* g, int32_t on_device)
 {
