@@ -15,7 +15,10 @@ Prints ONE JSON line:
                              on the launch stream) against 8 TB/s, and the
                              measured HBM traffic per launch when a counter
                              profile of the current kernel source is
-                             committed under profiles/
+                             committed under profiles/; and the
+                             same-pattern ceiling: a kernel with the step's
+                             loads and stores and none of its arithmetic
+                             (libgocceiling.so), beside a one-stream copy
   cpu_baseline               the FP64 oracle on the host cores (all of them,
                              and one), on a bounded sample of the workload
   forms                      the same GPU on the same workload in FP32 and the
@@ -127,22 +130,31 @@ def cpu_baseline(case, seconds: float):
 
 
 def copy_calibration(mib: int, reps: int):
-    """A plain device-to-device copy of known size, for scaling the HBM byte
-    counters of a profiler run: prints the bytes moved per copy and the rate."""
-    import torch
-    n = mib * (1 << 20) // 4
-    a = torch.ones(n, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
-    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
-                      "GB_s": round(8 * n / dt / 1e9, 1)}), flush=True)
+    """A plain device-to-device copy of known size (the instrument library's
+    copy kernel), for scaling the HBM byte counters of a profiler run: prints
+    the bytes moved per copy and the rate."""
+    from paper_2607_15362_amd import ceiling as CL
+    nb = mib * (1 << 20)
+    us = CL.copy_us(nb, reps)
+    print(json.dumps({"copy_bytes_read": nb, "copy_bytes_written": nb,
+                      "GB_s": round(2 * nb / us / 1e3, 1)}), flush=True)
+
+
+def pattern_ceiling(case, launch, bytes_per_launch: float, launch_us: float):
+    """The same-pattern ceiling of the tiled step on this workload: the
+    instrument kernel with the step's loads and stores (same layout, tile
+    shape and store policy) and no arithmetic, and a 1 GiB one-stream copy.
+    None for the march and for FP64 storage, which it does not mirror."""
+    from paper_2607_15362_amd import ceiling as CL
+    if launch["waves_per_cu"] != 0 or case.storage == "f64" or case.bc_x != "periodic":
+        return None
+    sb = 4 if case.storage == "f32" else 2
+    us = CL.pattern_us(case.nx, case.ny, case.mhd, sb, int(launch["rows_per_segment"]), bool(launch["nontemporal"]))
+    cu = CL.copy_us(1 << 30)
+    return {"instrument": "goc_ceiling_pattern: the step's loads and stores without its arithmetic",
+            "pattern_us": round(us, 2), "pattern_GB_s_algorithmic": round(bytes_per_launch / us / 1e3, 1),
+            "step_over_pattern": round(launch_us / us, 4),
+            "copy_1GiB_GB_s": round(2 * (1 << 30) / cu / 1e3, 1)}
 
 
 def developed(run, case):
@@ -354,6 +366,7 @@ def main():
     ap.add_argument("--no-collisions", action="store_true")
     ap.add_argument("--no-curvilinear", action="store_true")
     ap.add_argument("--no-cache-resident", action="store_true")
+    ap.add_argument("--no-ceiling", action="store_true", help="skip the same-pattern ceiling of the roofline")
     ap.add_argument("--only-main", action="store_true", help="the main line only (all of the --no-* options)")
     ap.add_argument("--waves", type=float, default=-1.0, metavar="W",
                     help="fixed step form instead of the autotuner (for profiler runs): W > 0 the march with "
@@ -376,7 +389,7 @@ def main():
         return
     if args.only_main:
         args.no_cpu_baseline = args.no_forms = args.no_batch = args.no_collisions = True
-        args.no_curvilinear = args.no_cache_resident = True
+        args.no_curvilinear = args.no_cache_resident = args.no_ceiling = True
 
     from paper_2607_15362_amd import binding as B
     from paper_2607_15362_amd import workloads as W
@@ -443,6 +456,8 @@ def main():
                                                     if tuned["us_before"] == tuned["us_before"] else None)}},
     }
     run.close()
+    if not args.batch and not args.no_ceiling:
+        out["roofline"]["ceiling"] = pattern_ceiling(case, launch, bytes_per_launch, launch_s * 1e6)
 
     if not args.no_forms and not args.batch and case.flow == "hartmann" and case.storage == "f32":
         out["forms"] = storage_forms(case, args.steps)

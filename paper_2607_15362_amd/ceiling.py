@@ -1,0 +1,77 @@
+"""Binding of the bandwidth instruments (include/goc_ceiling.h, libgocceiling.so):
+argument marshalling only.
+
+    python -m paper_2607_15362_amd.ceiling [NX NY MHD STORAGE_BYTES ROWS NT]
+
+prints the same-pattern time of the tiled step (default: the 4096 x 1024
+Hartmann layout, FP32, D2Q5 slots, 64 x 4 tiles, non-temporal stores) and a
+1 GiB one-stream copy as one JSON line.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgocceiling.so")
+
+SIGNATURES = {
+    "goc_ceiling_pattern": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p,
+                                      C.POINTER(C.c_double)]),
+    "goc_ceiling_copy": (C.c_int, [C.c_int64, C.c_int, C.c_void_p, C.POINTER(C.c_double)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libgocceiling.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2607_15362_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise RuntimeError(f"{what} failed with status {rc}")
+
+
+def pattern_us(nx: int, ny: int, mhd: bool, storage_bytes: int, rows: int, nontemporal: bool, reps: int = 200,
+               stream: int = 0) -> float:
+    """Mean microseconds per launch of the tiled step's memory pattern."""
+    out = C.c_double(0.0)
+    _check(lib().goc_ceiling_pattern(nx, ny, int(bool(mhd)), storage_bytes, rows, int(bool(nontemporal)), reps,
+                                     C.c_void_p(stream or None), C.byref(out)), "goc_ceiling_pattern")
+    return out.value
+
+
+def copy_us(nbytes: int, reps: int = 50, stream: int = 0) -> float:
+    """Mean microseconds per launch of a one-stream copy of nbytes."""
+    out = C.c_double(0.0)
+    _check(lib().goc_ceiling_copy(nbytes, reps, C.c_void_p(stream or None), C.byref(out)), "goc_ceiling_copy")
+    return out.value
+
+
+def main(argv):
+    nx, ny, mhd, sb, rows, nt = (int(v) for v in argv) if argv else (4096, 1024, 1, 4, 4, 1)
+    us = pattern_us(nx, ny, bool(mhd), sb, rows, bool(nt))
+    nb = 1 << 30
+    cu = copy_us(nb)
+    print(json.dumps({"pattern": {"nx": nx, "ny": ny, "mhd": mhd, "storage_bytes": sb, "rows": rows,
+                                  "nontemporal": nt, "us_per_launch": round(us, 2)},
+                      "copy": {"bytes": nb, "us_per_launch": round(cu, 2),
+                               "GB_s_read_plus_write": round(2 * nb / (cu * 1e-6) / 1e9, 1)}}), flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

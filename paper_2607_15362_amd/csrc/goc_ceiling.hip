@@ -1,0 +1,310 @@
+// goc_ceiling.hip -- bandwidth instruments for the roofline of the tiled step
+// (libgocceiling.so, declared in include/goc_ceiling.h).
+//
+// A measurement aid, not part of the method: the pattern kernel moves the
+// bytes of one tiled time step (App. E: pull of every slot from its
+// neighbour, writes of the node's own slots, of the ghost rows and of the
+// lagged force; with the D2Q5 slots of App. G) in the library's layout and
+// launch geometry, and computes nothing but a sum per pulled node.  Its
+// duration bounds what the step can reach with this memory pattern; the copy
+// kernel gives the plain one-stream figure beside it.  Both allocate their
+// own buffers; nothing here is used by the step.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+
+#include "goc_tile.hpp"
+#include "../../include/goc_ceiling.h"
+#include "../../include/goc_lbm.h"
+
+namespace {
+
+using goc::kTileX;
+
+// The tiled step's memory traffic for one straight run: the same tile
+// placement (XCD bands, edge tiles shifted back), the same pulls of the own
+// node and of the ring around the tile (slot offsets of pull_off), one LDS
+// value per pulled node and a barrier, and the same stores (nine slots, ten
+// D2Q5 slots, the ghost rows of rows 0 and ny - 1, the two force planes).
+// Raw storage values are moved unchanged: the stored slot is the own pulled
+// slot plus the LDS sum of the left and right neighbours scaled by zero at
+// run time (so that no load can be dropped).
+template <class S, bool MHD, int TY, bool NT>
+__global__ void __launch_bounds__(kTileX * TY)
+pattern_kernel(goc::RunDesc d, goc::Pools<S, float> pl, float zero)
+{
+    using goc::kQ;
+    using goc::kM;
+    __shared__ float sm[TY + 2][kTileX + 2];
+    const int nx = d.nx, ny = d.ny;
+    const int gx = (nx + kTileX - 1) / kTileX, gy = (ny + TY - 1) / TY;
+    const int nt = gx * gy;
+    const int xcd = blockIdx.x & 7, q = nt >> 3, rem = nt & 7;
+    const int t = xcd * q + min(xcd, rem) + (int)(blockIdx.x >> 3);
+    const int tx = nx < kTileX ? nx : kTileX, ty = ny < TY ? ny : TY;
+    const int ox = (t % gx) * kTileX, oy = (t / gx) * TY;
+    const int x0 = ox < nx - tx ? ox : nx - tx, y0 = oy < ny - ty ? oy : ny - ty;
+    const int lx = threadIdx.x, ly = threadIdx.y;
+    const int i = x0 + lx, j = y0 + ly;
+    const bool in = lx < tx && ly < ty;
+    const bool px = d.bc_x == 0, py = d.bc_y == 0;
+    const goc::RunBytes b = goc::run_bytes(d, pl);
+    const uint32_t planeF = uint32_t(d.plane * sizeof(float));
+    const int ic = in ? i : x0, jc = in ? j : y0;
+    const int h = ly * kTileX + lx, nh = 2 * tx + 2 * ty;
+    int hx, hy;
+    if (h < 2 * tx) {
+        hx = h < tx ? h : h - tx;
+        hy = h < tx ? -1 : ty;
+    } else {
+        hx = h < 2 * tx + ty ? -1 : tx;
+        hy = h < 2 * tx + ty ? h - 2 * tx : h - 2 * tx - ty;
+    }
+    int hi = x0 + hx, hj = y0 + hy;
+    bool hv = h < nh;
+    if (hi < 0 || hi >= nx) {
+        hv = hv && px;
+        hi = hi < 0 ? hi + nx : hi - nx;
+    }
+    if (hj < 0 || hj >= ny) {
+        hv = hv && py;
+        hj = hj < 0 ? hj + ny : hj - ny;
+    }
+    hi = hv ? hi : ic;
+    hj = hv ? hj : jc;
+    S f[kQ], g[2][kM];
+    float F1, F2;
+#pragma unroll
+    for (int a = 0; a < kQ; ++a) f[a] = goc::ld_at<S>(b.f, goc::pull_off<S>(d, b, ic, jc, a));
+    {
+        const uint32_t nf = uint32_t(jc) * b.pitch_F + uint32_t(ic) * 4u;
+        F1 = goc::ld_at<float>(b.F, nf);
+        F2 = goc::ld_at<float>(b.F, nf + planeF);
+    }
+    if constexpr (MHD) {
+#pragma unroll
+        for (int a = 0; a < kM; ++a) {
+            const uint32_t off = goc::pull_off<S>(d, b, ic, jc, a);
+#pragma unroll
+            for (int ci = 0; ci < 2; ++ci) g[ci][a] = goc::ld_at<S>(b.g, ci * b.g_comp + off);
+        }
+    }
+    if (ly * kTileX < nh) {
+        float s = 0.f;
+#pragma unroll
+        for (int a = 0; a < kQ; ++a) s += float(goc::ld_at<S>(b.f, goc::pull_off<S>(d, b, hi, hj, a)));
+        const uint32_t nf = uint32_t(hj) * b.pitch_F + uint32_t(hi) * 4u;
+        s += goc::ld_at<float>(b.F, nf) + goc::ld_at<float>(b.F, nf + planeF);
+        if (hv) sm[hy + 1][hx + 1] = s;
+    }
+    if (in) {
+        float s = F1 + F2;
+#pragma unroll
+        for (int a = 0; a < kQ; ++a) s += float(f[a]);
+        sm[ly + 1][lx + 1] = s;
+    }
+    __syncthreads();
+    if (!in || i < ox || j < oy) return;
+    const float v = zero * (sm[ly + 1][lx] + sm[ly + 1][lx + 2]);
+    const uint32_t cs = uint32_t(sizeof(S));
+    const uint32_t own = uint32_t(j + 1) * b.pitch_s + uint32_t(i) * cs;
+    const int jw = __builtin_amdgcn_readfirstlane(jc);
+    const bool bot = jw == 0, top = jw == ny - 1;
+    const S dv = S(v);
+    if constexpr (MHD) {
+#pragma unroll
+        for (int ci = 0; ci < 2; ++ci)
+#pragma unroll
+            for (int a = 0; a < kM; ++a)
+                goc::st_nt<NT, S>(b.go, ci * b.g_comp + uint32_t(a) * b.plane_s + own, S(g[ci][a] + dv));
+        if (bot || top) {
+            const bool wall = !py;
+            const uint32_t grow = (wall ? bot : top) ? 0u : uint32_t(ny + 1) * b.pitch_s;
+            const uint32_t pg = (wall == bot) ? 2u : 4u;
+#pragma unroll
+            for (int ci = 0; ci < 2; ++ci)
+                goc::st_nt<NT, S>(b.go, grow + ci * b.g_comp + pg * b.plane_s + uint32_t(i) * cs,
+                                  bot ? g[ci][4] : g[ci][2]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < kQ; ++a) goc::st_nt<NT, S>(b.fo, uint32_t(a) * b.plane_s + own, S(f[a] + dv));
+    if (bot || top) {
+        const bool wall = !py;
+        const bool wxlo = !px && i == 0, wxhi = !px && i == nx - 1;
+        const uint32_t grow = (wall ? bot : top) ? 0u : uint32_t(ny + 1) * b.pitch_s;
+        const uint32_t p0 = (wall == bot) ? 2 : 4;
+        const uint32_t p1 = wall ? (bot ? 5 : 8) : (bot ? 7 : 6);
+        const uint32_t p2 = wall ? (bot ? 6 : 7) : (bot ? 8 : 5);
+        const int cm = px ? (i == 0 ? nx - 1 : i - 1) : i - 1;
+        const int cp = px ? (i == nx - 1 ? 0 : i + 1) : i + 1;
+        goc::st_nt<NT, S>(b.fo, grow + p0 * b.plane_s + uint32_t(i) * cs, bot ? f[4] : f[2]);
+        if (!wall) {
+            goc::st_nt<NT, S>(b.fo, grow + p1 * b.plane_s + uint32_t(i) * cs, bot ? f[7] : f[6]);
+            goc::st_nt<NT, S>(b.fo, grow + p2 * b.plane_s + uint32_t(i) * cs, bot ? f[8] : f[5]);
+        } else {
+            if (!wxlo) goc::st_nt<NT, S>(b.fo, grow + p1 * b.plane_s + uint32_t(cm) * cs, bot ? f[7] : f[6]);
+            if (!wxhi) goc::st_nt<NT, S>(b.fo, grow + p2 * b.plane_s + uint32_t(cp) * cs, bot ? f[8] : f[5]);
+        }
+    }
+    const uint32_t nf = uint32_t(j) * b.pitch_F + uint32_t(i) * 4u;
+    goc::st_nt<NT, float>(b.Fo, nf, F1 + v);
+    goc::st_nt<NT, float>(b.Fo, nf + planeF, F2 + v);
+}
+
+// One-stream copy: 16-byte vectors, grid-stride, four loads in flight per
+// thread before their stores.
+__global__ void __launch_bounds__(256) copy_kernel(const float4* __restrict__ a, float4* __restrict__ o, int64_t n)
+{
+    const int64_t s = (int64_t)gridDim.x * 256;
+    int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    for (; k + 3 * s < n; k += 4 * s) {
+        const float4 v0 = a[k], v1 = a[k + s], v2 = a[k + 2 * s], v3 = a[k + 3 * s];
+        o[k] = v0;
+        o[k + s] = v1;
+        o[k + 2 * s] = v2;
+        o[k + 3 * s] = v3;
+    }
+    for (; k < n; k += s) o[k] = a[k];
+}
+
+struct Events {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Events()
+    {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
+struct Buffers {
+    void* p[6] = {};
+    ~Buffers()
+    {
+        for (void* q : p)
+            if (q) (void)hipFree(q);
+    }
+};
+
+template <class S, bool MHD, int TY, bool NT>
+int run_pattern(const goc::RunDesc& d, int64_t f_elems, int64_t F_elems, int reps, hipStream_t st, double* us)
+{
+    Buffers buf;
+    const size_t fb = size_t(f_elems) * sizeof(S), Fb = size_t(F_elems) * sizeof(float);
+    const size_t sizes[6] = {fb, fb, Fb, Fb, MHD ? fb : 16, MHD ? fb : 16};
+    for (int k = 0; k < 6; ++k) {
+        if (hipMalloc(&buf.p[k], sizes[k]) != hipSuccess) return GOC_ENOMEM;
+        if (hipMemsetAsync(buf.p[k], 0, sizes[k], st) != hipSuccess) return GOC_EDEVICE;
+    }
+    const int gx = (d.nx + kTileX - 1) / kTileX, gy = (d.ny + TY - 1) / TY;
+    const dim3 grid(gx * gy), block(kTileX, TY);
+    auto launch = [&](int k) {
+        goc::Pools<S, float> pl{};
+        const int a = k & 1;
+        pl.fin = static_cast<const S*>(buf.p[a]);
+        pl.fout = static_cast<S*>(buf.p[1 - a]);
+        pl.Fin = static_cast<const float*>(buf.p[2 + a]);
+        pl.Fout = static_cast<float*>(buf.p[3 - a]);
+        pl.gin = static_cast<const S*>(buf.p[4 + a]);
+        pl.gout = static_cast<S*>(buf.p[5 - a]);
+        hipLaunchKernelGGL((pattern_kernel<S, MHD, TY, NT>), grid, block, 0, st, d, pl, 0.f);
+        return hipGetLastError();
+    };
+    for (int k = 0; k < 4; ++k)
+        if (launch(k) != hipSuccess) return GOC_EDEVICE;
+    Events ev;
+    if (hipEventCreate(&ev.e0) != hipSuccess || hipEventCreate(&ev.e1) != hipSuccess) return GOC_EDEVICE;
+    if (hipEventRecord(ev.e0, st) != hipSuccess) return GOC_EDEVICE;
+    for (int k = 0; k < reps; ++k)
+        if (launch(k) != hipSuccess) return GOC_EDEVICE;
+    if (hipEventRecord(ev.e1, st) != hipSuccess || hipEventSynchronize(ev.e1) != hipSuccess) return GOC_EDEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev.e0, ev.e1) != hipSuccess) return GOC_EDEVICE;
+    *us = 1e3 * double(ms) / reps;
+    return GOC_OK;
+}
+
+template <class S, bool MHD, int TY>
+int pick_nt(const goc::RunDesc& d, int64_t fe, int64_t Fe, int nt, int reps, hipStream_t st, double* us)
+{
+    return nt ? run_pattern<S, MHD, TY, true>(d, fe, Fe, reps, st, us)
+              : run_pattern<S, MHD, TY, false>(d, fe, Fe, reps, st, us);
+}
+
+template <class S, bool MHD>
+int pick_rows(const goc::RunDesc& d, int64_t fe, int64_t Fe, int rows, int nt, int reps, hipStream_t st, double* us)
+{
+    switch (rows) {
+    case 4: return pick_nt<S, MHD, 4>(d, fe, Fe, nt, reps, st, us);
+    case 8: return pick_nt<S, MHD, 8>(d, fe, Fe, nt, reps, st, us);
+    default: return pick_nt<S, MHD, 16>(d, fe, Fe, nt, reps, st, us);
+    }
+}
+
+}  // namespace
+
+extern "C" int goc_ceiling_pattern(int nx, int ny, int mhd, int storage_bytes, int tile_rows, int nontemporal,
+                                   int reps, void* stream, double* us_per_launch)
+{
+    if (!us_per_launch || nx < 3 || ny < 3 || reps < 1 || (storage_bytes != 4 && storage_bytes != 2) ||
+        (tile_rows != 4 && tile_rows != 8 && tile_rows != 16))
+        return GOC_EINVAL;
+    goc::RunDesc d{};
+    d.nx = nx;
+    d.ny = ny;
+    d.bc_x = GOC_BC_PERIODIC;
+    d.bc_y = GOC_BC_WALL;
+    d.mhd = mhd ? 1 : 0;
+    const int64_t row = goc::padded_row(nx);
+    d.plane = row;
+    d.pitch = int32_t((mhd ? 10 : 9) * row);
+    d.pitchF = int32_t(2 * row);
+    const int64_t region = (int64_t)d.pitch * (ny + 2) + 256, regionF = (int64_t)d.pitchF * ny + 256;
+    if (region * storage_bytes > (int64_t)UINT32_MAX) return GOC_EINVAL;
+    d.f_off = d.pitch;
+    d.g_off = d.pitch;
+    d.F_off = 0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int nt = nontemporal ? 1 : 0;
+    if (storage_bytes == 4)
+        return mhd ? pick_rows<float, true>(d, region, regionF, tile_rows, nt, reps, st, us_per_launch)
+                   : pick_rows<float, false>(d, region, regionF, tile_rows, nt, reps, st, us_per_launch);
+    return mhd ? pick_rows<__half, true>(d, region, regionF, tile_rows, nt, reps, st, us_per_launch)
+               : pick_rows<__half, false>(d, region, regionF, tile_rows, nt, reps, st, us_per_launch);
+}
+
+extern "C" int goc_ceiling_copy(int64_t bytes, int reps, void* stream, double* us_per_launch)
+{
+    if (!us_per_launch || bytes < 16 || bytes % 16 != 0 || reps < 1) return GOC_EINVAL;
+    Buffers buf;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (int k = 0; k < 2; ++k) {
+        if (hipMalloc(&buf.p[k], size_t(bytes)) != hipSuccess) return GOC_ENOMEM;
+        if (hipMemsetAsync(buf.p[k], 0, size_t(bytes), st) != hipSuccess) return GOC_EDEVICE;
+    }
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+    }
+    const int64_t n = bytes / 16;
+    const int blocks = 32 * ncu;
+    auto launch = [&](int k) {
+        hipLaunchKernelGGL(copy_kernel, dim3(blocks), dim3(256), 0, st, static_cast<const float4*>(buf.p[k & 1]),
+                           static_cast<float4*>(buf.p[1 - (k & 1)]), n);
+        return hipGetLastError();
+    };
+    for (int k = 0; k < 4; ++k)
+        if (launch(k) != hipSuccess) return GOC_EDEVICE;
+    Events ev;
+    if (hipEventCreate(&ev.e0) != hipSuccess || hipEventCreate(&ev.e1) != hipSuccess) return GOC_EDEVICE;
+    if (hipEventRecord(ev.e0, st) != hipSuccess) return GOC_EDEVICE;
+    for (int k = 0; k < reps; ++k)
+        if (launch(k) != hipSuccess) return GOC_EDEVICE;
+    if (hipEventRecord(ev.e1, st) != hipSuccess || hipEventSynchronize(ev.e1) != hipSuccess) return GOC_EDEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev.e0, ev.e1) != hipSuccess) return GOC_EDEVICE;
+    *us_per_launch = 1e3 * double(ms) / reps;
+    return GOC_OK;
+}

@@ -666,7 +666,7 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
             return bail(fail(GOC_EINVAL, "run %d: MHD runs need a straight metric", r));
         // the step kernel addresses a run's slot region (Q planes of padded
         // rows, two ghost rows) with 32-bit byte offsets
-        const int64_t row = (grid[r].nx + 63) / 64 * 64;
+        const int64_t row = goc::padded_row(grid[r].nx);
         const int64_t region = (params[r].mhd ? 10 : 9) * row * (grid[r].ny + 2) + 256;
         if (region * (int64_t)storage_bytes(storage) > (int64_t)UINT32_MAX)
             return bail(fail(GOC_EINVAL, "run %d: grid %d x %d too large for this storage "
@@ -706,7 +706,7 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
         std::memset(&d, 0, sizeof(d));
         d.nx = g.nx;
         d.ny = g.ny;
-        const int32_t row = (g.nx + 63) / 64 * 64;
+        const int32_t row = int32_t(goc::padded_row(g.nx));
         d.bc_x = g.bc_x;
         d.bc_y = g.bc_y;
         // rows interleaved: the planes of a row lie together (row stride

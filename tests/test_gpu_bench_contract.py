@@ -32,10 +32,25 @@ def test_bench_json_line():
         assert k in r, k
     assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
     assert 0.0 < r["frac"] < 1.0 and abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-3
+    # the same-pattern ceiling of the tiled step: the pattern alone is faster than the step
+    c = r["ceiling"]
+    if r["launch_plan"]["form"].startswith("tiled"):
+        assert 0 < c["pattern_us"] < r["launch_us"] * 1.02 and c["copy_1GiB_GB_s"] > 1000
     c = d["cpu_baseline"]
     for k in ("value", "unit", "cores", "kind", "sample"):
         assert k in c, k
     assert c["kind"] == "oracle" and c["value"] > 0 and c["cores"] >= 1 and c["one_core_value"] > 0
+
+
+@pytest.mark.gpu
+def test_ceiling_instrument_on_small_and_ragged_grids():
+    """The instrument runs (in bounds) on grids smaller than a tile and with
+    ragged edges, for both storage widths, and its copy moves a small buffer."""
+    from paper_2607_15362_amd import ceiling as CL
+    for nx, ny, mhd, sb, rows in [(3, 3, 1, 4, 16), (70, 37, 1, 4, 8), (130, 9, 0, 2, 4), (200, 66, 1, 2, 16)]:
+        us = CL.pattern_us(nx, ny, bool(mhd), sb, rows, True, reps=5)
+        assert 0 < us < 1e5
+    assert 0 < CL.copy_us(1 << 20, reps=5) < 1e5
 
 
 def test_bench_refuses_more_than_one_gpu():

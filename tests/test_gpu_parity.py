@@ -383,14 +383,15 @@ def test_checkpoint_resume_is_bitwise(oracle_lib):
 
 def test_set_state_refuses_blobs_of_other_grids():
     """A checkpoint of another grid is refused with GOC_ESTATE before any
-    copy, also where the total size matches: in FP32 without MHD a 768x3 and
-    a 64x54 run hold the same number of elements split differently between
-    slots and force, and a 60x54 and a 64x54 run the same slot and force
-    regions (rows padded to 64 columns)."""
+    copy, also where the total size matches: in FP32 without MHD (rows padded
+    to an odd number of 64-column pieces: 64 and 1472 elements) a 1472x3 and a
+    64x105 run hold the same number of elements split differently between
+    slots and force, and a 60x105 and a 64x105 run the same slot and force
+    regions."""
     def run(nx, ny):
         return B.Run(W.Case("st", nx, ny, "periodic", "wall", ("uniform", 0.0), ("tanh", 1.2), flow="channel",
                             Re=10.0, tau=0.8, storage="f32"))
-    a, b, c = run(64, 54), run(768, 3), run(60, 54)
+    a, b, c = run(64, 105), run(1472, 3), run(60, 105)
     blob_a = a.get_state()
     assert len(blob_a) == len(b.get_state())
     for target, blob in ((b, blob_a), (a, b.get_state()), (c, blob_a), (a, c.get_state())):

@@ -14,10 +14,10 @@ from paper_2607_15362_amd import workloads as W
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared_symbols():
-    txt = open(os.path.join(ROOT, "include", "goc_lbm.h")).read()
+def _declared_symbols(header="goc_lbm.h", prefix="goc_lbm_"):
+    txt = open(os.path.join(ROOT, "include", header)).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(goc_lbm_\w+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(" + prefix + r"\w+)\s*\(", txt)))
 
 
 @pytest.fixture(scope="module")
@@ -34,6 +34,32 @@ def test_library_exports_every_declared_symbol(lib):
     for s in syms:
         assert hasattr(lib, s), f"{s} declared in goc_lbm.h but not exported"
         assert s in B.SIGNATURES, f"{s} has no binding signature"
+
+
+def test_instrument_library_exports_every_declared_symbol():
+    from paper_2607_15362_amd import ceiling as CL
+    if not os.path.exists(CL.LIB_PATH):
+        from paper_2607_15362_amd import build
+        build.build_ceiling(force=True)
+    L = CL.lib()
+    syms = _declared_symbols("goc_ceiling.h", "goc_ceiling_")
+    assert syms == sorted(CL.SIGNATURES)
+    for s in syms:
+        assert hasattr(L, s), f"{s} declared in goc_ceiling.h but not exported"
+
+
+def test_instrument_rejects_bad_arguments():
+    """Argument checks run on the host, before any device call."""
+    import ctypes as C
+    from paper_2607_15362_amd import ceiling as CL
+    L = CL.lib()
+    out = C.c_double(0.0)
+    assert L.goc_ceiling_pattern(4096, 1024, 1, 8, 4, 1, 10, None, C.byref(out)) == B.GOC_EINVAL
+    assert L.goc_ceiling_pattern(4096, 1024, 1, 4, 5, 1, 10, None, C.byref(out)) == B.GOC_EINVAL
+    assert L.goc_ceiling_pattern(2, 1024, 1, 4, 4, 1, 10, None, C.byref(out)) == B.GOC_EINVAL
+    assert L.goc_ceiling_pattern(4096, 1024, 1, 4, 4, 1, 10, None, None) == B.GOC_EINVAL
+    assert L.goc_ceiling_copy(100, 10, None, C.byref(out)) == B.GOC_EINVAL
+    assert L.goc_ceiling_copy(1 << 20, 0, None, C.byref(out)) == B.GOC_EINVAL
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
