@@ -332,8 +332,11 @@ int goc_lbm_set_tile(goc_lbm_t *h, int32_t rows, int32_t nontemporal);
    of the fastest are timed again with three times the steps (at most
    10000), and the fastest of that second timing is kept (a run on a 2-D
    metric or in 16-bit storage has the tiled step only: its heights are
-   timed).  The state does not change: trial launches read the current
-   buffers and write the spare ones.  out[0] = chosen waves_per_cu (0: the
+   timed).  The trials step the state as a run does (each launch reads what
+   the previous one wrote) from a device copy of it, which is put back
+   afterwards, so the state does not change; the copy is freed before the
+   call returns (GOC_ENOMEM when it does not fit).  out[0] = chosen
+   waves_per_cu (0: the
    tiled step; its height and stores are launch_info's out[2], out[4]),
    out[1] = its
    microseconds per step (second timing), out[2] = microseconds per step of

@@ -1460,10 +1460,37 @@ int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
     } ev;
     HIPOK(hipEventCreate(&ev.e[0]));
     HIPOK(hipEventCreate(&ev.e[1]));
-    // every trial launch reads the current buffers and writes the others,
-    // which the next real step overwrites: the state does not change.  A
-    // candidate is (waves_per_cu, tile rows): waves_per_cu 0 is the tiled
+    // The trials step the state as a run does, each launch reading what the
+    // last one wrote (a trial that read the same buffer every time would find
+    // part of it still in the Infinity Cache, which a run never does, and
+    // favour the forms that keep it there); the state is copied first and
+    // put back afterwards, so the run does not change.  A candidate is
+    // (waves_per_cu, tile rows, store policy): waves_per_cu 0 is the tiled
     // step with that tile height, a positive one the march with that plan.
+    const size_t sb = storage_bytes(h->storage), fb = force_bytes(h->storage);
+    const size_t bytes[3] = {h->f_elems * sb, h->F_elems * fb, h->g_elems * sb};
+    void* const* bufs[3] = {h->f, h->F, h->g};
+    struct Saved {
+        void* p[3] = {nullptr, nullptr, nullptr};
+        ~Saved() { for (auto x : p) if (x) (void)hipFree(x); }
+    } saved;
+    const int cur0 = h->cur;
+    for (int k = 0; k < 3; ++k) {
+        if (!bytes[k]) continue;
+        if (hipMalloc(&saved.p[k], bytes[k]) != hipSuccess) {
+            saved.p[k] = nullptr;
+            return fail(GOC_ENOMEM, "tuner: no device memory for a copy of the state (%zu bytes)", bytes[k]);
+        }
+        HIPOK(hipMemcpyAsync(saved.p[k], bufs[k][cur0], bytes[k], hipMemcpyDeviceToDevice, h->stream));
+    }
+    auto restore = [&]() -> int {
+        h->cur = cur0;
+        for (int k = 0; k < 3; ++k)
+            if (bytes[k])
+                HIPOK(hipMemcpyAsync(bufs[k][cur0], saved.p[k], bytes[k], hipMemcpyDeviceToDevice, h->stream));
+        HIPOK(hipStreamSynchronize(h->stream));
+        return GOC_OK;
+    };
     struct Cand {
         double w;    // 0: the tiled step, > 0: the march with this plan
         int rows;    // tile height
@@ -1474,9 +1501,12 @@ int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
         int rc = select(c);
         if (rc) return rc;
         if ((rc = launch_step(h, 0))) return rc;
+        h->cur ^= 1;
         HIPOK(hipEventRecord(ev.e[0], h->stream));
-        for (int s = 0; s < steps; ++s)
+        for (int s = 0; s < steps; ++s) {
             if ((rc = launch_step(h, s))) return rc;
+            h->cur ^= 1;
+        }
         HIPOK(hipEventRecord(ev.e[1], h->stream));
         HIPOK(hipEventSynchronize(ev.e[1]));
         float ms = 0.0f;
@@ -1499,7 +1529,10 @@ int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
     std::vector<double> times;
     for (const auto& c : cands) {
         double us = 0.0;
-        if (int rc = time_form(c, trial_steps, us)) return rc;
+        if (int rc = time_form(c, trial_steps, us)) {
+            (void)restore();
+            return rc;
+        }
         times.push_back(us);
         if (c.w == prev.w && (prev.w != 0.0 || (c.rows == prev.rows && c.nt == prev.nt))) prev_us = us;
         if (us < best_us) {
@@ -1515,12 +1548,16 @@ int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
     for (size_t c = 0; c < cands.size(); ++c) {
         if (times[c] > 1.05 * best_us) continue;
         double us = 0.0;
-        if (int rc = time_form(cands[c], steps2, us)) return rc;
+        if (int rc = time_form(cands[c], steps2, us)) {
+            (void)restore();
+            return rc;
+        }
         if (us < best2) {
             best2 = us;
             best = cands[c];
         }
     }
+    if (int rc = restore()) return rc;
     if (int rc = select(best)) return rc;
     out[0] = best.w;
     out[1] = best2;
