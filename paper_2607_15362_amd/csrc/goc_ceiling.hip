@@ -178,10 +178,15 @@ struct Events {
     }
 };
 
+// Device buffers of one measurement, freed once the stream has drained (an
+// error return may leave work in flight).
 struct Buffers {
+    hipStream_t st = nullptr;
     void* p[6] = {};
+    explicit Buffers(hipStream_t s) : st(s) {}
     ~Buffers()
     {
+        (void)hipStreamSynchronize(st);
         for (void* q : p)
             if (q) (void)hipFree(q);
     }
@@ -190,7 +195,7 @@ struct Buffers {
 template <class S, bool MHD, int TY, bool NT>
 int run_pattern(const goc::RunDesc& d, int64_t f_elems, int64_t F_elems, int reps, hipStream_t st, double* us)
 {
-    Buffers buf;
+    Buffers buf(st);
     const size_t fb = size_t(f_elems) * sizeof(S), Fb = size_t(F_elems) * sizeof(float);
     const size_t sizes[6] = {fb, fb, Fb, Fb, MHD ? fb : 16, MHD ? fb : 16};
     for (int k = 0; k < 6; ++k) {
@@ -277,8 +282,8 @@ extern "C" int goc_ceiling_pattern(int nx, int ny, int mhd, int storage_bytes, i
 extern "C" int goc_ceiling_copy(int64_t bytes, int reps, void* stream, double* us_per_launch)
 {
     if (!us_per_launch || bytes < 16 || bytes % 16 != 0 || reps < 1) return GOC_EINVAL;
-    Buffers buf;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    Buffers buf(st);
     for (int k = 0; k < 2; ++k) {
         if (hipMalloc(&buf.p[k], size_t(bytes)) != hipSuccess) return GOC_ENOMEM;
         if (hipMemsetAsync(buf.p[k], 0, size_t(bytes), st) != hipSuccess) return GOC_EDEVICE;

@@ -1479,6 +1479,7 @@ int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
         if (!bytes[k]) continue;
         if (hipMalloc(&saved.p[k], bytes[k]) != hipSuccess) {
             saved.p[k] = nullptr;
+            (void)hipStreamSynchronize(h->stream);   // (copies into the earlier buffers may be in flight)
             return fail(GOC_ENOMEM, "tuner: no device memory for a copy of the state (%zu bytes)", bytes[k]);
         }
         HIPOK(hipMemcpyAsync(saved.p[k], bufs[k][cur0], bytes[k], hipMemcpyDeviceToDevice, h->stream));
