@@ -167,3 +167,20 @@ def test_create_checks_size_limits_before_touching_the_device(lib, nx, ny, stora
         assert "too large" in lib.goc_lbm_last_error().decode()
     if h.value:
         lib.goc_lbm_destroy(h)
+
+
+def test_committed_profiles_cover_the_current_kernels():
+    """The counter summaries under profiles/ were taken on the current kernel
+    sources, for every tiled form of the FP32 headline the autotuner has
+    picked or sits next to, so the benchmark reports measured traffic."""
+    import json
+    import bench
+    sha = bench.kernel_source_hash()
+    for form in ("tiled4nt", "tiled8nt", "tiled16nt"):
+        path = os.path.join(ROOT, "profiles", f"tile_step_kernel_hartmann_4096x1024_{form}_pmc.json")
+        with open(path) as fh:
+            d = json.load(fh)
+        assert d["kernel_source_sha"] == sha, path
+        t = bench.measured_traffic("goc::tile_step_kernel", "hartmann_4096x1024", form)
+        assert t == d["hbm_bytes_per_launch"]
+        assert 1.0 <= t / d["algorithmic_bytes_per_launch"] < 1.1
