@@ -362,6 +362,46 @@ def test_full_size_one_step_sampled(oracle_lib, which):
     assert d[7] == 0
 
 
+@pytest.mark.parametrize("storage,tol_f,tol_F", [("f32", 3e-6, 1e-5), ("f64", 1e-12, 1e-12)])
+def test_full_batch_256_one_step_sampled(oracle_lib, storage, tol_f, tol_F):
+    """The full seeded batch of 256 runs (44 M nodes) in the benchmark's
+    launch configuration (developed Hartmann starts, the tuned form, one
+    launch per step): one GPU step from the state after 50 steps against the
+    oracle evaluated at sampled nodes of 12 runs, the smallest and the largest
+    among them.  FP32: within 3e-6 of the largest population of each
+    direction class (the worst sampled run, 952x482, loses about 20 FP32
+    units of that size in one step's arithmetic, as its FP64 run loses about
+    90 FP64 units: cancellation in the step, not the storage); FP64: 1e-12."""
+    runs = [c.replace(storage=storage) for c in W.batch_256()]
+    g = B.Run(batch=runs)
+    for r, case in enumerate(runs):
+        d = g.derived(run=r)
+        g.init_run(r, *W.hartmann_start(case, d["nu"], d["F1"], d["eta"], d["B0"]))
+    g.tune(10)
+    print(f"[full batch] form {g.launch_info()}", flush=True)
+    g.step(50)
+    sizes = [c.nx * c.ny for c in runs]
+    rng = np.random.default_rng(11)
+    pick = sorted(set([int(np.argmin(sizes)), int(np.argmax(sizes))] +
+                      [int(k) for k in rng.choice(len(runs), 10, replace=False)]))
+    before = {r: g.populations(run=r) for r in pick}
+    g.step(1)
+    for r in pick:
+        case = runs[r]
+        f0, F0, g0 = before[r]
+        f1, F1, g1 = g.populations(run=r)
+        o = oracle_lib.Model(case)
+        o.set_state(f0, F0, g0)
+        ix, iy = W.sample_nodes(case.nx, case.ny, 200, seed=r)
+        fo, Fo, go = o.step_sample(ix, iy)
+        err_f = np.max(np.abs(f1[:, iy, ix] - fo) / np.abs(fo).max(axis=1, keepdims=True))
+        err_g = np.max(np.abs(g1[:, iy, ix] - go)) / np.max(np.abs(go))
+        err_F = np.max(np.abs(F1[:, iy, ix] - Fo)) / (np.max(np.abs(Fo)) + 1e-300)
+        print(f"[full batch {storage}] run {r} {case.nx}x{case.ny} beta {case.stretch_y[1]:.2f} Ha {case.Ha:.0f}: "
+              f"f {err_f:.1e} g {err_g:.1e} F {err_F:.1e}", flush=True)
+        assert err_f < tol_f and err_g < tol_f and err_F < tol_F, r
+
+
 def test_checkpoint_resume_is_bitwise(oracle_lib):
     case = W.Case("ck", 90, 60, "periodic", "wall", ("uniform", 0.0), ("tanh", 2.0), flow="hartmann",
                   Re=50.0, Ha=10.0, mhd=True, storage="f32")
