@@ -247,8 +247,8 @@ int goc_lbm_init_run(goc_lbm_t *h, int32_t run, const double *rho, const double 
    step, one fused kernel launch each; with a non-NULL stream, blocks of 100
    steps replay a captured HIP graph).  16-bit storage: the reference table
    is refreshed on the steps given above the storage enum, and graph blocks
-   start on them.  Asynchronous on the stream unless the watchdog interval
-   is due (goc_lbm_set_watchdog). */
+   start on them.  Asynchronous on the stream unless the watchdog check is
+   due at its return (goc_lbm_set_watchdog). */
 int goc_lbm_step(goc_lbm_t *h, int64_t n);
 
 /* Hydrodynamic and magnetic fields of the current state (App. E step 7,
@@ -282,8 +282,12 @@ int goc_lbm_diagnostics_run(goc_lbm_t *h, int32_t run, double out[8]);
    device other than the handle's. */
 int goc_lbm_diagnostics_noalloc(goc_lbm_t *h, int32_t run, double *out_dev);
 
-/* Check every `every` steps (0 = never) for non-finite populations; a hit
-   makes goc_lbm_step return GOC_EUNSTABLE. */
+/* The watchdog: when a goc_lbm_step call returns having completed at
+   least `every` steps since the last check (or since initialisation,
+   set_state or this call), every run's populations are checked for
+   non-finite values (the diagnostics pass, App. E step 7 sums), and a hit
+   makes that goc_lbm_step return GOC_EUNSTABLE.  Default 1000; 0 turns it
+   off.  The check synchronises the stream. */
 int goc_lbm_set_watchdog(goc_lbm_t *h, int64_t every);
 
 /* Form and launch plan of the step.  Two kernels compute the same step

@@ -310,7 +310,8 @@ struct goc_lbm {
     size_t f_elems = 0, F_elems = 0, g_elems = 0;
     int cur = 0;
     int64_t step = 0;
-    int64_t watchdog = 0;
+    int64_t watchdog = 1000;        // check for non-finite values at step return (0: never)
+    int64_t watch_last = 0;         // step of the last check
     double* diag_part = nullptr;
     double* diag_out = nullptr;
     int diag_cap = 0;
@@ -1320,6 +1321,7 @@ int goc_lbm_init_mhd(goc_lbm_t* h, const double* rho, const double* u1, const do
         if (int rc = init_fields(h, 0, rho, u1, u2, b1, b2, on_device)) return rc;
     }
     h->step = 0;
+    h->watch_last = 0;
     h->ref_base = 0;
     if (int rc = counter_op(h, 0, 0)) return rc;
     HIPOK(hipStreamSynchronize(h->stream));
@@ -1346,8 +1348,7 @@ int goc_lbm_step(goc_lbm_t* h, int64_t n)
     auto block_start = [&](int64_t s) { return !scaled || (s >= b0 && (s - b0) % kGraphSteps == 0); };
     auto refresh_at = [&](int64_t s) { return scaled && s >= b0 && (s - b0) % kGraphSteps == 0; };
     while (n > 0) {
-        int64_t chunk = n;
-        if (h->watchdog > 0) chunk = std::min<int64_t>(chunk, h->watchdog - (h->step % h->watchdog));
+        const int64_t chunk = n;
         int64_t done = 0;
         while (done < chunk) {
             const int64_t s = h->step + done;
@@ -1379,14 +1380,17 @@ int goc_lbm_step(goc_lbm_t* h, int64_t n)
         }
         h->step += chunk;
         n -= chunk;
-        if (h->watchdog > 0 && h->step % h->watchdog == 0) {
-            for (int r = 0; r < h->nruns; ++r) {
-                double o[8];
-                int rc = diag_run(h, r, o);
-                if (rc) return rc;
-                if (o[7] > 0) return fail(GOC_EUNSTABLE, "run %d: %g non-finite values at step %lld", r, o[7],
-                                          (long long)h->step);
-            }
+    }
+    // the watchdog: at the return of a call that completes at least
+    // `watchdog` steps since the last check, every run's non-finite count
+    if (h->watchdog > 0 && h->step - h->watch_last >= h->watchdog) {
+        h->watch_last = h->step;
+        for (int r = 0; r < h->nruns; ++r) {
+            double o[8];
+            int rc = diag_run(h, r, o);
+            if (rc) return rc;
+            if (o[7] > 0)
+                return fail(GOC_EUNSTABLE, "run %d: %g non-finite values at step %lld", r, o[7], (long long)h->step);
         }
     }
     return GOC_OK;
@@ -1572,6 +1576,7 @@ int goc_lbm_set_watchdog(goc_lbm_t* h, int64_t every)
     if (!check_handle(h)) return GOC_EINVAL;
     if (every < 0) return fail(GOC_EINVAL, "negative watchdog interval");
     h->watchdog = every;
+    h->watch_last = h->step;
     return GOC_OK;
 }
 
@@ -1771,6 +1776,7 @@ int goc_lbm_set_state(goc_lbm_t* h, const void* buf, size_t bytes)
         HIPOK(hipMemcpyAsync(h->g[h->cur], p + hd.f_bytes + hd.F_bytes, hd.g_bytes, hipMemcpyHostToDevice,
                              h->stream));
     h->step = hd.step;
+    h->watch_last = hd.step;
     h->ref_base = hd.ref_base;
     if (int rc = counter_op(h, (uint32_t)hd.step, 0)) return rc;
     HIPOK(hipStreamSynchronize(h->stream));

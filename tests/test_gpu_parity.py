@@ -566,6 +566,27 @@ def test_watchdog_reports_non_finite_state(oracle_lib):
     assert ei.value.code == B.GOC_EUNSTABLE
 
 
+def test_default_watchdog_checks_at_step_return(oracle_lib):
+    """Without set_watchdog, a step call that completes the 1000th step
+    since initialisation checks for non-finite values; shorter calls before
+    it do not, and set_watchdog(0) turns the check off."""
+    case = W.Case("wd0", 40, 30, "periodic", "wall", ("uniform", 0.0), ("tanh", 1.5), flow="channel",
+                  Re=10.0, tau=0.8, storage="f32")
+    g = B.Run(case)
+    f, F, _ = g.populations()
+    f[3, 10, 7] = np.nan
+    g.set_populations(f, F)
+    g.step(999)   # no check yet
+    with pytest.raises(B.GocError) as ei:
+        g.step(1)
+    assert ei.value.code == B.GOC_EUNSTABLE
+    h = B.Run(case)
+    h.set_populations(f, F)
+    h.set_watchdog(0)
+    h.step(1500)
+    assert h.diagnostics()[7] > 0
+
+
 def test_create_rejects_bad_grid():
     case = W.channel_64()
     g, m, p = B.derive(case)

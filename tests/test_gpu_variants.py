@@ -139,7 +139,13 @@ def _survives(collision, N, Re, steps=200000, chunk=10000):
     done = 0
     try:
         while done < steps:
-            run.step(chunk)
+            try:
+                run.step(chunk)
+            except B.GocError as e:   # the watchdog found non-finite values
+                if e.code != B.GOC_EUNSTABLE:
+                    raise
+                print(f"[stability] {collision} N={N} Re={Re:g}: watchdog at step {done + chunk}", flush=True)
+                return False
             done += chunk
             dg = run.diagnostics()
             if dg[7] > 0 or not np.isfinite(dg[6]) or dg[6] > 2.0 * lid:
