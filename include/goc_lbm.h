@@ -216,9 +216,10 @@ int goc_lbm_derive(goc_grid *grid, const goc_metric *metric, const goc_physics *
    stream: a hipStream_t (NULL = the default stream).  *out receives the
    handle, owned by the caller until goc_lbm_destroy.  Size limits: nx, ny
    >= 3, nx*ny <= 2^31, and the slot pool of one run (9 planes, 10 for the
-   D2Q5 buffers, of (ceil(nx/64)*64*ny + 256) storage elements) at most
-   4 GiB, i.e. about 53M nodes in FP64 with MHD, 107M in FP32, 214M in the
-   16-bit forms; GOC_EINVAL beyond. */
+   D2Q5 buffers, each row padded to an odd number of 64-node pieces, over
+   ny + 2 rows, plus 256 storage elements) at most 4 GiB, i.e. about 53M
+   nodes in FP64 with MHD, 107M in FP32, 214M in the 16-bit forms for wide
+   grids; GOC_EINVAL beyond. */
 int goc_lbm_create(goc_lbm_t **out, const goc_grid *grid, const goc_metric *metric,
                    const goc_params *params, int32_t storage, void *stream);
 
