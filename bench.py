@@ -69,7 +69,9 @@ def kernel_name(launch) -> str:
 def form_tag(launch) -> str:
     """Short name of a step form, as the profile summaries are named."""
     if launch["waves_per_cu"] == 0:
-        return f"tiled{int(launch['rows_per_segment'])}{'nt' if launch['nontemporal'] else ''}"
+        cols = int(launch.get("tile_cols", 64))
+        shape = f"{int(launch['rows_per_segment'])}" if cols == 64 else f"{cols}x{int(launch['rows_per_segment'])}"
+        return f"tiled{shape}{'nt' if launch['nontemporal'] else ''}"
     return f"march{launch['waves_per_cu']:g}"
 
 
@@ -149,7 +151,8 @@ def pattern_ceiling(case, launch, bytes_per_launch: float, launch_us: float):
     if launch["waves_per_cu"] != 0 or case.storage == "f64" or case.bc_x != "periodic":
         return None
     sb = 4 if case.storage == "f32" else 2
-    us = CL.pattern_us(case.nx, case.ny, case.mhd, sb, int(launch["rows_per_segment"]), bool(launch["nontemporal"]))
+    us = CL.pattern_us(case.nx, case.ny, case.mhd, sb, int(launch["rows_per_segment"]), bool(launch["nontemporal"]),
+                       cols=int(launch.get("tile_cols", 64)))
     cu = CL.copy_us(1 << 30)
     return {"instrument": "goc_ceiling_pattern: the step's loads and stores without its arithmetic",
             "pattern_us": round(us, 2), "pattern_GB_s_algorithmic": round(bytes_per_launch / us / 1e3, 1),
@@ -372,8 +375,8 @@ def main():
                     help="fixed step form instead of the autotuner (for profiler runs): W > 0 the march with "
                          "W waves per CU; W = 0 the tiled step with --tile rows")
     ap.add_argument("--tile", default="", metavar="ROWS[nt]",
-                    help="fixed tiled step (for profiler runs): 4, 8 or 16 rows, 'nt' for non-temporal "
-                         "stores, e.g. 4nt")
+                    help="fixed tiled step (for profiler runs): 4, 8 or 16 rows (64 columns) or 128x4, "
+                         "'nt' for non-temporal stores, e.g. 4nt, 128x4nt")
     ap.add_argument("--batch", action="store_true",
                     help="the main line is the seeded 256-run batch (FP32, developed flows)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -409,7 +412,9 @@ def main():
             developed(run, case)
         nodes = case.nx * case.ny
     if args.tile:
-        run.set_tile(int(args.tile.rstrip("nt")), args.tile.endswith("nt"))
+        shape = args.tile[:-2] if args.tile.endswith("nt") else args.tile
+        cols, rows = (int(v) for v in shape.split("x")) if "x" in shape else (64, int(shape))
+        run.set_tile(rows, args.tile.endswith("nt"), cols=cols)
         tuned = {"us_before": float("nan")}
     elif args.waves > 0:
         run.set_launch(args.waves)
@@ -451,6 +456,7 @@ def main():
                      "launch_plan": {"form": form_tag(launch),
                                      "waves_per_cu": launch["waves_per_cu"], "work_groups": launch["blocks"],
                                      "rows_per_segment": round(launch["rows_per_segment"], 2),
+                                     "tile_cols": launch["tile_cols"],
                                      "nontemporal_stores": bool(launch["nontemporal"]),
                                      "untuned_us": (round(tuned["us_before"], 2)
                                                     if tuned["us_before"] == tuned["us_before"] else None)}},

@@ -28,15 +28,15 @@ extern "C" {
    faces) in the solver's layout (rows of 9 slot planes, 10 with the D2Q5
    slots when mhd != 0, each padded to an odd number of 64-node pieces; two ghost
    rows; two force planes) for storage_bytes = 4 (FP32) or 2 (16-bit), in
-   tiles of 64 x tile_rows nodes (4, 8 or 16) with plain (nontemporal = 0)
-   or non-temporal stores.  Each launch pulls every slot and lagged force of
+   tiles of tile_cols x tile_rows nodes (64 x 4, 8 or 16, or 128 x 4) with
+   plain (nontemporal = 0) or non-temporal stores.  Each launch pulls every slot and lagged force of
    the tile and of the ring around it, writes one LDS value per pulled node,
    waits at a barrier and stores the node's slots, ghost rows and force.
    Runs `reps` launches (>= 1, after 4 untimed ones) alternating two state
    buffers and writes the mean microseconds per launch (HIP events on
    `stream`) to *us_per_launch. */
-int goc_ceiling_pattern(int nx, int ny, int mhd, int storage_bytes, int tile_rows, int nontemporal, int reps,
-                        void* stream, double* us_per_launch);
+int goc_ceiling_pattern(int nx, int ny, int mhd, int storage_bytes, int tile_cols, int tile_rows, int nontemporal,
+                        int reps, void* stream, double* us_per_launch);
 
 /* A plain one-stream copy of `bytes` (a positive multiple of 16) between two
    device buffers, 16-byte vectors (four loads in flight per thread), 32

@@ -302,7 +302,8 @@ int goc_lbm_set_watchdog(goc_lbm_t *h, int64_t every);
      segments fill the chip and balance uneven batches.  It can step every
      handle on straight metrics;
    - the tiled step: one thread per node, 64 x 4, 8 or 16 nodes per
-     work-group (by default 8, 4 in FP64; goc_lbm_set_tile), the moments
+     work-group (by default 8, 4 in FP64; goc_lbm_set_tile) or, on straight
+     metrics, 128 x 4 (goc_lbm_set_tile_shape), the moments
      of the tile and its ring in LDS, non-temporal or plain stores, one launch
      over the tiles of every run of the handle.  It steps straight runs,
      with or without MHD, alone or batched (the default for a single run:
@@ -315,9 +316,10 @@ int goc_lbm_set_watchdog(goc_lbm_t *h, int64_t every);
    goc_lbm_launch_info writes out[0] = waves_per_cu (0 for the tiled step),
    out[1] = work-groups per step, out[2] = mean rows per segment (rows per
    tile), out[3] = strips (column tiles), over all runs, out[4] = 1 when the
-   tiled step stores non-temporally, else 0. */
+   tiled step stores non-temporally, else 0, out[5] = columns per tile
+   (64 for the march's strips). */
 int goc_lbm_set_launch(goc_lbm_t *h, double waves_per_cu);
-int goc_lbm_launch_info(const goc_lbm_t *h, double out[5]);
+int goc_lbm_launch_info(const goc_lbm_t *h, double out[6]);
 /* Select the tiled step with tiles of `rows` rows (4, 8 or 16, FP64 4 or
    8; 64 columns each, one thread per node) and non-temporal stores
    (nontemporal = 1) or plain ones (0); GOC_EINVAL otherwise.  Taller tiles
@@ -327,11 +329,17 @@ int goc_lbm_launch_info(const goc_lbm_t *h, double out[5]);
    state the next step finds in the Infinity Cache.  Synchronous; captured
    step graphs are dropped. */
 int goc_lbm_set_tile(goc_lbm_t *h, int32_t rows, int32_t nontemporal);
+/* As goc_lbm_set_tile with the tile width too: cols = 64 with the heights
+   above, or cols = 128 with rows = 4 (two waves per row of the tile, whose
+   longer row pieces suit wide grids larger than the caches; straight
+   metrics only); GOC_EINVAL otherwise. */
+int goc_lbm_set_tile_shape(goc_lbm_t *h, int32_t cols, int32_t rows, int32_t nontemporal);
 
 /* Autotuner of the step form and launch plan: times trial_steps step
    launches (1..10000, plus one warm-up) for the tiled step at each tile
-   height (4, 8, 16 rows; FP64 4, 8), with non-temporal and with plain
-   stores, and, for straight FP64 / FP32 handles, the march
+   shape (64 x 4, 8, 16; FP64 64 x 4, 8; 128 x 4 on straight metrics), with
+   non-temporal and with plain stores, and, for straight FP64 / FP32
+   handles, the march
    at each waves_per_cu in {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128,
    192, 256, 384, 512}, on the handle's stream; the candidates within 5 %
    of the fastest are timed again with three times the steps (at most
@@ -342,7 +350,8 @@ int goc_lbm_set_tile(goc_lbm_t *h, int32_t rows, int32_t nontemporal);
    afterwards, so the state does not change; the copy is freed before the
    call returns (GOC_ENOMEM when it does not fit).  out[0] = chosen
    waves_per_cu (0: the
-   tiled step; its height and stores are launch_info's out[2], out[4]),
+   tiled step; its height, stores and width are launch_info's out[2],
+   out[4], out[5]),
    out[1] = its
    microseconds per step (second timing), out[2] = microseconds per step of
    the form in use before in the first timing (-1 if it was not a

@@ -97,6 +97,7 @@ SIGNATURES = {
     "goc_lbm_launch_info": (C.c_int, [VP, P_D]),
     "goc_lbm_tune": (C.c_int, [VP, C.c_int32, P_D]),
     "goc_lbm_set_tile": (C.c_int, [VP, C.c_int32, C.c_int32]),
+    "goc_lbm_set_tile_shape": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_int32]),
 }
 
 
@@ -391,18 +392,21 @@ class Run:
         _check(lib().goc_lbm_set_launch(self.h, float(waves_per_cu)))
         return self
 
-    def set_tile(self, rows, nontemporal=None):
-        """The tiled step with tiles of `rows` rows (4, 8 or 16) and
-        non-temporal (1) or plain (0) stores (None: as now)."""
+    def set_tile(self, rows, nontemporal=None, cols=64):
+        """The tiled step with tiles of `cols` x `rows` nodes (64 x 4, 8 or
+        16; 128 x 4) and non-temporal (1) or plain (0) stores (None: as now)."""
         nt = self.launch_info()["nontemporal"] if nontemporal is None else int(nontemporal)
-        _check(lib().goc_lbm_set_tile(self.h, int(rows), int(nt)))
+        if int(cols) == 64:
+            _check(lib().goc_lbm_set_tile(self.h, int(rows), int(nt)))
+        else:
+            _check(lib().goc_lbm_set_tile_shape(self.h, int(cols), int(rows), int(nt)))
         return self
 
     def launch_info(self):
-        out = np.zeros(5)
+        out = np.zeros(6)
         _check(lib().goc_lbm_launch_info(self.h, _dptr(out)))
         return dict(waves_per_cu=out[0], blocks=int(out[1]), rows_per_segment=out[2], strips=int(out[3]),
-                    nontemporal=int(out[4]))
+                    nontemporal=int(out[4]), tile_cols=int(out[5]))
 
     def tune(self, trial_steps=20):
         """Autotune the launch plan (the state does not change)."""

@@ -1,7 +1,7 @@
 """Binding of the bandwidth instruments (include/goc_ceiling.h, libgocceiling.so):
 argument marshalling only.
 
-    python -m paper_2607_15362_amd.ceiling [NX NY MHD STORAGE_BYTES ROWS NT]
+    python -m paper_2607_15362_amd.ceiling [NX NY MHD STORAGE_BYTES ROWS NT [COLS]]
 
 prints the same-pattern time of the tiled step (default: the 4096 x 1024
 Hartmann layout, FP32, D2Q5 slots, 64 x 4 tiles, non-temporal stores) and a
@@ -18,8 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgocceiling.so")
 
 SIGNATURES = {
-    "goc_ceiling_pattern": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p,
-                                      C.POINTER(C.c_double)]),
+    "goc_ceiling_pattern": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                      C.c_void_p, C.POINTER(C.c_double)]),
     "goc_ceiling_copy": (C.c_int, [C.c_int64, C.c_int, C.c_void_p, C.POINTER(C.c_double)]),
 }
 
@@ -47,11 +47,11 @@ def _check(rc: int, what: str):
 
 
 def pattern_us(nx: int, ny: int, mhd: bool, storage_bytes: int, rows: int, nontemporal: bool, reps: int = 200,
-               stream: int = 0) -> float:
+               stream: int = 0, cols: int = 64) -> float:
     """Mean microseconds per launch of the tiled step's memory pattern."""
     out = C.c_double(0.0)
-    _check(lib().goc_ceiling_pattern(nx, ny, int(bool(mhd)), storage_bytes, rows, int(bool(nontemporal)), reps,
-                                     C.c_void_p(stream or None), C.byref(out)), "goc_ceiling_pattern")
+    _check(lib().goc_ceiling_pattern(nx, ny, int(bool(mhd)), storage_bytes, cols, rows, int(bool(nontemporal)),
+                                     reps, C.c_void_p(stream or None), C.byref(out)), "goc_ceiling_pattern")
     return out.value
 
 
@@ -63,11 +63,13 @@ def copy_us(nbytes: int, reps: int = 50, stream: int = 0) -> float:
 
 
 def main(argv):
-    nx, ny, mhd, sb, rows, nt = (int(v) for v in argv) if argv else (4096, 1024, 1, 4, 4, 1)
-    us = pattern_us(nx, ny, bool(mhd), sb, rows, bool(nt))
+    vals = [int(v) for v in argv] if argv else [4096, 1024, 1, 4, 4, 1]
+    nx, ny, mhd, sb, rows, nt = vals[:6]
+    cols = vals[6] if len(vals) > 6 else 64
+    us = pattern_us(nx, ny, bool(mhd), sb, rows, bool(nt), cols=cols)
     nb = 1 << 30
     cu = copy_us(nb)
-    print(json.dumps({"pattern": {"nx": nx, "ny": ny, "mhd": mhd, "storage_bytes": sb, "rows": rows,
+    print(json.dumps({"pattern": {"nx": nx, "ny": ny, "mhd": mhd, "storage_bytes": sb, "cols": cols, "rows": rows,
                                   "nontemporal": nt, "us_per_launch": round(us, 2)},
                       "copy": {"bytes": nb, "us_per_launch": round(cu, 2),
                                "GB_s_read_plus_write": round(2 * nb / (cu * 1e-6) / 1e9, 1)}}), flush=True)

@@ -23,27 +23,27 @@ namespace {
 using goc::kTileX;
 
 // The tiled step's memory traffic for one straight run: the same tile
-// placement (XCD bands, edge tiles shifted back), the same pulls of the own
+// shape (TX x TY) and placement (XCD bands, edge tiles shifted back), the same pulls of the own
 // node and of the ring around the tile (slot offsets of pull_off), one LDS
 // value per pulled node and a barrier, and the same stores (nine slots, ten
 // D2Q5 slots, the ghost rows of rows 0 and ny - 1, the two force planes).
 // Raw storage values are moved unchanged: the stored slot is the own pulled
 // slot plus the LDS sum of the left and right neighbours scaled by zero at
 // run time (so that no load can be dropped).
-template <class S, bool MHD, int TY, bool NT>
-__global__ void __launch_bounds__(kTileX * TY)
+template <class S, bool MHD, int TY, bool NT, int TX>
+__global__ void __launch_bounds__(TX * TY)
 pattern_kernel(goc::RunDesc d, goc::Pools<S, float> pl, float zero)
 {
     using goc::kQ;
     using goc::kM;
-    __shared__ float sm[TY + 2][kTileX + 2];
+    __shared__ float sm[TY + 2][TX + 2];
     const int nx = d.nx, ny = d.ny;
-    const int gx = (nx + kTileX - 1) / kTileX, gy = (ny + TY - 1) / TY;
+    const int gx = (nx + TX - 1) / TX, gy = (ny + TY - 1) / TY;
     const int nt = gx * gy;
     const int xcd = blockIdx.x & 7, q = nt >> 3, rem = nt & 7;
     const int t = xcd * q + min(xcd, rem) + (int)(blockIdx.x >> 3);
-    const int tx = nx < kTileX ? nx : kTileX, ty = ny < TY ? ny : TY;
-    const int ox = (t % gx) * kTileX, oy = (t / gx) * TY;
+    const int tx = nx < TX ? nx : TX, ty = ny < TY ? ny : TY;
+    const int ox = (t % gx) * TX, oy = (t / gx) * TY;
     const int x0 = ox < nx - tx ? ox : nx - tx, y0 = oy < ny - ty ? oy : ny - ty;
     const int lx = threadIdx.x, ly = threadIdx.y;
     const int i = x0 + lx, j = y0 + ly;
@@ -52,7 +52,7 @@ pattern_kernel(goc::RunDesc d, goc::Pools<S, float> pl, float zero)
     const goc::RunBytes b = goc::run_bytes(d, pl);
     const uint32_t planeF = uint32_t(d.plane * sizeof(float));
     const int ic = in ? i : x0, jc = in ? j : y0;
-    const int h = ly * kTileX + lx, nh = 2 * tx + 2 * ty;
+    const int h = ly * TX + lx, nh = 2 * tx + 2 * ty;
     int hx, hy;
     if (h < 2 * tx) {
         hx = h < tx ? h : h - tx;
@@ -90,7 +90,7 @@ pattern_kernel(goc::RunDesc d, goc::Pools<S, float> pl, float zero)
             for (int ci = 0; ci < 2; ++ci) g[ci][a] = goc::ld_at<S>(b.g, ci * b.g_comp + off);
         }
     }
-    if (ly * kTileX < nh) {
+    if (ly * TX + (lx & ~63) < nh) {
         float s = 0.f;
 #pragma unroll
         for (int a = 0; a < kQ; ++a) s += float(goc::ld_at<S>(b.f, goc::pull_off<S>(d, b, hi, hj, a)));
@@ -192,7 +192,7 @@ struct Buffers {
     }
 };
 
-template <class S, bool MHD, int TY, bool NT>
+template <class S, bool MHD, int TY, bool NT, int TX>
 int run_pattern(const goc::RunDesc& d, int64_t f_elems, int64_t F_elems, int reps, hipStream_t st, double* us)
 {
     Buffers buf(st);
@@ -202,8 +202,8 @@ int run_pattern(const goc::RunDesc& d, int64_t f_elems, int64_t F_elems, int rep
         if (hipMalloc(&buf.p[k], sizes[k]) != hipSuccess) return GOC_ENOMEM;
         if (hipMemsetAsync(buf.p[k], 0, sizes[k], st) != hipSuccess) return GOC_EDEVICE;
     }
-    const int gx = (d.nx + kTileX - 1) / kTileX, gy = (d.ny + TY - 1) / TY;
-    const dim3 grid(gx * gy), block(kTileX, TY);
+    const int gx = (d.nx + TX - 1) / TX, gy = (d.ny + TY - 1) / TY;
+    const dim3 grid(gx * gy), block(TX, TY);
     auto launch = [&](int k) {
         goc::Pools<S, float> pl{};
         const int a = k & 1;
@@ -213,7 +213,7 @@ int run_pattern(const goc::RunDesc& d, int64_t f_elems, int64_t F_elems, int rep
         pl.Fout = static_cast<float*>(buf.p[3 - a]);
         pl.gin = static_cast<const S*>(buf.p[4 + a]);
         pl.gout = static_cast<S*>(buf.p[5 - a]);
-        hipLaunchKernelGGL((pattern_kernel<S, MHD, TY, NT>), grid, block, 0, st, d, pl, 0.f);
+        hipLaunchKernelGGL((pattern_kernel<S, MHD, TY, NT, TX>), grid, block, 0, st, d, pl, 0.f);
         return hipGetLastError();
     };
     for (int k = 0; k < 4; ++k)
@@ -230,30 +230,34 @@ int run_pattern(const goc::RunDesc& d, int64_t f_elems, int64_t F_elems, int rep
     return GOC_OK;
 }
 
-template <class S, bool MHD, int TY>
+template <class S, bool MHD, int TY, int TX>
 int pick_nt(const goc::RunDesc& d, int64_t fe, int64_t Fe, int nt, int reps, hipStream_t st, double* us)
 {
-    return nt ? run_pattern<S, MHD, TY, true>(d, fe, Fe, reps, st, us)
-              : run_pattern<S, MHD, TY, false>(d, fe, Fe, reps, st, us);
+    return nt ? run_pattern<S, MHD, TY, true, TX>(d, fe, Fe, reps, st, us)
+              : run_pattern<S, MHD, TY, false, TX>(d, fe, Fe, reps, st, us);
 }
 
 template <class S, bool MHD>
-int pick_rows(const goc::RunDesc& d, int64_t fe, int64_t Fe, int rows, int nt, int reps, hipStream_t st, double* us)
+int pick_shape(const goc::RunDesc& d, int64_t fe, int64_t Fe, int cols, int rows, int nt, int reps, hipStream_t st,
+               double* us)
 {
+    if (cols == goc::kTileXWide) return pick_nt<S, MHD, goc::kTileRowsWide, goc::kTileXWide>(d, fe, Fe, nt, reps, st, us);
     switch (rows) {
-    case 4: return pick_nt<S, MHD, 4>(d, fe, Fe, nt, reps, st, us);
-    case 8: return pick_nt<S, MHD, 8>(d, fe, Fe, nt, reps, st, us);
-    default: return pick_nt<S, MHD, 16>(d, fe, Fe, nt, reps, st, us);
+    case 4: return pick_nt<S, MHD, 4, kTileX>(d, fe, Fe, nt, reps, st, us);
+    case 8: return pick_nt<S, MHD, 8, kTileX>(d, fe, Fe, nt, reps, st, us);
+    default: return pick_nt<S, MHD, 16, kTileX>(d, fe, Fe, nt, reps, st, us);
     }
 }
 
 }  // namespace
 
-extern "C" int goc_ceiling_pattern(int nx, int ny, int mhd, int storage_bytes, int tile_rows, int nontemporal,
-                                   int reps, void* stream, double* us_per_launch)
+extern "C" int goc_ceiling_pattern(int nx, int ny, int mhd, int storage_bytes, int tile_cols, int tile_rows,
+                                   int nontemporal, int reps, void* stream, double* us_per_launch)
 {
+    const bool narrow = tile_cols == kTileX && (tile_rows == 4 || tile_rows == 8 || tile_rows == 16);
+    const bool wide = tile_cols == goc::kTileXWide && tile_rows == goc::kTileRowsWide;
     if (!us_per_launch || nx < 3 || ny < 3 || reps < 1 || (storage_bytes != 4 && storage_bytes != 2) ||
-        (tile_rows != 4 && tile_rows != 8 && tile_rows != 16))
+        !(narrow || wide))
         return GOC_EINVAL;
     goc::RunDesc d{};
     d.nx = nx;
@@ -273,10 +277,10 @@ extern "C" int goc_ceiling_pattern(int nx, int ny, int mhd, int storage_bytes, i
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int nt = nontemporal ? 1 : 0;
     if (storage_bytes == 4)
-        return mhd ? pick_rows<float, true>(d, region, regionF, tile_rows, nt, reps, st, us_per_launch)
-                   : pick_rows<float, false>(d, region, regionF, tile_rows, nt, reps, st, us_per_launch);
-    return mhd ? pick_rows<__half, true>(d, region, regionF, tile_rows, nt, reps, st, us_per_launch)
-               : pick_rows<__half, false>(d, region, regionF, tile_rows, nt, reps, st, us_per_launch);
+        return mhd ? pick_shape<float, true>(d, region, regionF, tile_cols, tile_rows, nt, reps, st, us_per_launch)
+                   : pick_shape<float, false>(d, region, regionF, tile_cols, tile_rows, nt, reps, st, us_per_launch);
+    return mhd ? pick_shape<__half, true>(d, region, regionF, tile_cols, tile_rows, nt, reps, st, us_per_launch)
+               : pick_shape<__half, false>(d, region, regionF, tile_cols, tile_rows, nt, reps, st, us_per_launch);
 }
 
 extern "C" int goc_ceiling_copy(int64_t bytes, int reps, void* stream, double* us_per_launch)

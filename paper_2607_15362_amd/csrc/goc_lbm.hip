@@ -324,6 +324,7 @@ struct goc_lbm {
     int32_t* tile_first_d = nullptr;   // device: first tile of each run of the tiled kernel, then the total
     int32_t total_tiles = 0;
     int tile_rows = 8;              // rows of a tile of the tiled step (goc::kTileRows)
+    int tile_cols = goc::kTileX;    // its columns (goc::kTileX, or goc::kTileXWide at 4 rows)
     bool tile_nt = false;           // the tiled step stores non-temporally
     int block_cap = 0;              // capacity of block_run_d (entries)
     // 16-bit storage: reference tables (the one in use, and the next one
@@ -396,36 +397,47 @@ int launch_step(goc_lbm* h, int k, bool refresh = false)
         }
         if (h->m2d || h->tiled) {   // tiled step: one launch for every run
             const bool raw = h->coll == goc::kCollRaw;
-            auto tiled = [&](auto rows, auto nts) {
+            auto tiled = [&](auto cols, auto rows, auto nts) {
+                constexpr int TX = decltype(cols)::value;
                 constexpr int TY = decltype(rows)::value;
                 constexpr bool NT = decltype(nts)::value;
-                const dim3 cg(h->total_tiles), cb(goc::kTileX, TY);
+                const dim3 cg(h->total_tiles), cb(TX, TY);
                 auto go = [&](auto kernel) {
                     hipLaunchKernelGGL(kernel, cg, cb, 0, h->stream, h->runs_d, h->tile_first_d, h->nruns, pl,
                                        h->step_ctr, k);
                 };
-                if constexpr (sizeof(S) == 8 && TY > 8) {   // (FP64: at most 8 rows, see tile_rows_built)
+                if constexpr (sizeof(S) == 8 && TY > 8) {   // (FP64: at most 8 rows, see tile_shape_built)
                     return;
                 } else if (h->m2d) {
-                    raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, true, false, TY, NT>)
-                        : go(goc::tile_step_kernel<S, goc::kCollCentral, true, false, TY, NT>);
+                    if constexpr (TX == goc::kTileX) {   // (2-D metrics: 64 columns only)
+                        raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, true, false, TY, NT>)
+                            : go(goc::tile_step_kernel<S, goc::kCollCentral, true, false, TY, NT>);
+                    }
                 } else if (h->any_mhd) {
-                    raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, false, true, TY, NT>)
-                        : go(goc::tile_step_kernel<S, goc::kCollCentral, false, true, TY, NT>);
+                    raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, false, true, TY, NT, TX>)
+                        : go(goc::tile_step_kernel<S, goc::kCollCentral, false, true, TY, NT, TX>);
                 } else {
-                    raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, false, false, TY, NT>)
-                        : go(goc::tile_step_kernel<S, goc::kCollCentral, false, false, TY, NT>);
+                    raw ? go(goc::tile_step_kernel<S, goc::kCollRaw, false, false, TY, NT, TX>)
+                        : go(goc::tile_step_kernel<S, goc::kCollCentral, false, false, TY, NT, TX>);
                 }
             };
-            auto tiled_nt = [&](auto rows) {
-                if (h->tile_nt) tiled(rows, std::true_type{});
-                else tiled(rows, std::false_type{});
+            auto tiled_nt = [&](auto cols, auto rows) {
+                if (h->tile_nt) tiled(cols, rows, std::true_type{});
+                else tiled(cols, rows, std::false_type{});
             };
-            switch (h->tile_rows) {
-            case 4: tiled_nt(std::integral_constant<int, 4>{}); break;
-            case 8: tiled_nt(std::integral_constant<int, 8>{}); break;
-            case 16: tiled_nt(std::integral_constant<int, 16>{}); break;
-            default: return fail(GOC_EINVAL, "tile height %d not built", h->tile_rows);
+            const std::integral_constant<int, goc::kTileX> narrow{};
+            if (h->tile_cols == goc::kTileXWide && h->tile_rows == goc::kTileRowsWide && !h->m2d) {
+                tiled_nt(std::integral_constant<int, goc::kTileXWide>{},
+                         std::integral_constant<int, goc::kTileRowsWide>{});
+            } else if (h->tile_cols != goc::kTileX) {
+                return fail(GOC_EINVAL, "tile shape %d x %d not built", h->tile_cols, h->tile_rows);
+            } else {
+                switch (h->tile_rows) {
+                case 4: tiled_nt(narrow, std::integral_constant<int, 4>{}); break;
+                case 8: tiled_nt(narrow, std::integral_constant<int, 8>{}); break;
+                case 16: tiled_nt(narrow, std::integral_constant<int, 16>{}); break;
+                default: return fail(GOC_EINVAL, "tile height %d not built", h->tile_rows);
+                }
             }
             HIPOK(hipGetLastError());
             if (goc::Store<S>::scaled && refresh) {
@@ -554,23 +566,26 @@ void plan_rows(goc_lbm* h, std::vector<int32_t>& block_run)
 // only form on 2-D metrics).
 bool tile_eligible(const goc_lbm* h) { return !h->m2d; }
 // First tile of every run of the tiled step (and the total) for the
-// handle's tile height.
+// handle's tile shape.
 void tile_table(const goc_lbm* h, std::vector<int32_t>& tile_first, bool& overflow)
 {
     tile_first.assign(h->nruns + 1, 0);
     overflow = false;
     for (int r = 0; r < h->nruns; ++r) {
-        const int64_t gx = (h->runs[r].nx + goc::kTileX - 1) / goc::kTileX;
+        const int64_t gx = (h->runs[r].nx + h->tile_cols - 1) / h->tile_cols;
         const int64_t nt = gx * ((h->runs[r].ny + h->tile_rows - 1) / h->tile_rows);
         if ((int64_t)tile_first[r] + nt > INT32_MAX) overflow = true;
         tile_first[r + 1] = overflow ? 0 : tile_first[r] + (int32_t)nt;
     }
 }
 
-// Tile heights built for a storage: 4, 8 and 16 rows; FP64 up to 8 (at 16
-// rows, 1024 threads per work-group, its registers would spill).
-bool tile_rows_built(int rows, int storage)
+// Tile shapes built for a storage: 64 columns x 4, 8 and 16 rows (FP64 up
+// to 8: at 16 rows, 1024 threads per work-group, its registers would
+// spill), and 128 x 4 on straight grids.
+bool tile_shape_built(int cols, int rows, int storage, bool m2d)
 {
+    if (cols == goc::kTileXWide) return rows == goc::kTileRowsWide && !m2d;
+    if (cols != goc::kTileX) return false;
     if (storage == GOC_F64 && rows > 8) return false;
     for (int r : goc::kTileRows)
         if (r == rows) return true;
@@ -586,23 +601,27 @@ void drop_graphs(goc_lbm* h)
         }
 }
 
-// Step an eligible handle with the tiled kernel, with tiles of `rows` rows
-// (0: the current height) and non-temporal stores or not (nt < 0: as now);
-// synchronous, captured step graphs are dropped.
-int use_tiled(goc_lbm* h, int rows = 0, int nt = -1)
+// Step an eligible handle with the tiled kernel, with tiles of `cols` x
+// `rows` nodes (0: the current shape) and non-temporal stores or not
+// (nt < 0: as now); synchronous, captured step graphs are dropped.
+int use_tiled(goc_lbm* h, int cols = 0, int rows = 0, int nt = -1)
 {
     HIPOK(hipStreamSynchronize(h->stream));
     drop_graphs(h);
     h->tiled = true;
     if (nt >= 0) h->tile_nt = nt != 0;
-    if (rows && rows != h->tile_rows) {
-        const int old = h->tile_rows;
+    if (!cols) cols = h->tile_cols;
+    if (!rows) rows = h->tile_rows;
+    if (cols != h->tile_cols || rows != h->tile_rows) {
+        const int old_cols = h->tile_cols, old_rows = h->tile_rows;
+        h->tile_cols = cols;
         h->tile_rows = rows;
         std::vector<int32_t> tf;
         bool overflow;
         tile_table(h, tf, overflow);
         if (overflow) {
-            h->tile_rows = old;
+            h->tile_cols = old_cols;
+            h->tile_rows = old_rows;
             return fail(GOC_EINVAL, "too many tiles in the launch");
         }
         HIPOK(hipMemcpy(h->tile_first_d, tf.data(), (h->nruns + 1) * 4, hipMemcpyHostToDevice));
@@ -1411,7 +1430,7 @@ int goc_lbm_set_launch(goc_lbm_t* h, double waves_per_cu)
     return apply_plan(h, waves_per_cu);
 }
 
-int goc_lbm_launch_info(const goc_lbm_t* h, double out[5])
+int goc_lbm_launch_info(const goc_lbm_t* h, double out[6])
 {
     if (!h || !out) return fail(GOC_EINVAL, "NULL handle or output");
     int64_t rows = 0, segs = 0, strips = 0;
@@ -1421,10 +1440,10 @@ int goc_lbm_launch_info(const goc_lbm_t* h, double out[5])
         strips += d.strips;
     }
     if (h->m2d || h->tiled) {
-        const int ty = h->tile_rows;
+        const int ty = h->tile_rows, tw = h->tile_cols;
         int64_t tiles = 0, cols = 0;
         for (const RunDesc& d : h->runs) {
-            const int64_t gx = (d.nx + goc::kTileX - 1) / goc::kTileX;
+            const int64_t gx = (d.nx + tw - 1) / tw;
             tiles += gx * ((d.ny + ty - 1) / ty);
             cols += gx;
         }
@@ -1433,6 +1452,7 @@ int goc_lbm_launch_info(const goc_lbm_t* h, double out[5])
         out[2] = ty;
         out[3] = (double)cols;
         out[4] = h->tile_nt ? 1.0 : 0.0;
+        out[5] = tw;
         return GOC_OK;
     }
     out[0] = h->waves_per_cu;
@@ -1440,16 +1460,23 @@ int goc_lbm_launch_info(const goc_lbm_t* h, double out[5])
     out[2] = segs ? double(rows) / double(segs) : 0.0;
     out[3] = (double)strips;
     out[4] = 0.0;
+    out[5] = goc::kWave;
     return GOC_OK;
+}
+
+int goc_lbm_set_tile_shape(goc_lbm_t* h, int32_t cols, int32_t rows, int32_t nontemporal)
+{
+    if (!check_handle(h)) return GOC_EINVAL;
+    if (!tile_shape_built(cols, rows, h->storage, h->m2d))
+        return fail(GOC_EINVAL, "tile shape %d x %d: 64 x 4, 8 or 16 (FP64: 4 or 8), or 128 x 4 on straight grids",
+                    cols, rows);
+    if (nontemporal != 0 && nontemporal != 1) return fail(GOC_EINVAL, "nontemporal must be 0 or 1");
+    return use_tiled(h, cols, rows, nontemporal);
 }
 
 int goc_lbm_set_tile(goc_lbm_t* h, int32_t rows, int32_t nontemporal)
 {
-    if (!check_handle(h)) return GOC_EINVAL;
-    if (!tile_rows_built(rows, h->storage))
-        return fail(GOC_EINVAL, "tile height %d: 4, 8 or 16 rows (FP64: 4 or 8)", rows);
-    if (nontemporal != 0 && nontemporal != 1) return fail(GOC_EINVAL, "nontemporal must be 0 or 1");
-    return use_tiled(h, rows, nontemporal);
+    return goc_lbm_set_tile_shape(h, goc::kTileX, rows, nontemporal);
 }
 
 int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
@@ -1500,8 +1527,11 @@ int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
         double w;    // 0: the tiled step, > 0: the march with this plan
         int rows;    // tile height
         int nt;      // non-temporal stores (tiled step)
+        int cols;    // tile width
     };
-    auto select = [&](const Cand& c) -> int { return c.w == 0.0 ? use_tiled(h, c.rows, c.nt) : apply_plan(h, c.w); };
+    auto select = [&](const Cand& c) -> int {
+        return c.w == 0.0 ? use_tiled(h, c.cols, c.rows, c.nt) : apply_plan(h, c.w);
+    };
     auto time_form = [&](const Cand& c, int steps, double& us) -> int {
         int rc = select(c);
         if (rc) return rc;
@@ -1519,16 +1549,19 @@ int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
         us = 1e3 * ms / steps;
         return GOC_OK;
     };
-    // the tiled step at every tile height, with and without non-temporal
+    // the tiled step at every tile shape, with and without non-temporal
     // stores, then (straight FP64 / FP32 runs) the march at every plan
     const bool march = tile_eligible(h) && !scaled_storage(h->storage);
-    const Cand prev = {(h->m2d || h->tiled) ? 0.0 : h->waves_per_cu, h->tile_rows, h->tile_nt ? 1 : 0};
+    const Cand prev = {(h->m2d || h->tiled) ? 0.0 : h->waves_per_cu, h->tile_rows, h->tile_nt ? 1 : 0,
+                       h->tile_cols};
     std::vector<Cand> cands;
     for (int rows : goc::kTileRows)
-        if (tile_rows_built(rows, h->storage))
-            for (int nt = 0; nt < 2; ++nt) cands.push_back({0.0, rows, nt});
+        if (tile_shape_built(goc::kTileX, rows, h->storage, h->m2d))
+            for (int nt = 0; nt < 2; ++nt) cands.push_back({0.0, rows, nt, goc::kTileX});
+    if (tile_shape_built(goc::kTileXWide, goc::kTileRowsWide, h->storage, h->m2d))
+        for (int nt = 0; nt < 2; ++nt) cands.push_back({0.0, goc::kTileRowsWide, nt, goc::kTileXWide});
     if (march)
-        for (double w : cand) cands.push_back({w, prev.rows, prev.nt});
+        for (double w : cand) cands.push_back({w, prev.rows, prev.nt, prev.cols});
     double best_us = 1e300, prev_us = -1.0;
     Cand best = prev;
     std::vector<double> times;
@@ -1539,7 +1572,8 @@ int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
             return rc;
         }
         times.push_back(us);
-        if (c.w == prev.w && (prev.w != 0.0 || (c.rows == prev.rows && c.nt == prev.nt))) prev_us = us;
+        if (c.w == prev.w && (prev.w != 0.0 || (c.rows == prev.rows && c.nt == prev.nt && c.cols == prev.cols)))
+            prev_us = us;
         if (us < best_us) {
             best_us = us;
             best = c;

@@ -2,7 +2,8 @@
 //
 // The same step as the march of goc_step.hpp (App. E, every node once),
 // organised for parallelism instead of in-register reuse: a work-group owns
-// a tile of 64 x 8 nodes (64 x 4 in FP64) and steps it in one pass.  Pull,
+// a tile of 64 columns x 4, 8 or 16 rows, or 128 x 4, and steps it in one
+// pass.  Pull,
 // decode and the moments rho - rho0, U1, U2 (App. E step 7, lagged force)
 // of the tile and of the ring of nodes around it go to LDS; after one
 // barrier the second-order differences of U and rho come from LDS
@@ -31,6 +32,11 @@ constexpr int kTileX = 64;   // work-group tile: 64 columns x TY rows (one wave 
 // and the default: 8 rows, 4 for FP64 storage, whose register count leaves
 // room for fewer waves per CU.
 constexpr int kTileRows[3] = {4, 8, 16};
+// The wide tile: 128 columns (two waves per row of the tile) at 4 rows.  Its
+// longer row pieces suit the memory system on wide grids larger than the
+// caches; its ring per node is that of the 64 x 4 tile.
+constexpr int kTileXWide = 128;
+constexpr int kTileRowsWide = 4;
 constexpr int default_tile_rows(int storage_bytes) { return storage_bytes == 8 ? 4 : 8; }
 
 // A value at a lane's 32-bit byte offset from a work-group-uniform base:
@@ -214,10 +220,11 @@ __device__ inline T tile_fd(V v, int l, int k, int n, bool periodic)
 }
 
 // The step of every node of every run.  Launch: grid = the tiles of all
-// runs (1-D), block (64, TY); NT: non-temporal stores; tile_first[r] = the
-// first tile of run r (tile_first[nruns] = all tiles), a run's tiles being
-// ceil(nx/64) * ceil(ny/TY) in row-major order.  A work-group owns the 64 x TY
-// nodes of tile (bx, by) of its run at (64 bx, Y by); its tile is shifted back at the
+// runs (1-D), block (TX, TY) with TX = 64 or 128 columns; NT: non-temporal
+// stores; tile_first[r] = the first tile of run r (tile_first[nruns] = all
+// tiles), a run's tiles being ceil(nx/TX) * ceil(ny/TY) in row-major order.
+// A work-group owns the TX x TY nodes of tile (bx, by) of its run at
+// (TX bx, TY by); its tile is shifted back at the
 // far edges of the grid so that the three nodes of a one-sided difference
 // lie in it (nodes of the shifted part belong to the neighbouring
 // work-group and are not written here).  The moments of the tile and of the
@@ -225,15 +232,15 @@ __device__ inline T tile_fd(V v, int l, int k, int n, bool periodic)
 // the eight XCDs in turn; the tiles are renumbered so that each XCD gets a
 // contiguous band of them (run by run, row-major), whose rings and
 // cross-tile pulls its L2 then serves.
-template <class S, int COLL, bool GEN, bool MHD, int TY, bool NT>
-__global__ void __launch_bounds__(kTileX * TY)
+template <class S, int COLL, bool GEN, bool MHD, int TY, bool NT, int TX = kTileX>
+__global__ void __launch_bounds__(TX * TY)
 tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ tile_first, int nruns,
                  Pools<S, typename ForceOf<S>::type> pl, const uint32_t* __restrict__ step_ctr, int k)
 {
     using T = typename ComputeOf<S>::type;
     using FT = typename ForceOf<S>::type;
     constexpr int kTileY = TY;
-    __shared__ T sm[3][kTileY + 2][kTileX + 2];   // rho - rho0, U1, U2 of the tile and its ring
+    __shared__ T sm[3][kTileY + 2][TX + 2];   // rho - rho0, U1, U2 of the tile and its ring
     // tile of this work-group over all runs, in XCD bands, then its run (the
     // last whose first tile is not beyond it) and its place in the run
     const int nt = tile_first[nruns];
@@ -249,9 +256,9 @@ tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ t
     const int t = tg - tile_first[run];
     const RunDesc& d = runs[run];
     const int nx = d.nx, ny = d.ny;
-    const int tx = nx < kTileX ? nx : kTileX, ty = ny < kTileY ? ny : kTileY;   // tile extent
-    const int gx = (nx + kTileX - 1) / kTileX;
-    const int ox = (t % gx) * kTileX, oy = (t / gx) * kTileY;          // first owned node
+    const int tx = nx < TX ? nx : TX, ty = ny < kTileY ? ny : kTileY;   // tile extent
+    const int gx = (nx + TX - 1) / TX;
+    const int ox = (t % gx) * TX, oy = (t / gx) * kTileY;          // first owned node
     const bool mhd_run = MHD && d.mhd;   // (a plain run of a mixed batch: no D2Q5 work)
     const int x0 = ox < nx - tx ? ox : nx - tx, y0 = oy < ny - ty ? oy : ny - ty;   // tile origin
     const int lx = threadIdx.x, ly = threadIdx.y;
@@ -266,8 +273,9 @@ tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ t
     const char* mt = reinterpret_cast<const char*>(table_of<T>(pl.met, pl.metf) + d.met_off);
     // the own node, clamped into the grid for the threads of a ragged tile
     // that have none (they load, but store nothing); its row, uniform over
-    // the wave (one row of the tile per wave: lane 0 always holds a node of
-    // it, and lanes without a node compute nothing that is kept)
+    // the wave (each wave lies in one row of the tile: lane 0 holds a node
+    // of that row whenever any lane of the wave does, and lanes without a
+    // node compute nothing that is kept)
     const int ic = in ? i : x0, jc = in ? j : y0;
     const int jw = __builtin_amdgcn_readfirstlane(jc);
     // this thread's node of the ring around the tile: rows -1 and ty over the
@@ -275,8 +283,8 @@ tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ t
     // reach the corners); wrapped across a periodic edge, absent beyond a
     // wall.  Ring node h goes to thread h in order (whole rows of the ring
     // per wave: contiguous loads), and the waves beyond the ring skip it.
-    static_assert(2 * kTileX + 2 * kTileY <= kTileX * kTileY, "one ring node per thread");
-    const int h = ly * kTileX + lx, nh = 2 * tx + 2 * ty;
+    static_assert(2 * TX + 2 * kTileY <= TX * kTileY, "one ring node per thread");
+    const int h = ly * TX + lx, nh = 2 * tx + 2 * ty;
     int hx, hy;
     if (h < 2 * tx) {
         hx = h < tx ? h : h - tx;
@@ -341,7 +349,7 @@ tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ t
     T dg[2][kM];   // D2Q5 deviations (MHD)
     const T sginv = Store<S>::scaled ? sp[P_ISCG] : T(1);
     if (mhd_run) pull_g<S, T>(d, b, ic, jc, sginv, rin, dg);
-    if (ly * kTileX < nh) {   // (uniform over the wave: one wave per row of the block)
+    if (ly * TX + (lx & ~63) < nh) {   // (uniform over the wave: whether its first lane has a ring node)
         T hf[kQ], hF1, hF2;
         const float* hrf = Store<S>::scaled ? pl.ref_in + (d.row_off + hj) * kRef : nullptr;
         tile_pull9<S, T, FT>(d, b, planeF, hi, hj, hrf, hf, hF1, hF2);

@@ -47,8 +47,9 @@ def test_ceiling_instrument_on_small_and_ragged_grids():
     """The instrument runs (in bounds) on grids smaller than a tile and with
     ragged edges, for both storage widths, and its copy moves a small buffer."""
     from paper_2607_15362_amd import ceiling as CL
-    for nx, ny, mhd, sb, rows in [(3, 3, 1, 4, 16), (70, 37, 1, 4, 8), (130, 9, 0, 2, 4), (200, 66, 1, 2, 16)]:
-        us = CL.pattern_us(nx, ny, bool(mhd), sb, rows, True, reps=5)
+    for nx, ny, mhd, sb, rows, cols in [(3, 3, 1, 4, 16, 64), (70, 37, 1, 4, 8, 64), (130, 9, 0, 2, 4, 64),
+                                        (200, 66, 1, 2, 16, 64), (3, 3, 1, 4, 4, 128), (200, 66, 1, 2, 4, 128)]:
+        us = CL.pattern_us(nx, ny, bool(mhd), sb, rows, True, reps=5, cols=cols)
         assert 0 < us < 1e5
     assert 0 < CL.copy_us(1 << 20, reps=5) < 1e5
 

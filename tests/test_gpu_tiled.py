@@ -185,12 +185,12 @@ def test_fp64_agrees_with_march_after_201_steps(name):
 
 def test_default_and_tuner_selection():
     """A single straight run starts on the tiled step; the tuner times it at
-    its three tile heights, each with non-temporal and with plain stores,
+    its four tile shapes, each with non-temporal and with plain stores,
     beside the 17 plans of the march and keeps whichever is fastest."""
     r = B.Run(cav(256, 256, "f32"))
     assert r.launch_info()["waves_per_cu"] == 0
     info = r.tune(5)
-    assert info["candidates"] == 23   # three heights x two store policies, 17 march plans
+    assert info["candidates"] == 25   # four shapes x two store policies, 17 march plans
     assert info["us_before"] > 0.0   # the tiled step was in use and was timed
     li = r.launch_info()
     assert li["waves_per_cu"] == info["waves_per_cu"]
@@ -290,7 +290,7 @@ def test_16bit_storage_has_only_the_tiled_step(storage):
         h.set_launch(8)
     assert ei.value.code == B.GOC_EINVAL
     info = h.tune(3)
-    assert info["candidates"] == 6 and info["waves_per_cu"] == 0
+    assert info["candidates"] == 8 and info["waves_per_cu"] == 0   # four tile shapes x two store policies
     assert h.launch_info()["rows_per_segment"] in (4, 8, 16)
     h.close()
     b = B.Run(batch=[c.replace(storage=storage) for c in W.batch_256(n=3)])
@@ -300,45 +300,56 @@ def test_16bit_storage_has_only_the_tiled_step(storage):
 
 @pytest.mark.parametrize("name", ["cavity_f64_ragged", "mhd_f64_ragged", "moving_xi1_walls"])
 def test_tile_heights_agree_fp64(name):
-    """The tiled step at 4 and 8 rows per tile (FP64's heights) computes the
-    same step: fields within 1e-13 after 201 steps."""
+    """The tiled step at 4 and 8 rows per 64-column tile (FP64's heights) and
+    in 128 x 4 tiles computes the same step: fields within 1e-13 after 201
+    steps."""
     case, init_fields, lid = CASES[name]
     runs = {}
-    for rows in (4, 8):
+    for rows in (4, 8, "128x4"):
         r = _run(case, init_fields, lid, 0)
-        r.set_tile(rows)
-        assert r.launch_info()["rows_per_segment"] == rows
+        if rows == "128x4":
+            r.set_tile(4, cols=128)
+        else:
+            r.set_tile(rows)
+            assert r.launch_info()["rows_per_segment"] == rows
         for steps in (1, 40, 160):
             r.step(steps)
         runs[rows] = r
-    a, b = runs[8].fields(), runs[4].fields()
+    b = runs[4].fields()
     un = np.linalg.norm(np.hypot(b["U1"], b["U2"]))
-    for k in a:
-        ref = un if k.startswith("U") else np.linalg.norm(b[k])
-        assert np.linalg.norm(a[k] - b[k]) <= 1e-13 * ref, (name, k)
+    for other in (8, "128x4"):
+        a = runs[other].fields()
+        for k in a:
+            ref = un if k.startswith("U") else np.linalg.norm(b[k])
+            assert np.linalg.norm(a[k] - b[k]) <= 1e-13 * ref, (name, other, k)
     for r in runs.values():
         r.close()
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16dev", "bf16dev"])
 def test_tile_heights_agree(storage):
-    """The tiled step at 4, 8 and 16 rows per tile from the same developed
-    state (a batch of plain and MHD runs): FP32 stores the same values within
-    a few eps of the largest; the 16-bit forms' fields agree far inside their
-    rounding (an ulp of FP32 difference can flip a stochastic rounding)."""
+    """The tiled step at 4, 8 and 16 rows per 64-column tile and in 128 x 4
+    tiles from the same developed state (a batch of plain and MHD runs): FP32
+    stores the same values within a few eps of the largest; the 16-bit forms'
+    fields agree far inside their rounding (an ulp of FP32 difference can flip
+    a stochastic rounding)."""
     runs = [c.replace(storage=storage) for c in W.batch_256(n=3)] + [cav(130, 70, storage)]
     base = B.Run(batch=runs)
     base.set_launch(0)
     base.step(120)
     blob = base.get_state()
     out = {}
-    for rows in (4, 8, 16):
+    for rows in (4, 8, 16, "128x4"):
         r = B.Run(batch=runs)
-        r.set_tile(rows, rows == 8)   # (both store policies)
+        if rows == "128x4":
+            r.set_tile(4, True, cols=128)
+            assert r.launch_info()["tile_cols"] == 128
+        else:
+            r.set_tile(rows, rows == 8)   # (both store policies)
         r.set_state(blob)
         r.step(1)
         out[rows] = r
-    for rows in (8, 16):
+    for rows in (8, 16, "128x4"):
         for k, case in enumerate(runs):
             if storage == "f32":
                 fa, Fa, ga = out[rows].populations(run=k)
