@@ -59,8 +59,10 @@ def field_errors(gf, of, o, storage):
     return e
 
 
-def run_pair(oracle_lib, case, steps, init_fields=None):
+def run_pair(oracle_lib, case, steps, init_fields=None, tune=0):
     g = B.Run(case)
+    if tune:
+        g.tune(tune)   # (the form the benchmark times)
     o = oracle_lib.Model(case)
     if init_fields is not None:
         g.init(*init_fields)
@@ -73,8 +75,8 @@ def run_pair(oracle_lib, case, steps, init_fields=None):
     return g, o
 
 
-def check(oracle_lib, case, steps, tol, init_fields=None, field_tol=None):
-    g, o = run_pair(oracle_lib, case, steps, init_fields)
+def check(oracle_lib, case, steps, tol, init_fields=None, field_tol=None, tune=0):
+    g, o = run_pair(oracle_lib, case, steps, init_fields, tune)
     e = field_errors(g.fields(), o.fields(), o, case.storage)
     print(case.name, case.storage, {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
     for k, v in e.items():
@@ -220,11 +222,13 @@ def hartmann_full_oracle(oracle_lib):
 @pytest.mark.parametrize("storage", ["f16dev", "bf16dev"])
 def test_16bit_full_size_hartmann_1000_steps(hartmann_full_oracle, storage):
     """The precision form at the full 4096x1024 Ha=100 channel, as the
-    benchmark launches it, from the developed Hartmann state: every field
-    within 1e-3 of the FP64 oracle after 1000 steps."""
+    benchmark launches it (autotuned step form), from the developed Hartmann
+    state: every field within 1e-3 of the FP64 oracle after 1000 steps."""
     case, init, o = hartmann_full_oracle
     g = B.Run(case.replace(storage=storage))
     g.init(*init)
+    g.tune(20)
+    print(f"[full-size] {storage} tuned form", g.launch_info(), flush=True)
     g.step(1000)
     e = field_errors(g.fields(), o.fields(), o, storage)
     print(storage, "4096x1024", {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
@@ -275,10 +279,13 @@ def test_fp32_developed_hartmann_1000_steps(oracle_lib):
 
 @pytest.mark.slow
 def test_fp32_full_size_hartmann_1000_steps(oracle_lib):
-    """The 4096x1024 Ha=100 channel in FP32, as the benchmark launches it,
-    from the developed Hartmann state: 1000 steps within 1e-5 of the FP64
-    oracle on every field (about a minute of oracle time on 16 cores)."""
+    """The 4096x1024 Ha=100 channel in FP32, as the benchmark launches it
+    (autotuned step form), from the developed Hartmann state: 1000 steps
+    within 1e-5 of the FP64 oracle on every field (about a minute of oracle
+    time on 16 cores)."""
     case, g, o = developed_hartmann(oracle_lib, "f32", nx=4096, ny=1024)
+    g.tune(20)
+    print("[full-size] tuned form", g.launch_info(), flush=True)
     g.step(1000)
     o.step(1000)
     e = field_errors(g.fields(), o.fields(), o, "f32")
@@ -289,9 +296,10 @@ def test_fp32_full_size_hartmann_1000_steps(oracle_lib):
 
 @pytest.mark.slow
 def test_fp32_full_size_cavity_1000_steps(oracle_lib):
-    """The 1024x1024 Re=1000 cavity in FP32, as the benchmark launches it,
-    from rest: 1000 steps within 1e-5 of the FP64 oracle."""
-    check(oracle_lib, W.cavity_1024(), 1000, 1e-5)
+    """The 1024x1024 Re=1000 cavity in FP32, as the benchmark launches it
+    (autotuned step form), from rest: 1000 steps within 1e-5 of the FP64
+    oracle."""
+    check(oracle_lib, W.cavity_1024(), 1000, 1e-5, tune=20)
 
 
 def test_periodic_random_fields_fp64(oracle_lib):
@@ -328,14 +336,30 @@ def test_populations_roundtrip_and_resume_from_oracle_state(oracle_lib):
     assert max(e.values()) < 1e-12
 
 
-@pytest.mark.parametrize("which", ["cavity_1024", "hartmann_4096"])
-def test_full_size_one_step_sampled(oracle_lib, which):
-    """Full-size configurations in the benchmark's launch configuration: one
-    GPU step from a developed state against the oracle evaluated at sampled
-    nodes (corners and wall rows included)."""
+# the step forms the autotuner chooses among on the full-size straight runs:
+# tuned (what the benchmark times), then every tile shape with either store
+# policy fixed
+FULL_SIZE_FORMS = [("cavity_1024", "tuned"), ("hartmann_4096", "tuned")] + [
+    ("hartmann_4096", (cols, rows, nt)) for cols, rows in ((128, 4), (64, 4), (64, 8), (64, 16)) for nt in (1, 0)]
+
+
+@pytest.mark.parametrize("which,form", FULL_SIZE_FORMS, ids=lambda v: v if isinstance(v, str) else "x".join(map(str, v)))
+def test_full_size_one_step_sampled(oracle_lib, which, form):
+    """Full-size configurations in the benchmark's launch configuration (the
+    autotuned form, and each tile shape it may pick): one GPU step from a
+    developed state against the oracle evaluated at sampled nodes (corners
+    and wall rows included)."""
     case = W.cavity_1024() if which == "cavity_1024" else W.hartmann_4096()
     g = B.Run(case)
-    print(f"[full-size] {case.name}", flush=True)
+    if form == "tuned":
+        g.tune(10)
+    else:
+        cols, rows, nt = form
+        g.set_tile(rows, nt, cols=cols)
+    info = g.launch_info()
+    print(f"[full-size] {case.name} {form} {info}", flush=True)
+    if form != "tuned":
+        assert (info["tile_cols"], info["rows_per_segment"], info["nontemporal"]) == form
     g.step(200)
     f0, F0, g0 = g.populations()
     g.step(1)
