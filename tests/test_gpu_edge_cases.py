@@ -2,8 +2,9 @@
 the method allows (3 nodes per axis, where the one-sided wall differences
 span the whole axis and a segment is a single partial group of rows), grids
 one node past a 64-column strip or a 4-row group, each boundary combination,
-MHD on the smallest channel, the curvilinear step on tiny grids, and zero
-steps."""
+MHD on the smallest channel (each in 64-column tiles and in 128 x 4 tiles,
+including grids one node past a 128-column tile), the curvilinear step on
+tiny grids, and zero steps."""
 import numpy as np
 import pytest
 
@@ -14,10 +15,13 @@ from paper_2607_15362_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def _pair(oracle_lib, case, lid=0.0, metric2d=None):
+def _pair(oracle_lib, case, lid=0.0, metric2d=None, wide=False):
     gs, ms, ps = B.derive(case)
     gs.u_wall_hi = lid
     g = B.Run(case, structs=(gs, ms, ps))
+    if wide:   # 128 x 4 tiles (two waves per tile row)
+        g.set_tile(4, cols=128)
+        assert g.launch_info()["tile_cols"] == 128
     o = oracle_lib.Model(case, metric2d=metric2d)
     if lid:
         o.lat.u_wall_hi = lid
@@ -25,8 +29,8 @@ def _pair(oracle_lib, case, lid=0.0, metric2d=None):
     return g, o
 
 
-def _run(oracle_lib, case, steps=60, lid=0.0, metric2d=None, amp=0.01):
-    g, o = _pair(oracle_lib, case, lid, metric2d)
+def _run(oracle_lib, case, steps=60, lid=0.0, metric2d=None, amp=0.01, wide=False):
+    g, o = _pair(oracle_lib, case, lid, metric2d, wide)
     init = W.smooth_fields(case.nx, case.ny, seed=21, amp=amp)
     if case.mhd:
         g.init(*init, np.zeros((case.ny, case.nx)), np.full((case.ny, case.nx), g.derived()["B0"]))
@@ -34,7 +38,8 @@ def _run(oracle_lib, case, steps=60, lid=0.0, metric2d=None, amp=0.01):
     else:
         g.init(*init)
         o.init(*init)
-    print(f"[edge] {case.name} {case.nx}x{case.ny} {case.bc_x}/{case.bc_y} mhd={case.mhd} steps={steps}", flush=True)
+    print(f"[edge] {case.name} {case.nx}x{case.ny} {case.bc_x}/{case.bc_y} mhd={case.mhd} wide={wide} steps={steps}",
+          flush=True)
     g.step(steps)
     o.step(steps)
     f, F, gg = g.populations()
@@ -50,24 +55,27 @@ def _run(oracle_lib, case, steps=60, lid=0.0, metric2d=None, amp=0.01):
 @pytest.mark.parametrize("nx,ny,bcx,bcy", [
     (3, 3, "wall", "wall"), (3, 3, "periodic", "periodic"), (3, 3, "periodic", "wall"), (3, 3, "wall", "periodic"),
     (3, 7, "wall", "wall"), (7, 3, "wall", "wall"), (65, 5, "wall", "wall"), (64, 9, "periodic", "wall"),
-    (66, 3, "periodic", "periodic"), (3, 70, "periodic", "wall"),
+    (66, 3, "periodic", "periodic"), (3, 70, "periodic", "wall"), (129, 5, "wall", "wall"),
+    (130, 9, "periodic", "wall"),
 ])
 @pytest.mark.parametrize("collision", ["central", "raw"])
-def test_smallest_and_edge_sizes_fp64(oracle_lib, nx, ny, bcx, bcy, collision):
+@pytest.mark.parametrize("wide", [False, True], ids=["tile64", "tile128x4"])
+def test_smallest_and_edge_sizes_fp64(oracle_lib, nx, ny, bcx, bcy, collision, wide):
     case = W.Case(f"edge_{nx}x{ny}", nx, ny, bcx, bcy, ("tanh", 1.0) if bcx == "wall" else ("uniform", 0.0),
                   ("tanh", 1.2) if bcy == "wall" else ("uniform", 0.0), flow="free", tau=0.8,
                   body_force=(1e-6, 5e-7), v_wall=(0.003, -0.002), collision=collision, storage="f64")
-    _run(oracle_lib, case, lid=0.01 if bcy == "wall" else 0.0)
+    _run(oracle_lib, case, lid=0.01 if bcy == "wall" else 0.0, wide=wide)
 
 
-@pytest.mark.parametrize("nx,ny", [(3, 3), (3, 5), (65, 4)])
-def test_smallest_mhd_channels_fp64(oracle_lib, nx, ny):
+@pytest.mark.parametrize("nx,ny", [(3, 3), (3, 5), (65, 4), (129, 5)])
+@pytest.mark.parametrize("wide", [False, True], ids=["tile64", "tile128x4"])
+def test_smallest_mhd_channels_fp64(oracle_lib, nx, ny, wide):
     # (mild clustering: with tanh beta = 1.5 over three rows the channel
     # diverges within 60 steps in the oracle too, which then amplifies
     # rounding differences)
     case = W.Case(f"edge_mhd_{nx}x{ny}", nx, ny, "periodic", "wall", ("uniform", 0.0), ("tanh", 0.5),
                   flow="hartmann", Re=2.0, Ha=2.0, Ma=0.1, mhd=True, storage="f64")
-    _run(oracle_lib, case)
+    _run(oracle_lib, case, wide=wide)
 
 
 @pytest.mark.parametrize("nx,ny,bcx,bcy", [(3, 3, "wall", "wall"), (3, 4, "wall", "periodic"),
