@@ -211,15 +211,16 @@ int goc_lbm_derive(goc_grid *grid, const goc_metric *metric, const goc_physics *
 
 /* Create a run on the current HIP device.  Copies the metric (FP64
    precompute on the device: theta = dh/h^2, q = min h), allocates the
-   state (two slot buffers, the lagged force and, with MHD, the D2Q5
-   buffers) and initialises it at rest (rho0, U = 0, B = (0, B0)).
+   state (two slot buffers, holding with MHD the D2Q5 slots too, and the
+   lagged force) and initialises it at rest (rho0, U = 0, B = (0, B0)).
    stream: a hipStream_t (NULL = the default stream).  *out receives the
    handle, owned by the caller until goc_lbm_destroy.  Size limits: nx, ny
-   >= 3, nx*ny <= 2^31, and the slot pool of one run (9 planes, 10 for the
-   D2Q5 buffers, each row padded to an odd number of 64-node pieces, over
-   ny + 2 rows, plus 256 storage elements) at most 4 GiB, i.e. about 53M
-   nodes in FP64 with MHD, 107M in FP32, 214M in the 16-bit forms for wide
-   grids; GOC_EINVAL beyond. */
+   >= 3, nx*ny <= 2^31, and the slot pool of one run (9 planes, or 20 with
+   the D2Q5 slots, which share its rows; each plane padded to an odd number
+   of 64-node pieces, over ny + 2 rows, plus 256 storage elements) at most
+   4 GiB, i.e. about 27M nodes in FP64 with MHD (59M without), 53M in FP32
+   (119M), 107M in the 16-bit forms (238M) for wide grids; GOC_EINVAL
+   beyond. */
 int goc_lbm_create(goc_lbm_t **out, const goc_grid *grid, const goc_metric *metric,
                    const goc_params *params, int32_t storage, void *stream);
 
@@ -369,10 +370,12 @@ int goc_lbm_set_populations(goc_lbm_t *h, const double *f, const double *F, cons
 
 /* Checkpoint in storage precision (host buffer).  get: with buf NULL writes
    the required size to *bytes; otherwise *bytes must be >= that size.
-   The blob holds a header (format version 2, storage, run count, step
+   The blob holds a header (format version 3, storage, run count, step
    counter, the byte sizes of its regions, the step of the last
    initialisation), each run's (nx, ny, mhd), then the raw device state: the
-   16-bit reference table, the slots, the lagged force and the D2Q5 slots.
+   16-bit reference table, the slots (with MHD, the D2Q5 slots in their
+   rows) and the lagged force.  Blobs of another format version are
+   refused.
    set: checks the header, the region sizes and every run's shape against
    the handle before copying anything and returns GOC_ESTATE on any
    mismatch (the handle is then unchanged).  Restoring a blob and stepping

@@ -7,8 +7,10 @@
 // lagged force; with the D2Q5 slots of App. G) in the library's layout and
 // launch geometry, and computes nothing but a sum per pulled node.  Its
 // duration bounds what the step can reach with this memory pattern; the copy
-// kernel gives the plain one-stream figure beside it.  Both allocate their
-// own buffers; nothing here is used by the step.
+// kernel gives the plain one-stream figure beside it, and the mix kernel
+// plain streams in other read / write proportions (HBM delivers less when
+// reads and writes interleave).  All allocate their own buffers; nothing
+// here is used by the step.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -169,6 +171,67 @@ __global__ void __launch_bounds__(256) copy_kernel(const float4* __restrict__ a,
     for (; k < n; k += s) o[k] = a[k];
 }
 
+// Streams of 16-byte vectors in a chosen read / write mix: R input and W
+// output buffers of n vectors each, element k of every output written from
+// element k of every input (grid-stride, four elements in flight per thread);
+// with no output each thread folds what it reads into one value, written
+// only if it matches a value the inputs never hold (so no load is dropped).
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__device__ inline void st4(f4v* p, f4v v)
+{
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+template <int R, int W, bool NT>
+__global__ void __launch_bounds__(256) mix_kernel(const f4v* __restrict__ a0, const f4v* __restrict__ a1,
+                                                  f4v* __restrict__ o0, f4v* __restrict__ o1, int64_t n,
+                                                  float* __restrict__ sink)
+{
+    const int64_t s = (int64_t)gridDim.x * 256;
+    int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    f4v acc = {0.f, 0.f, 0.f, 0.f};
+    auto in = [&](int64_t e) {
+        f4v v = {1.f, 1.f, 1.f, 1.f};
+        if constexpr (R >= 1) v = a0[e];
+        if constexpr (R >= 2) v += a1[e];
+        return v;
+    };
+    auto out = [&](int64_t e, f4v v) {
+        if constexpr (W >= 1) st4<NT>(o0 + e, v);
+        if constexpr (W >= 2) st4<NT>(o1 + e, v + 1.f);
+        if constexpr (W == 0) acc += v;
+    };
+    for (; k + 3 * s < n; k += 4 * s) {
+        const f4v v0 = in(k), v1 = in(k + s), v2 = in(k + 2 * s), v3 = in(k + 3 * s);
+        out(k, v0);
+        out(k + s, v1);
+        out(k + 2 * s, v2);
+        out(k + 3 * s, v3);
+    }
+    for (; k < n; k += s) out(k, in(k));
+    if constexpr (W == 0)
+        if (acc.x + acc.y + acc.z + acc.w == -1.f) sink[0] = acc.x;   // (the buffers hold zeros)
+}
+
+template <int R, int W, bool NT>
+hipError_t launch_mix(int blocks, hipStream_t st, void* const* p, int64_t n, float* sink)
+{
+    hipLaunchKernelGGL((mix_kernel<R, W, NT>), dim3(blocks), dim3(256), 0, st, static_cast<const f4v*>(p[0]),
+                       static_cast<const f4v*>(p[1]), static_cast<f4v*>(p[2]), static_cast<f4v*>(p[3]), n, sink);
+    return hipGetLastError();
+}
+
+template <int R, int W>
+hipError_t launch_mix_nt(bool nt, int blocks, hipStream_t st, void* const* p, int64_t n, float* sink)
+{
+    return nt ? launch_mix<R, W, true>(blocks, st, p, n, sink) : launch_mix<R, W, false>(blocks, st, p, n, sink);
+}
+
 struct Events {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     ~Events()
@@ -197,8 +260,8 @@ int run_pattern(const goc::RunDesc& d, int64_t f_elems, int64_t F_elems, int rep
 {
     Buffers buf(st);
     const size_t fb = size_t(f_elems) * sizeof(S), Fb = size_t(F_elems) * sizeof(float);
-    const size_t sizes[6] = {fb, fb, Fb, Fb, MHD ? fb : 16, MHD ? fb : 16};
-    for (int k = 0; k < 6; ++k) {
+    const size_t sizes[4] = {fb, fb, Fb, Fb};
+    for (int k = 0; k < 4; ++k) {
         if (hipMalloc(&buf.p[k], sizes[k]) != hipSuccess) return GOC_ENOMEM;
         if (hipMemsetAsync(buf.p[k], 0, sizes[k], st) != hipSuccess) return GOC_EDEVICE;
     }
@@ -211,8 +274,8 @@ int run_pattern(const goc::RunDesc& d, int64_t f_elems, int64_t F_elems, int rep
         pl.fout = static_cast<S*>(buf.p[1 - a]);
         pl.Fin = static_cast<const float*>(buf.p[2 + a]);
         pl.Fout = static_cast<float*>(buf.p[3 - a]);
-        pl.gin = static_cast<const S*>(buf.p[4 + a]);
-        pl.gout = static_cast<S*>(buf.p[5 - a]);
+        pl.gin = pl.fin;   // (the D2Q5 planes lie in the rows of the slot pool)
+        pl.gout = pl.fout;
         hipLaunchKernelGGL((pattern_kernel<S, MHD, TY, NT, TX>), grid, block, 0, st, d, pl, 0.f);
         return hipGetLastError();
     };
@@ -267,12 +330,12 @@ extern "C" int goc_ceiling_pattern(int nx, int ny, int mhd, int storage_bytes, i
     d.mhd = mhd ? 1 : 0;
     const int64_t row = goc::padded_row(nx);
     d.plane = row;
-    d.pitch = int32_t((mhd ? 10 : 9) * row);
+    d.pitch = int32_t((mhd ? 2 * goc::kGPlanes : 9) * row);
     d.pitchF = int32_t(2 * row);
     const int64_t region = (int64_t)d.pitch * (ny + 2) + 256, regionF = (int64_t)d.pitchF * ny + 256;
     if (region * storage_bytes > (int64_t)UINT32_MAX) return GOC_EINVAL;
     d.f_off = d.pitch;
-    d.g_off = d.pitch;
+    d.g_off = d.pitch + (mhd ? goc::kGPlanes * row : 0);
     d.F_off = 0;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int nt = nontemporal ? 1 : 0;
@@ -311,6 +374,57 @@ extern "C" int goc_ceiling_copy(int64_t bytes, int reps, void* stream, double* u
     if (hipEventRecord(ev.e0, st) != hipSuccess) return GOC_EDEVICE;
     for (int k = 0; k < reps; ++k)
         if (launch(k) != hipSuccess) return GOC_EDEVICE;
+    if (hipEventRecord(ev.e1, st) != hipSuccess || hipEventSynchronize(ev.e1) != hipSuccess) return GOC_EDEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev.e0, ev.e1) != hipSuccess) return GOC_EDEVICE;
+    *us_per_launch = 1e3 * double(ms) / reps;
+    return GOC_OK;
+}
+
+extern "C" int goc_ceiling_mix(int64_t bytes, int reads, int writes, int nontemporal, int wg_per_cu, int reps,
+                               void* stream, double* us_per_launch)
+{
+    if (!us_per_launch || bytes < 16 || bytes % 16 != 0 || reads < 0 || reads > 2 || writes < 0 || writes > 2 ||
+        reads + writes < 1 || (nontemporal != 0 && nontemporal != 1) || wg_per_cu < 1 || wg_per_cu > 64 || reps < 1)
+        return GOC_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Buffers buf(st);
+    // p[0], p[1]: inputs; p[2], p[3]: outputs; p[4]: the sink
+    const int used[4] = {reads >= 1, reads >= 2, writes >= 1, writes >= 2};
+    for (int k = 0; k < 4; ++k) {
+        if (!used[k]) continue;
+        if (hipMalloc(&buf.p[k], size_t(bytes)) != hipSuccess) return GOC_ENOMEM;
+        if (hipMemsetAsync(buf.p[k], 0, size_t(bytes), st) != hipSuccess) return GOC_EDEVICE;
+    }
+    if (hipMalloc(&buf.p[4], 16) != hipSuccess) return GOC_ENOMEM;
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+    }
+    const int64_t n = bytes / 16;
+    const int blocks = wg_per_cu * ncu;
+    float* sink = static_cast<float*>(buf.p[4]);
+    const bool nt = nontemporal != 0;
+    auto launch = [&]() -> hipError_t {
+        switch (reads * 3 + writes) {
+            case 1: return launch_mix_nt<0, 1>(nt, blocks, st, buf.p, n, sink);
+            case 2: return launch_mix_nt<0, 2>(nt, blocks, st, buf.p, n, sink);
+            case 3: return launch_mix_nt<1, 0>(nt, blocks, st, buf.p, n, sink);
+            case 4: return launch_mix_nt<1, 1>(nt, blocks, st, buf.p, n, sink);
+            case 5: return launch_mix_nt<1, 2>(nt, blocks, st, buf.p, n, sink);
+            case 6: return launch_mix_nt<2, 0>(nt, blocks, st, buf.p, n, sink);
+            case 7: return launch_mix_nt<2, 1>(nt, blocks, st, buf.p, n, sink);
+            default: return launch_mix_nt<2, 2>(nt, blocks, st, buf.p, n, sink);
+        }
+    };
+    for (int k = 0; k < 4; ++k)
+        if (launch() != hipSuccess) return GOC_EDEVICE;
+    Events ev;
+    if (hipEventCreate(&ev.e0) != hipSuccess || hipEventCreate(&ev.e1) != hipSuccess) return GOC_EDEVICE;
+    if (hipEventRecord(ev.e0, st) != hipSuccess) return GOC_EDEVICE;
+    for (int k = 0; k < reps; ++k)
+        if (launch() != hipSuccess) return GOC_EDEVICE;
     if (hipEventRecord(ev.e1, st) != hipSuccess || hipEventSynchronize(ev.e1) != hipSuccess) return GOC_EDEVICE;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, ev.e0, ev.e1) != hipSuccess) return GOC_EDEVICE;

@@ -17,11 +17,12 @@
 //
 // State layout in HBM (one plane per direction, rows interleaved): the
 // element of plane a at node (i, j) is at a * plane + j * pitch + i, with
-// plane the padded row length (nx rounded up to 64) and pitch the row
-// stride, Q * plane for the Q planes of a pool (9 for the populations; 10
-// for both the populations and the D2Q5 slots of an MHD run), so that the
-// planes of one row lie together; the two force planes have the row stride
-// pitchF = 2 * plane.
+// plane the padded row length (nx rounded up to an odd number of 64-node
+// pieces) and pitch the row stride, so that the planes of one row lie
+// together: 9 population planes per row, or for an MHD run 20 (the nine
+// population planes, one unused, then the ten D2Q5 planes from g_off =
+// f_off + 10 plane, in the same pool); the two force planes have the row
+// stride pitchF = 2 * plane.
 //   slot(a, x) in plane a at the writer node x holds the population that
 //   leaves x along e_a after collision, minus the rest-state population of
 //   its reader (the node that pulls it), with the reader's wall condition
@@ -204,6 +205,11 @@ constexpr int kRefG = 9;    // first D2Q5 entry
 // crowd into a few of the memory channels: a 4096-column FP32 run with D2Q5
 // slots stepped 142 us per launch with 65 pieces per plane against 152 us
 // with 64).  The padding is never read or written.
+// Planes of a slot-pool row before the D2Q5 planes of an MHD run (the nine
+// population planes and one unused one); the ten D2Q5 planes follow, so an
+// MHD row holds 2 kGPlanes planes.
+constexpr int kGPlanes = 10;
+
 __host__ __device__ constexpr int64_t padded_row(int nx)
 {
     const int64_t p = (int64_t(nx) + 63) / 64;

@@ -306,8 +306,7 @@ struct goc_lbm {
     float *colf_d = nullptr, *rowf_d = nullptr;   // their FP32 copies
     void* f[2] = {nullptr, nullptr};
     void* F[2] = {nullptr, nullptr};
-    void* g[2] = {nullptr, nullptr};
-    size_t f_elems = 0, F_elems = 0, g_elems = 0;
+    size_t f_elems = 0, F_elems = 0;   // (an MHD run's D2Q5 planes lie in the rows of the slot pool)
     int cur = 0;
     int64_t step = 0;
     int64_t watchdog = 1000;        // check for non-finite values at step return (0: never)
@@ -349,8 +348,8 @@ PoolsOf<S> pools(const goc_lbm* h, int in)
     p.fout = static_cast<S*>(h->f[1 - in]);
     p.Fin = static_cast<const FT*>(h->F[in]);
     p.Fout = static_cast<FT*>(h->F[1 - in]);
-    p.gin = static_cast<const S*>(h->g[in]);
-    p.gout = static_cast<S*>(h->g[1 - in]);
+    p.gin = p.fin;   // (the D2Q5 planes lie in the rows of the slot pool)
+    p.gout = p.fout;
     p.col = h->col_d;
     p.row = h->row_d;
     p.colf = h->colf_d;
@@ -490,7 +489,6 @@ int free_all(goc_lbm* h)
         if (h->graph[k]) (void)hipGraphExecDestroy(h->graph[k]);
         (void)hipFree(h->f[k]);
         (void)hipFree(h->F[k]);
-        (void)hipFree(h->g[k]);
         (void)hipFree(h->ref_d[k]);
     }
     (void)hipFree(h->runs_d);
@@ -685,9 +683,10 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
         if (is_2d(metric[r]) && params[r].mhd)
             return bail(fail(GOC_EINVAL, "run %d: MHD runs need a straight metric", r));
         // the step kernel addresses a run's slot region (Q planes of padded
-        // rows, two ghost rows) with 32-bit byte offsets
+        // rows, two ghost rows; Q = 20 with the D2Q5 slots in its rows) with
+        // 32-bit byte offsets
         const int64_t row = goc::padded_row(grid[r].nx);
-        const int64_t region = (params[r].mhd ? 10 : 9) * row * (grid[r].ny + 2) + 256;
+        const int64_t region = (params[r].mhd ? 2 * goc::kGPlanes : 9) * row * (grid[r].ny + 2) + 256;
         if (region * (int64_t)storage_bytes(storage) > (int64_t)UINT32_MAX)
             return bail(fail(GOC_EINVAL, "run %d: grid %d x %d too large for this storage "
                              "(slot region of one run above 4 GiB)", r, grid[r].nx, grid[r].ny));
@@ -712,7 +711,7 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
     h->mx.resize(nruns);
     h->my.resize(nruns);
     h->q.resize(nruns);
-    int64_t sum_nx = 0, sum_ny = 0, f_elems = 0, F_elems = 0, g_elems = 0;
+    int64_t sum_nx = 0, sum_ny = 0, f_elems = 0, F_elems = 0;
     int64_t met_elems = 0, face_elems = 0;
     // one wave per work-group; aim for ~16 waves per CU over the whole batch
     std::vector<int32_t> block_run;
@@ -730,9 +729,14 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
         d.bc_x = g.bc_x;
         d.bc_y = g.bc_y;
         // rows interleaved: the planes of a row lie together (row stride
-        // Q * plane, Q = 9 planes, or 10 with the D2Q5 slots, which share it)
+        // Q * plane).  A plain run's row holds its 9 population planes; an
+        // MHD run's row holds them, one unused plane and the 10 D2Q5 planes
+        // (Q = 20): the step then streams one region per buffer rather than
+        // two, which HBM serves faster (the step's memory pattern without
+        // arithmetic, 4096 x 1024 FP32 with 128 x 4 tiles: 131.5 us per launch
+        // with the D2Q5 slots in a pool of their own, 127.5 us interleaved)
         d.plane = row;
-        d.pitch = (p.mhd ? 10 : 9) * row;
+        d.pitch = (p.mhd ? 2 * goc::kGPlanes : 9) * row;
         d.pitchF = 2 * row;
         // slot regions (populations, D2Q5) hold two ghost rows, -1 and ny, for
         // the step kernel's pulls beyond the domain in y
@@ -743,13 +747,10 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
                              "(slot region of one run above 4 GiB)", r, g.nx, g.ny));
         d.f_off = f_elems + d.pitch;   // row 0 (row -1 before it)
         d.F_off = F_elems;
-        d.g_off = g_elems + d.pitch;
+        d.g_off = d.f_off + (p.mhd ? goc::kGPlanes * row : 0);   // (the D2Q5 planes share the slot pool)
         f_elems += region;
         F_elems += regionF;
-        if (p.mhd) {
-            g_elems += region;
-            h->any_mhd = true;
-        }
+        if (p.mhd) h->any_mhd = true;
         d.col_off = sum_nx;
         d.row_off = sum_ny;
         d.metric2d = h->m2d ? 1 : 0;
@@ -794,7 +795,6 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
     h->tiled = tile_eligible(h) && (nruns == 1 || scaled_storage(storage));
     h->f_elems = f_elems;
     h->F_elems = F_elems;
-    h->g_elems = g_elems;
 
     // metric pools and the FP64 precompute (theta, q)
     std::vector<double> h1(sum_nx), dh1(sum_nx), h2(sum_ny), dh2(sum_ny);
@@ -919,7 +919,7 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
     tile_table(h, tile_first, overflow);
     // non-temporal stores where one copy of the state exceeds half the
     // 256 MiB Infinity Cache (the autotuner times both)
-    h->tile_nt = f_elems * sb + F_elems * fb + g_elems * sb > (size_t(128) << 20);
+    h->tile_nt = f_elems * sb + F_elems * fb > (size_t(128) << 20);
     h->total_tiles = tile_first[nruns];
     if ((rc = dev_alloc((void**)&h->runs_d, nruns * sizeof(RunDesc))) ||
         (rc = dev_alloc((void**)&h->block_run_d, block_run.size() * 4)) ||
@@ -943,10 +943,8 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
     for (int k = 0; k < 2; ++k) {
         if ((rc = dev_alloc(&h->f[k], f_elems * sb)) || (rc = dev_alloc(&h->F[k], F_elems * fb)))
             return bail(rc);
-        if (g_elems && (rc = dev_alloc(&h->g[k], g_elems * sb))) return bail(rc);
         if (hipMemsetAsync(h->f[k], 0, f_elems * sb, h->stream) != hipSuccess ||
-            hipMemsetAsync(h->F[k], 0, F_elems * fb, h->stream) != hipSuccess ||
-            (g_elems && hipMemsetAsync(h->g[k], 0, g_elems * sb, h->stream) != hipSuccess))
+            hipMemsetAsync(h->F[k], 0, F_elems * fb, h->stream) != hipSuccess)
             return bail(fail(GOC_EDEVICE, "state clear failed"));
     }
     *out = h;
@@ -1499,14 +1497,14 @@ int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
     // (waves_per_cu, tile rows, store policy): waves_per_cu 0 is the tiled
     // step with that tile height, a positive one the march with that plan.
     const size_t sb = storage_bytes(h->storage), fb = force_bytes(h->storage);
-    const size_t bytes[3] = {h->f_elems * sb, h->F_elems * fb, h->g_elems * sb};
-    void* const* bufs[3] = {h->f, h->F, h->g};
+    const size_t bytes[2] = {h->f_elems * sb, h->F_elems * fb};
+    void* const* bufs[2] = {h->f, h->F};
     struct Saved {
-        void* p[3] = {nullptr, nullptr, nullptr};
+        void* p[2] = {nullptr, nullptr};
         ~Saved() { for (auto x : p) if (x) (void)hipFree(x); }
     } saved;
     const int cur0 = h->cur;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 2; ++k) {
         if (!bytes[k]) continue;
         if (hipMalloc(&saved.p[k], bytes[k]) != hipSuccess) {
             saved.p[k] = nullptr;
@@ -1517,7 +1515,7 @@ int goc_lbm_tune(goc_lbm_t* h, int32_t trial_steps, double out[4])
     }
     auto restore = [&]() -> int {
         h->cur = cur0;
-        for (int k = 0; k < 3; ++k)
+        for (int k = 0; k < 2; ++k)
             if (bytes[k])
                 HIPOK(hipMemcpyAsync(bufs[k][cur0], saved.p[k], bytes[k], hipMemcpyDeviceToDevice, h->stream));
         HIPOK(hipStreamSynchronize(h->stream));
@@ -1704,14 +1702,15 @@ int goc_lbm_set_populations(goc_lbm_t* h, const double* f, const double* F, cons
 
 namespace {
 // Checkpoint blob: this header, then per run (nx, ny, mhd) as int32, then
-// the reference table of the 16-bit storage, the slots, the lagged force
-// and the D2Q5 slots, each as the raw device bytes.
+// the reference table of the 16-bit storage, the slot pool (with the D2Q5
+// slots of MHD runs in its rows) and the lagged force, each as the raw
+// device bytes.
 struct StateHeader {
     char magic[8];
     int32_t version, storage, nruns, mhd;
-    int64_t step, f_bytes, F_bytes, g_bytes, ref_bytes, ref_base;
+    int64_t step, f_bytes, F_bytes, ref_bytes, ref_base;
 };
-constexpr int32_t kStateVersion = 2;
+constexpr int32_t kStateVersion = 3;
 
 StateHeader state_header(const goc_lbm* h)
 {
@@ -1726,7 +1725,6 @@ StateHeader state_header(const goc_lbm* h)
     hd.step = h->step;
     hd.f_bytes = h->f_elems * sb;
     hd.F_bytes = h->F_elems * fb;
-    hd.g_bytes = h->g_elems * sb;
     hd.ref_bytes = scaled_storage(h->storage) ? h->ref_rows * goc::kRef * 4 : 0;
     hd.ref_base = h->ref_base;
     return hd;
@@ -1751,7 +1749,7 @@ int goc_lbm_get_state(goc_lbm_t* h, void* buf, size_t* bytes)
     std::vector<int32_t> shapes;
     run_shapes(h, shapes);
     const size_t sh_bytes = shapes.size() * 4;
-    const size_t need = sizeof(hd) + sh_bytes + hd.ref_bytes + hd.f_bytes + hd.F_bytes + hd.g_bytes;
+    const size_t need = sizeof(hd) + sh_bytes + hd.ref_bytes + hd.f_bytes + hd.F_bytes;
     if (!buf) {
         *bytes = need;
         return GOC_OK;
@@ -1766,9 +1764,6 @@ int goc_lbm_get_state(goc_lbm_t* h, void* buf, size_t* bytes)
     p += hd.ref_bytes;
     HIPOK(hipMemcpyAsync(p, h->f[h->cur], hd.f_bytes, hipMemcpyDeviceToHost, h->stream));
     HIPOK(hipMemcpyAsync(p + hd.f_bytes, h->F[h->cur], hd.F_bytes, hipMemcpyDeviceToHost, h->stream));
-    if (hd.g_bytes)
-        HIPOK(hipMemcpyAsync(p + hd.f_bytes + hd.F_bytes, h->g[h->cur], hd.g_bytes, hipMemcpyDeviceToHost,
-                             h->stream));
     HIPOK(hipStreamSynchronize(h->stream));
     *bytes = need;
     return GOC_OK;
@@ -1788,13 +1783,12 @@ int goc_lbm_set_state(goc_lbm_t* h, const void* buf, size_t bytes)
     if (std::memcmp(hd.magic, "GOCLBM01", 8) != 0 || hd.version != kStateVersion || hd.storage != h->storage ||
         hd.nruns != h->nruns || hd.mhd != mine.mhd)
         return fail(GOC_ESTATE, "state blob does not match this run (magic, version, storage, run count or MHD)");
-    if (hd.f_bytes != mine.f_bytes || hd.F_bytes != mine.F_bytes || hd.g_bytes != mine.g_bytes ||
-        hd.ref_bytes != mine.ref_bytes)
-        return fail(GOC_ESTATE, "state blob sizes (slots %lld, force %lld, D2Q5 %lld, reference %lld bytes) do not "
-                    "match this run's (%lld, %lld, %lld, %lld)", (long long)hd.f_bytes, (long long)hd.F_bytes,
-                    (long long)hd.g_bytes, (long long)hd.ref_bytes, (long long)mine.f_bytes, (long long)mine.F_bytes,
-                    (long long)mine.g_bytes, (long long)mine.ref_bytes);
-    const size_t need = sizeof(hd) + sh_bytes + hd.ref_bytes + hd.f_bytes + hd.F_bytes + hd.g_bytes;
+    if (hd.f_bytes != mine.f_bytes || hd.F_bytes != mine.F_bytes || hd.ref_bytes != mine.ref_bytes)
+        return fail(GOC_ESTATE, "state blob sizes (slots %lld, force %lld, reference %lld bytes) do not "
+                    "match this run's (%lld, %lld, %lld)", (long long)hd.f_bytes, (long long)hd.F_bytes,
+                    (long long)hd.ref_bytes, (long long)mine.f_bytes, (long long)mine.F_bytes,
+                    (long long)mine.ref_bytes);
+    const size_t need = sizeof(hd) + sh_bytes + hd.ref_bytes + hd.f_bytes + hd.F_bytes;
     if (bytes != need) return fail(GOC_ESTATE, "state blob of %zu bytes, this run needs %zu", bytes, need);
     const char* p = static_cast<const char*>(buf) + sizeof(hd);
     if (std::memcmp(p, shapes.data(), sh_bytes) != 0)
@@ -1806,9 +1800,6 @@ int goc_lbm_set_state(goc_lbm_t* h, const void* buf, size_t bytes)
     p += hd.ref_bytes;
     HIPOK(hipMemcpyAsync(h->f[h->cur], p, hd.f_bytes, hipMemcpyHostToDevice, h->stream));
     HIPOK(hipMemcpyAsync(h->F[h->cur], p + hd.f_bytes, hd.F_bytes, hipMemcpyHostToDevice, h->stream));
-    if (hd.g_bytes)
-        HIPOK(hipMemcpyAsync(h->g[h->cur], p + hd.f_bytes + hd.F_bytes, hd.g_bytes, hipMemcpyHostToDevice,
-                             h->stream));
     h->step = hd.step;
     h->watch_last = hd.step;
     h->ref_base = hd.ref_base;

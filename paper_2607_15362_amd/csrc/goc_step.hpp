@@ -214,7 +214,9 @@ __device__ inline RunBytes run_bytes(const RunDesc& d, const Pools<S, FT>& pl)
     b.plane_s = uint32_t(d.plane * sizeof(S));
     b.f_all = uint32_t((int64_t)d.pitch * (d.ny + 2) * sizeof(S));
     b.F_all = uint32_t((int64_t)d.pitchF * d.ny * sizeof(FT));
-    b.g_all = b.f_all;
+    // (the D2Q5 planes start g_off - f_off elements into the rows of the slot
+    // pool: their region ends where the pool's does)
+    b.g_all = b.f_all - uint32_t((d.g_off - d.f_off) * (int64_t)sizeof(S));
     b.g_comp = uint32_t(kM * d.plane * sizeof(S));
     b.ny = d.ny;
     return b;

@@ -87,22 +87,23 @@ def _run(case, init_fields, lid, waves):
 
 
 # checkpoint header: magic, version, storage, nruns, mhd, step, the sizes of
-# the slots, force, D2Q5 slots and reference table, the reference base step;
-# then (nx, ny, mhd) per run and the four regions
-HEADER = struct.Struct("<8s4i6q")
+# the slot pool (D2Q5 slots in its rows), force and reference table, the
+# reference base step; then (nx, ny, mhd) per run and the three regions
+HEADER = struct.Struct("<8s4i5q")
 STORED = {"f64": (np.float64, np.float64), "f32": (np.float32, np.float32)}
 
 
 def _stored(blob, storage):
-    """Raw populations (storage format), lagged force and D2Q5 populations
-    (empty without MHD) of a checkpoint."""
-    _, _, _, nruns, _, step, fb, Fb, gb, rb, _ = HEADER.unpack_from(blob)
+    """Raw slot pool (storage format: populations and, with MHD, the D2Q5
+    slots) and lagged force of a checkpoint."""
+    _, version, _, nruns, _, step, fb, Fb, rb, _ = HEADER.unpack_from(blob)
+    assert version == 3
     o = HEADER.size + 12 * nruns + rb
     tf, tF = STORED[storage]
     f = np.frombuffer(blob, dtype=tf, count=fb // np.dtype(tf).itemsize, offset=o)
     F = np.frombuffer(blob, dtype=tF, count=Fb // np.dtype(tF).itemsize, offset=o + fb)
-    g = np.frombuffer(blob, dtype=tf, count=gb // np.dtype(tf).itemsize, offset=o + fb + Fb)
-    return step, np.concatenate([f, g]), F
+    assert len(blob) == o + fb + Fb
+    return step, f, F
 
 
 # a few units of rounding: eps of FP64 / FP32

@@ -62,6 +62,16 @@ def test_instrument_rejects_bad_arguments():
     assert L.goc_ceiling_pattern(4096, 1024, 1, 4, 64, 4, 1, 10, None, None) == B.GOC_EINVAL
     assert L.goc_ceiling_copy(100, 10, None, C.byref(out)) == B.GOC_EINVAL
     assert L.goc_ceiling_copy(1 << 20, 0, None, C.byref(out)) == B.GOC_EINVAL
+    for args in [(100, 1, 1, 0, 32, 10),        # not a multiple of 16
+                 (1 << 20, 3, 1, 0, 32, 10),    # reads beyond 2
+                 (1 << 20, 1, -1, 0, 32, 10),   # negative writes
+                 (1 << 20, 0, 0, 0, 32, 10),    # nothing moved
+                 (1 << 20, 1, 1, 2, 32, 10),    # store policy neither 0 nor 1
+                 (1 << 20, 1, 1, 0, 0, 10),     # work-groups per CU outside 1 .. 64
+                 (1 << 20, 1, 1, 0, 65, 10),
+                 (1 << 20, 1, 1, 0, 32, 0)]:    # no timed launch
+        assert L.goc_ceiling_mix(*args, None, C.byref(out)) == B.GOC_EINVAL, args
+    assert L.goc_ceiling_mix(1 << 20, 1, 1, 0, 32, 10, None, None) == B.GOC_EINVAL
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
@@ -145,8 +155,10 @@ def test_create_rejects_bad_collision_choice_before_touching_the_device(lib):
 
 
 @pytest.mark.parametrize("nx,ny,storage,mhd,ok", [
-    (8192, 8192, 1, 1, True),      # FP32 with the D2Q5 slots: 2.7 GB per slot region
-    (8192, 8192, 0, 1, False),     # FP64: 5.4 GB, above the 4 GiB of 32-bit offsets
+    (8192, 4096, 1, 1, True),      # FP32 with the D2Q5 slots in the slot pool's rows: 2.7 GB
+    (8192, 8192, 1, 1, False),     # the same at 8192 rows: 5.4 GB, above the 4 GiB of 32-bit offsets
+    (8192, 4096, 0, 1, False),     # FP64 with the D2Q5 slots: 5.4 GB
+    (8192, 8192, 0, 0, False),     # FP64 plain: 4.9 GB
     (12288, 12288, 2, 0, True),    # 16-bit: 2.7 GB
     (16384, 16384, 1, 0, False),   # FP32: 9.7 GB
     (65536, 65536, 2, 0, False),   # beyond 2^31 nodes
