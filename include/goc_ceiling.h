@@ -51,11 +51,13 @@ int goc_ceiling_copy(int64_t bytes, int reps, void* stream, double* us_per_launc
    each (a positive multiple of 16), 16-byte vectors, element k of every
    output written from element k of every input (four in flight per
    thread), with plain (nontemporal = 0) or non-temporal stores, wg_per_cu
-   (1 .. 64) work-groups of 256 threads per compute unit; mean microseconds
-   per launch over `reps` launches after 4 untimed ones.  A launch moves
-   (reads + writes) * bytes. */
-int goc_ceiling_mix(int64_t bytes, int reads, int writes, int nontemporal, int wg_per_cu, int reps, void* stream,
-                    double* us_per_launch);
+   (1 .. 64) work-groups of 256 threads per compute unit, swept grid-stride
+   (chunked = 0: the whole grid moves through the buffers together) or in
+   contiguous shares (chunked = 1: each work-group sweeps one share of them
+   on its own); mean microseconds per launch over `reps` launches after 4
+   untimed ones.  A launch moves (reads + writes) * bytes. */
+int goc_ceiling_mix(int64_t bytes, int reads, int writes, int nontemporal, int chunked, int wg_per_cu, int reps,
+                    void* stream, double* us_per_launch);
 
 #ifdef __cplusplus
 }

@@ -5,7 +5,14 @@ argument marshalling only.
 
 prints the same-pattern time of the tiled step (default: the 4096 x 1024
 Hartmann layout, FP32, D2Q5 slots, 64 x 4 tiles, non-temporal stores) and a
-1 GiB one-stream copy as one JSON line.
+1 GiB one-stream copy as one JSON line;
+
+    python -m paper_2607_15362_amd.ceiling mix
+
+prints one JSON line per read / write mix of plain 1 GiB streams (reads
+only, writes only, 1:1, 2:1, 1:2, 2:2), swept grid-stride or in one
+contiguous share per work-group, plain and non-temporal stores, at 2 to 32
+work-groups per compute unit.
 """
 from __future__ import annotations
 
@@ -21,6 +28,8 @@ SIGNATURES = {
     "goc_ceiling_pattern": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                       C.c_void_p, C.POINTER(C.c_double)]),
     "goc_ceiling_copy": (C.c_int, [C.c_int64, C.c_int, C.c_void_p, C.POINTER(C.c_double)]),
+    "goc_ceiling_mix": (C.c_int, [C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p,
+                                  C.POINTER(C.c_double)]),
 }
 
 _lib = None
@@ -62,7 +71,38 @@ def copy_us(nbytes: int, reps: int = 50, stream: int = 0) -> float:
     return out.value
 
 
+def mix_us(nbytes: int, reads: int, writes: int, nontemporal: bool = False, wg_per_cu: int = 32, reps: int = 20,
+           stream: int = 0, chunked: bool = False) -> float:
+    """Mean microseconds per launch of plain streams: `reads` inputs and
+    `writes` outputs of nbytes each, swept grid-stride or (chunked) in one
+    contiguous share per work-group."""
+    out = C.c_double(0.0)
+    _check(lib().goc_ceiling_mix(nbytes, reads, writes, int(bool(nontemporal)), int(bool(chunked)), wg_per_cu, reps,
+                                 C.c_void_p(stream or None), C.byref(out)), "goc_ceiling_mix")
+    return out.value
+
+
+def mix_table(nbytes: int = 1 << 30):
+    """One record per read / write mix, sweep order, store policy and launch
+    width."""
+    rows = []
+    for reads, writes in ((1, 0), (2, 0), (0, 1), (0, 2), (1, 1), (2, 1), (1, 2), (2, 2)):
+        for chunked in (False, True):
+            for nt in ((False,) if writes == 0 else (False, True)):
+                for wg in (2, 4, 8, 16, 32):
+                    us = mix_us(nbytes, reads, writes, nt, wg, chunked=chunked)
+                    moved = (reads + writes) * nbytes
+                    rows.append({"reads": reads, "writes": writes, "chunked": int(chunked), "nontemporal": int(nt),
+                                 "wg_per_cu": wg, "us_per_launch": round(us, 2),
+                                 "GB_s": round(moved / (us * 1e-6) / 1e9, 1)})
+    return rows
+
+
 def main(argv):
+    if argv[:1] == ["mix"]:
+        for row in mix_table():
+            print(json.dumps(row), flush=True)
+        return
     vals = [int(v) for v in argv] if argv else [4096, 1024, 1, 4, 4, 1]
     nx, ny, mhd, sb, rows, nt = vals[:6]
     cols = vals[6] if len(vals) > 6 else 64

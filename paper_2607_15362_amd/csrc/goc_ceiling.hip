@@ -173,9 +173,11 @@ __global__ void __launch_bounds__(256) copy_kernel(const float4* __restrict__ a,
 
 // Streams of 16-byte vectors in a chosen read / write mix: R input and W
 // output buffers of n vectors each, element k of every output written from
-// element k of every input (grid-stride, four elements in flight per thread);
-// with no output each thread folds what it reads into one value, written
-// only if it matches a value the inputs never hold (so no load is dropped).
+// element k of every input, four elements in flight per thread, in one of
+// two orders: grid-stride (the whole grid sweeps the buffers together) or
+// CHUNK (each work-group sweeps a contiguous share of them on its own); with
+// no output each thread folds what it reads into one value, written only if
+// it matches a value the inputs never hold (so no load is dropped).
 typedef float f4v __attribute__((ext_vector_type(4)));
 
 template <bool NT>
@@ -187,13 +189,19 @@ __device__ inline void st4(f4v* p, f4v v)
         *p = v;
 }
 
-template <int R, int W, bool NT>
+template <int R, int W, bool NT, bool CHUNK>
 __global__ void __launch_bounds__(256) mix_kernel(const f4v* __restrict__ a0, const f4v* __restrict__ a1,
                                                   f4v* __restrict__ o0, f4v* __restrict__ o1, int64_t n,
                                                   float* __restrict__ sink)
 {
-    const int64_t s = (int64_t)gridDim.x * 256;
-    int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    // the elements [lo, hi) this thread's work-group covers, with stride s
+    int64_t s = (int64_t)gridDim.x * 256, k = (int64_t)blockIdx.x * 256 + threadIdx.x, hi = n;
+    if constexpr (CHUNK) {
+        const int64_t per = (n + gridDim.x - 1) / gridDim.x, lo = (int64_t)blockIdx.x * per;
+        hi = lo + per < n ? lo + per : n;
+        s = 256;
+        k = lo + threadIdx.x;
+    }
     f4v acc = {0.f, 0.f, 0.f, 0.f};
     auto in = [&](int64_t e) {
         f4v v = {1.f, 1.f, 1.f, 1.f};
@@ -206,30 +214,35 @@ __global__ void __launch_bounds__(256) mix_kernel(const f4v* __restrict__ a0, co
         if constexpr (W >= 2) st4<NT>(o1 + e, v + 1.f);
         if constexpr (W == 0) acc += v;
     };
-    for (; k + 3 * s < n; k += 4 * s) {
+    for (; k + 3 * s < hi; k += 4 * s) {
         const f4v v0 = in(k), v1 = in(k + s), v2 = in(k + 2 * s), v3 = in(k + 3 * s);
         out(k, v0);
         out(k + s, v1);
         out(k + 2 * s, v2);
         out(k + 3 * s, v3);
     }
-    for (; k < n; k += s) out(k, in(k));
+    for (; k < hi; k += s) out(k, in(k));
     if constexpr (W == 0)
         if (acc.x + acc.y + acc.z + acc.w == -1.f) sink[0] = acc.x;   // (the buffers hold zeros)
 }
 
-template <int R, int W, bool NT>
+template <int R, int W, bool NT, bool CHUNK>
 hipError_t launch_mix(int blocks, hipStream_t st, void* const* p, int64_t n, float* sink)
 {
-    hipLaunchKernelGGL((mix_kernel<R, W, NT>), dim3(blocks), dim3(256), 0, st, static_cast<const f4v*>(p[0]),
-                       static_cast<const f4v*>(p[1]), static_cast<f4v*>(p[2]), static_cast<f4v*>(p[3]), n, sink);
+    hipLaunchKernelGGL((mix_kernel<R, W, NT, CHUNK>), dim3(blocks), dim3(256), 0, st,
+                       static_cast<const f4v*>(p[0]), static_cast<const f4v*>(p[1]), static_cast<f4v*>(p[2]),
+                       static_cast<f4v*>(p[3]), n, sink);
     return hipGetLastError();
 }
 
 template <int R, int W>
-hipError_t launch_mix_nt(bool nt, int blocks, hipStream_t st, void* const* p, int64_t n, float* sink)
+hipError_t launch_mix_nt(bool nt, bool chunk, int blocks, hipStream_t st, void* const* p, int64_t n, float* sink)
 {
-    return nt ? launch_mix<R, W, true>(blocks, st, p, n, sink) : launch_mix<R, W, false>(blocks, st, p, n, sink);
+    if (chunk)
+        return nt ? launch_mix<R, W, true, true>(blocks, st, p, n, sink)
+                  : launch_mix<R, W, false, true>(blocks, st, p, n, sink);
+    return nt ? launch_mix<R, W, true, false>(blocks, st, p, n, sink)
+              : launch_mix<R, W, false, false>(blocks, st, p, n, sink);
 }
 
 struct Events {
@@ -381,11 +394,12 @@ extern "C" int goc_ceiling_copy(int64_t bytes, int reps, void* stream, double* u
     return GOC_OK;
 }
 
-extern "C" int goc_ceiling_mix(int64_t bytes, int reads, int writes, int nontemporal, int wg_per_cu, int reps,
-                               void* stream, double* us_per_launch)
+extern "C" int goc_ceiling_mix(int64_t bytes, int reads, int writes, int nontemporal, int chunked, int wg_per_cu,
+                               int reps, void* stream, double* us_per_launch)
 {
     if (!us_per_launch || bytes < 16 || bytes % 16 != 0 || reads < 0 || reads > 2 || writes < 0 || writes > 2 ||
-        reads + writes < 1 || (nontemporal != 0 && nontemporal != 1) || wg_per_cu < 1 || wg_per_cu > 64 || reps < 1)
+        reads + writes < 1 || (nontemporal != 0 && nontemporal != 1) || (chunked != 0 && chunked != 1) ||
+        wg_per_cu < 1 || wg_per_cu > 64 || reps < 1)
         return GOC_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
     Buffers buf(st);
@@ -405,17 +419,17 @@ extern "C" int goc_ceiling_mix(int64_t bytes, int reads, int writes, int nontemp
     const int64_t n = bytes / 16;
     const int blocks = wg_per_cu * ncu;
     float* sink = static_cast<float*>(buf.p[4]);
-    const bool nt = nontemporal != 0;
+    const bool nt = nontemporal != 0, ch = chunked != 0;
     auto launch = [&]() -> hipError_t {
         switch (reads * 3 + writes) {
-            case 1: return launch_mix_nt<0, 1>(nt, blocks, st, buf.p, n, sink);
-            case 2: return launch_mix_nt<0, 2>(nt, blocks, st, buf.p, n, sink);
-            case 3: return launch_mix_nt<1, 0>(nt, blocks, st, buf.p, n, sink);
-            case 4: return launch_mix_nt<1, 1>(nt, blocks, st, buf.p, n, sink);
-            case 5: return launch_mix_nt<1, 2>(nt, blocks, st, buf.p, n, sink);
-            case 6: return launch_mix_nt<2, 0>(nt, blocks, st, buf.p, n, sink);
-            case 7: return launch_mix_nt<2, 1>(nt, blocks, st, buf.p, n, sink);
-            default: return launch_mix_nt<2, 2>(nt, blocks, st, buf.p, n, sink);
+            case 1: return launch_mix_nt<0, 1>(nt, ch, blocks, st, buf.p, n, sink);
+            case 2: return launch_mix_nt<0, 2>(nt, ch, blocks, st, buf.p, n, sink);
+            case 3: return launch_mix_nt<1, 0>(nt, ch, blocks, st, buf.p, n, sink);
+            case 4: return launch_mix_nt<1, 1>(nt, ch, blocks, st, buf.p, n, sink);
+            case 5: return launch_mix_nt<1, 2>(nt, ch, blocks, st, buf.p, n, sink);
+            case 6: return launch_mix_nt<2, 0>(nt, ch, blocks, st, buf.p, n, sink);
+            case 7: return launch_mix_nt<2, 1>(nt, ch, blocks, st, buf.p, n, sink);
+            default: return launch_mix_nt<2, 2>(nt, ch, blocks, st, buf.p, n, sink);
         }
     };
     for (int k = 0; k < 4; ++k)

@@ -45,13 +45,21 @@ def test_bench_json_line():
 @pytest.mark.gpu
 def test_ceiling_instrument_on_small_and_ragged_grids():
     """The instrument runs (in bounds) on grids smaller than a tile and with
-    ragged edges, for both storage widths, and its copy moves a small buffer."""
+    ragged edges, for both storage widths, and its copy and read / write
+    mixes move small buffers."""
     from paper_2607_15362_amd import ceiling as CL
     for nx, ny, mhd, sb, rows, cols in [(3, 3, 1, 4, 16, 64), (70, 37, 1, 4, 8, 64), (130, 9, 0, 2, 4, 64),
                                         (200, 66, 1, 2, 16, 64), (3, 3, 1, 4, 4, 128), (200, 66, 1, 2, 4, 128)]:
         us = CL.pattern_us(nx, ny, bool(mhd), sb, rows, True, reps=5, cols=cols)
         assert 0 < us < 1e5
     assert 0 < CL.copy_us(1 << 20, reps=5) < 1e5
+    # the read / write mixes, on sizes that are not a multiple of the grid
+    # stride (the tail loop) and smaller than one work-group's share
+    for nbytes in (16, 48, (1 << 20) + 16 * 37):
+        for reads, writes in ((1, 0), (2, 0), (0, 1), (0, 2), (1, 1), (2, 1), (1, 2), (2, 2)):
+            for nt in (False, True):
+                for chunked in (False, True):
+                    assert 0 < CL.mix_us(nbytes, reads, writes, nt, wg_per_cu=8, reps=2, chunked=chunked) < 1e5
 
 
 def test_bench_refuses_more_than_one_gpu():

@@ -62,16 +62,17 @@ def test_instrument_rejects_bad_arguments():
     assert L.goc_ceiling_pattern(4096, 1024, 1, 4, 64, 4, 1, 10, None, None) == B.GOC_EINVAL
     assert L.goc_ceiling_copy(100, 10, None, C.byref(out)) == B.GOC_EINVAL
     assert L.goc_ceiling_copy(1 << 20, 0, None, C.byref(out)) == B.GOC_EINVAL
-    for args in [(100, 1, 1, 0, 32, 10),        # not a multiple of 16
-                 (1 << 20, 3, 1, 0, 32, 10),    # reads beyond 2
-                 (1 << 20, 1, -1, 0, 32, 10),   # negative writes
-                 (1 << 20, 0, 0, 0, 32, 10),    # nothing moved
-                 (1 << 20, 1, 1, 2, 32, 10),    # store policy neither 0 nor 1
-                 (1 << 20, 1, 1, 0, 0, 10),     # work-groups per CU outside 1 .. 64
-                 (1 << 20, 1, 1, 0, 65, 10),
-                 (1 << 20, 1, 1, 0, 32, 0)]:    # no timed launch
+    for args in [(100, 1, 1, 0, 0, 32, 10),        # not a multiple of 16
+                 (1 << 20, 3, 1, 0, 0, 32, 10),    # reads beyond 2
+                 (1 << 20, 1, -1, 0, 0, 32, 10),   # negative writes
+                 (1 << 20, 0, 0, 0, 0, 32, 10),    # nothing moved
+                 (1 << 20, 1, 1, 2, 0, 32, 10),    # store policy neither 0 nor 1
+                 (1 << 20, 1, 1, 0, 2, 32, 10),    # sweep order neither 0 nor 1
+                 (1 << 20, 1, 1, 0, 0, 0, 10),     # work-groups per CU outside 1 .. 64
+                 (1 << 20, 1, 1, 0, 0, 65, 10),
+                 (1 << 20, 1, 1, 0, 0, 32, 0)]:    # no timed launch
         assert L.goc_ceiling_mix(*args, None, C.byref(out)) == B.GOC_EINVAL, args
-    assert L.goc_ceiling_mix(1 << 20, 1, 1, 0, 32, 10, None, None) == B.GOC_EINVAL
+    assert L.goc_ceiling_mix(1 << 20, 1, 1, 0, 0, 32, 10, None, None) == B.GOC_EINVAL
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
