@@ -25,7 +25,7 @@ namespace {
 using goc::kTileX;
 
 // The tiled step's memory traffic for one straight run: the same tile
-// shape (TX x TY) and placement (XCD bands, edge tiles shifted back), the same pulls of the own
+// shape (TX x TY) and placement (XCD bands, partial edge tiles), the same pulls of the own
 // node and of the ring around the tile (slot offsets of pull_off), one LDS
 // value per pulled node and a barrier, and the same stores (nine slots, ten
 // D2Q5 slots, the ghost rows of rows 0 and ny - 1, the two force planes).
@@ -44,13 +44,14 @@ pattern_kernel(goc::RunDesc d, goc::Pools<S, float> pl, float zero)
     const int nt = gx * gy;
     const int xcd = blockIdx.x & 7, q = nt >> 3, rem = nt & 7;
     const int t = xcd * q + min(xcd, rem) + (int)(blockIdx.x >> 3);
-    const int tx = nx < TX ? nx : TX, ty = ny < TY ? ny : TY;
     const int ox = (t % gx) * TX, oy = (t / gx) * TY;
-    const int x0 = ox < nx - tx ? ox : nx - tx, y0 = oy < ny - ty ? oy : ny - ty;
+    const bool px = d.bc_x == 0, py = d.bc_y == 0;
+    int tx, ty, x0, y0;
+    goc::tile_span(nx, TX, ox, px, tx, x0);
+    goc::tile_span(ny, TY, oy, py, ty, y0);
     const int lx = threadIdx.x, ly = threadIdx.y;
     const int i = x0 + lx, j = y0 + ly;
     const bool in = lx < tx && ly < ty;
-    const bool px = d.bc_x == 0, py = d.bc_y == 0;
     const goc::RunBytes b = goc::run_bytes(d, pl);
     const uint32_t planeF = uint32_t(d.plane * sizeof(float));
     const int ic = in ? i : x0, jc = in ? j : y0;

@@ -219,16 +219,32 @@ __device__ inline T tile_fd(V v, int l, int k, int n, bool periodic)
     return T(0.5) * (v(l + 1) - v(l - 1));
 }
 
+// Extent and origin along one axis of n nodes of the tile whose first owned
+// node is o (tile size T): the owned part, which is shorter than T at the
+// far edge of the axis; only where a wall ends the axis with fewer than
+// three nodes left is the tile shifted back to full size instead, so that
+// the three nodes of a one-sided difference lie in it (the nodes of the
+// shifted part belong to the neighbouring work-group and are not written).
+__host__ __device__ inline void tile_span(int n, int T, int o, bool periodic, int& ext, int& org)
+{
+    const int rest = n - o;
+    if (rest >= T || periodic || rest >= 3) {
+        ext = rest < T ? rest : T;
+        org = o;
+    } else {
+        ext = n < T ? n : T;
+        org = n - ext;
+    }
+}
+
 // The step of every node of every run.  Launch: grid = the tiles of all
 // runs (1-D), block (TX, TY) with TX = 64 or 128 columns; NT: non-temporal
 // stores; tile_first[r] = the first tile of run r (tile_first[nruns] = all
 // tiles), a run's tiles being ceil(nx/TX) * ceil(ny/TY) in row-major order.
 // A work-group owns the TX x TY nodes of tile (bx, by) of its run at
-// (TX bx, TY by); its tile is shifted back at the
-// far edges of the grid so that the three nodes of a one-sided difference
-// lie in it (nodes of the shifted part belong to the neighbouring
-// work-group and are not written here).  The moments of the tile and of the
-// ring around it go to LDS.  The hardware deals consecutive work-groups to
+// (TX bx, TY by), fewer at the far edges of the grid (tile_span; the threads
+// beyond them load a node of the tile and store nothing).  The moments of
+// the tile and of the ring around it go to LDS.  The hardware deals consecutive work-groups to
 // the eight XCDs in turn; the tiles are renumbered so that each XCD gets a
 // contiguous band of them (run by run, row-major), whose rings and
 // cross-tile pulls its L2 then serves.
@@ -256,15 +272,16 @@ tile_step_kernel(const RunDesc* __restrict__ runs, const int32_t* __restrict__ t
     const int t = tg - tile_first[run];
     const RunDesc& d = runs[run];
     const int nx = d.nx, ny = d.ny;
-    const int tx = nx < TX ? nx : TX, ty = ny < kTileY ? ny : kTileY;   // tile extent
     const int gx = (nx + TX - 1) / TX;
     const int ox = (t % gx) * TX, oy = (t / gx) * kTileY;          // first owned node
     const bool mhd_run = MHD && d.mhd;   // (a plain run of a mixed batch: no D2Q5 work)
-    const int x0 = ox < nx - tx ? ox : nx - tx, y0 = oy < ny - ty ? oy : ny - ty;   // tile origin
+    const bool px = d.bc_x == 0, py = d.bc_y == 0;
+    int tx, ty, x0, y0;   // tile extent and origin
+    tile_span(nx, TX, ox, px, tx, x0);
+    tile_span(ny, kTileY, oy, py, ty, y0);
     const int lx = threadIdx.x, ly = threadIdx.y;
     const int i = x0 + lx, j = y0 + ly;
     const bool in = lx < tx && ly < ty;
-    const bool px = d.bc_x == 0, py = d.bc_y == 0;
     const int64_t NB = (int64_t)nx * ny * sizeof(T);   // one metric plane in bytes
     const RunBytes b = run_bytes(d, pl);
     const uint32_t planeF = uint32_t(d.plane * sizeof(FT));
