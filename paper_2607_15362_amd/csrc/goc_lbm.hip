@@ -2,7 +2,8 @@
 //
 // The runtime owns, per handle: a table of run descriptors (one per
 // independent run; the single-run API is a batch of one), pooled device
-// state (two slot buffers for ping-pong, the lagged force, the D2Q5 slots),
+// state (two slot buffers for ping-pong, which hold the D2Q5 slots of MHD
+// runs in their rows, and two lagged-force buffers),
 // the metric pools (FP64), and HIP graphs of blocks of steps.
 #include <hip/hip_runtime.h>
 
@@ -738,7 +739,7 @@ int create_impl(goc_lbm_t** out, int nruns, const goc_grid* grid, const goc_metr
         d.plane = row;
         d.pitch = (p.mhd ? 2 * goc::kGPlanes : 9) * row;
         d.pitchF = 2 * row;
-        // slot regions (populations, D2Q5) hold two ghost rows, -1 and ny, for
+        // slot regions (populations and D2Q5 slots) hold two ghost rows, -1 and ny, for
         // the step kernel's pulls beyond the domain in y
         const int64_t region = (int64_t)d.pitch * (g.ny + 2) + 256, regionF = (int64_t)d.pitchF * g.ny + 256;
         // the step kernel addresses a run's regions with 32-bit byte offsets
