@@ -128,7 +128,19 @@ def cpu_baseline(case, seconds: float):
     return {"value": v, "unit": "MLUPS", "cores": all_cores, "kind": "oracle",
             "sample": f"{n} steps of the full {case.nx}x{case.ny} {case.name} grid in FP64 on {all_cores} "
                       f"threads ({dt:.1f} s), and {n1} on one ({dt1:.1f} s), each after one untimed step",
-            "one_core_value": v1}
+            "one_core_value": v1, "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+
+
+def cpu_model() -> str:
+    """The host processor's model name (first entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def copy_calibration(mib: int, reps: int):

@@ -40,6 +40,7 @@ def test_bench_json_line():
     for k in ("value", "unit", "cores", "kind", "sample"):
         assert k in c, k
     assert c["kind"] == "oracle" and c["value"] > 0 and c["cores"] >= 1 and c["one_core_value"] > 0
+    assert isinstance(c["cpu_model"], str) and c["cpu_model"] and c["host_cpus"] >= 1
 
 
 @pytest.mark.gpu
