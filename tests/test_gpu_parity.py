@@ -445,6 +445,28 @@ def test_checkpoint_resume_is_bitwise(oracle_lib):
     assert ei.value.code == B.GOC_ESTATE
 
 
+def test_set_state_refuses_other_format_versions():
+    """A checkpoint whose header names another format version (the layout of
+    the slot pool differs between versions) is refused with GOC_ESTATE and
+    leaves the run unchanged."""
+    case = W.Case("ver", 70, 33, "periodic", "wall", ("uniform", 0.0), ("tanh", 1.5), flow="hartmann",
+                  Re=20.0, Ha=5.0, mhd=True, storage="f32")
+    a = B.Run(case)
+    a.step(5)
+    blob = bytearray(a.get_state())
+    version = int.from_bytes(blob[8:12], "little")
+    assert version == 3
+    for other in (version - 1, version + 1):
+        blob[8:12] = other.to_bytes(4, "little")
+        before = a.get_state()
+        with pytest.raises(B.GocError) as ei:
+            a.set_state(bytes(blob))
+        assert ei.value.code == B.GOC_ESTATE
+        assert a.get_state() == before
+    blob[8:12] = version.to_bytes(4, "little")
+    a.set_state(bytes(blob))
+
+
 def test_set_state_refuses_blobs_of_other_grids():
     """A checkpoint of another grid is refused with GOC_ESTATE before any
     copy, also where the total size matches: in FP32 without MHD (rows padded
